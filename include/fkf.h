@@ -1,0 +1,251 @@
+/*
+ * fkf.h - C ABI of the MI355X fast random-walk Kalman filter library (libfkf.so).
+ *
+ * The library implements the fast Kalman filter for the random-walk forecast
+ * model of Saibaba, Miller & Kitanidis ("Fast Kalman filter using hierarchical
+ * matrices and a low-rank perturbative approach"):
+ *
+ *   s_{k} = s_{k-1} + w_k,  w_k ~ N(0, Gamma)        (Section 2.1, F_k = I)
+ *   y_k   = H_k s_k + v_k,  v_k ~ N(0, R_k)
+ *
+ * with the posterior covariance carried as Sigma_{k|k} = alpha_k Gamma - W D W^T
+ * (Section 2.3, eq. sigmakk) and Gamma, a Matern covariance (eq. maternfamily),
+ * held as a hierarchical matrix (Section 2.2.1).
+ *
+ * Conventions shared by every entry point
+ *   - Every function is extern "C", never throws and never exits.  It returns
+ *     FKF_OK or a negative fkf_status; fkf_last_error() then describes the
+ *     failure (thread-local string, valid until the next failing call).
+ *   - Arrays named *_host are host memory, read during the call and copied.
+ *     Arrays named *_dev are device memory on the current HIP device, owned by
+ *     the caller and accessed in stream order on `stream` (a hipStream_t passed
+ *     as void*; NULL means the default stream).  All floating-point boundary
+ *     buffers are float64.
+ *   - Multi-column arrays are column-major with an explicit leading dimension.
+ *   - Handles own all device memory they allocate; *_destroy frees it (after
+ *     synchronising the device).  A handle is used by one thread at a time.
+ *   - Argument errors are reported synchronously.  Numeric failures detected
+ *     on the device (non-finite data, a non-positive-definite Gram matrix) are
+ *     latched in the filter and reported by fkf_filter_status() and by the next
+ *     fkf_filter_step(); a filter that has failed refuses further steps.
+ *   - Points are given in the caller's order and every vector of length N
+ *     (state, variance, draws) uses that order.
+ */
+#ifndef FKF_H
+#define FKF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FKF_OK = 0,
+  FKF_E_ARG = -1,          /* invalid argument (null, size, mismatch) */
+  FKF_E_NOMEM = -2,        /* device allocation failed */
+  FKF_E_HIP = -3,          /* a HIP runtime call failed */
+  FKF_E_NOT_SPD = -4,      /* a matrix that must be positive definite is not */
+  FKF_E_RANK = -5,         /* the low-rank term would exceed max_rank */
+  FKF_E_NONFINITE = -6,    /* NaN/Inf met in data or state */
+  FKF_E_ORDER = -7,        /* call out of order (e.g. step after a failure) */
+  FKF_E_UNSUPPORTED = -8   /* valid request that this build does not support */
+} fkf_status;
+
+/* Matern smoothness nu = 1/2, 3/2, 5/2: the half-integer cases whose Bessel
+ * form (eq. maternfamily) reduces to an exponential times a polynomial. */
+typedef enum { FKF_MATERN_12 = 0, FKF_MATERN_32 = 1, FKF_MATERN_52 = 2 } fkf_kernel;
+
+typedef enum { FKF_FP64 = 0 } fkf_precision;
+
+/* Gamma[i,j] = variance * C_nu(|x_i - x_j| / length).  The paper's scaling
+ * factor alpha of eq. maternfamily is 1/length; the variance multiplies it. */
+typedef struct {
+  uint32_t struct_size;   /* sizeof(fkf_kernel_params) */
+  int32_t kind;           /* fkf_kernel */
+  double variance;        /* theta > 0 */
+  double length;          /* ell > 0 */
+} fkf_kernel_params;
+
+/* Hierarchical-matrix parameters (Section 2.2.1).  Clusters are built by
+ * bisecting the longest side of each cluster's bounding box until at most
+ * leaf_size points remain; (s, t) is admissible when
+ * max(diam s, diam t) <= eta * dist(s, t).  Admissible blocks are
+ * U_s K(xi_s, xi_t) U_t^T with tensor Chebyshev interpolation at p nodes per
+ * dimension.  With block_tol > 0, p is raised per tree level (up to
+ * cheb_order_max) until the sampled relative Frobenius error of the closest
+ * admissible block of that level is <= block_tol (the paper chooses block
+ * ranks by a relative Frobenius tolerance, Section 4.1.2); with
+ * block_tol <= 0, p = cheb_order everywhere. */
+typedef struct {
+  uint32_t struct_size;   /* sizeof(fkf_hmat_params) */
+  int32_t leaf_size;      /* 1..64 */
+  int32_t cheb_order;     /* minimum p, 2..16 */
+  int32_t cheb_order_max; /* maximum p when block_tol > 0 (>= cheb_order, <= 16) */
+  double eta;             /* admissibility parameter, > 0 */
+  double block_tol;       /* per-level block tolerance, or <= 0 */
+  int32_t precision;      /* fkf_precision */
+} fkf_hmat_params;
+
+typedef struct {
+  uint32_t struct_size;   /* sizeof(fkf_filter_params) */
+  int32_t max_rank;       /* capacity of the low-rank term W (>= n_m) */
+  double rank_rtol;       /* relative truncation tolerance for W (Algorithm 5) */
+} fkf_filter_params;
+
+/* Statistics of a built covariance operator. */
+typedef struct {
+  int64_t n;                 /* number of points */
+  int32_t dim;               /* spatial dimension */
+  int32_t n_leaves;
+  int32_t n_levels;          /* tree depth + 1 */
+  int64_t n_near_blocks;     /* stored near-field blocks (symmetric half) */
+  int64_t n_near_pairs;      /* ordered near-field leaf pairs */
+  int64_t n_far_pairs;       /* ordered admissible pairs */
+  int64_t near_bytes;        /* bytes of stored near-field entries */
+  int64_t far_coef_per_rhs;  /* sum over far clusters of p^dim */
+  int32_t cheb_p[32];        /* Chebyshev nodes per dimension at each level */
+  int64_t covered_entries;   /* sum of |s|*|t| over all blocks (= n*n for a partition) */
+} fkf_cov_info_t;
+
+typedef struct fkf_cov fkf_cov;
+typedef struct fkf_obs fkf_obs;
+typedef struct fkf_filter fkf_filter;
+
+/* ---------------------------------------------------------------- Gamma --- */
+
+/* Build Gamma_sys as an H-matrix over n points of dimension d (2 or 3).
+ * pts_host: n x d row-major coordinates.  Assembles the near-field blocks on
+ * the device (Section 2.2.1; the paper's construction cost is O(k^2 N),
+ * Section 4.1.2).  On success *out owns all device memory of the operator. */
+fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d,
+                         const fkf_kernel_params *kernel,
+                         const fkf_hmat_params *hmat, void *stream,
+                         fkf_cov **out);
+
+/* Y = Gamma X for X_dev (n x nrhs, leading dimension ldx >= n) into Y_dev
+ * (n x nrhs, ldy >= n).  X and Y must not overlap.  This is the matrix-vector
+ * product the paper names as the dominant cost (Section 2.5): the cross
+ * covariance Gamma H^T and the products inside the eigensolver.  nrhs = 0 is
+ * a no-op.  Uses a workspace held by the handle (grown on demand). */
+fkf_status fkf_cov_apply(fkf_cov *cov, const double *X_dev, int64_t ldx,
+                         int32_t nrhs, double *Y_dev, int64_t ldy, void *stream);
+
+fkf_status fkf_cov_info(const fkf_cov *cov, fkf_cov_info_t *info);
+
+/* Host-only planning: builds the cluster tree, the block partition and the
+ * per-level Chebyshev orders exactly as fkf_cov_build does and reports them,
+ * without touching the GPU. */
+fkf_status fkf_cov_plan(const double *pts_host, int64_t n, int32_t d,
+                        const fkf_kernel_params *kernel, const fkf_hmat_params *hmat,
+                        fkf_cov_info_t *info);
+
+/* Tree-order permutation (perm_host[i] = caller index of tree position i). */
+fkf_status fkf_cov_perm(const fkf_cov *cov, int64_t *perm_host);
+
+void fkf_cov_destroy(fkf_cov *cov);
+
+/* ----------------------------------------------------------- observations --- */
+
+/* Measurement operator H (n_m x n) from host CSR arrays (rowptr has n_m+1
+ * entries, col in [0, n)), plus the diagonal of the noise covariance R
+ * (noise_var_host, n_m entries, each > 0). */
+fkf_status fkf_obs_create_csr(int32_t n_m, int64_t n, const int64_t *rowptr_host,
+                              const int32_t *col_host, const double *val_host,
+                              const double *noise_var_host, void *stream,
+                              fkf_obs **out);
+
+/* Straight-ray travel-time operator on a regular grid of the unit square/cube
+ * (Section 4.1, eq. lineartomography): H[m, c] is the length of the segment
+ * src_m -> rcv_m inside cell c.  grid_host holds d cell counts; cell
+ * (i, j[, k]) has flat index i + nx*(j + ny*k).  A ray is cut at every grid
+ * line/plane crossing; a piece lying exactly on an interior grid line/plane is
+ * shared equally by the cells on both sides.  src_host, rcv_host: n_m x d
+ * row-major. */
+fkf_status fkf_obs_create_rays(int32_t d, const int32_t *grid_host, int32_t n_m,
+                               const double *src_host, const double *rcv_host,
+                               const double *noise_var_host, void *stream,
+                               fkf_obs **out);
+
+/* Host-only form of the ray operator above (no GPU): writes rowptr_host
+ * (n_m + 1 entries) and *nnz; when col_host/val_host are non-NULL they must
+ * hold `capacity` entries and receive the CSR columns/values (FKF_E_ARG when
+ * capacity < nnz). */
+fkf_status fkf_rays_host(int32_t d, const int32_t *grid_host, int32_t n_m,
+                         const double *src_host, const double *rcv_host,
+                         int64_t *rowptr_host, int64_t *nnz, int32_t *col_host,
+                         double *val_host, int64_t capacity);
+
+/* Sizes of H; nnz may be NULL. */
+fkf_status fkf_obs_shape(const fkf_obs *obs, int32_t *n_m, int64_t *n, int64_t *nnz);
+
+/* Copy H out as CSR to host arrays sized from fkf_obs_shape. */
+fkf_status fkf_obs_get_csr(const fkf_obs *obs, int64_t *rowptr_host,
+                           int32_t *col_host, double *val_host);
+
+/* y_dev (n_m) = H x_dev (n). */
+fkf_status fkf_obs_apply(const fkf_obs *obs, const double *x_dev, double *y_dev,
+                         void *stream);
+
+void fkf_obs_destroy(fkf_obs *obs);
+
+/* ----------------------------------------------------------------- filter --- */
+
+/* Create a filter with s_{0|0} = s0_dev (NULL: zero) and
+ * Sigma_{0|0} = alpha0 * Gamma, alpha0 >= 0 (Section 2.3; the experiments use
+ * s_0 = Sigma_0 = 0, i.e. alpha0 = 0).  params may be NULL for defaults. */
+fkf_status fkf_filter_create(fkf_cov *cov, const double *s0_dev, double alpha0,
+                             const fkf_filter_params *params, void *stream,
+                             fkf_filter **out);
+
+/* One predict + update with observations y_dev (n_m values) of operator obs.
+ * Prediction: alpha <- alpha + 1, estimate unchanged (F = I).  Update:
+ * while the filter's low-rank basis is that of obs (the first step, and every
+ * later step with the same obs), the constant-H update of Algorithms 2/3
+ * using the generalized eigenpairs of obs (computed once, Section 2.2.2);
+ * a step with a different obs after that uses the update of Section 2.4. */
+fkf_status fkf_filter_step(fkf_filter *f, const fkf_obs *obs, const double *y_dev,
+                           void *stream);
+
+/* Synchronise `stream` and return the latched device-side status. */
+fkf_status fkf_filter_status(fkf_filter *f, void *stream);
+
+/* s_dev (n) = current estimate s_{k|k}. */
+fkf_status fkf_filter_mean(const fkf_filter *f, double *s_dev, void *stream);
+
+/* var_dev (n) = diag Sigma_{k|k} = alpha_k diag Gamma - diag(W D W^T)
+ * (Section 3.1). */
+fkf_status fkf_filter_variance(const fkf_filter *f, double *var_dev, void *stream);
+
+/* Conditional realizations (Section 3.3):
+ * out[:, j] = s_{k|k} + alpha^{1/2} (g_j - W Sigma_- W^T Gamma^{-1} g_j), with
+ * Sigma_- = I - (I - D/alpha)^{1/2}.  g_dev holds ns unconditional draws
+ * g ~ N(0, Gamma) (n x ns, leading dimension ldg); out_dev is n x ns (ldo). */
+fkf_status fkf_filter_realize(const fkf_filter *f, const double *g_dev, int32_t ns,
+                              int64_t ldg, double *out_dev, int64_t ldo, void *stream);
+
+/* Step count k, alpha_k and the rank of the low-rank term (any may be NULL). */
+fkf_status fkf_filter_info(const fkf_filter *f, int64_t *k, double *alpha,
+                           int32_t *rank);
+
+/* Constant-H basis: the generalized eigenvalues lambda (descending) and the
+ * per-mode weights c = alpha - D of Sigma in the basis Gamma^{-1} U, copied to
+ * host arrays of length `rank` (as returned by fkf_filter_info).  Returns
+ * FKF_E_ORDER when the filter is not in the constant-H form. */
+fkf_status fkf_filter_modes(const fkf_filter *f, double *lambda_host,
+                            double *weight_host);
+
+void fkf_filter_destroy(fkf_filter *f);
+
+/* -------------------------------------------------------------------- misc --- */
+
+const char *fkf_last_error(void);
+
+/* Library version string. */
+const char *fkf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FKF_H */

@@ -1,0 +1,235 @@
+"""Python binding of libfkf.so, the MI355X fast random-walk Kalman filter.
+
+Argument marshalling only: every numeric step runs in the library's HIP
+kernels.  Device arrays are torch CUDA (ROCm) float64 tensors; the library is
+driven on torch's current stream.  Importing this package fails loudly when
+the library has not been built (``python -m paper_1405_2276_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfkf.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1405_2276_amd.build`")
+try:
+    _lib = ctypes.CDLL(LIB_PATH)
+except OSError as e:  # pragma: no cover
+    raise ImportError(f"cannot load {LIB_PATH}: {e}") from e
+
+_c_dbl_p = ctypes.POINTER(ctypes.c_double)
+_c_i64_p = ctypes.POINTER(ctypes.c_int64)
+_c_i32_p = ctypes.POINTER(ctypes.c_int32)
+_vp = ctypes.c_void_p
+
+MATERN = {0.5: 0, 1.5: 1, 2.5: 2}
+
+STATUS = {0: "FKF_OK", -1: "FKF_E_ARG", -2: "FKF_E_NOMEM", -3: "FKF_E_HIP",
+          -4: "FKF_E_NOT_SPD", -5: "FKF_E_RANK", -6: "FKF_E_NONFINITE",
+          -7: "FKF_E_ORDER", -8: "FKF_E_UNSUPPORTED"}
+
+
+class FkfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+
+
+class KernelParams(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("kind", ctypes.c_int32),
+                ("variance", ctypes.c_double), ("length", ctypes.c_double)]
+
+
+class HmatParams(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("leaf_size", ctypes.c_int32),
+                ("cheb_order", ctypes.c_int32), ("cheb_order_max", ctypes.c_int32),
+                ("eta", ctypes.c_double), ("block_tol", ctypes.c_double),
+                ("precision", ctypes.c_int32)]
+
+
+class FilterParams(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("max_rank", ctypes.c_int32),
+                ("rank_rtol", ctypes.c_double)]
+
+
+class CovInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("dim", ctypes.c_int32), ("n_leaves", ctypes.c_int32),
+                ("n_levels", ctypes.c_int32), ("n_near_blocks", ctypes.c_int64),
+                ("n_near_pairs", ctypes.c_int64), ("n_far_pairs", ctypes.c_int64),
+                ("near_bytes", ctypes.c_int64), ("far_coef_per_rhs", ctypes.c_int64),
+                ("cheb_p", ctypes.c_int32 * 32), ("covered_entries", ctypes.c_int64)]
+
+
+def _sig(name, res, args):
+    fn = getattr(_lib, name)
+    fn.restype = res
+    fn.argtypes = args
+    return fn
+
+
+_i = ctypes.c_int
+_lib.fkf_last_error.restype = ctypes.c_char_p
+_lib.fkf_version.restype = ctypes.c_char_p
+_sig("fkf_cov_build", _i, [_c_dbl_p, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(KernelParams),
+                           ctypes.POINTER(HmatParams), _vp, ctypes.POINTER(_vp)])
+_sig("fkf_cov_apply", _i, [_vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp, ctypes.c_int64, _vp])
+_sig("fkf_cov_info", _i, [_vp, ctypes.POINTER(CovInfo)])
+_sig("fkf_cov_perm", _i, [_vp, _c_i64_p])
+_sig("fkf_cov_plan", _i, [_c_dbl_p, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(KernelParams),
+                          ctypes.POINTER(HmatParams), ctypes.POINTER(CovInfo)])
+_sig("fkf_rays_host", _i, [ctypes.c_int32, _c_i32_p, ctypes.c_int32, _c_dbl_p, _c_dbl_p, _c_i64_p,
+                           _c_i64_p, _c_i32_p, _c_dbl_p, ctypes.c_int64])
+_sig("fkf_cov_destroy", None, [_vp])
+
+EXPORTED = ["fkf_cov_build", "fkf_cov_apply", "fkf_cov_info", "fkf_cov_perm", "fkf_cov_destroy",
+            "fkf_cov_plan", "fkf_rays_host", "fkf_last_error", "fkf_version"]
+
+
+def _check(code: int):
+    if code != 0:
+        raise FkfError(code, _lib.fkf_last_error().decode(errors="replace"))
+
+
+def version() -> str:
+    return _lib.fkf_version().decode()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _colmajor(t):
+    """View a CUDA float64 tensor (n,) or (n, k) as column-major (ptr, ld, k)."""
+    torch = _torch()
+    if not (t.is_cuda and t.dtype == torch.float64):
+        raise TypeError("expected a CUDA float64 tensor")
+    if t.dim() == 1:
+        if t.stride(0) != 1:
+            raise ValueError("vector must be contiguous")
+        return t.data_ptr(), t.shape[0], 1
+    if t.dim() != 2:
+        raise ValueError("expected a 1-D or 2-D tensor")
+    if t.stride(0) != 1 and t.shape[1] > 1:
+        raise ValueError("matrix must be column-major: use x.t().contiguous().t()")
+    ld = t.stride(1) if t.shape[1] > 1 else t.shape[0]
+    return t.data_ptr(), max(ld, t.shape[0]), t.shape[1]
+
+
+def fortran_empty(n: int, k: int, device="cuda"):
+    """Uninitialised column-major (n, k) float64 CUDA tensor."""
+    torch = _torch()
+    return torch.empty((k, n), dtype=torch.float64, device=device).t()
+
+
+def _params(nu, length, variance, leaf_size, cheb_order, cheb_order_max, eta, block_tol):
+    if nu not in MATERN:
+        raise ValueError("nu must be 0.5, 1.5 or 2.5")
+    kp = KernelParams(ctypes.sizeof(KernelParams), MATERN[nu], variance, length)
+    hp = HmatParams(ctypes.sizeof(HmatParams), leaf_size, cheb_order, cheb_order_max,
+                    eta, block_tol, 0)
+    return kp, hp
+
+
+def _info_dict(inf: CovInfo) -> dict:
+    d = {f: getattr(inf, f) for f, _ in CovInfo._fields_ if f != "cheb_p"}
+    d["cheb_p"] = list(inf.cheb_p)[: inf.n_levels]
+    return d
+
+
+def plan(points, nu=1.5, length=0.1, variance=1.0, leaf_size=64, cheb_order=6,
+         cheb_order_max=16, eta=1.5, block_tol=1e-7) -> dict:
+    """Host-only H-matrix plan (tree, partition, Chebyshev orders); no GPU."""
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    kp, hp = _params(nu, length, variance, leaf_size, cheb_order, cheb_order_max, eta, block_tol)
+    inf = CovInfo()
+    _check(_lib.fkf_cov_plan(pts.ctypes.data_as(_c_dbl_p), pts.shape[0], pts.shape[1],
+                             ctypes.byref(kp), ctypes.byref(hp), ctypes.byref(inf)))
+    return _info_dict(inf)
+
+
+def rays_host(shape, src, rcv):
+    """Host-only straight-ray operator as (rowptr, col, val) CSR arrays; no GPU."""
+    src = np.ascontiguousarray(src, dtype=np.float64)
+    rcv = np.ascontiguousarray(rcv, dtype=np.float64)
+    grid = np.ascontiguousarray(shape, dtype=np.int32)
+    n_m, d = src.shape
+    rowptr = np.empty(n_m + 1, dtype=np.int64)
+    nnz = ctypes.c_int64()
+    args = (d, grid.ctypes.data_as(_c_i32_p), n_m, src.ctypes.data_as(_c_dbl_p),
+            rcv.ctypes.data_as(_c_dbl_p), rowptr.ctypes.data_as(_c_i64_p), ctypes.byref(nnz))
+    _check(_lib.fkf_rays_host(*args, None, None, 0))
+    col = np.empty(nnz.value, dtype=np.int32)
+    val = np.empty(nnz.value, dtype=np.float64)
+    _check(_lib.fkf_rays_host(*args, col.ctypes.data_as(_c_i32_p), val.ctypes.data_as(_c_dbl_p),
+                              nnz.value))
+    return rowptr, col, val
+
+
+class Cov:
+    """Gamma_sys (Matern) as an H-matrix on the GPU (fkf_cov_*)."""
+
+    def __init__(self, points, nu: float = 1.5, length: float = 0.1, variance: float = 1.0,
+                 leaf_size: int = 64, cheb_order: int = 6, cheb_order_max: int = 16,
+                 eta: float = 1.5, block_tol: float = 1e-7, stream=None):
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        if pts.ndim != 2:
+            raise ValueError("points must be (N, d)")
+        self.n, self.d = pts.shape
+        self.nu, self.length, self.variance = nu, length, variance
+        kp, hp = _params(nu, length, variance, leaf_size, cheb_order, cheb_order_max, eta,
+                         block_tol)
+        h = ctypes.c_void_p()
+        _check(_lib.fkf_cov_build(pts.ctypes.data_as(_c_dbl_p), self.n, self.d,
+                                  ctypes.byref(kp), ctypes.byref(hp), _stream(stream),
+                                  ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def apply(self, X, out=None, stream=None):
+        """Y = Gamma X for a CUDA float64 (N,) or column-major (N, k) tensor."""
+        ptr, ldx, k = _colmajor(X)
+        if X.shape[0] != self.n:
+            raise ValueError("X has the wrong number of rows")
+        if out is None:
+            out = (_torch().empty(self.n, dtype=X.dtype, device=X.device) if X.dim() == 1
+                   else fortran_empty(self.n, k, X.device))
+        optr, ldy, _ = _colmajor(out)
+        _check(_lib.fkf_cov_apply(self._h, ptr, ldx, k, optr, ldy, _stream(stream)))
+        return out
+
+    def info(self) -> dict:
+        inf = CovInfo()
+        _check(_lib.fkf_cov_info(self._h, ctypes.byref(inf)))
+        return _info_dict(inf)
+
+    def perm(self) -> np.ndarray:
+        out = np.empty(self.n, dtype=np.int64)
+        _check(_lib.fkf_cov_perm(self._h, out.ctypes.data_as(_c_i64_p)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.fkf_cov_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
