@@ -86,9 +86,25 @@ _sig("fkf_cov_plan", _i, [_c_dbl_p, ctypes.c_int64, ctypes.c_int32, ctypes.POINT
 _sig("fkf_rays_host", _i, [ctypes.c_int32, _c_i32_p, ctypes.c_int32, _c_dbl_p, _c_dbl_p, _c_i64_p,
                            _c_i64_p, _c_i32_p, _c_dbl_p, ctypes.c_int64])
 _sig("fkf_cov_destroy", None, [_vp])
+_sig("fkf_obs_create_csr", _i, [ctypes.c_int32, ctypes.c_int64, _c_i64_p, _c_i32_p, _c_dbl_p,
+                                _c_dbl_p, _vp, ctypes.POINTER(_vp)])
+_sig("fkf_obs_create_rays", _i, [ctypes.c_int32, _c_i32_p, ctypes.c_int32, _c_dbl_p, _c_dbl_p,
+                                 _c_dbl_p, _vp, ctypes.POINTER(_vp)])
+_sig("fkf_obs_shape", _i, [_vp, _c_i32_p, _c_i64_p, _c_i64_p])
+_sig("fkf_obs_get_csr", _i, [_vp, _c_i64_p, _c_i32_p, _c_dbl_p])
+_sig("fkf_obs_apply", _i, [_vp, _vp, _vp, _vp])
+_sig("fkf_obs_destroy", None, [_vp])
+_sig("fkf_filter_create", _i, [_vp, _vp, ctypes.c_double, ctypes.POINTER(FilterParams), _vp,
+                               ctypes.POINTER(_vp)])
+_sig("fkf_filter_step", _i, [_vp, _vp, _vp, _vp])
+_sig("fkf_filter_status", _i, [_vp, _vp])
+_sig("fkf_filter_mean", _i, [_vp, _vp, _vp])
+_sig("fkf_filter_variance", _i, [_vp, _vp, _vp])
+_sig("fkf_filter_realize", _i, [_vp, _vp, ctypes.c_int32, ctypes.c_int64, _vp, ctypes.c_int64, _vp])
+_sig("fkf_filter_info", _i, [_vp, _c_i64_p, _c_dbl_p, _c_i32_p])
+_sig("fkf_filter_modes", _i, [_vp, _c_dbl_p, _c_dbl_p])
+_sig("fkf_filter_destroy", None, [_vp])
 
-EXPORTED = ["fkf_cov_build", "fkf_cov_apply", "fkf_cov_info", "fkf_cov_perm", "fkf_cov_destroy",
-            "fkf_cov_plan", "fkf_rays_host", "fkf_last_error", "fkf_version"]
 
 
 def _check(code: int):
@@ -226,6 +242,161 @@ class Cov:
     def close(self):
         if getattr(self, "_h", None):
             _lib.fkf_cov_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def to_device(a):
+    """float64 numpy array -> CUDA tensor (column-major for 2-D)."""
+    torch = _torch()
+    if hasattr(a, "is_cuda"):
+        return a
+    a = np.asarray(a, dtype=np.float64)
+    if a.ndim == 1:
+        return torch.from_numpy(a.copy()).cuda()
+    return torch.from_numpy(np.ascontiguousarray(a.T)).cuda().t()
+
+
+class Obs:
+    """Measurement operator H with diagonal noise covariance R (fkf_obs_*)."""
+
+    def __init__(self, handle, n_m, n):
+        self._h, self.n_m, self.n = handle, n_m, n
+
+    @classmethod
+    def from_rays(cls, shape, src, rcv, noise_var, stream=None):
+        src = np.ascontiguousarray(src, dtype=np.float64)
+        rcv = np.ascontiguousarray(rcv, dtype=np.float64)
+        grid = np.ascontiguousarray(shape, dtype=np.int32)
+        n_m, d = src.shape
+        nv = np.ascontiguousarray(np.broadcast_to(np.asarray(noise_var, dtype=np.float64), (n_m,)))
+        h = ctypes.c_void_p()
+        _check(_lib.fkf_obs_create_rays(d, grid.ctypes.data_as(_c_i32_p), n_m,
+                                        src.ctypes.data_as(_c_dbl_p), rcv.ctypes.data_as(_c_dbl_p),
+                                        nv.ctypes.data_as(_c_dbl_p), _stream(stream), ctypes.byref(h)))
+        return cls(h, n_m, int(np.prod(shape)))
+
+    @classmethod
+    def from_csr(cls, H, noise_var, stream=None):
+        import scipy.sparse as sp
+        H = sp.csr_matrix(H)
+        H.sort_indices()
+        n_m, n = H.shape
+        rp = np.ascontiguousarray(H.indptr, dtype=np.int64)
+        col = np.ascontiguousarray(H.indices, dtype=np.int32)
+        val = np.ascontiguousarray(H.data, dtype=np.float64)
+        nv = np.ascontiguousarray(np.broadcast_to(np.asarray(noise_var, dtype=np.float64), (n_m,)))
+        h = ctypes.c_void_p()
+        _check(_lib.fkf_obs_create_csr(n_m, n, rp.ctypes.data_as(_c_i64_p),
+                                       col.ctypes.data_as(_c_i32_p), val.ctypes.data_as(_c_dbl_p),
+                                       nv.ctypes.data_as(_c_dbl_p), _stream(stream), ctypes.byref(h)))
+        return cls(h, n_m, n)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def csr(self):
+        import scipy.sparse as sp
+        nm, n, nnz = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.fkf_obs_shape(self._h, ctypes.byref(nm), ctypes.byref(n), ctypes.byref(nnz)))
+        rp = np.empty(nm.value + 1, dtype=np.int64)
+        col = np.empty(nnz.value, dtype=np.int32)
+        val = np.empty(nnz.value, dtype=np.float64)
+        _check(_lib.fkf_obs_get_csr(self._h, rp.ctypes.data_as(_c_i64_p),
+                                    col.ctypes.data_as(_c_i32_p), val.ctypes.data_as(_c_dbl_p)))
+        return sp.csr_matrix((val, col, rp), shape=(nm.value, n.value))
+
+    def apply(self, x, out=None, stream=None):
+        torch = _torch()
+        x = to_device(x)
+        if out is None:
+            out = torch.empty(self.n_m, dtype=torch.float64, device=x.device)
+        _check(_lib.fkf_obs_apply(self._h, x.data_ptr(), out.data_ptr(), _stream(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.fkf_obs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Filter:
+    """The fast random-walk Kalman filter (fkf_filter_*)."""
+
+    def __init__(self, cov: Cov, s0=None, alpha0: float = 0.0, max_rank: int = 4096,
+                 rank_rtol: float = 0.0, stream=None):
+        self.cov = cov
+        self.n = cov.n
+        fp = FilterParams(ctypes.sizeof(FilterParams), max_rank, rank_rtol)
+        s0p = None
+        if s0 is not None:
+            self._s0 = to_device(s0)
+            s0p = self._s0.data_ptr()
+        h = ctypes.c_void_p()
+        _check(_lib.fkf_filter_create(cov.handle, s0p, float(alpha0), ctypes.byref(fp),
+                                      _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    def step(self, obs: Obs, y, stream=None):
+        y = to_device(y)
+        self._y = y     # keep alive until the stream consumes it
+        _check(_lib.fkf_filter_step(self._h, obs.handle, y.data_ptr(), _stream(stream)))
+
+    def status(self, stream=None):
+        _check(_lib.fkf_filter_status(self._h, _stream(stream)))
+
+    def mean(self, out=None, stream=None):
+        torch = _torch()
+        out = torch.empty(self.n, dtype=torch.float64, device="cuda") if out is None else out
+        _check(_lib.fkf_filter_mean(self._h, out.data_ptr(), _stream(stream)))
+        return out
+
+    def variance(self, out=None, stream=None):
+        torch = _torch()
+        out = torch.empty(self.n, dtype=torch.float64, device="cuda") if out is None else out
+        _check(_lib.fkf_filter_variance(self._h, out.data_ptr(), _stream(stream)))
+        return out
+
+    def realize(self, g, out=None, stream=None):
+        g = to_device(g)
+        if g.dim() == 1:
+            g2 = g.reshape(self.n, 1)
+        else:
+            g2 = g
+        ptr, ldg, ns = _colmajor(g2)
+        if out is None:
+            out = fortran_empty(self.n, ns)
+        optr, ldo, _ = _colmajor(out if out.dim() == 2 else out.reshape(self.n, 1))
+        _check(_lib.fkf_filter_realize(self._h, ptr, ns, ldg, optr, ldo, _stream(stream)))
+        return out[:, 0] if g.dim() == 1 else out
+
+    def info(self) -> dict:
+        k, a, r = ctypes.c_int64(), ctypes.c_double(), ctypes.c_int32()
+        _check(_lib.fkf_filter_info(self._h, ctypes.byref(k), ctypes.byref(a), ctypes.byref(r)))
+        return {"k": k.value, "alpha": a.value, "rank": r.value}
+
+    def modes(self):
+        r = self.info()["rank"]
+        lam = np.empty(r)
+        w = np.empty(r)
+        _check(_lib.fkf_filter_modes(self._h, lam.ctypes.data_as(_c_dbl_p), w.ctypes.data_as(_c_dbl_p)))
+        return lam, w
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.fkf_filter_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -781,3 +781,8 @@ extern "C" fkf_status fkf_cov_plan(const double *pts_host, int64_t n, int32_t d,
     for (int l = 0; l < 32 && l < (int)lp.size(); ++l) info->cheb_p[l] = lp[l];
   });
 }
+
+namespace fkf {
+double cov_variance(const fkf_cov *cov) { return cov->theta; }
+int64_t cov_n(const fkf_cov *cov) { return cov->n; }
+}  // namespace fkf

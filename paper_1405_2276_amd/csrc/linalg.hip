@@ -1,0 +1,442 @@
+// Dense and sparse FP64 linear algebra on the GPU for the filter's data-space
+// quantities: the measurement operator products, the n_m x n_m innovation
+// Gram matrix and its eigen-decomposition (the projected eigenproblem of the
+// generalized eigenvalue problem, Section 2.2.2), and tall GEMMs.
+#include <algorithm>
+
+#include "kernels.h"
+#include "linalg.h"
+
+namespace fkf {
+
+// ===================================================== block Jacobi eigen ===
+// Two-sided block Jacobi.  The padded matrix (np = multiple of 32) is split
+// into nb = np/16 blocks of 16 indices.  A round pairs the blocks by a
+// round-robin tournament; each pair's 32 x 32 principal submatrix is fully
+// diagonalised in LDS by cyclic (parallel-ordered) Jacobi, giving an
+// orthogonal J_k, and then every 32 x 32 tile of A is updated as
+// J_k1^T A J_k2 and V as V J_k.  A sweep visits every block pair once; the
+// iteration stops after a sweep without rotations.  Padding indices carry
+// zero rows/columns and are never rotated.
+
+constexpr int kJB = 16;   // block size
+constexpr int kJT = 32;   // tile (pair) size
+
+__device__ __forceinline__ int rr_player(int pos, int round, int m) {
+  return pos == 0 ? 0 : 1 + ((pos - 1 + round) % (m - 1));
+}
+
+__device__ __forceinline__ int pair_index(int k, int i, int round, int nb) {
+  int P = rr_player(k, round, nb), Q = rr_player(nb - 1 - k, round, nb);
+  return i < kJB ? P * kJB + i : Q * kJB + (i - kJB);
+}
+
+__device__ __forceinline__ bool jacobi_rotation(double app, double aqq, double apq, double tol_rel,
+                                                double tol_abs, double &c, double &s) {
+  double thr = fmax(tol_rel * sqrt(fabs(app * aqq)), tol_abs);
+  if (!(fabs(apq) > thr)) {
+    c = 1.0;
+    s = 0.0;
+    return false;
+  }
+  double tau = (aqq - app) / (2.0 * apq);
+  double t;
+  if (fabs(tau) > 1e150)
+    t = 0.5 / tau;
+  else
+    t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+  c = 1.0 / sqrt(1.0 + t * t);
+  s = t * c;
+  return true;
+}
+
+__global__ void k_jacobi_init(const double *__restrict__ A, int64_t lda, int n, int np,
+                              double *__restrict__ Ap, double *__restrict__ V) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)np * np) return;
+  int i = (int)(e % np), j = (int)(e / np);
+  Ap[e] = (i < n && j < n) ? A[i + lda * j] : 0.0;
+  V[e] = (i == j) ? 1.0 : 0.0;
+}
+
+__global__ void __launch_bounds__(1024) k_frob(const double *__restrict__ A, int64_t len,
+                                               double *__restrict__ out) {
+  __shared__ double red[16];
+  double s = 0;
+  for (int64_t e = threadIdx.x; e < len; e += 1024) s += A[e] * A[e];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int w = 0; w < 16; ++w) t += red[w];
+    out[0] = sqrt(t);
+  }
+}
+
+__global__ void k_set_int(int *p, int v) { *p = v; }
+
+__global__ void __launch_bounds__(256) k_jacobi_solve(const double *__restrict__ A, int np, int nb,
+                                                      int round, const double *__restrict__ fro,
+                                                      double *__restrict__ Jout, int *cnt) {
+  __shared__ double S[kJT][kJT + 1];
+  __shared__ double Jm[kJT][kJT + 1];
+  __shared__ double rc[kJB], rs[kJB];
+  __shared__ int pp[kJB], qq[kJB], rotp[kJB];
+  __shared__ int rot_sweep, rot_any;
+  const int k = blockIdx.x, tid = threadIdx.x;
+  for (int e = tid; e < kJT * kJT; e += 256) {
+    int i = e & 31, j = e >> 5;
+    int gi = pair_index(k, i, round, nb), gj = pair_index(k, j, round, nb);
+    S[i][j] = A[gi + (int64_t)np * gj];
+    Jm[i][j] = (i == j) ? 1.0 : 0.0;
+  }
+  if (tid == 0) rot_any = 0;
+  const double tol_abs = 1e-15 * fro[0], tol_rel = 1e-15;
+  __syncthreads();
+  for (int sw = 0; sw < 40; ++sw) {
+    if (tid == 0) rot_sweep = 0;
+    __syncthreads();
+    for (int ir = 0; ir < kJT - 1; ++ir) {
+      if (tid < kJB) {
+        int p = rr_player(tid, ir, kJT), q = rr_player(kJT - 1 - tid, ir, kJT);
+        double c, s;
+        bool r = jacobi_rotation(S[p][p], S[q][q], S[p][q], tol_rel, tol_abs, c, s);
+        pp[tid] = p;
+        qq[tid] = q;
+        rc[tid] = c;
+        rs[tid] = s;
+        rotp[tid] = r;
+        if (r) rot_sweep = 1;
+      }
+      __syncthreads();
+      {
+        int P1 = tid >> 4, P2 = tid & 15;
+        int p1 = pp[P1], q1 = qq[P1], p2 = pp[P2], q2 = qq[P2];
+        double c1 = rc[P1], s1 = rs[P1], c2 = rc[P2], s2 = rs[P2];
+        double b11 = S[p1][p2], b12 = S[p1][q2], b21 = S[q1][p2], b22 = S[q1][q2];
+        double t11 = c2 * b11 - s2 * b12, t12 = s2 * b11 + c2 * b12;
+        double t21 = c2 * b21 - s2 * b22, t22 = s2 * b21 + c2 * b22;
+        double n11 = c1 * t11 - s1 * t21, n12 = c1 * t12 - s1 * t22;
+        double n21 = s1 * t11 + c1 * t21, n22 = s1 * t12 + c1 * t22;
+        if (P1 == P2 && rotp[P1]) {
+          n12 = 0.0;
+          n21 = 0.0;
+        }
+        S[p1][p2] = n11;
+        S[p1][q2] = n12;
+        S[q1][p2] = n21;
+        S[q1][q2] = n22;
+      }
+      for (int e = tid; e < kJT * kJB; e += 256) {
+        int row = e >> 4, P = e & 15;
+        int p = pp[P], q = qq[P];
+        double c = rc[P], s = rs[P];
+        double jp = Jm[row][p], jq = Jm[row][q];
+        Jm[row][p] = c * jp - s * jq;
+        Jm[row][q] = s * jp + c * jq;
+      }
+      __syncthreads();
+    }
+    bool any = rot_sweep != 0;
+    __syncthreads();
+    if (!any) break;
+    if (tid == 0) rot_any = 1;
+  }
+  double *Jo = Jout + (int64_t)k * kJT * kJT;
+  for (int e = tid; e < kJT * kJT; e += 256) {
+    int i = e & 31, j = e >> 5;
+    Jo[i + kJT * j] = Jm[i][j];
+  }
+  if (tid == 0 && rot_any) atomicAdd(cnt, 1);
+}
+
+__global__ void __launch_bounds__(256) k_jacobi_update(double *__restrict__ A, double *__restrict__ V,
+                                                       int np, int nb, int round,
+                                                       const double *__restrict__ Jbuf) {
+  __shared__ double Tl[kJT][kJT + 1];
+  __shared__ double J1[kJT][kJT + 1];
+  __shared__ double J2[kJT][kJT + 1];
+  const int npair = nb / 2;
+  const int tilesA = npair * npair;
+  int w = blockIdx.x;
+  const int tid = threadIdx.x;
+  bool isA = w < tilesA;
+  int k1, k2, rc0 = 0;
+  if (isA) {
+    k1 = w / npair;
+    k2 = w % npair;
+  } else {
+    w -= tilesA;
+    rc0 = (w / npair) * kJT;
+    k1 = -1;
+    k2 = w % npair;
+  }
+  for (int e = tid; e < kJT * kJT; e += 256) {
+    int i = e & 31, j = e >> 5;
+    int gj = pair_index(k2, j, round, nb);
+    if (isA) {
+      int gi = pair_index(k1, i, round, nb);
+      Tl[i][j] = A[gi + (int64_t)np * gj];
+      J1[i][j] = Jbuf[(int64_t)k1 * kJT * kJT + i + kJT * j];
+    } else {
+      Tl[i][j] = V[rc0 + i + (int64_t)np * gj];
+    }
+    J2[i][j] = Jbuf[(int64_t)k2 * kJT * kJT + i + kJT * j];
+  }
+  __syncthreads();
+  double t[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int e = tid + 256 * q, i = e & 31, j = e >> 5;
+    double s = 0;
+#pragma unroll 8
+    for (int m = 0; m < kJT; ++m) s = fma(Tl[i][m], J2[m][j], s);
+    t[q] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int e = tid + 256 * q, i = e & 31, j = e >> 5;
+    Tl[i][j] = t[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int e = tid + 256 * q, i = e & 31, j = e >> 5;
+    int gj = pair_index(k2, j, round, nb);
+    if (isA) {
+      double s = 0;
+#pragma unroll 8
+      for (int m = 0; m < kJT; ++m) s = fma(J1[m][i], Tl[m][j], s);
+      int gi = pair_index(k1, i, round, nb);
+      A[gi + (int64_t)np * gj] = s;
+    } else {
+      V[rc0 + i + (int64_t)np * gj] = Tl[i][j];
+    }
+  }
+}
+
+// Eigenvalues from the diagonal, ranked in descending order (ties by index).
+__global__ void __launch_bounds__(1024) k_eig_rank(const double *__restrict__ Ap, int np, int n,
+                                                   double *__restrict__ w, int *__restrict__ rank) {
+  for (int i = threadIdx.x; i < n; i += 1024) {
+    double li = Ap[i + (int64_t)np * i];
+    int r = 0;
+    for (int j = 0; j < n; ++j) {
+      double lj = Ap[j + (int64_t)np * j];
+      r += (lj > li) || (lj == li && j < i);
+    }
+    w[r] = li;
+    rank[i] = r;
+  }
+}
+
+__global__ void k_eig_vecs(const double *__restrict__ V, int np, int n, const int *__restrict__ rank,
+                           double *__restrict__ W, int64_t ldw) {
+  int r = blockIdx.y * blockDim.x + threadIdx.x;
+  int i = blockIdx.x;
+  if (r < n) W[r + ldw * rank[i]] = V[r + (int64_t)np * i];
+}
+
+EigWork::~EigWork() {
+  if (cnt_host) (void)hipHostFree(cnt_host);
+}
+
+int sym_eig(const double *A, int64_t lda, int n, double *w, double *W, int64_t ldw,
+            hipStream_t st, EigWork &ws) {
+  if (n <= 0) return 0;
+  const int np = (n + kJT - 1) / kJT * kJT;
+  const int nb = np / kJB;
+  const int npair = nb / 2;
+  ws.A.reserve((size_t)np * np);
+  ws.V.reserve((size_t)np * np);
+  ws.J.reserve((size_t)npair * kJT * kJT);
+  ws.fro.reserve(1);
+  ws.cnt.reserve(1 + np);   // counter + rank scratch
+  if (!ws.cnt_host) FKF_CHECK_HIP(hipHostMalloc((void **)&ws.cnt_host, sizeof(int)));
+  int64_t tot = (int64_t)np * np;
+  hipLaunchKernelGGL(k_jacobi_init, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, A, lda,
+                     n, np, ws.A.p, ws.V.p);
+  hipLaunchKernelGGL(k_frob, dim3(1), dim3(1024), 0, st, ws.A.p, tot, ws.fro.p);
+  const unsigned grid_upd = (unsigned)(npair * npair + (np / kJT) * npair);
+  int sweeps = 0;
+  for (int sw = 0; sw < 30; ++sw) {
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, ws.cnt.p, 0);
+    for (int r = 0; r < nb - 1; ++r) {
+      hipLaunchKernelGGL(k_jacobi_solve, dim3(npair), dim3(256), 0, st, ws.A.p, np, nb, r,
+                         ws.fro.p, ws.J.p, ws.cnt.p);
+      hipLaunchKernelGGL(k_jacobi_update, dim3(grid_upd), dim3(256), 0, st, ws.A.p, ws.V.p, np, nb,
+                         r, ws.J.p);
+    }
+    FKF_CHECK_HIP(hipMemcpyAsync(ws.cnt_host, ws.cnt.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    FKF_CHECK_HIP(hipStreamSynchronize(st));
+    ++sweeps;
+    if (*ws.cnt_host == 0) break;
+  }
+  int *rank = ws.cnt.p + 1;
+  hipLaunchKernelGGL(k_eig_rank, dim3(1), dim3(1024), 0, st, ws.A.p, np, n, w, rank);
+  hipLaunchKernelGGL(k_eig_vecs, dim3(n, (unsigned)((n + 255) / 256)), dim3(256), 0, st, ws.V.p,
+                     np, n, rank, W, ldw);
+  FKF_CHECK_HIP(hipGetLastError());
+  return sweeps;
+}
+
+// ========================================================= sparse products ===
+__global__ void __launch_bounds__(256) k_spmv(const int64_t *__restrict__ rowptr,
+                                              const int32_t *__restrict__ col,
+                                              const double *__restrict__ val, int n_m,
+                                              const double *__restrict__ x, double *__restrict__ y) {
+  int m = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (m >= n_m) return;
+  int l = threadIdx.x & 63;
+  double s = 0;
+  for (int64_t e = rowptr[m] + l; e < rowptr[m + 1]; e += 64) s = fma(val[e], x[col[e]], s);
+  s = wave_sum(s);
+  if (l == 0) y[m] = s;
+}
+
+void spmv(const int64_t *rowptr, const int32_t *col, const double *val, int n_m, const double *x,
+          double *y, hipStream_t st) {
+  if (n_m <= 0) return;
+  hipLaunchKernelGGL(k_spmv, dim3((n_m + 3) / 4), dim3(256), 0, st, rowptr, col, val, n_m, x, y);
+}
+
+__global__ void k_fill(double *__restrict__ p, int64_t n, double v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+void fill(double *p, int64_t n, double v, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+}
+
+__global__ void __launch_bounds__(64) k_scatter_ht(const int64_t *__restrict__ rowptr,
+                                                   const int32_t *__restrict__ col,
+                                                   const double *__restrict__ val, int64_t n,
+                                                   double *__restrict__ D) {
+  int m = blockIdx.x;
+  for (int64_t e = rowptr[m] + threadIdx.x; e < rowptr[m + 1]; e += 64)
+    D[col[e] + n * m] = val[e];
+}
+
+void dense_ht(const int64_t *rowptr, const int32_t *col, const double *val, int n_m, int64_t n,
+              double *D, hipStream_t st) {
+  fill(D, n * n_m, 0.0, st);
+  if (n_m > 0)
+    hipLaunchKernelGGL(k_scatter_ht, dim3(n_m), dim3(64), 0, st, rowptr, col, val, n, D);
+}
+
+// G[m, j] = H_m . P[:, j]: one wavefront per entry, lanes split the row's nnz.
+__global__ void __launch_bounds__(256) k_gram_hp(const int64_t *__restrict__ rowptr,
+                                                 const int32_t *__restrict__ col,
+                                                 const double *__restrict__ val, int n_m, int64_t n,
+                                                 const double *__restrict__ P,
+                                                 double *__restrict__ G) {
+  int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (e >= (int64_t)n_m * n_m) return;
+  int m = (int)(e % n_m), j = (int)(e / n_m);
+  int l = threadIdx.x & 63;
+  const double *Pj = P + n * j;
+  double s = 0;
+  for (int64_t q = rowptr[m] + l; q < rowptr[m + 1]; q += 64) s = fma(val[q], Pj[col[q]], s);
+  s = wave_sum(s);
+  if (l == 0) G[m + (int64_t)n_m * j] = s;
+}
+
+__global__ void k_gram_sym(const double *__restrict__ G, int n_m, const double *__restrict__ r,
+                           double *__restrict__ A) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n_m * n_m) return;
+  int m = (int)(e % n_m), j = (int)(e / n_m);
+  A[e] = 0.5 * (G[e] + G[j + (int64_t)n_m * m]) / sqrt(r[m] * r[j]);
+}
+
+void innovation_gram(const int64_t *rowptr, const int32_t *col, const double *val, int n_m,
+                     int64_t n, const double *P, const double *noise_var, double *G, double *A,
+                     hipStream_t st) {
+  int64_t e = (int64_t)n_m * n_m;
+  if (e == 0) return;
+  hipLaunchKernelGGL(k_gram_hp, dim3((unsigned)((e + 3) / 4)), dim3(256), 0, st, rowptr, col, val,
+                     n_m, n, P, G);
+  hipLaunchKernelGGL(k_gram_sym, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, st, G, n_m,
+                     noise_var, A);
+}
+
+// ==================================================================== GEMM ===
+// C = A B, 64 x 64 output tile per workgroup, 4 x 4 per thread, k in chunks of 16.
+__global__ void __launch_bounds__(256) k_gemm_nn(int64_t m, int n, int k, const double *__restrict__ A,
+                                                 int64_t lda, const double *__restrict__ B,
+                                                 int64_t ldb, double *__restrict__ C, int64_t ldc) {
+  __shared__ double As[16][64 + 1];
+  __shared__ double Bs[16][64 + 1];
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int64_t m0 = (int64_t)blockIdx.x * 64;
+  const int n0 = blockIdx.y * 64;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int k0 = 0; k0 < k; k0 += 16) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int e = tid + 256 * q;
+      int r = e & 63, kk = e >> 6;
+      int64_t gr = m0 + r;
+      int gk = k0 + kk;
+      As[kk][r] = (gr < m && gk < k) ? A[gr + lda * gk] : 0.0;
+      int kb = e & 15, c = e >> 4;
+      int gkb = k0 + kb, gc = n0 + c;
+      Bs[kb][c] = (gkb < k && gc < n) ? B[gkb + ldb * gc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[kk][tx + 16 * a];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = Bs[kk][ty + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      int64_t gr = m0 + tx + 16 * a;
+      int gc = n0 + ty + 16 * b;
+      if (gr < m && gc < n) C[gr + ldc * gc] = acc[a][b];
+    }
+}
+
+void gemm_nn(int64_t m, int n, int k, const double *A, int64_t lda, const double *B, int64_t ldb,
+             double *C, int64_t ldc, hipStream_t st) {
+  if (m <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(k_gemm_nn, dim3((unsigned)((m + 63) / 64), (unsigned)((n + 63) / 64)),
+                     dim3(256), 0, st, m, n, k, A, lda, B, ldb, C, ldc);
+}
+
+__global__ void k_scale_rows(int64_t m, int n, const double *__restrict__ s, double *__restrict__ A,
+                             int64_t lda) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * n) return;
+  int64_t i = e % m, j = e / m;
+  A[i + lda * j] *= s[i];
+}
+
+void scale_rows(int64_t m, int n, const double *s, double *A, int64_t lda, hipStream_t st) {
+  int64_t e = m * n;
+  if (e <= 0) return;
+  hipLaunchKernelGGL(k_scale_rows, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, st, m, n, s, A,
+                     lda);
+}
+
+}  // namespace fkf
