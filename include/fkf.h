@@ -241,6 +241,16 @@ void fkf_filter_destroy(fkf_filter *f);
 
 const char *fkf_last_error(void);
 
+/* Tracing: when enabled (on != 0), the library records a HIP event pair on the
+ * launch stream around each instrumented launch site; fkf_trace_query returns
+ * the number of recorded launches of a site and their summed duration in
+ * milliseconds (synchronising on the recorded events).  Enabling or disabling
+ * synchronises the device and clears all records.  Site names are listed,
+ * comma-separated, by fkf_trace_names (FKF_E_ARG when cap is too small). */
+fkf_status fkf_trace_enable(int32_t on);
+fkf_status fkf_trace_query(const char *name, int64_t *count, double *total_ms);
+fkf_status fkf_trace_names(char *buf, int64_t cap);
+
 /* Library version string. */
 const char *fkf_version(void);
 

@@ -3,7 +3,7 @@
 Argument marshalling only: every numeric step runs in the library's HIP
 kernels.  Device arrays are torch CUDA (ROCm) float64 tensors; the library is
 driven on torch's current stream.  Importing this package fails loudly when
-the library has not been built (``python -m paper_1405_2276_amd.build``).
+the library has not been built (``python paper_1405_2276_amd/build.py``).
 """
 from __future__ import annotations
 
@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfkf.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1405_2276_amd.build`")
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1405_2276_amd/build.py`")
 try:
     _lib = ctypes.CDLL(LIB_PATH)
 except OSError as e:  # pragma: no cover
@@ -104,12 +104,32 @@ _sig("fkf_filter_realize", _i, [_vp, _vp, ctypes.c_int32, ctypes.c_int64, _vp, c
 _sig("fkf_filter_info", _i, [_vp, _c_i64_p, _c_dbl_p, _c_i32_p])
 _sig("fkf_filter_modes", _i, [_vp, _c_dbl_p, _c_dbl_p])
 _sig("fkf_filter_destroy", None, [_vp])
+_sig("fkf_trace_enable", _i, [ctypes.c_int32])
+_sig("fkf_trace_query", _i, [ctypes.c_char_p, _c_i64_p, _c_dbl_p])
+_sig("fkf_trace_names", _i, [ctypes.c_char_p, ctypes.c_int64])
 
 
 
 def _check(code: int):
     if code != 0:
         raise FkfError(code, _lib.fkf_last_error().decode(errors="replace"))
+
+
+def trace_enable(on: bool = True):
+    """Enable/disable per-launch event timing in the library (clears records)."""
+    _check(_lib.fkf_trace_enable(1 if on else 0))
+
+
+def trace_report() -> dict:
+    """{site: (launches, total_ms)} for every recorded launch site."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(_lib.fkf_trace_names(buf, len(buf)))
+    out = {}
+    for name in filter(None, buf.value.decode().split(",")):
+        c, ms = ctypes.c_int64(), ctypes.c_double()
+        _check(_lib.fkf_trace_query(name.encode(), ctypes.byref(c), ctypes.byref(ms)))
+        out[name] = (c.value, ms.value)
+    return out
 
 
 def version() -> str:

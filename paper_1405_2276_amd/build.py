@@ -1,6 +1,6 @@
 """Build libfkf.so (HIP for gfx950) in-tree with hipcc.
 
-    python -m paper_1405_2276_amd.build
+    python paper_1405_2276_amd/build.py
 
 Every source under csrc/ is compiled to an object in _build/ and linked into
 paper_1405_2276_amd/libfkf.so.  Device code is compiled for gfx950 only, with

@@ -22,6 +22,7 @@
 
 #include "kernels.h"
 #include "linalg.h"
+#include "trace.h"
 
 struct fkf_obs {
   int n_m = 0;
@@ -252,6 +253,7 @@ __global__ void k_copy_strided(const double *__restrict__ src, double *__restric
 static unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
 static void gemv_seg(const fkf_filter *f, const double *z, bool square, hipStream_t st) {
+  FKF_TRACE(square ? "filter_gemv_sq" : "filter_gemv", st);
   int nseg = (f->n_m + kSegCols - 1) / kSegCols;
   dim3 grid(blocks(f->n, kRowsPerWG), (unsigned)nseg);
   if (square)
@@ -265,24 +267,35 @@ static void gemv_seg(const fkf_filter *f, const double *z, bool square, hipStrea
 // Generalized eigenpairs of H^T R^-1 H against Gamma^-1 by Rayleigh-Ritz on
 // range(Gamma H^T), and the constant-H basis U0 = P Ve.
 static void build_basis(fkf_filter *f, const fkf_obs *o, hipStream_t st) {
+  FKF_TRACE("gep_total", st);
   const int64_t n = f->n;
   const int nm = o->n_m;
   DevBuf<double> Ht((size_t)n * nm), P((size_t)n * nm);
   dense_ht(o->rowptr.p, o->col.p, o->val.p, nm, n, Ht.p, st);
-  fkf_status rc = fkf_cov_apply(f->cov, Ht.p, n, nm, P.p, n, (void *)st);
+  fkf_status rc;
+  {
+    FKF_TRACE("gep_cross_cov", st);
+    rc = fkf_cov_apply(f->cov, Ht.p, n, nm, P.p, n, (void *)st);
+  }
   if (rc != FKF_OK) throw Error{rc, std::string("covariance product failed: ") + fkf_last_error()};
   Ht.release();
   DevBuf<double> G((size_t)nm * nm), A((size_t)nm * nm);
   innovation_gram(o->rowptr.p, o->col.p, o->val.p, nm, n, P.p, o->noise.p, G.p, A.p, st);
   f->lam.alloc(nm);
   f->Ve.alloc((size_t)nm * nm);
-  sym_eig(A.p, nm, nm, f->lam.p, f->Ve.p, nm, st, f->eig);
+  {
+    FKF_TRACE("gep_eig", st);
+    sym_eig(A.p, nm, nm, f->lam.p, f->Ve.p, nm, st, f->eig);
+  }
   hipLaunchKernelGGL(k_clamp_nonneg, dim3(blocks(nm)), dim3(256), 0, st, f->lam.p, nm);
   scale_rows(nm, nm, o->inv_sqrt_noise.p, f->Ve.p, nm, st);
   f->ldu = (n + 63) / 64 * 64;
   f->U0.alloc((size_t)f->ldu * nm);
   fill(f->U0.p, f->ldu * nm, 0.0, st);
-  gemm_nn(n, nm, nm, P.p, n, f->Ve.p, nm, f->U0.p, f->ldu, st);
+  {
+    FKF_TRACE("gep_basis_gemm", st);
+    gemm_nn(n, nm, nm, P.p, n, f->Ve.p, nm, f->U0.p, f->ldu, st);
+  }
   f->delta.alloc(nm);
   fill(f->delta.p, nm, 0.0, st);
   f->nu.alloc(nm);
@@ -470,6 +483,7 @@ extern "C" fkf_status fkf_filter_step(fkf_filter *f, const fkf_obs *o, const dou
     }
     const double alpha_new = f->alpha + 1.0;   // prediction (F = I)
     const int nm = f->n_m;
+    FKF_TRACE("filter_step", st);
     hipLaunchKernelGGL(k_innov, dim3(blocks(nm, 4), 1), dim3(256), 0, st, o->rowptr.p, o->col.p,
                        o->val.p, nm, f->s.p, y, f->nu.p, f->err.p);
     hipLaunchKernelGGL(k_modes_step, dim3(blocks(nm, 4)), dim3(256), 0, st, f->Ve.p, nm, f->nu.p,

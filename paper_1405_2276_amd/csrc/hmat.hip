@@ -21,6 +21,7 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "trace.h"
 
 namespace fkf {
 
@@ -655,16 +656,21 @@ extern "C" fkf_status fkf_cov_apply(fkf_cov *cov, const double *X, int64_t ldx, 
     const int64_t n = cov->n;
     cov->xt.reserve((size_t)n * nrhs);
     dim3 gg((unsigned)((n + 255) / 256), (unsigned)nrhs);
-    hipLaunchKernelGGL(k_gather, gg, dim3(256), 0, st, X, ldx, nrhs, cov->perm.p, n, cov->xt.p);
+    {
+      FKF_TRACE("hmat_gather", st);
+      hipLaunchKernelGGL(k_gather, gg, dim3(256), 0, st, X, ldx, nrhs, cov->perm.p, n, cov->xt.p);
+    }
     const bool one = (nrhs == 1);
     if (one) {
       cov->part.reserve((size_t)std::max<int64_t>(cov->n_blk, 1) * 128);
+      FKF_TRACE("hmat_near_1rhs", st);
       if (cov->n_blk)
         hipLaunchKernelGGL(k_near_sym1, dim3((unsigned)((cov->n_blk + 3) / 4)), dim3(256), 0, st,
                            cov->blk.p, cov->blk_s.p, cov->blk_t.p, cov->leaf_off.p, cov->xt.p,
                            cov->n_blk, cov->part.p);
     } else {
       cov->yt.reserve((size_t)n * nrhs);
+      FKF_TRACE("hmat_near_multi", st);
       hipLaunchKernelGGL(k_near_multi, dim3(cov->n_leaves, (unsigned)((nrhs + 31) / 32)), dim3(256),
                          0, st, cov->blk.p, cov->near_ptr.p, cov->near_idx.p, cov->blk_s.p,
                          cov->blk_t.p, cov->leaf_off.p, cov->xt.p, n, nrhs, cov->yt.p);
@@ -674,6 +680,7 @@ extern "C" fkf_status fkf_cov_apply(fkf_cov *cov, const double *X, int64_t ldx, 
     if (cov->n_fc > 0) {
       cov->xhat.reserve((size_t)cov->n_coef * nrhs);
       cov->yhat.reserve((size_t)cov->n_coef * nrhs);
+      FKF_TRACE(one ? "hmat_far_1rhs" : "hmat_far_multi", st);
       if (one) {
         hipLaunchKernelGGL(k_far_up<1>, dim3(cov->n_fc, 1), dim3(256), 0, st, cov->fc.p,
                            cov->pts.p, n, cov->d, cov->cheb.p, cov->xt.p, nrhs, cov->xhat.p);
@@ -697,6 +704,7 @@ extern "C" fkf_status fkf_cov_apply(fkf_cov *cov, const double *X, int64_t ldx, 
         }
       }
     }
+    FKF_TRACE(one ? "hmat_finalize_1rhs" : "hmat_finalize_multi", st);
     if (one) {
       hipLaunchKernelGGL(k_finalize<1>, dim3(cov->n_leaves, 1), dim3(256), 0, st,
                          cov->leaf_off.p, cov->pts.p, n, cov->d, cov->cheb.p, cov->fc.p,
