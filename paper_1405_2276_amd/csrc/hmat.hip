@@ -32,6 +32,23 @@ struct FarCluster {
   double ctr[kMaxDim], hw[kMaxDim];
 };
 
+// Upward work item: a chunk of <= kUpChunk points of one far cluster.
+constexpr int64_t kUpChunk = 128;
+constexpr int64_t kUpChunkM = 1024;   // chunk for the several-column path
+struct UpItem {
+  int32_t fc;       // far cluster
+  int32_t pad;
+  int64_t begin, end;
+  int64_t poff;     // offset of this item's partial in the upward partial buffer
+};
+
+// Unordered admissible pair {s, t} (s < t) with the offset of its partials:
+// [off, off + pd_s) for s, then [off + pd_s, off + pd_s + pd_t) for t.
+struct PairItem {
+  int32_t s, t;
+  int64_t off;
+};
+
 }  // namespace fkf
 
 struct fkf_cov {
@@ -57,8 +74,27 @@ struct fkf_cov {
   fkf::DevBuf<int32_t> far_ptr, far_col;     // partners per target far cluster
   fkf::DevBuf<int32_t> anc_ptr, anc_idx;     // far-cluster ancestors of each leaf
   fkf::DevBuf<double> cheb;                  // [p][a] nodes and weights
+  // one-column far field work lists
+  fkf::DevBuf<fkf::UpItem> up_items;
+  fkf::DevBuf<int32_t> up_ptr;               // items of each far cluster
+  fkf::DevBuf<fkf::PairItem> pairs;          // unordered admissible pairs (large first)
+  int64_t n_pairs_large = 0;                 // pairs with a side of more than 64 nodes
+  fkf::DevBuf<int32_t> cp_ptr;               // pair partials of each far cluster
+  fkf::DevBuf<int64_t> cp_off;
+  int64_t n_up_items = 0, n_part_up = 0, n_pairs = 0, n_part_pair = 0;
+  fkf::DevBuf<fkf::UpItem> up_items_m;       // several-column upward chunks
+  fkf::DevBuf<int32_t> up_ptr_m;
+  int64_t n_up_items_m = 0, n_part_up_m = 0;
   // workspace
-  fkf::DevBuf<double> xt, yt, part, xhat, yhat;
+  fkf::DevBuf<double> xt, yt, part, xhat, yhat, part_up, part_pair, part_up_m;
+  // fork/join of the near field onto a second stream
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  ~fkf_cov() {
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
+  }
 };
 
 namespace fkf {
@@ -474,6 +510,779 @@ __global__ void __launch_bounds__(256) k_finalize(
   }
 }
 
+
+// ------------------------------------------------ one-column far field ---
+// Lagrange basis with compile-time bound PM (loops fully unrolled so that L
+// stays in registers); u, w point to the node/weight table of p nodes.
+template <int PM>
+__device__ __forceinline__ void lagrange_reg(int p, const double *__restrict__ u,
+                                             const double *__restrict__ w, double x,
+                                             double (&L)[PM]) {
+  double s = 0;
+  int exact = -1;
+#pragma unroll
+  for (int a = 0; a < PM; ++a) {
+    L[a] = 0.0;
+    if (a < p) {
+      double dx = x - u[a];
+      if (dx == 0.0) exact = a;
+      double q = w[a] / dx;
+      L[a] = q;
+      s += q;
+    }
+  }
+  if (exact >= 0) {
+#pragma unroll
+    for (int a = 0; a < PM; ++a) L[a] = (a == exact) ? 1.0 : 0.0;
+  } else {
+    double is = 1.0 / s;
+#pragma unroll
+    for (int a = 0; a < PM; ++a) L[a] *= is;
+  }
+}
+
+template <int D> struct PMax { static constexpr int v = D == 2 ? kMaxCheb : 10; };
+
+// Upward: one wavefront per chunk of <= kUpChunk points of a far cluster; the
+// chunk's partial U_c^T x_c goes to part_up, reduced per cluster afterwards.
+
+template <int D>
+__global__ void __launch_bounds__(64) k_up1(const UpItem *__restrict__ items,
+                                            const FarCluster *__restrict__ fc,
+                                            const double *__restrict__ pts, int64_t n,
+                                            const double *__restrict__ cheb,
+                                            const double *__restrict__ xt,
+                                            double *__restrict__ part_up) {
+  constexpr int PM = PMax<D>::v;
+  constexpr int QMAX = (D == 2 ? 256 : 1000 + 63) / 64;
+  __shared__ double Ls[D][64][PM + 1];
+  __shared__ double Xs[64];
+  const UpItem it = items[blockIdx.x];
+  const FarCluster c = fc[it.fc];
+  const int p = c.p, pd = c.pd;
+  const int l = threadIdx.x;
+  const double *cu = cheb + p * 2 * kMaxCheb;
+  int oa[QMAX][D];
+  double acc[QMAX];
+  const int nq = (pd + 63) / 64;
+#pragma unroll
+  for (int q = 0; q < QMAX; ++q) {
+    acc[q] = 0.0;
+    int o = l + 64 * q, r = o < pd ? o : 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      oa[q][k] = r % p;
+      r /= p;
+    }
+  }
+  for (int64_t i0 = it.begin; i0 < it.end; i0 += 64) {
+    const int cnt = (int)min((int64_t)64, it.end - i0);
+    if (l < cnt) {
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        double x = pts[k * n + i0 + l];
+        double z = c.hw[k] > 0 ? (x - c.ctr[k]) / c.hw[k] : 0.0;
+        double L[PM];
+        lagrange_reg<PM>(p, cu, cu + kMaxCheb, z, L);
+#pragma unroll
+        for (int a = 0; a < PM; ++a) Ls[k][l][a] = L[a];
+      }
+      Xs[l] = xt[i0 + l];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+      if (q < nq) {
+        double s = 0;
+        if (D == 2) {
+          const int a0 = oa[q][0], a1 = oa[q][1];
+          for (int i = 0; i < cnt; ++i) s = fma(Ls[0][i][a0] * Ls[1][i][a1], Xs[i], s);
+        } else {
+          const int a0 = oa[q][0], a1 = oa[q][1], a2 = oa[q][D - 1];
+          for (int i = 0; i < cnt; ++i)
+            s = fma(Ls[0][i][a0] * Ls[1][i][a1] * Ls[D - 1][i][a2], Xs[i], s);
+        }
+        acc[q] += s;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < QMAX; ++q) {
+    int o = l + 64 * q;
+    if (q < nq && o < pd) part_up[it.poff + o] = acc[q];
+  }
+}
+
+// Sum the chunk partials of each far cluster (fixed order).
+__global__ void __launch_bounds__(256) k_up_reduce(const FarCluster *__restrict__ fc,
+                                                   const int32_t *__restrict__ item_ptr,
+                                                   const UpItem *__restrict__ items,
+                                                   const double *__restrict__ part_up,
+                                                   double *__restrict__ xhat) {
+  const FarCluster c = fc[blockIdx.x];
+  const int i0 = item_ptr[blockIdx.x], i1 = item_ptr[blockIdx.x + 1];
+  for (int a = threadIdx.x; a < c.pd; a += 256) {
+    double s = 0;
+    for (int it = i0; it < i1; ++it) s += part_up[items[it].poff + a];
+    xhat[c.coef_off + a] = s;
+  }
+}
+
+// Couplings over unordered admissible pairs {s, t}: every entry of
+// K(xi_s, xi_t) is evaluated once and used for both yhat_s += K xhat_t and
+// yhat_t += K^T xhat_s.  K is produced in LDS row blocks of at most kKTile
+// entries (all threads evaluate, balanced), then the block's row sums
+// (K xhat_t) and column sums (K^T xhat_s) are taken from LDS.  Results go to
+// part_pair (yhat_s part first, then yhat_t part).
+constexpr int kKTile = 2048;
+
+template <int D>
+__global__ void __launch_bounds__(256) k_couple1(const PairItem *__restrict__ pairs,
+                                                 const FarCluster *__restrict__ fc,
+                                                 const double *__restrict__ cheb, int kind,
+                                                 double inv_ell, double theta,
+                                                 const double *__restrict__ xhat,
+                                                 double *__restrict__ part_pair) {
+  constexpr int PDM = D == 2 ? kMaxCheb * kMaxCheb : 1024;   // max p^D
+  __shared__ double Kt[kKTile];
+  __shared__ double xi_s[D][PDM];                    // nodes of s (scaled by the kernel rate)
+  __shared__ double xs_s[PDM], xs_t[PDM];
+  __shared__ double yt[PDM];
+  const PairItem pr = pairs[blockIdx.x];
+  const FarCluster cs = fc[pr.s], ct = fc[pr.t];
+  const int ps = cs.p, pt = ct.p, pds = cs.pd, pdt = ct.pd;
+  const int tid = threadIdx.x;
+  const double sq = kind == FKF_MATERN_12 ? 1.0 : (kind == FKF_MATERN_32 ? 1.7320508075688772
+                                                                          : 2.2360679774997896);
+  const double scale = sq * inv_ell;   // t = scale * r
+  const double *us = cheb + ps * 2 * kMaxCheb, *ut = cheb + pt * 2 * kMaxCheb;
+  for (int a = tid; a < pds; a += 256) {
+    xs_s[a] = xhat[cs.coef_off + a];
+    int r = a;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      xi_s[k][a] = scale * (cs.ctr[k] + cs.hw[k] * us[r % ps]);
+      r /= ps;
+    }
+  }
+  for (int c = tid; c < pdt; c += 256) {
+    xs_t[c] = xhat[ct.coef_off + c];
+    yt[c] = 0.0;
+  }
+  __syncthreads();
+  // thread -> fixed column(s) b = bb (+256...), rows rr, rr + nrp, ...
+  const int pdt_c = min(pdt, 256);
+  const int nrp = 256 / pdt_c;
+  const int bb = tid % pdt_c, rr = tid / pdt_c;
+  const bool active = rr < nrp;
+  const int rb = max(1, min(pds, kKTile / pdt));      // rows per LDS block
+  for (int A0 = 0; A0 < pds; A0 += rb) {
+    const int rows = min(rb, pds - A0);
+    if (active) {
+      for (int b = bb; b < pdt; b += 256) {
+        double xb[D];
+        int r = b;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          xb[k] = scale * (ct.ctr[k] + ct.hw[k] * ut[r % pt]);
+          r /= pt;
+        }
+        for (int rw = rr; rw < rows; rw += nrp) {
+          const int a = A0 + rw;
+          double dx = xi_s[0][a] - xb[0];
+          double t2 = dx * dx;
+#pragma unroll
+          for (int k = 1; k < D; ++k) {
+            dx = xi_s[k][a] - xb[k];
+            t2 = fma(dx, dx, t2);
+          }
+          const double t = sqrt_pos(t2);
+          const double ex = exp_nonpos(-t);
+          const double kv = kind == FKF_MATERN_12
+                                ? ex
+                                : (kind == FKF_MATERN_32 ? fma(t, ex, ex)
+                                                         : fma(fma(t, 1.0 / 3.0, 1.0) * t, ex, ex));
+          Kt[rw * pdt + b] = theta * kv;
+        }
+      }
+    }
+    __syncthreads();
+    // row sums (K xhat_t)[A0 + r]: four lanes per row, combined by shuffles
+    for (int r0 = 0; r0 < rows; r0 += 64) {
+      const int r = r0 + (tid >> 2), q0 = tid & 3;
+      double s = 0;
+      if (r < rows) {
+        const double *kr = Kt + r * pdt;
+#pragma unroll 4
+        for (int q = q0; q < pdt; q += 4) s = fma(kr[q], xs_t[q], s);
+      }
+      s += __shfl_xor(s, 1);
+      s += __shfl_xor(s, 2);
+      if (r < rows && q0 == 0) part_pair[pr.off + A0 + r] = s;
+    }
+    // column sums (K^T xhat_s)[c], accumulated over row blocks
+    for (int c0 = 0; c0 < pdt; c0 += 64) {
+      const int c = c0 + (tid >> 2), r1 = tid & 3;
+      double s = 0;
+      if (c < pdt) {
+#pragma unroll 4
+        for (int r = r1; r < rows; r += 4) s = fma(Kt[r * pdt + c], xs_s[A0 + r], s);
+      }
+      s += __shfl_xor(s, 1);
+      s += __shfl_xor(s, 2);
+      if (c < pdt && r1 == 0) yt[c] += s;
+    }
+    __syncthreads();
+  }
+  for (int c = tid; c < pdt; c += 256) part_pair[pr.off + pds + c] = yt[c];
+}
+
+// Couplings for pairs whose clusters both have at most 64 nodes (the fine
+// levels, which carry most pairs): one wavefront per pair, four pairs per
+// workgroup.  Lane b owns column b of K: it evaluates K[a][b] for every row a,
+// accumulates (K^T xhat_s)[b] in a register and keeps the 64 row terms
+// K[a][b] xhat_t[b]; a butterfly reduce-scatter over the wavefront (63
+// shuffles) leaves (K xhat_t)[l] on lane l.
+template <int D>
+__global__ void __launch_bounds__(256) k_couple_small(const PairItem *__restrict__ pairs,
+                                                      int64_t n_pairs,
+                                                      const FarCluster *__restrict__ fc,
+                                                      const double *__restrict__ cheb, int kind,
+                                                      double inv_ell, double theta,
+                                                      const double *__restrict__ xhat,
+                                                      double *__restrict__ part_pair) {
+  __shared__ double xi[4][D][64];
+  __shared__ double xsv[4][64];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
+  const int64_t q = (int64_t)blockIdx.x * 4 + w;
+  if (q >= n_pairs) return;   // whole wavefront leaves together
+  const PairItem pr = pairs[q];
+  const FarCluster cs = fc[pr.s], ct = fc[pr.t];
+  const int ps = cs.p, pt = ct.p, pds = cs.pd, pdt = ct.pd;
+  const double sq = kind == FKF_MATERN_12 ? 1.0 : (kind == FKF_MATERN_32 ? 1.7320508075688772
+                                                                          : 2.2360679774997896);
+  const double scale = sq * inv_ell;
+  const double *us = cheb + ps * 2 * kMaxCheb, *ut = cheb + pt * 2 * kMaxCheb;
+  if (l < pds) {
+    int r = l;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      xi[w][k][l] = scale * (cs.ctr[k] + cs.hw[k] * us[r % ps]);
+      r /= ps;
+    }
+    xsv[w][l] = xhat[cs.coef_off + l];
+  }
+  double xb[D];
+  {
+    int r = l < pdt ? l : 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      xb[k] = scale * (ct.ctr[k] + ct.hw[k] * ut[r % pt]);
+      r /= pt;
+    }
+  }
+  const double xtb = l < pdt ? xhat[ct.coef_off + l] : 0.0;
+  const bool col_ok = l < pdt;
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_wave_barrier();
+  double v[64];
+  double cacc = 0.0;
+#pragma unroll
+  for (int a = 0; a < 64; ++a) {
+    v[a] = 0.0;
+    if (a < pds) {
+      double dx = xi[w][0][a] - xb[0];
+      double t2 = dx * dx;
+#pragma unroll
+      for (int k = 1; k < D; ++k) {
+        dx = xi[w][k][a] - xb[k];
+        t2 = fma(dx, dx, t2);
+      }
+      const double t = sqrt_pos(t2);
+      const double ex = exp_nonpos(-t);
+      double kv = kind == FKF_MATERN_12
+                      ? ex
+                      : (kind == FKF_MATERN_32 ? fma(t, ex, ex)
+                                               : fma(fma(t, 1.0 / 3.0, 1.0) * t, ex, ex));
+      kv = col_ok ? theta * kv : 0.0;
+      v[a] = kv * xtb;
+      cacc = fma(kv, xsv[w][a], cacc);
+    }
+  }
+  // reduce-scatter: after the step with mask m, v[i] holds row i + (bits of l above m)
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const bool up = (l & m) != 0;
+#pragma unroll
+    for (int i = 0; i < m; ++i) {
+      const double keep = up ? v[i + m] : v[i];
+      const double send = up ? v[i] : v[i + m];
+      v[i] = keep + __shfl_xor(send, m);
+    }
+  }
+  if (l < pds) part_pair[pr.off + l] = v[0];
+  if (col_ok) part_pair[pr.off + pds + l] = cacc;
+}
+
+// yhat_c = sum of the pair partials that belong to far cluster c (fixed order).
+__global__ void __launch_bounds__(256) k_couple_reduce(const FarCluster *__restrict__ fc,
+                                                       const int32_t *__restrict__ cp_ptr,
+                                                       const int64_t *__restrict__ cp_off,
+                                                       const double *__restrict__ part_pair,
+                                                       double *__restrict__ yhat) {
+  const FarCluster c = fc[blockIdx.x];
+  const int e0 = cp_ptr[blockIdx.x], e1 = cp_ptr[blockIdx.x + 1];
+  for (int a = threadIdx.x; a < c.pd; a += 256) {
+    double s = 0;
+    for (int e = e0; e < e1; ++e) s += part_pair[cp_off[e] + a];
+    yhat[c.coef_off + a] = s;
+  }
+}
+
+// Downward pass + near-field partials + scatter, one column.  Four waves split
+// the far ancestors of the leaf; lane i owns point i; the tensor Lagrange
+// contraction is factorised per axis.
+template <int D>
+__global__ void __launch_bounds__(256) k_final1(
+    const int64_t *__restrict__ leaf_off, const double *__restrict__ pts, int64_t n,
+    const double *__restrict__ cheb, const FarCluster *__restrict__ fc,
+    const int32_t *__restrict__ anc_ptr, const int32_t *__restrict__ anc_idx,
+    const double *__restrict__ yhat, const double *__restrict__ part,
+    const int32_t *__restrict__ part_ptr, const int32_t *__restrict__ part_idx,
+    const int64_t *__restrict__ perm, double *__restrict__ Y) {
+  constexpr int PM = PMax<D>::v;
+  __shared__ double wsum[4][64];
+  const int leaf = blockIdx.x;
+  const int tid = threadIdx.x, w = tid >> 6, i = tid & 63;
+  const int64_t s0 = leaf_off[leaf], m = leaf_off[leaf + 1] - s0;
+  double acc = 0;
+  if (i < m) {
+    double x[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[k] = pts[k * n + s0 + i];
+    for (int e = anc_ptr[leaf] + w; e < anc_ptr[leaf + 1]; e += 4) {
+      const FarCluster c = fc[__builtin_amdgcn_readfirstlane(anc_idx[e])];
+      const int p = c.p;
+      const double *cu = cheb + p * 2 * kMaxCheb;
+      const double *yh = yhat + c.coef_off;
+      double L[D][PM];
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        double z = c.hw[k] > 0 ? (x[k] - c.ctr[k]) / c.hw[k] : 0.0;
+        lagrange_reg<PM>(p, cu, cu + kMaxCheb, z, L[k]);
+      }
+      double s = 0;
+      if (D == 2) {
+#pragma unroll
+        for (int a1 = 0; a1 < PM; ++a1) {
+          if (a1 < p) {
+            double t = 0;
+#pragma unroll
+            for (int a0 = 0; a0 < PM; ++a0)
+              if (a0 < p) t = fma(L[0][a0], yh[a0 + p * a1], t);
+            s = fma(L[D - 1][a1], t, s);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int a2 = 0; a2 < PM; ++a2) {
+          if (a2 < p) {
+            double t2 = 0;
+#pragma unroll
+            for (int a1 = 0; a1 < PM; ++a1) {
+              if (a1 < p) {
+                double t = 0;
+#pragma unroll
+                for (int a0 = 0; a0 < PM; ++a0)
+                  if (a0 < p) t = fma(L[0][a0], yh[a0 + p * (a1 + p * a2)], t);
+                t2 = fma(L[1][a1], t, t2);
+              }
+            }
+            s = fma(L[D - 1][a2], t2, s);
+          }
+        }
+      }
+      acc += s;
+    }
+  }
+  wsum[w][i] = acc;
+  __syncthreads();
+  if (w == 0 && i < m) {
+    double v = wsum[0][i] + wsum[1][i] + wsum[2][i] + wsum[3][i];
+    for (int e = part_ptr[leaf]; e < part_ptr[leaf + 1]; ++e) {
+      int code = part_idx[e];
+      v += part[(int64_t)(code >> 1) * 128 + (code & 1) * 64 + i];
+    }
+    Y[perm[s0 + i]] = v;
+  }
+}
+
+
+// ================================================= several columns (MFMA) ===
+// FP64 matrix cores, v_mfma_f64_16x16x4f64.  Operand layout per lane l of a
+// wavefront: A[l % 16][l / 16] (16 x 4), B[l / 16][l % 16] (4 x 16); the
+// 16 x 16 result has D[(l / 16) + 4 r][l % 16] in register r.
+// Every kernel below computes a tile of RB16 * 16 rows x NCB * 16 columns per
+// workgroup of four wavefronts; wavefront w owns row blocks w, w + 4, ... and
+// all NCB column blocks.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma4(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Upward: partial Xhat_c = U_c^T X_c over one chunk of <= kUpChunkM points.
+// A[a][i] = prod_k L_k(x_i)[a_k] is formed from per-point Lagrange values in
+// LDS; B = X rows of the chunk (64 points at a time).
+
+template <int D, int NCB, int RBW>
+__global__ void __launch_bounds__(256) k_up_mfma(const UpItem *__restrict__ items,
+                                                 const FarCluster *__restrict__ fc,
+                                                 const double *__restrict__ pts, int64_t n,
+                                                 const double *__restrict__ cheb,
+                                                 const double *__restrict__ xt, int nrhs,
+                                                 double *__restrict__ part) {
+  constexpr int PM = PMax<D>::v;
+  constexpr int NC = NCB * 16;
+  __shared__ double Ls[D][64][PM + 1];
+  __shared__ double Bs[64][NC + 1];
+  const UpItem it = items[blockIdx.x];
+  const FarCluster c = fc[it.fc];
+  const int p = c.p, pd = c.pd;
+  const int c0 = blockIdx.y * NC;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int lr = l & 15, lk = l >> 4;
+  const double *cu = cheb + p * 2 * kMaxCheb;
+  int ai[RBW][D];
+  bool aval[RBW];
+#pragma unroll
+  for (int q = 0; q < RBW; ++q) {
+    int a = (w + 4 * q) * 16 + lr;
+    aval[q] = a < pd;
+    int r = aval[q] ? a : 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      ai[q][k] = r % p;
+      r /= p;
+    }
+  }
+  v4d acc[RBW][NCB];
+#pragma unroll
+  for (int q = 0; q < RBW; ++q)
+#pragma unroll
+    for (int j = 0; j < NCB; ++j) acc[q][j] = v4d{0, 0, 0, 0};
+  const int nrb = (pd + 15) / 16;
+  for (int64_t i0 = it.begin; i0 < it.end; i0 += 64) {
+    const int cnt = (int)min((int64_t)64, it.end - i0);
+    if (tid < 64) {
+      const int i = tid;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        double L[PM];
+        if (i < cnt) {
+          double x = pts[k * n + i0 + i];
+          double z = c.hw[k] > 0 ? (x - c.ctr[k]) / c.hw[k] : 0.0;
+          lagrange_reg<PM>(p, cu, cu + kMaxCheb, z, L);
+        } else {
+#pragma unroll
+          for (int a = 0; a < PM; ++a) L[a] = 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < PM; ++a) Ls[k][i][a] = L[a];
+      }
+    }
+    for (int e = tid; e < 64 * NC; e += 256) {
+      int i = e & 63, cc = e >> 6;
+      Bs[i][cc] = (i < cnt && c0 + cc < nrhs) ? xt[i0 + i + n * (c0 + cc)] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int kk = 0; kk < 16; ++kk) {
+      const int i = kk * 4 + lk;
+      double b[NCB];
+#pragma unroll
+      for (int j = 0; j < NCB; ++j) b[j] = Bs[i][j * 16 + lr];
+#pragma unroll
+      for (int q = 0; q < RBW; ++q) {
+        if (w + 4 * q < nrb) {
+          double a = Ls[0][i][ai[q][0]];
+#pragma unroll
+          for (int k = 1; k < D; ++k) a *= Ls[k][i][ai[q][k]];
+          a = aval[q] ? a : 0.0;
+#pragma unroll
+          for (int j = 0; j < NCB; ++j) acc[q][j] = mfma4(a, b[j], acc[q][j]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double *o = part + it.poff * nrhs;
+#pragma unroll
+  for (int q = 0; q < RBW; ++q)
+#pragma unroll
+    for (int j = 0; j < NCB; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int a = (w + 4 * q) * 16 + lk + 4 * r;
+        int cc = c0 + j * 16 + lr;
+        if (a < pd && cc < nrhs) o[a + (int64_t)pd * cc] = acc[q][j][r];
+      }
+}
+
+// Sum the chunk partials (pd x nrhs each) of every far cluster.
+__global__ void __launch_bounds__(256) k_up_reduce_m(const FarCluster *__restrict__ fc,
+                                                     const int32_t *__restrict__ item_ptr,
+                                                     const UpItem *__restrict__ items, int nrhs,
+                                                     const double *__restrict__ part,
+                                                     double *__restrict__ xhat) {
+  const FarCluster c = fc[blockIdx.x];
+  const int i0 = item_ptr[blockIdx.x], i1 = item_ptr[blockIdx.x + 1];
+  const int64_t tot = (int64_t)c.pd * nrhs;
+  for (int64_t e = (int64_t)blockIdx.y * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.y * 256) {
+    double s = 0;
+    for (int it = i0; it < i1; ++it) s += part[items[it].poff * nrhs + e];
+    xhat[c.coef_off * nrhs + e] = s;
+  }
+}
+
+// Couplings: Yhat_s = sum over admissible t of K(xi_s, xi_t) Xhat_t.  The
+// kernel entries are evaluated in registers directly as MFMA A operands; B is
+// a 64-row chunk of Xhat_t staged in LDS.
+template <int D, int NCB, int RBW>
+__global__ void __launch_bounds__(256) k_couple_mfma(const FarCluster *__restrict__ fc,
+                                                     const int32_t *__restrict__ far_ptr,
+                                                     const int32_t *__restrict__ far_col,
+                                                     const double *__restrict__ cheb, int kind,
+                                                     double inv_ell, double theta,
+                                                     const double *__restrict__ xhat, int nrhs,
+                                                     double *__restrict__ yhat) {
+  constexpr int NC = NCB * 16;
+  __shared__ double Bs[64][NC + 1];
+  __shared__ double xit[D][64];
+  const int sidx = blockIdx.x;
+  const FarCluster cs = fc[sidx];
+  const int c0 = blockIdx.y * NC;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int lr = l & 15, lk = l >> 4;
+  const int ps = cs.p, pds = cs.pd;
+  const double sq = kind == FKF_MATERN_12 ? 1.0 : (kind == FKF_MATERN_32 ? 1.7320508075688772
+                                                                          : 2.2360679774997896);
+  const double scale = sq * inv_ell;
+  const double *us = cheb + ps * 2 * kMaxCheb;
+  double xa[RBW][D];
+  bool aval[RBW];
+#pragma unroll
+  for (int q = 0; q < RBW; ++q) {
+    int a = (w + 4 * q) * 16 + lr;
+    aval[q] = a < pds;
+    int r = aval[q] ? a : 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      xa[q][k] = scale * (cs.ctr[k] + cs.hw[k] * us[r % ps]);
+      r /= ps;
+    }
+  }
+  const int nrb = (pds + 15) / 16;
+  v4d acc[RBW][NCB];
+#pragma unroll
+  for (int q = 0; q < RBW; ++q)
+#pragma unroll
+    for (int j = 0; j < NCB; ++j) acc[q][j] = v4d{0, 0, 0, 0};
+  for (int e = far_ptr[sidx]; e < far_ptr[sidx + 1]; ++e) {
+    const FarCluster ct = fc[far_col[e]];
+    const int pt = ct.p, pdt = ct.pd;
+    const double *ut = cheb + pt * 2 * kMaxCheb;
+    for (int b0 = 0; b0 < pdt; b0 += 64) {
+      const int cnt = min(64, pdt - b0);
+      __syncthreads();
+      for (int q = tid; q < 64 * NC; q += 256) {
+        int kb = q & 63, cc = q >> 6;
+        Bs[kb][cc] = (kb < cnt && c0 + cc < nrhs)
+                         ? xhat[ct.coef_off * nrhs + b0 + kb + (int64_t)pdt * (c0 + cc)]
+                         : 0.0;
+      }
+      if (tid < 64) {
+        int b = b0 + tid, r = tid < cnt ? b : 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          xit[k][tid] = scale * (ct.ctr[k] + ct.hw[k] * ut[r % pt]);
+          r /= pt;
+        }
+      }
+      __syncthreads();
+      const int nk = (cnt + 3) / 4;
+      for (int kk = 0; kk < nk; ++kk) {
+        const int kb = kk * 4 + lk;
+        double b[NCB];
+#pragma unroll
+        for (int j = 0; j < NCB; ++j) b[j] = Bs[kb][j * 16 + lr];
+        double xb[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) xb[k] = xit[k][kb];
+#pragma unroll
+        for (int q = 0; q < RBW; ++q) {
+          if (w + 4 * q < nrb) {
+            double dx = xa[q][0] - xb[0];
+            double t2 = dx * dx;
+#pragma unroll
+            for (int k = 1; k < D; ++k) {
+              dx = xa[q][k] - xb[k];
+              t2 = fma(dx, dx, t2);
+            }
+            const double t = sqrt_pos(t2);
+            const double ex = exp_nonpos(-t);
+            double kv = kind == FKF_MATERN_12
+                            ? ex
+                            : (kind == FKF_MATERN_32 ? fma(t, ex, ex)
+                                                     : fma(fma(t, 1.0 / 3.0, 1.0) * t, ex, ex));
+            kv = (aval[q] && kb < cnt) ? theta * kv : 0.0;
+#pragma unroll
+            for (int j = 0; j < NCB; ++j) acc[q][j] = mfma4(kv, b[j], acc[q][j]);
+          }
+        }
+      }
+    }
+  }
+  double *o = yhat + cs.coef_off * nrhs;
+#pragma unroll
+  for (int q = 0; q < RBW; ++q)
+#pragma unroll
+    for (int j = 0; j < NCB; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int a = (w + 4 * q) * 16 + lk + 4 * r;
+        int cc = c0 + j * 16 + lr;
+        if (a < pds && cc < nrhs) o[a + (int64_t)pds * cc] = acc[q][j][r];
+      }
+}
+
+// Near field + downward pass + scatter for one leaf and NC columns:
+// Y_s = sum_{t near s} Gamma_st X_t + sum_{far ancestors c} U_c|_s Yhat_c.
+template <int D, int NCB>
+__global__ void __launch_bounds__(256) k_down_mfma(
+    const double *__restrict__ blk, const int32_t *__restrict__ near_ptr,
+    const int32_t *__restrict__ near_idx, const int32_t *__restrict__ bs,
+    const int32_t *__restrict__ bt, const int64_t *__restrict__ leaf_off,
+    const double *__restrict__ pts, int64_t n, const double *__restrict__ cheb,
+    const FarCluster *__restrict__ fc, const int32_t *__restrict__ anc_ptr,
+    const int32_t *__restrict__ anc_idx, const double *__restrict__ xt,
+    const double *__restrict__ yhat, const int64_t *__restrict__ perm, int nrhs,
+    double *__restrict__ Y, int64_t ldy) {
+  constexpr int PM = PMax<D>::v;
+  constexpr int NC = NCB * 16;
+  __shared__ double As[64][65];
+  __shared__ double Bs[64][NC + 1];
+  __shared__ double Ls[D][64][PM + 1];
+  __shared__ int32_t aidx[D == 2 ? 256 : 1024];   // packed per-axis node indices
+  const int s = blockIdx.x;
+  const int c0 = blockIdx.y * NC;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int lr = l & 15, lk = l >> 4;
+  const int64_t s0 = leaf_off[s], ms = leaf_off[s + 1] - s0;
+  const int row = w * 16 + lr;   // A row of this lane (point of the leaf)
+  v4d acc[NCB];
+#pragma unroll
+  for (int j = 0; j < NCB; ++j) acc[j] = v4d{0, 0, 0, 0};
+  // near field
+  for (int e = near_ptr[s]; e < near_ptr[s + 1]; ++e) {
+    const int code = near_idx[e];
+    const int64_t b = code >> 1;
+    const bool trans = code & 1;
+    const int t = trans ? bs[b] : bt[b];
+    const int64_t t0 = leaf_off[t], mt = leaf_off[t + 1] - t0;
+    __syncthreads();
+    const v2d *src = reinterpret_cast<const v2d *>(blk + b * 4096);
+    for (int q = tid; q < 2048; q += 256) {
+      int k = q >> 6, lane = q & 63;
+      int i = 8 * (lane & 7) + (k >> 2), j = 8 * (lane >> 3) + 2 * (k & 3);
+      v2d v = src[q];
+      if (!trans) {
+        As[i][j] = v.x;
+        As[i][j + 1] = v.y;
+      } else {
+        As[j][i] = v.x;
+        As[j + 1][i] = v.y;
+      }
+    }
+    for (int q = tid; q < 64 * NC; q += 256) {
+      int j = q & 63, cc = q >> 6;
+      Bs[j][cc] = (j < mt && c0 + cc < nrhs) ? xt[t0 + j + n * (c0 + cc)] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < 16; ++kk) {
+      const int k = kk * 4 + lk;
+      const double a = As[row][k];
+#pragma unroll
+      for (int j = 0; j < NCB; ++j) acc[j] = mfma4(a, Bs[k][j * 16 + lr], acc[j]);
+    }
+  }
+  // far field: U_c restricted to the leaf's points times Yhat_c
+  for (int e = anc_ptr[s]; e < anc_ptr[s + 1]; ++e) {
+    const FarCluster c = fc[anc_idx[e]];
+    const int p = c.p, pd = c.pd;
+    const double *cu = cheb + p * 2 * kMaxCheb;
+    __syncthreads();
+    for (int a = tid; a < pd; a += 256) {
+      int r = a, code = 0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        code |= (r % p) << (8 * k);
+        r /= p;
+      }
+      aidx[a] = code;
+    }
+    if (tid < 64) {
+      const int i = tid;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        double L[PM];
+        if (i < ms) {
+          double x = pts[k * n + s0 + i];
+          double z = c.hw[k] > 0 ? (x - c.ctr[k]) / c.hw[k] : 0.0;
+          lagrange_reg<PM>(p, cu, cu + kMaxCheb, z, L);
+        } else {
+#pragma unroll
+          for (int a = 0; a < PM; ++a) L[a] = 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < PM; ++a) Ls[k][i][a] = L[a];
+      }
+    }
+    for (int a0 = 0; a0 < pd; a0 += 64) {
+      const int cnt = min(64, pd - a0);
+      __syncthreads();
+      for (int q = tid; q < 64 * NC; q += 256) {
+        int ka = q & 63, cc = q >> 6;
+        Bs[ka][cc] = (ka < cnt && c0 + cc < nrhs)
+                         ? yhat[c.coef_off * nrhs + a0 + ka + (int64_t)pd * (c0 + cc)]
+                         : 0.0;
+      }
+      __syncthreads();
+      const int nk = (cnt + 3) / 4;
+      for (int kk = 0; kk < nk; ++kk) {
+        const int ka = kk * 4 + lk;
+        const int code = aidx[a0 + ka < pd ? a0 + ka : 0];
+        double a = Ls[0][row][code & 255];
+#pragma unroll
+        for (int k = 1; k < D; ++k) a *= Ls[k][row][(code >> (8 * k)) & 255];
+        a = (ka < cnt) ? a : 0.0;
+#pragma unroll
+        for (int j = 0; j < NCB; ++j) acc[j] = mfma4(a, Bs[ka][j * 16 + lr], acc[j]);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NCB; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int i = w * 16 + lk + 4 * r;
+      int cc = c0 + j * 16 + lr;
+      if (i < ms && cc < nrhs) Y[perm[s0 + i] + ldy * cc] = acc[j][r];
+    }
+}
+
 }  // namespace fkf
 
 // ------------------------------------------------------------------ host ---
@@ -636,6 +1445,82 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
     cov->far_col.upload(fcol, st);
     cov->anc_ptr.upload(ap, st);
     cov->anc_idx.upload(ai, st);
+    // one-column work lists: upward chunks and unordered pairs
+    {
+      std::vector<UpItem> ups;
+      std::vector<int32_t> uptr(1, 0);
+      int64_t poff = 0;
+      for (int c = 0; c < cov->n_fc; ++c) {
+        for (int64_t b = fcs[c].begin; b < fcs[c].end; b += kUpChunk) {
+          UpItem u{};
+          u.fc = c;
+          u.begin = b;
+          u.end = std::min(b + kUpChunk, fcs[c].end);
+          u.poff = poff;
+          poff += fcs[c].pd;
+          ups.push_back(u);
+        }
+        uptr.push_back((int32_t)ups.size());
+      }
+      cov->n_up_items = (int64_t)ups.size();
+      cov->n_part_up = poff;
+      cov->up_items.upload(ups, st);
+      cov->up_ptr.upload(uptr, st);
+      std::vector<UpItem> upm;
+      std::vector<int32_t> uptrm(1, 0);
+      int64_t poffm = 0;
+      for (int c = 0; c < cov->n_fc; ++c) {
+        for (int64_t b = fcs[c].begin; b < fcs[c].end; b += kUpChunkM) {
+          UpItem u{};
+          u.fc = c;
+          u.begin = b;
+          u.end = std::min(b + kUpChunkM, fcs[c].end);
+          u.poff = poffm;
+          poffm += fcs[c].pd;
+          upm.push_back(u);
+        }
+        uptrm.push_back((int32_t)upm.size());
+      }
+      cov->n_up_items_m = (int64_t)upm.size();
+      cov->n_part_up_m = poffm;
+      cov->up_items_m.upload(upm, st);
+      cov->up_ptr_m.upload(uptrm, st);
+      std::vector<PairItem> prs;
+      std::vector<std::vector<int64_t>> cpl(cov->n_fc);
+      int64_t off = 0, n_lt = 0, n_gt = 0;
+      for (auto &pr : fpairs) {
+        if (pr.first < pr.second) {
+          ++n_lt;
+          PairItem q{};
+          q.s = pr.first;
+          q.t = pr.second;
+          q.off = off;
+          cpl[pr.first].push_back(off);
+          cpl[pr.second].push_back(off + fcs[pr.first].pd);
+          off += fcs[pr.first].pd + fcs[pr.second].pd;
+          prs.push_back(q);
+        } else {
+          ++n_gt;
+        }
+      }
+      if (n_lt != n_gt) throw Error{FKF_E_ARG, "fkf_cov_build: admissible pairs are not symmetric"};
+      std::stable_partition(prs.begin(), prs.end(), [&](const PairItem &q) {
+        return fcs[q.s].pd > 64 || fcs[q.t].pd > 64;
+      });
+      cov->n_pairs_large = 0;
+      for (auto &q : prs) cov->n_pairs_large += (fcs[q.s].pd > 64 || fcs[q.t].pd > 64);
+      cov->n_pairs = (int64_t)prs.size();
+      cov->n_part_pair = off;
+      cov->pairs.upload(prs, st);
+      std::vector<int32_t> cptr(1, 0);
+      std::vector<int64_t> coff;
+      for (auto &v : cpl) {
+        coff.insert(coff.end(), v.begin(), v.end());
+        cptr.push_back((int32_t)coff.size());
+      }
+      cov->cp_ptr.upload(cptr, st);
+      cov->cp_off.upload(coff, st);
+    }
     std::vector<double> ch((kMaxCheb + 1) * 2 * kMaxCheb, 0.0);
     for (int p = 1; p <= kMaxCheb; ++p) cheb_nodes(p, &ch[p * 2 * kMaxCheb], &ch[p * 2 * kMaxCheb + kMaxCheb]);
     cov->cheb.upload(ch, st);
@@ -643,6 +1528,136 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
     *out = cov.release();
   });
 }
+
+namespace {
+
+// One column: near field (HBM-bound) on a forked stream, far field (ALU-bound)
+// on the caller's stream, joined before the final pass.
+void apply_one(fkf_cov *cov, double *Y, hipStream_t st) {
+  const int64_t n = cov->n;
+  if (!cov->side) {
+    FKF_CHECK_HIP(hipStreamCreateWithFlags(&cov->side, hipStreamNonBlocking));
+    FKF_CHECK_HIP(hipEventCreateWithFlags(&cov->ev_fork, hipEventDisableTiming));
+    FKF_CHECK_HIP(hipEventCreateWithFlags(&cov->ev_join, hipEventDisableTiming));
+  }
+  cov->part.reserve((size_t)std::max<int64_t>(cov->n_blk, 1) * 128);
+  FKF_CHECK_HIP(hipEventRecord(cov->ev_fork, st));
+  FKF_CHECK_HIP(hipStreamWaitEvent(cov->side, cov->ev_fork, 0));
+  {
+    FKF_TRACE("hmat_near_1rhs", cov->side);
+    if (cov->n_blk)
+      hipLaunchKernelGGL(k_near_sym1, dim3((unsigned)((cov->n_blk + 3) / 4)), dim3(256), 0,
+                         cov->side, cov->blk.p, cov->blk_s.p, cov->blk_t.p, cov->leaf_off.p,
+                         cov->xt.p, cov->n_blk, cov->part.p);
+  }
+  FKF_CHECK_HIP(hipEventRecord(cov->ev_join, cov->side));
+  const bool d3 = cov->d == 3;
+  if (cov->n_fc > 0) {
+    cov->xhat.reserve((size_t)cov->n_coef);
+    cov->yhat.reserve((size_t)cov->n_coef);
+    cov->part_up.reserve((size_t)std::max<int64_t>(cov->n_part_up, 1));
+    cov->part_pair.reserve((size_t)std::max<int64_t>(cov->n_part_pair, 1));
+    {
+      FKF_TRACE("hmat_far_up_1rhs", st);
+      if (d3)
+        hipLaunchKernelGGL(k_up1<3>, dim3((unsigned)cov->n_up_items), dim3(64), 0, st,
+                           cov->up_items.p, cov->fc.p, cov->pts.p, n, cov->cheb.p, cov->xt.p,
+                           cov->part_up.p);
+      else
+        hipLaunchKernelGGL(k_up1<2>, dim3((unsigned)cov->n_up_items), dim3(64), 0, st,
+                           cov->up_items.p, cov->fc.p, cov->pts.p, n, cov->cheb.p, cov->xt.p,
+                           cov->part_up.p);
+      hipLaunchKernelGGL(k_up_reduce, dim3(cov->n_fc), dim3(256), 0, st, cov->fc.p, cov->up_ptr.p,
+                         cov->up_items.p, cov->part_up.p, cov->xhat.p);
+    }
+    {
+      FKF_TRACE("hmat_far_couple_1rhs", st);
+      const int64_t nl = cov->n_pairs_large, ns = cov->n_pairs - cov->n_pairs_large;
+      if (nl > 0) {
+        if (d3)
+          hipLaunchKernelGGL(k_couple1<3>, dim3((unsigned)nl), dim3(256), 0, st, cov->pairs.p,
+                             cov->fc.p, cov->cheb.p, cov->kind, 1.0 / cov->ell, cov->theta,
+                             cov->xhat.p, cov->part_pair.p);
+        else
+          hipLaunchKernelGGL(k_couple1<2>, dim3((unsigned)nl), dim3(256), 0, st, cov->pairs.p,
+                             cov->fc.p, cov->cheb.p, cov->kind, 1.0 / cov->ell, cov->theta,
+                             cov->xhat.p, cov->part_pair.p);
+      }
+      if (ns > 0) {
+        const PairItem *sp = cov->pairs.p + nl;
+        const unsigned g = (unsigned)((ns + 3) / 4);
+        if (d3)
+          hipLaunchKernelGGL(k_couple_small<3>, dim3(g), dim3(256), 0, st, sp, ns, cov->fc.p,
+                             cov->cheb.p, cov->kind, 1.0 / cov->ell, cov->theta, cov->xhat.p,
+                             cov->part_pair.p);
+        else
+          hipLaunchKernelGGL(k_couple_small<2>, dim3(g), dim3(256), 0, st, sp, ns, cov->fc.p,
+                             cov->cheb.p, cov->kind, 1.0 / cov->ell, cov->theta, cov->xhat.p,
+                             cov->part_pair.p);
+      }
+      hipLaunchKernelGGL(k_couple_reduce, dim3(cov->n_fc), dim3(256), 0, st, cov->fc.p,
+                         cov->cp_ptr.p, cov->cp_off.p, cov->part_pair.p, cov->yhat.p);
+    }
+  }
+  FKF_CHECK_HIP(hipStreamWaitEvent(st, cov->ev_join, 0));
+  {
+    FKF_TRACE("hmat_final_1rhs", st);
+    if (d3)
+      hipLaunchKernelGGL(k_final1<3>, dim3(cov->n_leaves), dim3(256), 0, st, cov->leaf_off.p,
+                         cov->pts.p, n, cov->cheb.p, cov->fc.p, cov->anc_ptr.p, cov->anc_idx.p,
+                         cov->yhat.p, cov->part.p, cov->part_ptr.p, cov->part_idx.p, cov->perm.p,
+                         Y);
+    else
+      hipLaunchKernelGGL(k_final1<2>, dim3(cov->n_leaves), dim3(256), 0, st, cov->leaf_off.p,
+                         cov->pts.p, n, cov->cheb.p, cov->fc.p, cov->anc_ptr.p, cov->anc_idx.p,
+                         cov->yhat.p, cov->part.p, cov->part_ptr.p, cov->part_idx.p, cov->perm.p,
+                         Y);
+  }
+}
+
+// Several columns on the FP64 matrix cores: upward chunks + reduction,
+// couplings per target cluster, then near field + downward + scatter per leaf.
+template <int D, int NCB, int RBW>
+void apply_multi_t(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t st) {
+  constexpr int NC = NCB * 16;
+  const int64_t n = cov->n;
+  const unsigned gy = (unsigned)((nrhs + NC - 1) / NC);
+  if (cov->n_fc > 0) {
+    cov->xhat.reserve((size_t)cov->n_coef * nrhs);
+    cov->yhat.reserve((size_t)cov->n_coef * nrhs);
+    cov->part_up_m.reserve((size_t)cov->n_part_up_m * nrhs);
+    {
+      FKF_TRACE("hmat_far_up_multi", st);
+      hipLaunchKernelGGL((k_up_mfma<D, NCB, RBW>), dim3((unsigned)cov->n_up_items_m, gy), dim3(256),
+                         0, st, cov->up_items_m.p, cov->fc.p, cov->pts.p, n, cov->cheb.p,
+                         cov->xt.p, nrhs, cov->part_up_m.p);
+      hipLaunchKernelGGL(k_up_reduce_m, dim3(cov->n_fc, 8), dim3(256), 0, st, cov->fc.p,
+                         cov->up_ptr_m.p, cov->up_items_m.p, nrhs, cov->part_up_m.p, cov->xhat.p);
+    }
+    {
+      FKF_TRACE("hmat_far_couple_multi", st);
+      hipLaunchKernelGGL((k_couple_mfma<D, NCB, RBW>), dim3(cov->n_fc, gy), dim3(256), 0, st,
+                         cov->fc.p, cov->far_ptr.p, cov->far_col.p, cov->cheb.p, cov->kind,
+                         1.0 / cov->ell, cov->theta, cov->xhat.p, nrhs, cov->yhat.p);
+    }
+  }
+  FKF_TRACE("hmat_near_down_multi", st);
+  hipLaunchKernelGGL((k_down_mfma<D, NCB>), dim3(cov->n_leaves, gy), dim3(256), 0, st, cov->blk.p,
+                     cov->near_ptr.p, cov->near_idx.p, cov->blk_s.p, cov->blk_t.p,
+                     cov->leaf_off.p, cov->pts.p, n, cov->cheb.p, cov->fc.p, cov->anc_ptr.p,
+                     cov->anc_idx.p, cov->xt.p, cov->yhat.p, cov->perm.p, nrhs, Y, ldy);
+}
+
+void apply_multi(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t st) {
+  if (cov->d == 2)
+    apply_multi_t<2, 4, 4>(cov, nrhs, Y, ldy, st);
+  else if (cov->max_pd <= 256)
+    apply_multi_t<3, 4, 4>(cov, nrhs, Y, ldy, st);
+  else
+    apply_multi_t<3, 1, 16>(cov, nrhs, Y, ldy, st);
+}
+
+}  // namespace
 
 extern "C" fkf_status fkf_cov_apply(fkf_cov *cov, const double *X, int64_t ldx, int32_t nrhs,
                                     double *Y, int64_t ldy, void *stream) {
@@ -660,64 +1675,10 @@ extern "C" fkf_status fkf_cov_apply(fkf_cov *cov, const double *X, int64_t ldx, 
       FKF_TRACE("hmat_gather", st);
       hipLaunchKernelGGL(k_gather, gg, dim3(256), 0, st, X, ldx, nrhs, cov->perm.p, n, cov->xt.p);
     }
-    const bool one = (nrhs == 1);
-    if (one) {
-      cov->part.reserve((size_t)std::max<int64_t>(cov->n_blk, 1) * 128);
-      FKF_TRACE("hmat_near_1rhs", st);
-      if (cov->n_blk)
-        hipLaunchKernelGGL(k_near_sym1, dim3((unsigned)((cov->n_blk + 3) / 4)), dim3(256), 0, st,
-                           cov->blk.p, cov->blk_s.p, cov->blk_t.p, cov->leaf_off.p, cov->xt.p,
-                           cov->n_blk, cov->part.p);
+    if (nrhs == 1) {
+      apply_one(cov, Y, st);
     } else {
-      cov->yt.reserve((size_t)n * nrhs);
-      FKF_TRACE("hmat_near_multi", st);
-      hipLaunchKernelGGL(k_near_multi, dim3(cov->n_leaves, (unsigned)((nrhs + 31) / 32)), dim3(256),
-                         0, st, cov->blk.p, cov->near_ptr.p, cov->near_idx.p, cov->blk_s.p,
-                         cov->blk_t.p, cov->leaf_off.p, cov->xt.p, n, nrhs, cov->yt.p);
-    }
-    // columns per far-field workgroup: NC * max(p^d) must fit the 4096-entry LDS staging
-    const int NCm = cov->max_pd <= 512 ? 8 : 4;
-    if (cov->n_fc > 0) {
-      cov->xhat.reserve((size_t)cov->n_coef * nrhs);
-      cov->yhat.reserve((size_t)cov->n_coef * nrhs);
-      FKF_TRACE(one ? "hmat_far_1rhs" : "hmat_far_multi", st);
-      if (one) {
-        hipLaunchKernelGGL(k_far_up<1>, dim3(cov->n_fc, 1), dim3(256), 0, st, cov->fc.p,
-                           cov->pts.p, n, cov->d, cov->cheb.p, cov->xt.p, nrhs, cov->xhat.p);
-        hipLaunchKernelGGL(k_far_couple<1>, dim3(cov->n_fc, 1), dim3(256), 0, st, cov->fc.p,
-                           cov->far_ptr.p, cov->far_col.p, cov->d, cov->cheb.p, cov->kind,
-                           1.0 / cov->ell, cov->theta, cov->xhat.p, nrhs, cov->yhat.p);
-      } else {
-        unsigned gy = (unsigned)((nrhs + NCm - 1) / NCm);
-        if (NCm == 8) {
-          hipLaunchKernelGGL(k_far_up<8>, dim3(cov->n_fc, gy), dim3(256), 0, st, cov->fc.p,
-                             cov->pts.p, n, cov->d, cov->cheb.p, cov->xt.p, nrhs, cov->xhat.p);
-          hipLaunchKernelGGL(k_far_couple<8>, dim3(cov->n_fc, gy), dim3(256), 0, st, cov->fc.p,
-                             cov->far_ptr.p, cov->far_col.p, cov->d, cov->cheb.p, cov->kind,
-                             1.0 / cov->ell, cov->theta, cov->xhat.p, nrhs, cov->yhat.p);
-        } else {
-          hipLaunchKernelGGL(k_far_up<4>, dim3(cov->n_fc, gy), dim3(256), 0, st, cov->fc.p,
-                             cov->pts.p, n, cov->d, cov->cheb.p, cov->xt.p, nrhs, cov->xhat.p);
-          hipLaunchKernelGGL(k_far_couple<4>, dim3(cov->n_fc, gy), dim3(256), 0, st, cov->fc.p,
-                             cov->far_ptr.p, cov->far_col.p, cov->d, cov->cheb.p, cov->kind,
-                             1.0 / cov->ell, cov->theta, cov->xhat.p, nrhs, cov->yhat.p);
-        }
-      }
-    }
-    FKF_TRACE(one ? "hmat_finalize_1rhs" : "hmat_finalize_multi", st);
-    if (one) {
-      hipLaunchKernelGGL(k_finalize<1>, dim3(cov->n_leaves, 1), dim3(256), 0, st,
-                         cov->leaf_off.p, cov->pts.p, n, cov->d, cov->cheb.p, cov->fc.p,
-                         cov->anc_ptr.p, cov->anc_idx.p, cov->yhat.p, cov->part.p,
-                         cov->part_ptr.p, cov->part_idx.p, (const double *)nullptr, cov->perm.p,
-                         nrhs, Y, ldy);
-    } else {
-      auto fin = NCm == 8 ? k_finalize<8> : k_finalize<4>;
-      hipLaunchKernelGGL(fin, dim3(cov->n_leaves, (unsigned)((nrhs + NCm - 1) / NCm)),
-                         dim3(256), 0, st, cov->leaf_off.p, cov->pts.p, n, cov->d, cov->cheb.p,
-                         cov->fc.p, cov->anc_ptr.p, cov->anc_idx.p, cov->yhat.p,
-                         (const double *)nullptr, cov->part_ptr.p, cov->part_idx.p, cov->yt.p,
-                         cov->perm.p, nrhs, Y, ldy);
+      apply_multi(cov, nrhs, Y, ldy, st);
     }
     FKF_CHECK_HIP(hipGetLastError());
   });

@@ -14,4 +14,42 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// exp(x) for x <= 0 (finite), used for Matern kernel entries.  Method: Cody &
+// Waite argument reduction x = k ln2 + r with |r| <= ln2/2 (ln2 split into a
+// 32-bit-exact high part and a low correction), a degree-12 Taylor polynomial
+// for e^r (truncation error below 2e-16 relative on that interval), and an
+// exact scaling by 2^k.  No NaN/overflow handling: callers pass x <= 0.
+__device__ __forceinline__ double exp_nonpos(double x) {
+  const double kLog2e = 1.4426950408889634074;
+  const double kLn2Hi = 0.6931471803691238164902;       // ln 2 truncated to 32 significant bits
+  const double kLn2Lo = 1.9082149292705877000e-10;      // ln 2 - kLn2Hi
+  double k = rint(x * kLog2e);
+  double r = fma(-k, kLn2Hi, x);
+  r = fma(-k, kLn2Lo, r);
+  double p = 1.0 / 479001600.0;                          // 1/12!
+  p = fma(p, r, 1.0 / 39916800.0);
+  p = fma(p, r, 1.0 / 3628800.0);
+  p = fma(p, r, 1.0 / 362880.0);
+  p = fma(p, r, 1.0 / 40320.0);
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return __builtin_amdgcn_ldexp(p, (int)k);
+}
+
+// sqrt(x) for x > 0 (finite, normal): hardware reciprocal square root refined
+// by two Newton steps y <- y (3 - x y^2) / 2, then x * y.
+__device__ __forceinline__ double sqrt_pos(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return x * y;
+}
+
 }  // namespace fkf
