@@ -52,4 +52,21 @@ __device__ __forceinline__ double sqrt_pos(double x) {
   return x * y;
 }
 
+// 1/x for finite normal x != 0: hardware reciprocal refined by two Newton steps.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = r * fma(-x, r, 2.0);
+  r = r * fma(-x, r, 2.0);
+  return r;
+}
+
+// 1/sqrt(x) for finite x > 0: hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+
 }  // namespace fkf

@@ -9,7 +9,7 @@ namespace fkf {
 struct EigWork {
   DevBuf<double> A, V, J, fro;
   DevBuf<int> cnt;
-  int *cnt_host = nullptr;   // pinned mirror of the rotation counter
+  int *cnt_host = nullptr;   // pinned host scratch (8 bytes)
   ~EigWork();
 };
 

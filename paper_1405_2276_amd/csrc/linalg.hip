@@ -12,12 +12,12 @@ namespace fkf {
 // ===================================================== block Jacobi eigen ===
 // Two-sided block Jacobi.  The padded matrix (np = multiple of 32) is split
 // into nb = np/16 blocks of 16 indices.  A round pairs the blocks by a
-// round-robin tournament; each pair's 32 x 32 principal submatrix is fully
-// diagonalised in LDS by cyclic (parallel-ordered) Jacobi, giving an
-// orthogonal J_k, and then every 32 x 32 tile of A is updated as
-// J_k1^T A J_k2 and V as V J_k.  A sweep visits every block pair once; the
-// iteration stops after a sweep without rotations.  Padding indices carry
-// zero rows/columns and are never rotated.
+// round-robin tournament; each pair's 32 x 32 principal submatrix gets one
+// cyclic (parallel-ordered) Jacobi sweep in LDS, giving an orthogonal J_k,
+// and then every 32 x 32 tile of A is updated as J_k1^T A J_k2 and V as V J_k.
+// A sweep visits every block pair once; the iteration stops when the
+// off-diagonal Frobenius norm falls below 1e-12 ||A||_F (or nothing rotates).
+// Padding indices carry zero rows/columns and are never rotated.
 
 constexpr int kJB = 16;   // block size
 constexpr int kJT = 32;   // tile (pair) size
@@ -39,13 +39,18 @@ __device__ __forceinline__ bool jacobi_rotation(double app, double aqq, double a
     s = 0.0;
     return false;
   }
-  double tau = (aqq - app) / (2.0 * apq);
+  // tau = (aqq - app) / (2 apq); t = sign(tau) / (|tau| + sqrt(1 + tau^2)) is the
+  // smaller root of t^2 + 2 tau t - 1 = 0; c = 1/sqrt(1 + t^2), s = t c.
+  double tau = (aqq - app) * rcp_nr(2.0 * apq);
   double t;
-  if (fabs(tau) > 1e150)
-    t = 0.5 / tau;
-  else
-    t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-  c = 1.0 / sqrt(1.0 + t * t);
+  if (fabs(tau) > 1e150) {
+    t = 0.5 * rcp_nr(tau);
+  } else {
+    double q = 1.0 + tau * tau;
+    double sq = q * rsq_nr(q);
+    t = (tau >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(tau) + sq);
+  }
+  c = rsq_nr(1.0 + t * t);
   s = t * c;
   return true;
 }
@@ -76,9 +81,31 @@ __global__ void __launch_bounds__(1024) k_frob(const double *__restrict__ A, int
 
 __global__ void k_set_int(int *p, int v) { *p = v; }
 
+// off[0] = sqrt(sum of squared off-diagonal entries) / fro  (single workgroup)
+__global__ void __launch_bounds__(1024) k_offnorm(const double *__restrict__ A, int np,
+                                                  const double *__restrict__ fro,
+                                                  double *__restrict__ off) {
+  __shared__ double red[16];
+  double s = 0;
+  const int64_t len = (int64_t)np * np;
+  for (int64_t e = threadIdx.x; e < len; e += 1024) {
+    int i = (int)(e % np), j = (int)(e / np);
+    if (i != j) s += A[e] * A[e];
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int w = 0; w < 16; ++w) t += red[w];
+    off[0] = fro[0] > 0 ? sqrt(t) / fro[0] : 0.0;
+  }
+}
+
 __global__ void __launch_bounds__(256) k_jacobi_solve(const double *__restrict__ A, int np, int nb,
                                                       int round, const double *__restrict__ fro,
-                                                      double *__restrict__ Jout, int *cnt) {
+                                                      int max_inner, double *__restrict__ Jout,
+                                                      int *cnt) {
   __shared__ double S[kJT][kJT + 1];
   __shared__ double Jm[kJT][kJT + 1];
   __shared__ double rc[kJB], rs[kJB];
@@ -94,7 +121,7 @@ __global__ void __launch_bounds__(256) k_jacobi_solve(const double *__restrict__
   if (tid == 0) rot_any = 0;
   const double tol_abs = 1e-15 * fro[0], tol_rel = 1e-15;
   __syncthreads();
-  for (int sw = 0; sw < 40; ++sw) {
+  for (int sw = 0; sw < max_inner; ++sw) {
     if (tid == 0) rot_sweep = 0;
     __syncthreads();
     for (int ir = 0; ir < kJT - 1; ++ir) {
@@ -252,27 +279,33 @@ int sym_eig(const double *A, int64_t lda, int n, double *w, double *W, int64_t l
   ws.A.reserve((size_t)np * np);
   ws.V.reserve((size_t)np * np);
   ws.J.reserve((size_t)npair * kJT * kJT);
-  ws.fro.reserve(1);
+  ws.fro.reserve(2);        // ||A||_F, relative off-diagonal norm
   ws.cnt.reserve(1 + np);   // counter + rank scratch
-  if (!ws.cnt_host) FKF_CHECK_HIP(hipHostMalloc((void **)&ws.cnt_host, sizeof(int)));
+  if (!ws.cnt_host) FKF_CHECK_HIP(hipHostMalloc((void **)&ws.cnt_host, sizeof(double)));
   int64_t tot = (int64_t)np * np;
   hipLaunchKernelGGL(k_jacobi_init, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, A, lda,
                      n, np, ws.A.p, ws.V.p);
   hipLaunchKernelGGL(k_frob, dim3(1), dim3(1024), 0, st, ws.A.p, tot, ws.fro.p);
   const unsigned grid_upd = (unsigned)(npair * npair + (np / kJT) * npair);
+  // Stop when the relative off-diagonal norm is below 1e-12 (a perturbation of
+  // at most 1e-12 ||A||_F on the eigenvalues) or a sweep rotates nothing.
   int sweeps = 0;
-  for (int sw = 0; sw < 30; ++sw) {
+  double *off_host = reinterpret_cast<double *>(ws.cnt_host);
+  for (int sw = 0; sw < 40; ++sw) {
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, ws.cnt.p, 0);
     for (int r = 0; r < nb - 1; ++r) {
       hipLaunchKernelGGL(k_jacobi_solve, dim3(npair), dim3(256), 0, st, ws.A.p, np, nb, r,
-                         ws.fro.p, ws.J.p, ws.cnt.p);
+                         ws.fro.p, 1, ws.J.p, ws.cnt.p);
       hipLaunchKernelGGL(k_jacobi_update, dim3(grid_upd), dim3(256), 0, st, ws.A.p, ws.V.p, np, nb,
                          r, ws.J.p);
     }
-    FKF_CHECK_HIP(hipMemcpyAsync(ws.cnt_host, ws.cnt.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    hipLaunchKernelGGL(k_offnorm, dim3(1), dim3(1024), 0, st, ws.A.p, np, ws.fro.p, ws.fro.p + 1);
+    FKF_CHECK_HIP(hipMemcpyAsync(off_host, ws.fro.p + 1, sizeof(double), hipMemcpyDeviceToHost, st));
+    int rotated = 0;
+    FKF_CHECK_HIP(hipMemcpyAsync(&rotated, ws.cnt.p, sizeof(int), hipMemcpyDeviceToHost, st));
     FKF_CHECK_HIP(hipStreamSynchronize(st));
     ++sweeps;
-    if (*ws.cnt_host == 0) break;
+    if (*off_host <= 1e-12 || rotated == 0) break;
   }
   int *rank = ws.cnt.p + 1;
   hipLaunchKernelGGL(k_eig_rank, dim3(1), dim3(1024), 0, st, ws.A.p, np, n, w, rank);
