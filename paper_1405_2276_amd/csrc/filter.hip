@@ -15,6 +15,15 @@
 // gain applied to the innovation is U0 diag(a / (1 + a lambda)) Ve^T nu, and
 // D <- D + a^2 lambda / (1 + a lambda) (the printed update
 // D + ((a)^-1 Lambda^-1 + I)^-1 a), i.e. delta <- delta + a^2 / (1 + a lambda).
+//
+// General form (a step with an operator other than the basis', Section 2.4):
+// Sigma = alpha Gamma - W D W^T with W^T Gamma^-1 W = I, stored with its dual
+// Wd = Gamma^-1 W so that no product with Gamma^-1 is ever formed: every
+// column the filter creates lies in range(Gamma H^T), whose dual is H^T Z.
+// The step uses the gain F = Sigma_{k+1|k} H^T = alpha P - W D (H W)^T, the
+// innovation covariance S = H F + R (FP64 Cholesky), and updates the
+// covariance by adding the low-rank terms of Sigma^-1 with Algorithm 5
+// (B = Gamma^-1 realised through the duals), then D = alpha^2 Dh / (1 + alpha Dh).
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -43,7 +52,7 @@ struct fkf_filter {
   fkf_filter_params params{};
   int64_t k = 0;
   double alpha = 0.0;
-  int mode = 0;            // 0: no low-rank term yet, 1: constant-H basis
+  int mode = 0;            // 0: no low-rank term yet, 1: constant-H basis, 2: general
   uint64_t basis_gen = 0;
   int n_m = 0;
   fkf_status failed = FKF_OK;
@@ -54,6 +63,11 @@ struct fkf_filter {
   fkf::DevBuf<int> err;
   int *err_host = nullptr;
   fkf::EigWork eig;
+  // general form (mode 2): W, Wd = Gamma^-1 W (n x rg, ld ldu), D (rg)
+  fkf::DevBuf<double> W, Wd, Dg;
+  int rg = 0;
+  // scratch reused across general steps
+  fkf::DevBuf<double> gP, gHt, gG, gA, gWe, glam, gwork, gtmp;
   ~fkf_filter() {
     if (err_host) (void)hipHostFree(err_host);
   }
@@ -252,42 +266,60 @@ __global__ void k_copy_strided(const double *__restrict__ src, double *__restric
 // --------------------------------------------------------------- helpers ---
 static unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
-static void gemv_seg(const fkf_filter *f, const double *z, bool square, hipStream_t st) {
+// part[seg][i] = sum_j f(M[i, j]) z[j] over column segments of M (n x ncols, ld ld)
+static void gemv_seg_m(const double *M, int64_t ld, int ncols, int64_t n, const double *z,
+                       bool square, double *part, hipStream_t st) {
   FKF_TRACE(square ? "filter_gemv_sq" : "filter_gemv", st);
-  int nseg = (f->n_m + kSegCols - 1) / kSegCols;
-  dim3 grid(blocks(f->n, kRowsPerWG), (unsigned)nseg);
+  int nseg = (ncols + kSegCols - 1) / kSegCols;
+  dim3 grid(blocks(n, kRowsPerWG), (unsigned)nseg);
   if (square)
-    hipLaunchKernelGGL(k_gemv_seg<true>, grid, dim3(256), 0, st, f->U0.p, f->n, f->ldu, f->n_m, z,
-                       f->part.p);
+    hipLaunchKernelGGL(k_gemv_seg<true>, grid, dim3(256), 0, st, M, n, ld, ncols, z, part);
   else
-    hipLaunchKernelGGL(k_gemv_seg<false>, grid, dim3(256), 0, st, f->U0.p, f->n, f->ldu, f->n_m, z,
-                       f->part.p);
+    hipLaunchKernelGGL(k_gemv_seg<false>, grid, dim3(256), 0, st, M, n, ld, ncols, z, part);
 }
 
-// Generalized eigenpairs of H^T R^-1 H against Gamma^-1 by Rayleigh-Ritz on
-// range(Gamma H^T), and the constant-H basis U0 = P Ve.
+static void gemv_seg(const fkf_filter *f, const double *z, bool square, hipStream_t st) {
+  gemv_seg_m(f->U0.p, f->ldu, f->n_m, f->n, z, square, f->part.p, st);
+}
+
+// Rayleigh-Ritz for the generalized eigenproblem H^T R^-1 H x = lambda Gamma^-1 x
+// on range(Gamma H^T): P = Gamma H^T (H-matrix product), G = H P, and the
+// eigenpairs (lam descending, We) of A = R^-1/2 sym(G) R^-1/2.  Ht holds the
+// dense H^T (the dual of P's range).  Negative rounding-level eigenvalues are
+// set to zero.
+static void compute_gep(fkf_filter *f, const fkf_obs *o, DevBuf<double> &Ht, DevBuf<double> &P,
+                        DevBuf<double> &G, DevBuf<double> &A, DevBuf<double> &lam,
+                        DevBuf<double> &We, hipStream_t st) {
+  const int64_t n = f->n;
+  const int nm = o->n_m;
+  Ht.reserve((size_t)n * nm);
+  P.reserve((size_t)n * nm);
+  G.reserve((size_t)nm * nm);
+  A.reserve((size_t)nm * nm);
+  lam.reserve(nm);
+  We.reserve((size_t)nm * nm);
+  dense_ht(o->rowptr.p, o->col.p, o->val.p, nm, n, Ht.p, st);
+  {
+    FKF_TRACE("gep_cross_cov", st);
+    fkf_status rc = fkf_cov_apply(f->cov, Ht.p, n, nm, P.p, n, (void *)st);
+    if (rc != FKF_OK) throw Error{rc, std::string("covariance product failed: ") + fkf_last_error()};
+  }
+  innovation_gram(o->rowptr.p, o->col.p, o->val.p, nm, n, P.p, o->noise.p, G.p, A.p, st);
+  {
+    FKF_TRACE("gep_eig", st);
+    sym_eig(A.p, nm, nm, lam.p, We.p, nm, st, f->eig);
+  }
+  hipLaunchKernelGGL(k_clamp_nonneg, dim3(blocks(nm)), dim3(256), 0, st, lam.p, nm);
+}
+
+// Constant-H basis U0 = P R^-1/2 W_e (the generalized eigenvectors times
+// Lambda^1/2), Ve = R^-1/2 W_e, lambda; delta = D / lambda starts at zero.
 static void build_basis(fkf_filter *f, const fkf_obs *o, hipStream_t st) {
   FKF_TRACE("gep_total", st);
   const int64_t n = f->n;
   const int nm = o->n_m;
-  DevBuf<double> Ht((size_t)n * nm), P((size_t)n * nm);
-  dense_ht(o->rowptr.p, o->col.p, o->val.p, nm, n, Ht.p, st);
-  fkf_status rc;
-  {
-    FKF_TRACE("gep_cross_cov", st);
-    rc = fkf_cov_apply(f->cov, Ht.p, n, nm, P.p, n, (void *)st);
-  }
-  if (rc != FKF_OK) throw Error{rc, std::string("covariance product failed: ") + fkf_last_error()};
-  Ht.release();
-  DevBuf<double> G((size_t)nm * nm), A((size_t)nm * nm);
-  innovation_gram(o->rowptr.p, o->col.p, o->val.p, nm, n, P.p, o->noise.p, G.p, A.p, st);
-  f->lam.alloc(nm);
-  f->Ve.alloc((size_t)nm * nm);
-  {
-    FKF_TRACE("gep_eig", st);
-    sym_eig(A.p, nm, nm, f->lam.p, f->Ve.p, nm, st, f->eig);
-  }
-  hipLaunchKernelGGL(k_clamp_nonneg, dim3(blocks(nm)), dim3(256), 0, st, f->lam.p, nm);
+  DevBuf<double> Ht, P, G, A;
+  compute_gep(f, o, Ht, P, G, A, f->lam, f->Ve, st);
   scale_rows(nm, nm, o->inv_sqrt_noise.p, f->Ve.p, nm, st);
   f->ldu = (n + 63) / 64 * 64;
   f->U0.alloc((size_t)f->ldu * nm);
@@ -310,6 +342,199 @@ static void build_basis(fkf_filter *f, const fkf_obs *o, hipStream_t st) {
   f->mode = 1;
   f->basis_gen = o->gen;
   FKF_CHECK_HIP(hipStreamSynchronize(st));   // P, Ht, G, A are released on return
+}
+
+static std::vector<double> to_host(const double *p, size_t n, hipStream_t st) {
+  std::vector<double> h(n);
+  if (n) {
+    FKF_CHECK_HIP(hipMemcpyAsync(h.data(), p, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    FKF_CHECK_HIP(hipStreamSynchronize(st));
+  }
+  return h;
+}
+
+static void upload_vec(DevBuf<double> &d, const std::vector<double> &h, hipStream_t st) {
+  d.reserve(std::max<size_t>(h.size(), 1));
+  d.upload(h.data(), h.size(), st);
+}
+
+// Number of leading (descending) values strictly above thr.
+static int count_above(const std::vector<double> &v, double thr) {
+  int r = 0;
+  while (r < (int)v.size() && v[r] > thr) ++r;
+  return r;
+}
+
+// Constant-H form -> general form: W = U0 Lambda^-1/2 (= U), Wd = H_b^T Ve
+// Lambda^-1/2 (= Gamma^-1 U), D = delta lambda, keeping the modes with
+// lambda > 1e-13 lambda_max (the others carry Gamma^-1-norm sqrt(lambda)).
+static void to_general(fkf_filter *f, hipStream_t st) {
+  const int64_t n = f->n;
+  const int nm = f->n_m;
+  std::vector<double> lam = to_host(f->lam.p, nm, st), del = to_host(f->delta.p, nm, st);
+  const int r = count_above(lam, 1e-13 * (lam.empty() ? 0.0 : lam[0]));
+  std::vector<double> isl(r), dg(r);
+  for (int j = 0; j < r; ++j) {
+    isl[j] = 1.0 / std::sqrt(lam[j]);
+    dg[j] = del[j] * lam[j];
+  }
+  DevBuf<double> s_isl;
+  upload_vec(s_isl, isl, st);
+  f->W.alloc((size_t)f->ldu * std::max(r, 1));
+  f->Wd.alloc((size_t)f->ldu * std::max(r, 1));
+  copy2d(n, r, f->U0.p, f->ldu, f->W.p, f->ldu, st);
+  scale_cols(n, r, s_isl.p, f->W.p, f->ldu, st);
+  DevBuf<double> Hbt((size_t)n * nm);
+  dense_ht(f->b_rowptr.p, f->b_col.p, f->b_val.p, nm, n, Hbt.p, st);
+  gemm(false, false, n, r, nm, 1.0, Hbt.p, n, f->Ve.p, nm, 0.0, f->Wd.p, f->ldu, st, nullptr);
+  scale_cols(n, r, s_isl.p, f->Wd.p, f->ldu, st);
+  upload_vec(f->Dg, dg, st);
+  f->rg = r;
+  f->mode = 2;
+  FKF_CHECK_HIP(hipStreamSynchronize(st));
+}
+
+__global__ void k_general_coefs(const double *__restrict__ D, int r, double alpha,
+                                const double *__restrict__ HWt, int nm, double *__restrict__ T) {
+  // T (r x nm) = diag(D) (H W)^T, HWt holds H W (nm x r)
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)r * nm) return;
+  int j = (int)(e % r), m = (int)(e / r);
+  T[j + (int64_t)r * m] = D[j] * HWt[m + (int64_t)nm * j];
+}
+
+__global__ void k_add_diag(double *__restrict__ S, int m, const double *__restrict__ d) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) S[i + (int64_t)m * i] += d[i];
+}
+
+// Realization coefficients of the general form: zz_j = z_j Sigma_-_j with
+// Sigma_- = 1 - (1 - D/alpha)^1/2 = (D/alpha) / (1 + (1 - D/alpha)^1/2).
+__global__ void k_sigma_minus(const double *__restrict__ D, const double *__restrict__ z, int r,
+                              double alpha, double *__restrict__ zz) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= r) return;
+  double x = D[j] / alpha;
+  zz[j] = z[j] * x / (1.0 + sqrt(fmax(0.0, 1.0 - x)));
+}
+
+// One step of the general form (Section 2.4 with Algorithm 5).
+static void step_general(fkf_filter *f, const fkf_obs *o, const double *y, hipStream_t st) {
+  FKF_TRACE("general_step", st);
+  const int64_t n = f->n, ldu = f->ldu;
+  const int nm = o->n_m;
+  const int r = f->rg;
+  const double a1 = f->alpha + 1.0;
+  DevBuf<double> &P = f->gP, &Ht = f->gHt, &G = f->gG, &A = f->gA, &We = f->gWe, &lam = f->glam;
+  compute_gep(f, o, Ht, P, G, A, lam, We, st);
+  // eigenpairs with lambda > 1e-13 lambda_max: Z = R^-1/2 We Lambda^-1/2, U = P Z, Ud = H^T Z
+  std::vector<double> lh = to_host(lam.p, nm, st);
+  const int rk = count_above(lh, 1e-13 * (lh.empty() ? 0.0 : lh[0]));
+  std::vector<double> isl(rk);
+  for (int j = 0; j < rk; ++j) isl[j] = 1.0 / std::sqrt(lh[j]);
+  DevBuf<double> s_isl, Z((size_t)nm * std::max(rk, 1));
+  upload_vec(s_isl, isl, st);
+  copy2d(nm, rk, We.p, nm, Z.p, nm, st);
+  scale_rows(nm, rk, o->inv_sqrt_noise.p, Z.p, nm, st);
+  scale_cols(nm, rk, s_isl.p, Z.p, nm, st);
+  DevBuf<double> U((size_t)ldu * std::max(rk, 1)), Ud((size_t)ldu * std::max(rk, 1));
+  gemm(false, false, n, rk, nm, 1.0, P.p, n, Z.p, nm, 0.0, U.p, ldu, st, nullptr);
+  gemm(false, false, n, rk, nm, 1.0, Ht.p, n, Z.p, nm, 0.0, Ud.p, ldu, st, nullptr);
+  // gain: F = a1 P - W diag(D) (H W)^T ; S = a1 G - (H W) diag(D) (H W)^T + R
+  DevBuf<double> F((size_t)n * nm), S((size_t)nm * nm), HW((size_t)nm * std::max(r, 1)),
+      T((size_t)std::max(r, 1) * nm), c(nm);
+  copy2d(n, nm, P.p, n, F.p, n, st);
+  copy2d(nm, nm, G.p, nm, S.p, nm, st);
+  if (r > 0) {
+    sp_dense(o->rowptr.p, o->col.p, o->val.p, nm, f->W.p, ldu, r, HW.p, st);
+    hipLaunchKernelGGL(k_general_coefs, dim3(blocks((int64_t)r * nm)), dim3(256), 0, st, f->Dg.p,
+                       r, a1, HW.p, nm, T.p);
+    gemm(false, false, n, nm, r, -1.0, f->W.p, ldu, T.p, r, a1, F.p, n, st, nullptr);
+    gemm(false, false, nm, nm, r, -1.0, HW.p, nm, T.p, r, a1, S.p, nm, st, nullptr);
+  } else {
+    scale2d(n, nm, a1, F.p, n, st);
+    scale2d(nm, nm, a1, S.p, nm, st);
+  }
+  symmetrize(S.p, nm, st);
+  hipLaunchKernelGGL(k_add_diag, dim3(blocks(nm)), dim3(256), 0, st, S.p, nm, o->noise.p);
+  // state: c = S^-1 (y - H s), s += F c
+  hipLaunchKernelGGL(k_innov, dim3(blocks(nm, 4)), dim3(256), 0, st, o->rowptr.p, o->col.p,
+                     o->val.p, nm, f->s.p, y, c.p, f->err.p);
+  chol_solve(S.p, nm, c.p, f->err.p, st);
+  gemm(false, false, n, 1, nm, 1.0, F.p, n, c.p, nm, 1.0, f->s.p, n, st, nullptr);
+  // covariance: Dbar = D / (a1 (a1 - D)); AddLowRank(W, Dbar, U, Lambda; Gamma^-1)
+  std::vector<double> dh = to_host(f->Dg.p, r, st);
+  std::vector<double> dbar(r);
+  for (int j = 0; j < r; ++j) dbar[j] = dh[j] / (a1 * (a1 - dh[j]));
+  DevBuf<double> C((size_t)std::max(r, 1) * std::max(rk, 1));
+  DevBuf<double> Vt((size_t)ldu * std::max(rk, 1)), Vtd((size_t)ldu * std::max(rk, 1));
+  copy2d(n, rk, U.p, ldu, Vt.p, ldu, st);
+  copy2d(n, rk, Ud.p, ldu, Vtd.p, ldu, st);
+  if (r > 0) {
+    // C = W^T Gamma^-1 U = Wd^T U; Vt = U - W C (block Gram-Schmidt), dual likewise
+    gemm(true, false, r, rk, n, 1.0, f->Wd.p, ldu, U.p, ldu, 0.0, C.p, r, st, &f->gwork);
+    gemm(false, false, n, rk, r, -1.0, f->W.p, ldu, C.p, r, 1.0, Vt.p, ldu, st, nullptr);
+    gemm(false, false, n, rk, r, -1.0, f->Wd.p, ldu, C.p, r, 1.0, Vtd.p, ldu, st, nullptr);
+  }
+  // Gamma^-1-orthonormal basis of Vt: Gram = Vtd^T Vt = Q Theta Q^T, keep theta > 1e-12
+  DevBuf<double> Gm((size_t)std::max(rk, 1) * std::max(rk, 1)), th(std::max(rk, 1)),
+      Q((size_t)std::max(rk, 1) * std::max(rk, 1));
+  gemm(true, false, rk, rk, n, 1.0, Vtd.p, ldu, Vt.p, ldu, 0.0, Gm.p, rk, st, &f->gwork);
+  symmetrize(Gm.p, rk, st);
+  sym_eig(Gm.p, rk, rk, th.p, Q.p, rk, st, f->eig);
+  std::vector<double> thh = to_host(th.p, rk, st);
+  const int rp = count_above(thh, 1e-12);
+  std::vector<double> ith(rp);
+  for (int j = 0; j < rp; ++j) ith[j] = 1.0 / std::sqrt(thh[j]);
+  DevBuf<double> s_ith;
+  upload_vec(s_ith, ith, st);
+  scale_cols(rk, rp, s_ith.p, Q.p, rk, st);                 // Q Theta^-1/2
+  const int rt = r + rp;
+  DevBuf<double> Wc((size_t)ldu * std::max(rt, 1)), Wcd((size_t)ldu * std::max(rt, 1));
+  copy2d(n, r, f->W.p, ldu, Wc.p, ldu, st);
+  copy2d(n, r, f->Wd.p, ldu, Wcd.p, ldu, st);
+  gemm(false, false, n, rp, rk, 1.0, Vt.p, ldu, Q.p, rk, 0.0, Wc.p + ldu * r, ldu, st, nullptr);
+  gemm(false, false, n, rp, rk, 1.0, Vtd.p, ldu, Q.p, rk, 0.0, Wcd.p + ldu * r, ldu, st, nullptr);
+  // B1 = [C; Vh^T Gamma^-1 U] (rt x rk), M = diag(Dbar, 0) + B1 Lambda B1^T
+  DevBuf<double> B1((size_t)std::max(rt, 1) * std::max(rk, 1)), B1L((size_t)std::max(rt, 1) * std::max(rk, 1)),
+      M((size_t)std::max(rt, 1) * std::max(rt, 1));
+  copy2d(r, rk, C.p, r, B1.p, rt, st);
+  gemm(true, false, rp, rk, n, 1.0, Wcd.p + ldu * r, ldu, U.p, ldu, 0.0, B1.p + r, rt, st,
+       &f->gwork);
+  std::vector<double> lamk(lh.begin(), lh.begin() + rk);
+  DevBuf<double> s_lam;
+  upload_vec(s_lam, lamk, st);
+  copy2d(rt, rk, B1.p, rt, B1L.p, rt, st);
+  scale_cols(rt, rk, s_lam.p, B1L.p, rt, st);
+  gemm(false, true, rt, rt, rk, 1.0, B1L.p, rt, B1.p, rt, 0.0, M.p, rt, st, nullptr);
+  std::vector<double> dfull(rt, 0.0);
+  for (int j = 0; j < r; ++j) dfull[j] = dbar[j];
+  DevBuf<double> s_df;
+  upload_vec(s_df, dfull, st);
+  hipLaunchKernelGGL(k_add_diag, dim3(blocks(rt)), dim3(256), 0, st, M.p, rt, s_df.p);
+  symmetrize(M.p, rt, st);
+  DevBuf<double> mu(std::max(rt, 1)), Sm((size_t)std::max(rt, 1) * std::max(rt, 1));
+  sym_eig(M.p, rt, rt, mu.p, Sm.p, rt, st, f->eig);
+  std::vector<double> muh = to_host(mu.p, rt, st);
+  const double mmax = muh.empty() ? 0.0 : muh[0];
+  const double rtol = f->params.rank_rtol > 0 ? f->params.rank_rtol : 1e-14;
+  const int rn = count_above(muh, rtol * mmax);
+  if (rn > f->params.max_rank)
+    throw Error{FKF_E_RANK, "fkf_filter_step: the low-rank term exceeds max_rank"};
+  // W <- [W Vh] S, Wd <- [Wd Vhd] S, D <- a1^2 mu / (1 + a1 mu)
+  DevBuf<double> Wn((size_t)ldu * std::max(rn, 1)), Wdn((size_t)ldu * std::max(rn, 1));
+  gemm(false, false, n, rn, rt, 1.0, Wc.p, ldu, Sm.p, rt, 0.0, Wn.p, ldu, st, nullptr);
+  gemm(false, false, n, rn, rt, 1.0, Wcd.p, ldu, Sm.p, rt, 0.0, Wdn.p, ldu, st, nullptr);
+  std::vector<double> dn(rn);
+  for (int j = 0; j < rn; ++j) dn[j] = a1 * a1 * muh[j] / (1.0 + a1 * muh[j]);
+  upload_vec(f->Dg, dn, st);
+  FKF_CHECK_HIP(hipStreamSynchronize(st));
+  f->W = std::move(Wn);
+  f->Wd = std::move(Wdn);
+  f->rg = rn;
+  f->part.reserve((size_t)((rn + kSegCols - 1) / kSegCols + 1) * n);
+  f->tmp.reserve(std::max(rn, 1));
+  f->nu.reserve(std::max(rn, 1));
 }
 
 }  // namespace fkf
@@ -477,9 +702,16 @@ extern "C" fkf_status fkf_filter_step(fkf_filter *f, const fkf_obs *o, const dou
     hipStream_t st = as_stream(stream);
     if (f->mode == 0) {
       build_basis(f, o, st);
-    } else if (o->gen != f->basis_gen) {
-      throw Error{FKF_E_UNSUPPORTED, "fkf_filter_step: a new measurement operator after the "
-                                     "first step needs the general update"};
+    } else if (f->mode == 1 && o->gen != f->basis_gen) {
+      to_general(f, st);
+    }
+    if (f->mode == 2) {
+      step_general(f, o, y, st);
+      FKF_CHECK_HIP(hipMemcpyAsync(f->err_host, f->err.p, sizeof(int), hipMemcpyDeviceToHost, st));
+      FKF_CHECK_HIP(hipGetLastError());
+      f->alpha += 1.0;
+      f->k += 1;
+      return;
     }
     const double alpha_new = f->alpha + 1.0;   // prediction (F = I)
     const int nm = f->n_m;
@@ -532,6 +764,14 @@ extern "C" fkf_status fkf_filter_variance(const fkf_filter *f, double *var, void
       return;
     }
     fkf_filter *mf = const_cast<fkf_filter *>(f);
+    if (f->mode == 2) {
+      gemv_seg_m(f->W.p, f->ldu, f->rg, f->n, f->Dg.p, true, mf->part.p, st);
+      int nseg = (f->rg + kSegCols - 1) / kSegCols;
+      hipLaunchKernelGGL(k_seg_var, dim3(blocks(f->n)), dim3(256), 0, st, f->part.p, nseg, f->n,
+                         base, var);
+      FKF_CHECK_HIP(hipGetLastError());
+      return;
+    }
     gemv_seg(mf, f->delta.p, true, st);
     int nseg = (f->n_m + kSegCols - 1) / kSegCols;
     hipLaunchKernelGGL(k_seg_var, dim3(blocks(f->n)), dim3(256), 0, st, f->part.p, nseg, f->n, base,
@@ -555,10 +795,22 @@ extern "C" fkf_status fkf_filter_realize(const fkf_filter *f, const double *g, i
     for (int c = 0; c < ns; ++c) {
       const double *gc = g + ldg * c;
       double *oc = out + ldo * c;
-      if (f->mode == 0 || f->alpha == 0.0) {
+      if (f->mode == 0 || f->alpha == 0.0 || (f->mode == 2 && f->rg == 0)) {
         // no low-rank term: Sigma = alpha Gamma and the realization is s + alpha^1/2 g
         hipLaunchKernelGGL(k_axpy_out, dim3(blocks(f->n)), dim3(256), 0, st, f->s.p, gc, sa, oc,
                            f->n);
+        continue;
+      }
+      if (f->mode == 2) {
+        // zz = Sigma_- (Wd^T g); out = s + a^1/2 (g - W zz)
+        gemm(true, false, f->rg, 1, f->n, 1.0, f->Wd.p, f->ldu, gc, f->n, 0.0, mf->nu.p, f->rg, st,
+             &mf->gwork);
+        hipLaunchKernelGGL(k_sigma_minus, dim3(blocks(f->rg)), dim3(256), 0, st, f->Dg.p, f->nu.p,
+                           f->rg, f->alpha, mf->tmp.p);
+        gemv_seg_m(f->W.p, f->ldu, f->rg, f->n, f->tmp.p, false, mf->part.p, st);
+        int ns2 = (f->rg + kSegCols - 1) / kSegCols;
+        hipLaunchKernelGGL(k_seg_realize, dim3(blocks(f->n)), dim3(256), 0, st, f->part.p, ns2,
+                           f->n, f->s.p, gc, sa, oc);
         continue;
       }
       // h = H g with the basis' operator; zz = (Sigma_- / lambda) Ve^T h; out = s + a^1/2 (g - U0 zz)
@@ -580,7 +832,7 @@ extern "C" fkf_status fkf_filter_info(const fkf_filter *f, int64_t *k, double *a
     FKF_REQUIRE(f != nullptr, "fkf_filter_info: NULL handle");
     if (k) *k = f->k;
     if (alpha) *alpha = f->alpha;
-    if (rank) *rank = f->mode == 0 ? 0 : f->n_m;
+    if (rank) *rank = f->mode == 0 ? 0 : (f->mode == 1 ? f->n_m : f->rg);
   });
 }
 

@@ -42,4 +42,24 @@ void scale_rows(int64_t m, int n, const double *s, double *A, int64_t lda, hipSt
 
 void fill(double *p, int64_t n, double v, hipStream_t st);
 
+// C = alpha op(A) op(B) + beta C (FP64, column-major; op = transpose when the
+// flag is set).  When work is given and the output has few tiles, the k range
+// is split across workgroups and the slices are summed in a fixed order.
+void gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double alpha, const double *A,
+          int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
+          hipStream_t st, DevBuf<double> *work);
+
+// out (n_m x cols, ld n_m) = H X for CSR H and dense X (n x cols, ld ldx).
+void sp_dense(const int64_t *rowptr, const int32_t *col, const double *val, int n_m,
+              const double *X, int64_t ldx, int cols, double *out, hipStream_t st);
+
+// In-place Cholesky of the SPD m x m matrix S (ld m) and solve S x = b (b
+// overwritten).  Sets *err = FKF_E_NOT_SPD on a non-positive pivot.
+void chol_solve(double *S, int m, double *b, int *err, hipStream_t st);
+
+void scale_cols(int64_t m, int n, const double *s, double *A, int64_t lda, hipStream_t st);
+void symmetrize(double *A, int m, hipStream_t st);
+void scale2d(int64_t m, int n, double a, double *A, int64_t lda, hipStream_t st);
+void copy2d(int64_t m, int n, const double *A, int64_t lda, double *B, int64_t ldb, hipStream_t st);
+
 }  // namespace fkf

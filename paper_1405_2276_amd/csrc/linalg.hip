@@ -473,3 +473,290 @@ void scale_rows(int64_t m, int n, const double *s, double *A, int64_t lda, hipSt
 }
 
 }  // namespace fkf
+
+namespace fkf {
+
+// ============================================================ general GEMM ===
+// C = alpha op(A) op(B) + beta C (FP64, column-major), 64 x 64 output tiles,
+// 4 x 4 per thread, k in chunks of 16.  With split > 1 the k range is divided
+// among grid.z slices whose partial products go to a workspace and are summed
+// in slice order by k_gemm_combine (deterministic).
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(256) k_gemm_gen(int64_t m, int64_t n, int64_t k, double alpha,
+                                                  const double *__restrict__ A, int64_t lda,
+                                                  const double *__restrict__ B, int64_t ldb,
+                                                  double beta, double *__restrict__ C, int64_t ldc,
+                                                  int64_t kslice, double *__restrict__ part) {
+  __shared__ double As[16][64 + 1];
+  __shared__ double Bs[16][64 + 1];
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int64_t m0 = (int64_t)blockIdx.x * 64, n0 = (int64_t)blockIdx.y * 64;
+  const int64_t kb = (int64_t)blockIdx.z * kslice, ke = min(k, kb + kslice);
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int64_t k0 = kb; k0 < ke; k0 += 16) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int e = tid + 256 * q;
+      // A tile: As[kk][r] = op(A)[m0 + r][k0 + kk]
+      {
+        int r, kk;
+        if (!TA) { r = e & 63; kk = e >> 6; } else { kk = e & 15; r = e >> 4; }
+        int64_t gr = m0 + r, gk = k0 + kk;
+        double v = 0.0;
+        if (gr < m && gk < ke) v = TA ? A[gk + lda * gr] : A[gr + lda * gk];
+        As[kk][r] = v;
+      }
+      // B tile: Bs[kk][c] = op(B)[k0 + kk][n0 + c]
+      {
+        int c, kk;
+        if (!TB) { kk = e & 15; c = e >> 4; } else { c = e & 63; kk = e >> 6; }
+        int64_t gk = k0 + kk, gc = n0 + c;
+        double v = 0.0;
+        if (gc < n && gk < ke) v = TB ? B[gc + ldb * gk] : B[gk + ldb * gc];
+        Bs[kk][c] = v;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[kk][tx + 16 * a];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = Bs[kk][ty + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      int64_t gr = m0 + tx + 16 * a, gc = n0 + ty + 16 * b;
+      if (gr < m && gc < n) {
+        if (part) {
+          part[(int64_t)blockIdx.z * m * n + gr + m * gc] = acc[a][b];
+        } else {
+          double v = alpha * acc[a][b];
+          if (beta != 0.0) v += beta * C[gr + ldc * gc];
+          C[gr + ldc * gc] = v;
+        }
+      }
+    }
+}
+
+__global__ void k_gemm_combine(int64_t m, int64_t n, int splits, double alpha,
+                               const double *__restrict__ part, double beta,
+                               double *__restrict__ C, int64_t ldc) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * n) return;
+  int64_t i = e % m, j = e / m;
+  double s = 0;
+  for (int z = 0; z < splits; ++z) s += part[(int64_t)z * m * n + e];
+  double v = alpha * s;
+  if (beta != 0.0) v += beta * C[i + ldc * j];
+  C[i + ldc * j] = v;
+}
+
+void gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double alpha, const double *A,
+          int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
+          hipStream_t st, DevBuf<double> *work) {
+  if (m <= 0 || n <= 0) return;
+  if (k <= 0) {
+    // C = beta C
+    if (beta == 0.0) {
+      for (int64_t j = 0; j < n; ++j) fill(C + ldc * j, m, 0.0, st);
+    } else if (beta != 1.0) {
+      throw Error{FKF_E_UNSUPPORTED, "gemm: k = 0 with beta not in {0, 1}"};
+    }
+    return;
+  }
+  const int64_t tm = (m + 63) / 64, tn = (n + 63) / 64;
+  int splits = 1;
+  if (work && tm * tn < 256 && k >= 1024) {
+    splits = (int)std::min<int64_t>((256 + tm * tn - 1) / (tm * tn), k / 512);
+    splits = std::max(splits, 1);
+  }
+  int64_t kslice = (k + splits - 1) / splits;
+  kslice = (kslice + 15) / 16 * 16;
+  splits = (int)((k + kslice - 1) / kslice);
+  double *part = nullptr;
+  if (splits > 1) {
+    work->reserve((size_t)splits * m * n);
+    part = work->p;
+  }
+  dim3 grid((unsigned)tm, (unsigned)tn, (unsigned)splits);
+  auto kern = ta ? (tb ? k_gemm_gen<true, true> : k_gemm_gen<true, false>)
+                 : (tb ? k_gemm_gen<false, true> : k_gemm_gen<false, false>);
+  hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                     kslice, part);
+  if (splits > 1)
+    hipLaunchKernelGGL(k_gemm_combine, dim3((unsigned)((m * n + 255) / 256)), dim3(256), 0, st, m,
+                       n, splits, alpha, part, beta, C, ldc);
+}
+
+// ========================================================= sparse x dense ===
+// out (n_m x cols, ld n_m) = H X for CSR H and X (n x cols, ld ldx).
+__global__ void __launch_bounds__(256) k_sp_dense(const int64_t *__restrict__ rowptr,
+                                                  const int32_t *__restrict__ col,
+                                                  const double *__restrict__ val, int n_m,
+                                                  const double *__restrict__ X, int64_t ldx,
+                                                  int cols, double *__restrict__ out) {
+  int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (e >= (int64_t)n_m * cols) return;
+  int m = (int)(e % n_m), j = (int)(e / n_m);
+  int l = threadIdx.x & 63;
+  const double *Xj = X + ldx * j;
+  double s = 0;
+  for (int64_t q = rowptr[m] + l; q < rowptr[m + 1]; q += 64) s = fma(val[q], Xj[col[q]], s);
+  s = wave_sum(s);
+  if (l == 0) out[m + (int64_t)n_m * j] = s;
+}
+
+void sp_dense(const int64_t *rowptr, const int32_t *col, const double *val, int n_m,
+              const double *X, int64_t ldx, int cols, double *out, hipStream_t st) {
+  int64_t e = (int64_t)n_m * cols;
+  if (e <= 0) return;
+  hipLaunchKernelGGL(k_sp_dense, dim3((unsigned)((e + 3) / 4)), dim3(256), 0, st, rowptr, col, val,
+                     n_m, X, ldx, cols, out);
+}
+
+// ======================================================== Cholesky solve ===
+// S (m x m, ld m) = L L^T in place (lower), then x = S^-1 b overwriting b.
+// One workgroup; right-looking, column by column.  A non-positive pivot sets
+// *err = FKF_E_NOT_SPD and leaves b unchanged.
+__global__ void __launch_bounds__(1024) k_chol_solve(double *__restrict__ S, int m,
+                                                     double *__restrict__ b, int *err) {
+  __shared__ double piv;
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int j = 0; j < m; ++j) {
+    if (tid == 0) {
+      double d = S[j + (int64_t)m * j];
+      if (!(d > 0.0) || !isfinite(d)) {
+        bad = 1;
+        piv = 1.0;
+      } else {
+        piv = sqrt(d);
+      }
+      S[j + (int64_t)m * j] = piv;
+    }
+    __syncthreads();
+    if (bad) break;
+    const double ip = 1.0 / piv;
+    for (int i = j + 1 + tid; i < m; i += 1024) S[i + (int64_t)m * j] *= ip;
+    __syncthreads();
+    // trailing update of the lower triangle
+    const int r = m - j - 1;
+    const int64_t tot = (int64_t)r * (r + 1) / 2;
+    for (int64_t e = tid; e < tot; e += 1024) {
+      // e -> (i, k) with 0 <= k <= i < r, column-wise packing
+      int64_t kk = (int64_t)((sqrt(8.0 * (double)e + 1.0) - 1.0) / 2.0);
+      while (kk * (kk + 1) / 2 > e) --kk;
+      while ((kk + 1) * (kk + 2) / 2 <= e) ++kk;
+      int64_t i = kk, c = e - kk * (kk + 1) / 2;   // row index i >= column index c
+      int gi = j + 1 + (int)i, gc = j + 1 + (int)c;
+      S[gi + (int64_t)m * gc] -= S[gi + (int64_t)m * j] * S[gc + (int64_t)m * j];
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (tid == 0) atomicExch(err, (int)FKF_E_NOT_SPD);
+    return;
+  }
+  // forward: L y = b
+  for (int j = 0; j < m; ++j) {
+    if (tid == 0) b[j] /= S[j + (int64_t)m * j];
+    __syncthreads();
+    const double yj = b[j];
+    for (int i = j + 1 + tid; i < m; i += 1024) b[i] -= S[i + (int64_t)m * j] * yj;
+    __syncthreads();
+  }
+  // backward: L^T x = y
+  for (int j = m - 1; j >= 0; --j) {
+    if (tid == 0) b[j] /= S[j + (int64_t)m * j];
+    __syncthreads();
+    const double xj = b[j];
+    for (int i = tid; i < j; i += 1024) b[i] -= S[j + (int64_t)m * i] * xj;
+    __syncthreads();
+  }
+}
+
+void chol_solve(double *S, int m, double *b, int *err, hipStream_t st) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), 0, st, S, m, b, err);
+}
+
+// Scale column j of a column-major m x n matrix by s[j] (in place).
+__global__ void k_scale_cols(int64_t m, int n, const double *__restrict__ s, double *__restrict__ A,
+                             int64_t lda) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * n) return;
+  int64_t i = e % m, j = e / m;
+  A[i + lda * j] *= s[j];
+}
+
+void scale_cols(int64_t m, int n, const double *s, double *A, int64_t lda, hipStream_t st) {
+  int64_t e = m * n;
+  if (e <= 0) return;
+  hipLaunchKernelGGL(k_scale_cols, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, st, m, n, s, A,
+                     lda);
+}
+
+__global__ void k_scale2d(int64_t m, int n, double a, double *__restrict__ A, int64_t lda) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * n) return;
+  A[e % m + lda * (e / m)] *= a;
+}
+
+void scale2d(int64_t m, int n, double a, double *A, int64_t lda, hipStream_t st) {
+  int64_t e = m * n;
+  if (e <= 0) return;
+  hipLaunchKernelGGL(k_scale2d, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, st, m, n, a, A, lda);
+}
+
+// A = (A + A^T) / 2 for a square m x m matrix (ld m).
+__global__ void k_symmetrize(double *__restrict__ A, int m) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)m * m) return;
+  int i = (int)(e % m), j = (int)(e / m);
+  if (i < j) {
+    double v = 0.5 * (A[i + (int64_t)m * j] + A[j + (int64_t)m * i]);
+    A[i + (int64_t)m * j] = v;
+    A[j + (int64_t)m * i] = v;
+  }
+}
+
+void symmetrize(double *A, int m, hipStream_t st) {
+  int64_t e = (int64_t)m * m;
+  if (e <= 0) return;
+  hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, st, A, m);
+}
+
+// Copy a column-major m x n block (lda) to (ldb).
+__global__ void k_copy2d(int64_t m, int n, const double *__restrict__ A, int64_t lda,
+                         double *__restrict__ B, int64_t ldb) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * n) return;
+  int64_t i = e % m, j = e / m;
+  B[i + ldb * j] = A[i + lda * j];
+}
+
+void copy2d(int64_t m, int n, const double *A, int64_t lda, double *B, int64_t ldb, hipStream_t st) {
+  int64_t e = m * n;
+  if (e <= 0) return;
+  hipLaunchKernelGGL(k_copy2d, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, st, m, n, A, lda, B,
+                     ldb);
+}
+
+}  // namespace fkf
