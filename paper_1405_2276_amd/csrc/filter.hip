@@ -56,7 +56,7 @@ struct fkf_filter {
   uint64_t basis_gen = 0;
   int n_m = 0;
   fkf_status failed = FKF_OK;
-  fkf::DevBuf<double> s, U0, Ve, lam, delta, nu, zp, part, tmp;
+  fkf::DevBuf<double> s, U0, Ve, lam, delta, nu, zp, part, tmp, eta;
   fkf::DevBuf<int64_t> b_rowptr;   // copy of the basis' measurement operator
   fkf::DevBuf<int32_t> b_col;
   fkf::DevBuf<double> b_val;
@@ -126,6 +126,51 @@ __global__ void __launch_bounds__(256) k_modes_step(const double *__restrict__ V
     delta[j] = dj + a * g;               // D_{k+1} / lambda
     if (!isfinite(zp[j]) || !isfinite(delta[j])) atomicExch(err, (int)FKF_E_NONFINITE);
   }
+}
+
+// One wavefront per mode j of the constant-H step: z_j = Ve[:, j] . y - eta_j
+// (eta = Ve^T H s is carried in data space: H U0 = H P Ve and
+// Ve^T H P Ve = Lambda, so the update s += U0 zp moves eta by Lambda zp),
+// then the per-mode gain and D update.
+__global__ void __launch_bounds__(256) k_modes_step_eta(const double *__restrict__ Ve, int n_m,
+                                                        const double *__restrict__ y,
+                                                        const double *__restrict__ lam,
+                                                        double *__restrict__ delta,
+                                                        double *__restrict__ eta, double alpha,
+                                                        double *__restrict__ zp, int *err) {
+  int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= n_m) return;
+  int l = threadIdx.x & 63;
+  const double *v = Ve + (int64_t)n_m * j;
+  double z = 0;
+  for (int m = l; m < n_m; m += 64) z = fma(v[m], y[m], z);
+  z = wave_sum(z);
+  if (l == 0) {
+    z -= eta[j];
+    double lj = lam[j], dj = delta[j];
+    double a = alpha - dj * lj;          // alpha_{k+1} - D_k
+    double den = 1.0 + a * lj;           // (alpha - D) lambda + 1: S_k in the eigenbasis
+    double g = a / den;
+    double zpj = g * z;
+    zp[j] = zpj;
+    delta[j] = dj + a * g;               // D_{k+1} / lambda
+    eta[j] += lj * zpj;
+    if (!isfinite(zpj) || !isfinite(delta[j])) atomicExch(err, (int)FKF_E_NONFINITE);
+  }
+}
+
+// eta = Ve^T h (one wavefront per mode)
+__global__ void __launch_bounds__(256) k_vet(const double *__restrict__ Ve, int n_m,
+                                             const double *__restrict__ h,
+                                             double *__restrict__ eta) {
+  int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= n_m) return;
+  int l = threadIdx.x & 63;
+  const double *v = Ve + (int64_t)n_m * j;
+  double z = 0;
+  for (int m = l; m < n_m; m += 64) z = fma(v[m], h[m], z);
+  z = wave_sum(z);
+  if (l == 0) eta[j] = z;
 }
 
 // One wavefront per mode j: realization coefficients
@@ -338,6 +383,10 @@ static void build_basis(fkf_filter *f, const fkf_obs *o, hipStream_t st) {
   f->b_rowptr.upload(o->rowptr_h, st);
   f->b_col.upload(o->col_h, st);
   f->b_val.upload(o->val_h, st);
+  // eta = Ve^T H s for the current estimate
+  f->eta.alloc(nm);
+  spmv(o->rowptr.p, o->col.p, o->val.p, nm, f->s.p, f->nu.p, st);
+  hipLaunchKernelGGL(k_vet, dim3(blocks(nm, 4)), dim3(256), 0, st, f->Ve.p, nm, f->nu.p, f->eta.p);
   f->n_m = nm;
   f->mode = 1;
   f->basis_gen = o->gen;
@@ -716,14 +765,14 @@ extern "C" fkf_status fkf_filter_step(fkf_filter *f, const fkf_obs *o, const dou
     const double alpha_new = f->alpha + 1.0;   // prediction (F = I)
     const int nm = f->n_m;
     FKF_TRACE("filter_step", st);
-    hipLaunchKernelGGL(k_innov, dim3(blocks(nm, 4), 1), dim3(256), 0, st, o->rowptr.p, o->col.p,
-                       o->val.p, nm, f->s.p, y, f->nu.p, f->err.p);
-    hipLaunchKernelGGL(k_modes_step, dim3(blocks(nm, 4)), dim3(256), 0, st, f->Ve.p, nm, f->nu.p,
-                       f->lam.p, f->delta.p, alpha_new, f->zp.p, f->err.p);
+    hipLaunchKernelGGL(k_modes_step_eta, dim3(blocks(nm, 4)), dim3(256), 0, st, f->Ve.p, nm, y,
+                       f->lam.p, f->delta.p, f->eta.p, alpha_new, f->zp.p, f->err.p);
     gemv_seg(f, f->zp.p, false, st);
-    int nseg = (nm + kSegCols - 1) / kSegCols;
-    hipLaunchKernelGGL(k_seg_add, dim3(blocks(f->n)), dim3(256), 0, st, f->part.p, nseg, f->n,
-                       f->s.p);
+    {
+      int nseg = (nm + kSegCols - 1) / kSegCols;
+      hipLaunchKernelGGL(k_seg_add, dim3(blocks(f->n)), dim3(256), 0, st, f->part.p, nseg, f->n,
+                         f->s.p);
+    }
     FKF_CHECK_HIP(hipMemcpyAsync(f->err_host, f->err.p, sizeof(int), hipMemcpyDeviceToHost, st));
     FKF_CHECK_HIP(hipGetLastError());
     f->alpha = alpha_new;

@@ -81,24 +81,35 @@ __global__ void __launch_bounds__(1024) k_frob(const double *__restrict__ A, int
 
 __global__ void k_set_int(int *p, int v) { *p = v; }
 
-// off[0] = sqrt(sum of squared off-diagonal entries) / fro  (single workgroup)
-__global__ void __launch_bounds__(1024) k_offnorm(const double *__restrict__ A, int np,
-                                                  const double *__restrict__ fro,
-                                                  double *__restrict__ off) {
-  __shared__ double red[16];
+// Off-diagonal sum of squares: one workgroup per column (partials), then
+// off[0] = sqrt(sum of partials) / fro in a fixed order.
+__global__ void __launch_bounds__(256) k_offnorm_cols(const double *__restrict__ A, int np,
+                                                      double *__restrict__ part, int with_diag) {
+  __shared__ double red[4];
+  const int j = blockIdx.x;
   double s = 0;
-  const int64_t len = (int64_t)np * np;
-  for (int64_t e = threadIdx.x; e < len; e += 1024) {
-    int i = (int)(e % np), j = (int)(e / np);
-    if (i != j) s += A[e] * A[e];
+  for (int i = threadIdx.x; i < np; i += 256) {
+    double v = A[i + (int64_t)np * j];
+    if (i != j || with_diag) s = fma(v, v, s);
   }
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
+  if (threadIdx.x == 0) part[j] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void __launch_bounds__(256) k_offnorm_final(const double *__restrict__ part, int np,
+                                                       const double *__restrict__ fro,
+                                                       double *__restrict__ off) {
+  __shared__ double red[4];
+  double s = 0;
+  for (int j = threadIdx.x; j < np; j += 256) s += part[j];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    double t = 0;
-    for (int w = 0; w < 16; ++w) t += red[w];
-    off[0] = fro[0] > 0 ? sqrt(t) / fro[0] : 0.0;
+    double t = red[0] + red[1] + red[2] + red[3];
+    off[0] = fro ? (fro[0] > 0 ? sqrt(t) / fro[0] : 0.0) : sqrt(t);
   }
 }
 
@@ -279,13 +290,15 @@ int sym_eig(const double *A, int64_t lda, int n, double *w, double *W, int64_t l
   ws.A.reserve((size_t)np * np);
   ws.V.reserve((size_t)np * np);
   ws.J.reserve((size_t)npair * kJT * kJT);
-  ws.fro.reserve(2);        // ||A||_F, relative off-diagonal norm
+  ws.fro.reserve(2 + np);   // ||A||_F, relative off-diagonal norm, column partials
   ws.cnt.reserve(1 + np);   // counter + rank scratch
   if (!ws.cnt_host) FKF_CHECK_HIP(hipHostMalloc((void **)&ws.cnt_host, sizeof(double)));
   int64_t tot = (int64_t)np * np;
   hipLaunchKernelGGL(k_jacobi_init, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, A, lda,
                      n, np, ws.A.p, ws.V.p);
-  hipLaunchKernelGGL(k_frob, dim3(1), dim3(1024), 0, st, ws.A.p, tot, ws.fro.p);
+  hipLaunchKernelGGL(k_offnorm_cols, dim3(np), dim3(256), 0, st, ws.A.p, np, ws.fro.p + 2, 1);
+  hipLaunchKernelGGL(k_offnorm_final, dim3(1), dim3(256), 0, st, ws.fro.p + 2, np,
+                     (const double *)nullptr, ws.fro.p);
   const unsigned grid_upd = (unsigned)(npair * npair + (np / kJT) * npair);
   // Stop when the relative off-diagonal norm is below 1e-12 (a perturbation of
   // at most 1e-12 ||A||_F on the eigenvalues) or a sweep rotates nothing.
@@ -299,7 +312,9 @@ int sym_eig(const double *A, int64_t lda, int n, double *w, double *W, int64_t l
       hipLaunchKernelGGL(k_jacobi_update, dim3(grid_upd), dim3(256), 0, st, ws.A.p, ws.V.p, np, nb,
                          r, ws.J.p);
     }
-    hipLaunchKernelGGL(k_offnorm, dim3(1), dim3(1024), 0, st, ws.A.p, np, ws.fro.p, ws.fro.p + 1);
+    hipLaunchKernelGGL(k_offnorm_cols, dim3(np), dim3(256), 0, st, ws.A.p, np, ws.fro.p + 2, 0);
+    hipLaunchKernelGGL(k_offnorm_final, dim3(1), dim3(256), 0, st, ws.fro.p + 2, np, ws.fro.p,
+                       ws.fro.p + 1);
     FKF_CHECK_HIP(hipMemcpyAsync(off_host, ws.fro.p + 1, sizeof(double), hipMemcpyDeviceToHost, st));
     int rotated = 0;
     FKF_CHECK_HIP(hipMemcpyAsync(&rotated, ws.cnt.p, sizeof(int), hipMemcpyDeviceToHost, st));

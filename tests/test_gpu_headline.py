@@ -1,0 +1,44 @@
+"""GPU parity at the full 256 x 256 size (N = 65536, 480 rays, 50 steps)
+against stored oracle values (tests/golden/headline_reference.npz, written
+by tests/golden/make_headline_reference.py from the oracle only) at 4096
+sampled cells, in the launch configuration bench.py times."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+REF = os.path.join(os.path.dirname(__file__), "golden", "headline_reference.npz")
+TOL = 1e-6
+
+
+def test_headline_filter_matches_oracle_at_sampled_cells():
+    import torch
+    import paper_1405_2276_amd as fkf
+    if not os.path.exists(REF):
+        pytest.skip("reference file not generated")
+    ref = np.load(REF)
+    wl = W.LARGE
+    print(f"[headline] n={wl.n} steps={wl.steps}", flush=True)
+    cov = fkf.Cov(wl.points(), nu=wl.nu, length=wl.length, variance=wl.variance,
+                  leaf_size=wl.leaf_size)
+    src, rcv = wl.rays()
+    obs = fkf.Obs.from_rays(wl.shape, src, rcv, wl.noise_var)
+    ys = torch.from_numpy(W.observations(wl)).cuda()
+    f = fkf.Filter(cov)
+    idx = ref["idx"]
+    for k in range(1, wl.steps + 1):
+        f.step(obs, ys[k - 1])
+        if k in set(ref["steps"].tolist()):
+            s = f.mean().cpu().numpy()
+            v = f.variance().cpu().numpy()
+            es = np.linalg.norm(s[idx] - ref[f"s{k}"]) / np.linalg.norm(ref[f"s{k}"])
+            ev = np.abs(v[idx] - ref[f"v{k}"]).max() / ref[f"v{k}_max"]
+            en = abs(np.linalg.norm(s) - ref[f"s{k}_norm"]) / ref[f"s{k}_norm"]
+            print(f"[headline] step={k} sampled state err={es:.2e} var err={ev:.2e} "
+                  f"norm err={en:.2e}", flush=True)
+            assert es <= TOL and ev <= TOL and en <= TOL
+    f.status()

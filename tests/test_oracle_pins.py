@@ -253,3 +253,18 @@ def test_realization_factor_reproduces_covariance_and_paper_formula():
     want = rec["s"][:, None] + math.sqrt(a) * (g - U @ (Sm[:, None] * (U.T @ np.linalg.solve(Gamma, g))))
     got = sampling.realize(rec["s"], rec["Sigma"], a, Gamma, g)
     np.testing.assert_allclose(got, want, atol=1e-9)
+
+
+def test_innovation_loglik_equals_joint_gaussian_log_density():
+    # the innovation decomposition of the log-likelihood equals the log density
+    # of the stacked observations under the joint Gaussian model
+    Gamma, Hs, Rs, ys = _tiny_problem(N=5, steps=3)
+    ll = kalman.innovation_loglik(Gamma, Hs, Rs, ys, alpha0=0.4)
+    K = len(Hs)
+    rows = [[(0.4 + min(i, j) + 1) * Hs[i] @ Gamma @ Hs[j].T for j in range(K)] for i in range(K)]
+    Syy = np.block(rows) + np.diag(np.concatenate(Rs))
+    y = np.concatenate(ys)
+    sign, logdet = np.linalg.slogdet(Syy)
+    want = -0.5 * (y @ np.linalg.solve(Syy, y) + logdet + len(y) * np.log(2 * np.pi))
+    assert sign > 0
+    assert ll == pytest.approx(want, rel=1e-11)

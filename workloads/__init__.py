@@ -193,12 +193,30 @@ class Truth:
 
 
 def observations(wl: Workload) -> np.ndarray:
-    """Noisy travel times y_k for k = 1..steps, shape (steps, n_m)."""
+    """Noisy travel times y_k for k = 1..steps, shape (steps, n_m).
+
+    Same values as Truth.travel_times(k) plus noise; the drift fields are
+    evaluated once at the quadrature points and accumulated step by step.
+    """
     tr = Truth(wl)
     g = rng(wl.cfg_id, STREAM_NOISE)
+    src, rcv = wl.rays()
+    t, wq = np.polynomial.legendre.leggauss(tr.n_quad)
+    t = 0.5 * (t + 1.0)
+    wq = 0.5 * wq
+    seg = rcv - src
+    L = np.linalg.norm(seg, axis=1)
+    pts = (src[:, None, :] + t[None, :, None] * seg[:, None, :]).reshape(-1, wl.dim)
+    K = max(wl.steps, 1)
+    r2 = np.sum((pts - tr.centre) ** 2, axis=-1)
+    drift = np.zeros(len(pts))
     ys = []
     for k in range(1, wl.steps + 1):
-        y = tr.travel_times(k)
+        if k - 1 < len(tr.fields):
+            drift = drift + wl.drift_sigma * tr.fields[k - 1](pts)
+        w = 0.05 + 0.15 * min(k / K, 1.0)
+        vals = tr.amp * min(k / K, 1.0) * np.exp(-r2 / (2 * w * w)) + drift
+        y = L * (vals.reshape(len(src), -1) @ wq)
         ys.append(y + math.sqrt(wl.noise_var) * g.standard_normal(len(y)))
     return np.array(ys)
 
