@@ -10,8 +10,12 @@ One benchmark step is one pass of the whole hot path over the 50 observation
 vectors: the generalized eigenproblem of the ray operator (cross covariance
 P = Gamma H^T by H-matrix products, innovation Gram matrix, FP64 eigensolver,
 basis), 50 constant-H filter steps, the variance field and 4 conditional
-realizations.  The value is filter steps per second over the whole pass.
-The one-column H-matrix product is benchmarked separately (HBM GB/s).
+realizations.  The value is filter steps per second over the whole pass in
+FP64.  The same pass is then timed in the mixed-precision form (FP32 storage
+and kernel evaluation, FP64 accumulation) and its speedup and per-result
+error (against stored oracle values at sampled cells and against the FP64
+form) are reported beside it.  The one-column H-matrix product is benchmarked
+separately (HBM GB/s), cold and warm, in both forms.
 
 Prints one JSON line.
 """
@@ -43,6 +47,7 @@ def parse():
     ap.add_argument("--realizations", type=int, default=4)
     ap.add_argument("--matvec-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
     return ap.parse_args()
 
 
@@ -91,6 +96,136 @@ def cpu_baseline(wl, H, n_panels=4, n_steps=5):
                       f"({t_pass:.1f} s)"}
 
 
+def time_passes(fkf, torch, cov, obs, ys, g, steps_per_pass, warmup, reps):
+    """Mean wall time of one hot-path pass over `reps` timed passes, and the
+    per-site trace (HIP events on the launching streams) of those passes."""
+    var_out = torch.empty(cov.n, dtype=torch.float64, device="cuda")
+    real_out = fkf.fortran_empty(cov.n, g.shape[1])
+
+    def one_pass():
+        f = fkf.Filter(cov)
+        for k in range(steps_per_pass):
+            f.step(obs, ys[k])
+        f.variance(out=var_out)
+        f.realize(g, out=real_out)
+        f.close()
+
+    for _ in range(warmup):
+        one_pass()
+    torch.cuda.synchronize()
+    fkf.trace_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        one_pass()
+    torch.cuda.synchronize()
+    t_pass = (time.perf_counter() - t0) / reps
+    trace = fkf.trace_report()
+    fkf.trace_enable(False)
+    return t_pass, trace
+
+
+def final_results(fkf, torch, cov, obs, ys, g, steps_per_pass):
+    """One instrumented pass: per-phase times and the final state, variance and
+    realizations (host copies)."""
+    st = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    f = fkf.Filter(cov)
+    ev[0].record(st)
+    f.step(obs, ys[0])                   # basis (GEP) + first step
+    ev[1].record(st)
+    for k in range(1, steps_per_pass):
+        f.step(obs, ys[k])
+    ev[2].record(st)
+    var = f.variance()
+    ev[3].record(st)
+    real = f.realize(g)
+    ev[4].record(st)
+    torch.cuda.synchronize()
+    f.status()
+    out = {"s": f.mean().cpu().numpy(), "var": var.cpu().numpy(), "real": real.cpu().numpy()}
+    f.close()
+    phases = {"gep_and_first_step": ev[0].elapsed_time(ev[1]),
+              "steps_2_to_K": ev[1].elapsed_time(ev[2]),
+              "variance": ev[2].elapsed_time(ev[3]),
+              "realizations": ev[3].elapsed_time(ev[4])}
+    return phases, out
+
+
+def hmatvec_bench(fkf, torch, cov, info, reps):
+    """One-column H-matrix product: warm (repeated) and cold (Infinity Cache
+    flushed by a 1 GiB write before each product)."""
+    n = cov.n
+    st = torch.cuda.current_stream()
+    x = torch.randn(n, dtype=torch.float64, device="cuda")
+    yv = torch.empty_like(x)
+    for _ in range(3):
+        cov.apply(x, out=yv)
+    torch.cuda.synchronize()
+    fkf.trace_enable(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        cov.apply(x, out=yv)
+    e1.record(st)
+    torch.cuda.synchronize()
+    warm_us = e0.elapsed_time(e1) * 1e3 / reps
+    tr_warm = fkf.trace_report()
+    fkf.trace_enable(False)
+    flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda")     # 1 GiB > 256 MB MALL
+    cold = []
+    fkf.trace_enable(True)
+    for _ in range(max(reps // 5, 5)):
+        flush.fill_(1.0)
+        e0.record(st)
+        cov.apply(x, out=yv)
+        e1.record(st)
+        torch.cuda.synchronize()
+        cold.append(e0.elapsed_time(e1) * 1e3)
+    tr_cold = fkf.trace_report()
+    fkf.trace_enable(False)
+    del flush
+    cold_us = float(np.mean(cold))
+    mv_bytes = info["near_bytes"] + 8 * n + 8 * n + 8 * 2 * n   # near tiles, x, y, coordinates
+    near_bytes = info["near_bytes"] + 8 * n
+    c_near, ms_near = tr_cold.get("hmat_near_1rhs", (1, float("nan")))
+    c_nw, ms_nw = tr_warm.get("hmat_near_1rhs", (1, float("nan")))
+    cold_near_us, warm_near_us = ms_near * 1e3 / c_near, ms_nw * 1e3 / c_nw
+    return {"cold_us": cold_us, "warm_us": warm_us,
+            "alg_bytes": mv_bytes, "cold_gbs": mv_bytes / cold_us * 1e-3,
+            "warm_gbs": mv_bytes / warm_us * 1e-3,
+            "near_kernel_cold_us": cold_near_us, "near_kernel_warm_us": warm_near_us,
+            "near_kernel_cold_gbs": near_bytes / cold_near_us * 1e-3,
+            "kernel_us": {k: v[1] * 1e3 / max(v[0], 1) for k, v in tr_cold.items()}}
+
+
+def accuracy(wl, res, ref64):
+    """Per-result error of a pass: against the oracle's stored values at
+    sampled cells (when the workload has them) and against the FP64 GPU form
+    over the whole field."""
+    out = {}
+    refp = os.path.join(ROOT, "tests", "golden", "headline_reference.npz")
+    k = wl.steps
+    if wl.name == "crosswell-256x256" and os.path.exists(refp):
+        ref = np.load(refp)
+        idx = ref["idx"]
+        if f"s{k}" in ref:
+            out["oracle_state_sampled"] = float(np.linalg.norm(res["s"][idx] - ref[f"s{k}"])
+                                                / np.linalg.norm(ref[f"s{k}"]))
+            out["oracle_var_sampled"] = float(np.abs(res["var"][idx] - ref[f"v{k}"]).max()
+                                              / ref[f"v{k}_max"])
+            out["oracle_state_norm"] = float(abs(np.linalg.norm(res["s"]) - ref[f"s{k}_norm"])
+                                             / ref[f"s{k}_norm"])
+    if ref64 is not None:
+        out["fp64gpu_state"] = float(np.linalg.norm(res["s"] - ref64["s"])
+                                     / np.linalg.norm(ref64["s"]))
+        out["fp64gpu_var"] = float(np.abs(res["var"] - ref64["var"]).max()
+                                   / np.abs(ref64["var"]).max())
+        out["fp64gpu_realizations"] = float(np.linalg.norm(res["real"] - ref64["real"])
+                                            / np.linalg.norm(ref64["real"]))
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -116,102 +251,47 @@ def main():
     obs = fkf.Obs.from_rays(wl.shape, src, rcv, wl.noise_var)
     H = obs.csr()
     n_m = obs.n_m
+    n = wl.n
     ys = torch.from_numpy(W.observations(wl)).to(dev)             # (steps, n_m), resident
     g = fkf.to_device(W.normals(wl, W.STREAM_DRAWS, (wl.n, args.realizations)))
-    var_out = torch.empty(wl.n, dtype=torch.float64, device=dev)
-    real_out = fkf.fortran_empty(wl.n, args.realizations)
     log(f"[bench] built Gamma in {t_build:.2f} s: {info}")
 
-    def one_pass():
-        f = fkf.Filter(cov)
-        for k in range(wl.steps):
-            f.step(obs, ys[k])
-        f.variance(out=var_out)
-        f.realize(g, out=real_out)
-        f.close()
-
-    for _ in range(args.warmup):
-        one_pass()
-    torch.cuda.synchronize()
-    fkf.trace_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        one_pass()
-    torch.cuda.synchronize()
-    t_pass = (time.perf_counter() - t0) / args.steps
-    trace = fkf.trace_report()
-    fkf.trace_enable(False)
-    log(f"[bench] pass {t_pass * 1e3:.2f} ms; trace {trace}")
-
-    # ---- per-phase timing (one extra instrumented pass, events on the stream)
-    st = torch.cuda.current_stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
-    f = fkf.Filter(cov)
-    ev[0].record(st)
-    f.step(obs, ys[0])                   # basis (GEP) + first step
-    ev[1].record(st)
-    for k in range(1, wl.steps):
-        f.step(obs, ys[k])
-    ev[2].record(st)
-    f.variance(out=var_out)
-    ev[3].record(st)
-    f.realize(g, out=real_out)
-    ev[4].record(st)
-    torch.cuda.synchronize()
-    f.close()
-    phases = {"gep_and_first_step": ev[0].elapsed_time(ev[1]),
-              "steps_2_to_K": ev[1].elapsed_time(ev[2]),
-              "variance": ev[2].elapsed_time(ev[3]),
-              "realizations": ev[3].elapsed_time(ev[4])}
+    # ---- FP64 form: the timed passes (the headline value)
+    t_pass, trace = time_passes(fkf, torch, cov, obs, ys, g, wl.steps, args.warmup, args.steps)
+    log(f"[bench] fp64 pass {t_pass * 1e3:.2f} ms; trace {trace}")
+    phases, res64 = final_results(fkf, torch, cov, obs, ys, g, wl.steps)
     step_us = phases["steps_2_to_K"] * 1e3 / max(wl.steps - 1, 1)
+    acc64 = accuracy(wl, res64, None)
+    log(f"[bench] fp64 phases {phases} accuracy {acc64}")
+    hmatvec = hmatvec_bench(fkf, torch, cov, info, args.matvec_reps)
+    log(f"[bench] hmatvec fp64 {hmatvec}")
 
-    # ---- one-column H-matrix product: warm and cold (Infinity Cache flushed)
-    x = torch.randn(wl.n, dtype=torch.float64, device=dev)
-    yv = torch.empty_like(x)
-    for _ in range(3):
-        cov.apply(x, out=yv)
-    torch.cuda.synchronize()
-    fkf.trace_enable(True)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    for _ in range(args.matvec_reps):
-        cov.apply(x, out=yv)
-    e1.record(st)
-    torch.cuda.synchronize()
-    warm_us = e0.elapsed_time(e1) * 1e3 / args.matvec_reps
-    tr_warm = fkf.trace_report()
-    fkf.trace_enable(False)
-    flush = torch.empty(1 << 27, dtype=torch.float64, device=dev)     # 1 GiB > 256 MB MALL
-    cold = []
-    fkf.trace_enable(True)
-    for _ in range(max(args.matvec_reps // 5, 5)):
-        flush.fill_(1.0)
-        e0.record(st)
-        cov.apply(x, out=yv)
-        e1.record(st)
+    # ---- mixed form (FP32 storage / kernel evaluation, FP64 accumulation)
+    mixed = None
+    if not args.no_mixed:
+        t0 = time.perf_counter()
+        cov_m = fkf.Cov(pts, nu=wl.nu, length=wl.length, variance=wl.variance,
+                        leaf_size=wl.leaf_size, precision="mixed")
         torch.cuda.synchronize()
-        cold.append(e0.elapsed_time(e1) * 1e3)
-    tr_cold = fkf.trace_report()
-    fkf.trace_enable(False)
-    del flush
-    cold_us = float(np.mean(cold))
-    n = wl.n
-    mv_bytes = info["near_bytes"] + 8 * n + 8 * n + 8 * 2 * n   # near tiles, x, y, coordinates
-    near_bytes = info["near_bytes"] + 8 * n
-    c_near, ms_near = tr_cold.get("hmat_near_1rhs", (1, float("nan")))
-    cold_near_us = ms_near * 1e3 / c_near
-    c_nw, ms_nw = tr_warm.get("hmat_near_1rhs", (1, float("nan")))
-    warm_near_us = ms_nw * 1e3 / c_nw
-    hmatvec = {"cold_us": cold_us, "warm_us": warm_us,
-               "alg_bytes": mv_bytes, "cold_gbs": mv_bytes / cold_us * 1e-3,
-               "warm_gbs": mv_bytes / warm_us * 1e-3,
-               "near_kernel_cold_us": cold_near_us, "near_kernel_warm_us": warm_near_us,
-               "near_kernel_cold_gbs": near_bytes / cold_near_us * 1e-3,
-               "kernel_us": {k: v[1] * 1e3 / max(v[0], 1) for k, v in tr_cold.items()}}
-    log(f"[bench] hmatvec {hmatvec}")
+        t_build_m = time.perf_counter() - t0
+        info_m = cov_m.info()
+        t_pass_m, trace_m = time_passes(fkf, torch, cov_m, obs, ys, g, wl.steps, args.warmup,
+                                        args.steps)
+        log(f"[bench] mixed pass {t_pass_m * 1e3:.2f} ms; trace {trace_m}")
+        phases_m, res_m = final_results(fkf, torch, cov_m, obs, ys, g, wl.steps)
+        acc_m = accuracy(wl, res_m, res64)
+        log(f"[bench] mixed phases {phases_m} accuracy {acc_m}")
+        hmv_m = hmatvec_bench(fkf, torch, cov_m, info_m, args.matvec_reps)
+        log(f"[bench] hmatvec mixed {hmv_m}")
+        step_us_m = phases_m["steps_2_to_K"] * 1e3 / max(wl.steps - 1, 1)
+        mixed = {"pass_ms": t_pass_m * 1e3, "steps_per_s": wl.steps / t_pass_m,
+                 "constant_h_step_us": step_us_m, "phases_ms": phases_m,
+                 "hmatvec_1rhs": hmv_m, "gamma_build_s": t_build_m,
+                 "near_bytes": info_m["near_bytes"], "errors": acc_m,
+                 "sites_ms_per_pass": {k: v[1] / args.steps for k, v in trace_m.items()}}
+        cov_m.close()
 
-    # ---- roofline of the dominant kernel of the pass
+    # ---- roofline of the dominant kernel of the FP64 pass
     per = {k: (c, ms) for k, (c, ms) in trace.items()}
     models = {
         # site: (bound, algorithmic units per launch, unit)
@@ -263,10 +343,17 @@ def main():
             "constant_h_step_us": step_us,
             "constant_h_steps_per_s": 1e6 / step_us,
             "phases_ms": phases,
+            "errors": acc64,
             "dominant_site": dom,
             "sites_ms_per_pass": {k: v[1] / args.steps for k, v in per.items()},
             "gamma_build_s": t_build,
-            "mixed_vs_fp64_speedup": None,
+            "mixed": mixed,
+            "mixed_vs_fp64_speedup": (t_pass * 1e3 / mixed["pass_ms"]) if mixed else None,
+            "mixed_vs_fp64_step_speedup": (step_us / mixed["constant_h_step_us"]) if mixed
+            else None,
+            "mixed_vs_fp64_hmatvec_cold_speedup": (hmatvec["cold_us"]
+                                                   / mixed["hmatvec_1rhs"]["cold_us"]) if mixed
+            else None,
         },
         "cpu_baseline": None,
     }

@@ -56,7 +56,13 @@ typedef enum {
  * form (eq. maternfamily) reduces to an exponential times a polynomial. */
 typedef enum { FKF_MATERN_12 = 0, FKF_MATERN_32 = 1, FKF_MATERN_52 = 2 } fkf_kernel;
 
-typedef enum { FKF_FP64 = 0 } fkf_precision;
+/* FKF_FP64: every H-matrix entry and every filter array in FP64.
+ * FKF_MIXED: near-field blocks stored in FP32 (half the HBM bytes of the
+ * dominant stream), far-field kernel entries evaluated in FP32, and the
+ * constant-H basis streamed every step stored in FP32; all sums are
+ * accumulated in FP64, and the projected eigenproblem, the innovation
+ * Cholesky and the Gamma^-1-orthogonalisation stay in FP64. */
+typedef enum { FKF_FP64 = 0, FKF_MIXED = 1 } fkf_precision;
 
 /* Gamma[i,j] = variance * C_nu(|x_i - x_j| / length).  The paper's scaling
  * factor alpha of eq. maternfamily is 1/length; the variance multiplies it. */

@@ -170,12 +170,18 @@ def fortran_empty(n: int, k: int, device="cuda"):
     return torch.empty((k, n), dtype=torch.float64, device=device).t()
 
 
-def _params(nu, length, variance, leaf_size, cheb_order, cheb_order_max, eta, block_tol):
+PRECISION = {"fp64": 0, "mixed": 1}
+
+
+def _params(nu, length, variance, leaf_size, cheb_order, cheb_order_max, eta, block_tol,
+            precision="fp64"):
     if nu not in MATERN:
         raise ValueError("nu must be 0.5, 1.5 or 2.5")
+    if precision not in PRECISION:
+        raise ValueError("precision must be 'fp64' or 'mixed'")
     kp = KernelParams(ctypes.sizeof(KernelParams), MATERN[nu], variance, length)
     hp = HmatParams(ctypes.sizeof(HmatParams), leaf_size, cheb_order, cheb_order_max,
-                    eta, block_tol, 0)
+                    eta, block_tol, PRECISION[precision])
     return kp, hp
 
 
@@ -186,10 +192,11 @@ def _info_dict(inf: CovInfo) -> dict:
 
 
 def plan(points, nu=1.5, length=0.1, variance=1.0, leaf_size=64, cheb_order=6,
-         cheb_order_max=16, eta=1.5, block_tol=1e-7) -> dict:
+         cheb_order_max=16, eta=1.5, block_tol=1e-7, precision="fp64") -> dict:
     """Host-only H-matrix plan (tree, partition, Chebyshev orders); no GPU."""
     pts = np.ascontiguousarray(points, dtype=np.float64)
-    kp, hp = _params(nu, length, variance, leaf_size, cheb_order, cheb_order_max, eta, block_tol)
+    kp, hp = _params(nu, length, variance, leaf_size, cheb_order, cheb_order_max, eta, block_tol,
+                     precision)
     inf = CovInfo()
     _check(_lib.fkf_cov_plan(pts.ctypes.data_as(_c_dbl_p), pts.shape[0], pts.shape[1],
                              ctypes.byref(kp), ctypes.byref(hp), ctypes.byref(inf)))
@@ -215,18 +222,24 @@ def rays_host(shape, src, rcv):
 
 
 class Cov:
-    """Gamma_sys (Matern) as an H-matrix on the GPU (fkf_cov_*)."""
+    """Gamma_sys (Matern) as an H-matrix on the GPU (fkf_cov_*).
+
+    precision: "fp64", or "mixed" (FP32 near-field storage and far-field kernel
+    evaluation, FP64 accumulation; filters built on it stream their basis in
+    FP32)."""
 
     def __init__(self, points, nu: float = 1.5, length: float = 0.1, variance: float = 1.0,
                  leaf_size: int = 64, cheb_order: int = 6, cheb_order_max: int = 16,
-                 eta: float = 1.5, block_tol: float = 1e-7, stream=None):
+                 eta: float = 1.5, block_tol: float = 1e-7, precision: str = "fp64",
+                 stream=None):
         pts = np.ascontiguousarray(points, dtype=np.float64)
         if pts.ndim != 2:
             raise ValueError("points must be (N, d)")
         self.n, self.d = pts.shape
         self.nu, self.length, self.variance = nu, length, variance
         kp, hp = _params(nu, length, variance, leaf_size, cheb_order, cheb_order_max, eta,
-                         block_tol)
+                         block_tol, precision)
+        self.precision = precision
         h = ctypes.c_void_p()
         _check(_lib.fkf_cov_build(pts.ctypes.data_as(_c_dbl_p), self.n, self.d,
                                   ctypes.byref(kp), ctypes.byref(hp), _stream(stream),

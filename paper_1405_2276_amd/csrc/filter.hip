@@ -57,6 +57,8 @@ struct fkf_filter {
   int n_m = 0;
   fkf_status failed = FKF_OK;
   fkf::DevBuf<double> s, U0, Ve, lam, delta, nu, zp, part, tmp, eta;
+  bool mixed = false;              // mixed-precision covariance: U0 also kept in FP32
+  fkf::DevBuf<float> U0f;          // FP32 copy of U0 streamed by the per-step GEMVs
   fkf::DevBuf<int64_t> b_rowptr;   // copy of the basis' measurement operator
   fkf::DevBuf<int32_t> b_col;
   fkf::DevBuf<double> b_val;
@@ -78,11 +80,13 @@ namespace fkf {
 // implemented in hmat.hip
 double cov_variance(const fkf_cov *cov);
 int64_t cov_n(const fkf_cov *cov);
+bool cov_mixed(const fkf_cov *cov);
 
 static std::atomic<uint64_t> g_obs_gen{1};
 
 constexpr int kSegCols = 32;    // columns per GEMV workgroup
 constexpr int kRowsPerWG = 512; // 256 threads x 2 rows
+constexpr int kRowsPerWG32 = 1024; // FP32 basis: 256 threads x 4 rows
 
 // ------------------------------------------------------------- kernels ---
 __global__ void __launch_bounds__(256) k_innov(const int64_t *__restrict__ rowptr,
@@ -101,30 +105,6 @@ __global__ void __launch_bounds__(256) k_innov(const int64_t *__restrict__ rowpt
     double v = y[m] - acc;
     if (!isfinite(v)) atomicExch(err, (int)FKF_E_NONFINITE);
     nu[m] = v;
-  }
-}
-
-// One wavefront per mode j: z_j = Ve[:, j] . nu, then the per-mode update.
-__global__ void __launch_bounds__(256) k_modes_step(const double *__restrict__ Ve, int n_m,
-                                                    const double *__restrict__ nu,
-                                                    const double *__restrict__ lam,
-                                                    double *__restrict__ delta, double alpha,
-                                                    double *__restrict__ zp, int *err) {
-  int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (j >= n_m) return;
-  int l = threadIdx.x & 63;
-  const double *v = Ve + (int64_t)n_m * j;
-  double z = 0;
-  for (int m = l; m < n_m; m += 64) z = fma(v[m], nu[m], z);
-  z = wave_sum(z);
-  if (l == 0) {
-    double lj = lam[j], dj = delta[j];
-    double a = alpha - dj * lj;          // alpha_{k+1} - D_k
-    double den = 1.0 + a * lj;           // (alpha - D) lambda + 1: S_k in the eigenbasis
-    double g = a / den;
-    zp[j] = g * z;
-    delta[j] = dj + a * g;               // D_{k+1} / lambda
-    if (!isfinite(zp[j]) || !isfinite(delta[j])) atomicExch(err, (int)FKF_E_NONFINITE);
   }
 }
 
@@ -243,6 +223,48 @@ __global__ void __launch_bounds__(256) k_gemv_seg(const double *__restrict__ U0,
   if (i0 + 1 < n) o[i0 + 1] = a1;
 }
 
+// As k_gemv_seg with an FP32 matrix (ld a multiple of 4): four rows per
+// thread with 16-byte loads, products and sums in FP64.
+template <bool SQUARE>
+__global__ void __launch_bounds__(256) k_gemv_seg32(const float *__restrict__ U, int64_t n,
+                                                    int64_t ldu, int n_m,
+                                                    const double *__restrict__ z,
+                                                    double *__restrict__ part) {
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  int64_t i0 = (int64_t)blockIdx.x * kRowsPerWG32 + 4 * threadIdx.x;
+  int j0 = blockIdx.y * kSegCols;
+  int jn = min(kSegCols, n_m - j0);
+  if (i0 >= n) return;
+  double a[4] = {0, 0, 0, 0};
+  const v4f *src = reinterpret_cast<const v4f *>(U + i0 + ldu * j0);
+  const int64_t ld4 = ldu / 4;
+  auto acc = [&](v4f u, double zj) {
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const double x = (double)u[h];
+      a[h] = SQUARE ? fma(x * x, zj, a[h]) : fma(x, zj, a[h]);
+    }
+  };
+  if (jn == kSegCols) {
+    v4f u[kSegCols];
+#pragma unroll
+    for (int jj = 0; jj < kSegCols; ++jj) u[jj] = __builtin_nontemporal_load(src + ld4 * jj);
+#pragma unroll
+    for (int jj = 0; jj < kSegCols; ++jj) acc(u[jj], z[j0 + jj]);
+  } else {
+    for (int jj = 0; jj < jn; ++jj) acc(src[ld4 * jj], z[j0 + jj]);
+  }
+  double *o = part + (int64_t)blockIdx.y * n;
+#pragma unroll
+  for (int h = 0; h < 4; ++h)
+    if (i0 + h < n) o[i0 + h] = a[h];
+}
+
+__global__ void k_to_f32(const double *__restrict__ src, float *__restrict__ dst, int64_t len) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) dst[i] = (float)src[i];
+}
+
 // s[i] += sum_seg part[seg][i]
 __global__ void k_seg_add(const double *__restrict__ part, int nseg, int64_t n,
                           double *__restrict__ s) {
@@ -324,6 +346,18 @@ static void gemv_seg_m(const double *M, int64_t ld, int ncols, int64_t n, const 
 }
 
 static void gemv_seg(const fkf_filter *f, const double *z, bool square, hipStream_t st) {
+  if (f->mixed) {
+    FKF_TRACE(square ? "filter_gemv_sq32" : "filter_gemv32", st);
+    int nseg = (f->n_m + kSegCols - 1) / kSegCols;
+    dim3 grid(blocks(f->n, kRowsPerWG32), (unsigned)nseg);
+    if (square)
+      hipLaunchKernelGGL(k_gemv_seg32<true>, grid, dim3(256), 0, st, f->U0f.p, f->n, f->ldu,
+                         f->n_m, z, f->part.p);
+    else
+      hipLaunchKernelGGL(k_gemv_seg32<false>, grid, dim3(256), 0, st, f->U0f.p, f->n, f->ldu,
+                         f->n_m, z, f->part.p);
+    return;
+  }
   gemv_seg_m(f->U0.p, f->ldu, f->n_m, f->n, z, square, f->part.p, st);
 }
 
@@ -372,6 +406,11 @@ static void build_basis(fkf_filter *f, const fkf_obs *o, hipStream_t st) {
   {
     FKF_TRACE("gep_basis_gemm", st);
     gemm_nn(n, nm, nm, P.p, n, f->Ve.p, nm, f->U0.p, f->ldu, st);
+  }
+  if (f->mixed) {
+    f->U0f.alloc((size_t)f->ldu * nm);
+    const int64_t len = f->ldu * (int64_t)nm;
+    if (len > 0) hipLaunchKernelGGL(k_to_f32, dim3(blocks(len)), dim3(256), 0, st, f->U0.p, f->U0f.p, len);
   }
   f->delta.alloc(nm);
   fill(f->delta.p, nm, 0.0, st);
@@ -716,6 +755,7 @@ extern "C" fkf_status fkf_filter_create(fkf_cov *cov, const double *s0, double a
     f->cov = cov;
     f->n = cov_n(cov);
     f->theta = cov_variance(cov);
+    f->mixed = cov_mixed(cov);
     f->alpha = alpha0;
     if (params) {
       f->params = *params;

@@ -67,7 +67,9 @@ struct fkf_cov {
   fkf::DevBuf<double> pts;          // d x n, tree order
   fkf::DevBuf<int64_t> leaf_off;    // n_leaves + 1
   fkf::DevBuf<int32_t> blk_s, blk_t;
-  fkf::DevBuf<double> blk;          // n_blk x 4096
+  fkf::DevBuf<double> blk;          // n_blk x 4096 (FP64 mode)
+  fkf::DevBuf<float> blk32;         // n_blk x 4096 (mixed mode)
+  bool mixed = false;
   fkf::DevBuf<int32_t> part_ptr, part_idx;   // per leaf: entries blk*2 + side
   fkf::DevBuf<int32_t> near_ptr, near_idx;   // per leaf: entries blk*2 + transposed
   fkf::DevBuf<fkf::FarCluster> fc;
@@ -108,6 +110,28 @@ __device__ __forceinline__ double matern_dev(double r, int kind, double inv_ell,
   }
   double t = 2.2360679774997896 * r * inv_ell;
   return theta * (1.0 + t + t * t * (1.0 / 3.0)) * exp(-t);
+}
+
+// Kernel entry theta C(t) at scaled distance t = c r / ell from its square t2
+// (c = 1, sqrt 3, sqrt 5 for nu = 1/2, 3/2, 5/2).  F32: evaluated with the
+// FP32 hardware square root and exponential (mixed precision).
+template <bool F32>
+__device__ __forceinline__ double kernel_t2(double t2, int kind, double theta) {
+  if (F32) {
+    const float t = __fsqrt_rn((float)t2);
+    const float ex = __expf(-t);
+    float kv = kind == FKF_MATERN_12 ? ex
+                                     : (kind == FKF_MATERN_32 ? fmaf(t, ex, ex)
+                                                              : fmaf(fmaf(t, 1.0f / 3.0f, 1.0f) * t, ex, ex));
+    return theta * (double)kv;
+  } else {
+    const double t = sqrt_pos(t2);
+    const double ex = exp_nonpos(-t);
+    double kv = kind == FKF_MATERN_12 ? ex
+                                      : (kind == FKF_MATERN_32 ? fma(t, ex, ex)
+                                                               : fma(fma(t, 1.0 / 3.0, 1.0) * t, ex, ex));
+    return theta * kv;
+  }
 }
 
 // Barycentric Lagrange basis at normalised coordinate x on Chebyshev nodes.
@@ -186,6 +210,109 @@ __global__ void __launch_bounds__(64) k_near_assemble(const double *__restrict__
   }
 }
 
+// FP32 near-field tile: slice k (16 slices of 1 KiB) holds four consecutive
+// entries (row 8ra + k/2, columns 8cb + 4(k%2) .. +3) of each lane's sub-tile.
+__global__ void __launch_bounds__(64) k_near_assemble32(const double *__restrict__ pts, int64_t n,
+                                                        int d, const int64_t *__restrict__ leaf_off,
+                                                        const int32_t *__restrict__ bs,
+                                                        const int32_t *__restrict__ bt, int kind,
+                                                        double inv_ell, double theta,
+                                                        float *__restrict__ blk) {
+  int64_t b = blockIdx.x;
+  int l = threadIdx.x;
+  int ra = l & 7, cb = l >> 3;
+  int s = bs[b], t = bt[b];
+  int64_t s0 = leaf_off[s], ms = leaf_off[s + 1] - s0;
+  int64_t t0 = leaf_off[t], mt = leaf_off[t + 1] - t0;
+  double xr[8][kMaxDim], xc[8][kMaxDim];
+  for (int r = 0; r < 8; ++r) {
+    int64_t i = 8 * ra + r, j = 8 * cb + r;
+    for (int k = 0; k < kMaxDim; ++k) {
+      xr[r][k] = (i < ms && k < d) ? pts[k * n + s0 + i] : 0.0;
+      xc[r][k] = (j < mt && k < d) ? pts[k * n + t0 + j] : 0.0;
+    }
+  }
+  float4 *out = reinterpret_cast<float4 *>(blk + b * 4096);
+  for (int r = 0; r < 8; ++r) {
+    int i = 8 * ra + r;
+    for (int cq = 0; cq < 2; ++cq) {
+      float v[4];
+      for (int h = 0; h < 4; ++h) {
+        int c = 4 * cq + h;
+        int j = 8 * cb + c;
+        double r2 = 0;
+        for (int k = 0; k < d; ++k) {
+          double dx = xr[r][k] - xc[c][k];
+          r2 += dx * dx;
+        }
+        v[h] = (i < ms && j < mt) ? (float)matern_dev(sqrt(r2), kind, inv_ell, theta) : 0.0f;
+      }
+      out[(2 * r + cq) * 64 + l] = make_float4(v[0], v[1], v[2], v[3]);
+    }
+  }
+}
+
+// One right-hand side, FP32 tiles (products and sums in FP64); otherwise as
+// k_near_sym1 below.
+__global__ void __launch_bounds__(256) k_near_sym1_32(const float *__restrict__ blk,
+                                                      const int32_t *__restrict__ bs,
+                                                      const int32_t *__restrict__ bt,
+                                                      const int64_t *__restrict__ leaf_off,
+                                                      const double *__restrict__ xt, int64_t n_blk,
+                                                      double *__restrict__ part) {
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (b >= n_blk) return;
+  int l = threadIdx.x & 63;
+  int ra = l & 7, cb = l >> 3;
+  const v4f *src = reinterpret_cast<const v4f *>(blk + b * 4096);
+  v4f v[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = __builtin_nontemporal_load(src + k * 64 + l);
+  int s = bs[b], t = bt[b];
+  int64_t s0 = leaf_off[s], ms = leaf_off[s + 1] - s0;
+  int64_t t0 = leaf_off[t], mt = leaf_off[t + 1] - t0;
+  double xs[8], xc[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    int i = 8 * ra + r, j = 8 * cb + r;
+    xs[r] = i < ms ? xt[s0 + i] : 0.0;
+    xc[r] = j < mt ? xt[t0 + j] : 0.0;
+  }
+  double racc[8], cacc[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) racc[r] = cacc[r] = 0.0;
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+#pragma unroll
+    for (int cq = 0; cq < 2; ++cq) {
+      v4f e = v[2 * r + cq];
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const double ev = (double)e[h];
+        racc[r] = fma(ev, xc[4 * cq + h], racc[r]);
+        cacc[4 * cq + h] = fma(ev, xs[r], cacc[4 * cq + h]);
+      }
+    }
+#pragma unroll
+  for (int m = 8; m < 64; m <<= 1)
+#pragma unroll
+    for (int r = 0; r < 8; ++r) racc[r] += __shfl_xor(racc[r], m);
+#pragma unroll
+  for (int m = 1; m < 8; m <<= 1)
+#pragma unroll
+    for (int r = 0; r < 8; ++r) cacc[r] += __shfl_xor(cacc[r], m);
+  double *o = part + b * 128;
+  if (cb == 0) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) o[8 * ra + r] = racc[r];
+  }
+  if (ra == 0) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) o[64 + 8 * cb + r] = cacc[r];
+  }
+}
+
 // Near field, one right-hand side, symmetric storage.  Wave w of the block
 // handles tile b: row partial sums Gamma_st x_t -> part[b][0:64] and column
 // partial sums Gamma_st^T x_s -> part[b][64:128].
@@ -246,270 +373,6 @@ __global__ void __launch_bounds__(256) k_near_sym1(const double *__restrict__ bl
     for (int r = 0; r < 8; ++r) o[64 + 8 * cb + r] = cacc[r];
   }
 }
-
-// Near field, several right-hand sides: one workgroup per (row leaf, 32
-// columns); tiles are staged through LDS (transposed where the stored tile is
-// the (t, s) half).
-__global__ void __launch_bounds__(256) k_near_multi(const double *__restrict__ blk,
-                                                    const int32_t *__restrict__ near_ptr,
-                                                    const int32_t *__restrict__ near_idx,
-                                                    const int32_t *__restrict__ bs,
-                                                    const int32_t *__restrict__ bt,
-                                                    const int64_t *__restrict__ leaf_off,
-                                                    const double *__restrict__ xt, int64_t n,
-                                                    int nrhs, double *__restrict__ yt) {
-  __shared__ double A[64][65];
-  __shared__ double Xs[64][33];
-  int s = blockIdx.x;
-  int c0 = blockIdx.y * 32;
-  int tid = threadIdx.x;
-  int row = tid & 63, cg = tid >> 6;
-  int64_t s0 = leaf_off[s], ms = leaf_off[s + 1] - s0;
-  double acc[8];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) acc[c] = 0.0;
-  for (int e = near_ptr[s]; e < near_ptr[s + 1]; ++e) {
-    int code = near_idx[e];
-    int64_t b = code >> 1;
-    bool trans = code & 1;
-    int t = trans ? bs[b] : bt[b];
-    int64_t t0 = leaf_off[t], mt = leaf_off[t + 1] - t0;
-    const double2 *src = reinterpret_cast<const double2 *>(blk + b * 4096);
-    for (int q = tid; q < 2048; q += 256) {
-      int k = q >> 6, lane = q & 63;
-      int i = 8 * (lane & 7) + (k >> 2), j = 8 * (lane >> 3) + 2 * (k & 3);
-      double2 v = src[q];
-      if (!trans) {
-        A[i][j] = v.x;
-        A[i][j + 1] = v.y;
-      } else {
-        A[j][i] = v.x;
-        A[j + 1][i] = v.y;
-      }
-    }
-    for (int q = tid; q < 64 * 32; q += 256) {
-      int j = q & 63, c = q >> 6;
-      Xs[j][c] = (j < mt && c0 + c < nrhs) ? xt[t0 + j + n * (c0 + c)] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int j = 0; j < 64; ++j) {
-      double a = A[row][j];
-#pragma unroll
-      for (int c = 0; c < 8; ++c) acc[c] = fma(a, Xs[j][cg * 8 + c], acc[c]);
-    }
-    __syncthreads();
-  }
-  if (row < ms)
-    for (int c = 0; c < 8; ++c) {
-      int col = c0 + cg * 8 + c;
-      if (col < nrhs) yt[s0 + row + n * col] = acc[c];
-    }
-}
-
-// Far field, upward pass: xhat_c = U_c^T x_c for every far cluster c.
-template <int NC>
-__global__ void __launch_bounds__(256) k_far_up(const FarCluster *__restrict__ fc,
-                                                const double *__restrict__ pts, int64_t n, int d,
-                                                const double *__restrict__ cheb,
-                                                const double *__restrict__ xt, int nrhs,
-                                                double *__restrict__ xhat) {
-  __shared__ double Ls[kMaxDim][64][kMaxCheb];
-  __shared__ double Xs[64][NC];
-  __shared__ double cu[kMaxCheb], cw[kMaxCheb];
-  const FarCluster c = fc[blockIdx.x];
-  const int c0 = blockIdx.y * NC;
-  const int p = c.p, pd = c.pd;
-  int tid = threadIdx.x;
-  if (tid < p) {
-    cu[tid] = cheb[p * 2 * kMaxCheb + tid];
-    cw[tid] = cheb[p * 2 * kMaxCheb + kMaxCheb + tid];
-  }
-  const int nout = pd * NC;
-  double acc[16];
-  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-  __syncthreads();
-  for (int64_t i0 = c.begin; i0 < c.end; i0 += 64) {
-    int64_t cnt = min((int64_t)64, c.end - i0);
-    if (tid < 64 * d) {
-      int i = tid & 63, k = tid >> 6;
-      if (i < cnt) {
-        double x = pts[k * n + i0 + i];
-        double z = c.hw[k] > 0 ? (x - c.ctr[k]) / c.hw[k] : 0.0;
-        lagrange_dev(p, cu, cw, z, Ls[k][i]);
-      }
-    }
-    for (int q = tid; q < 64 * NC; q += 256) {
-      int i = q % 64, cc = q / 64;
-      Xs[i][cc] = (i < cnt && c0 + cc < nrhs) ? xt[i0 + i + n * (c0 + cc)] : 0.0;
-    }
-    __syncthreads();
-    for (int q = 0; q < 16; ++q) {
-      int o = tid + 256 * q;
-      if (o >= nout) break;
-      int a = o % pd, cc = o / pd;
-      int a0 = a % p, a1 = (a / p) % p, a2 = a / (p * p);
-      double s = 0;
-      for (int i = 0; i < cnt; ++i) {
-        double u = Ls[0][i][a0] * Ls[1][i][a1];
-        if (d == 3) u *= Ls[2][i][a2];
-        s = fma(u, Xs[i][cc], s);
-      }
-      acc[q] += s;
-    }
-    __syncthreads();
-  }
-  for (int q = 0; q < 16; ++q) {
-    int o = tid + 256 * q;
-    if (o >= nout) break;
-    int a = o % pd, cc = o / pd;
-    if (c0 + cc < nrhs) xhat[c.coef_off * nrhs + a + (int64_t)pd * (c0 + cc)] = acc[q];
-  }
-}
-
-// Far field, couplings: yhat_s = sum_{t admissible with s} K(xi_s, xi_t) xhat_t,
-// with K evaluated from the node coordinates (no stored couplings).
-template <int NC>
-__global__ void __launch_bounds__(256) k_far_couple(const FarCluster *__restrict__ fc,
-                                                    const int32_t *__restrict__ far_ptr,
-                                                    const int32_t *__restrict__ far_col, int d,
-                                                    const double *__restrict__ cheb, int kind,
-                                                    double inv_ell, double theta,
-                                                    const double *__restrict__ xhat, int nrhs,
-                                                    double *__restrict__ yhat) {
-  __shared__ double xi_t[kMaxCheb * kMaxCheb * kMaxCheb / 4][kMaxDim];  // up to 1024 nodes
-  __shared__ double xh[4096];
-  const int sidx = blockIdx.x;
-  const FarCluster cs = fc[sidx];
-  const int c0 = blockIdx.y * NC;
-  const int tid = threadIdx.x;
-  const int ps = cs.p, pds = cs.pd;
-  double us[kMaxCheb];
-  for (int a = 0; a < ps; ++a) us[a] = cheb[ps * 2 * kMaxCheb + a];
-  for (int a0 = 0; a0 < pds; a0 += 256) {
-    int a = a0 + tid;
-    double xs[kMaxDim] = {0, 0, 0};
-    if (a < pds) {
-      int r = a;
-      for (int k = 0; k < d; ++k) {
-        xs[k] = cs.ctr[k] + cs.hw[k] * us[r % ps];
-        r /= ps;
-      }
-    }
-    double acc[NC];
-    for (int cc = 0; cc < NC; ++cc) acc[cc] = 0.0;
-    for (int e = far_ptr[sidx]; e < far_ptr[sidx + 1]; ++e) {
-      const FarCluster ct = fc[far_col[e]];
-      const int pt = ct.p, pdt = ct.pd;
-      __syncthreads();
-      for (int b = tid; b < pdt; b += 256) {
-        int r = b;
-        for (int k = 0; k < d; ++k) {
-          xi_t[b][k] = ct.ctr[k] + ct.hw[k] * cheb[pt * 2 * kMaxCheb + (r % pt)];
-          r /= pt;
-        }
-      }
-      for (int q = tid; q < pdt * NC; q += 256) {
-        int b = q % pdt, cc = q / pdt;
-        xh[q] = (c0 + cc < nrhs) ? xhat[ct.coef_off * nrhs + b + (int64_t)pdt * (c0 + cc)] : 0.0;
-      }
-      __syncthreads();
-      if (a < pds) {
-        for (int b = 0; b < pdt; ++b) {
-          double r2 = 0;
-          for (int k = 0; k < d; ++k) {
-            double dx = xs[k] - xi_t[b][k];
-            r2 += dx * dx;
-          }
-          double kv = matern_dev(sqrt(r2), kind, inv_ell, theta);
-#pragma unroll
-          for (int cc = 0; cc < NC; ++cc) acc[cc] = fma(kv, xh[b + pdt * cc], acc[cc]);
-        }
-      }
-    }
-    if (a < pds)
-      for (int cc = 0; cc < NC; ++cc)
-        if (c0 + cc < nrhs) yhat[cs.coef_off * nrhs + a + (int64_t)pds * (c0 + cc)] = acc[cc];
-  }
-}
-
-// Downward pass + near-field reduction + scatter to caller order:
-// y_i = (near part) + sum over far-cluster ancestors c of leaf: U_c(x_i) yhat_c.
-template <int NC>
-__global__ void __launch_bounds__(256) k_finalize(
-    const int64_t *__restrict__ leaf_off, const double *__restrict__ pts, int64_t n, int d,
-    const double *__restrict__ cheb, const FarCluster *__restrict__ fc,
-    const int32_t *__restrict__ anc_ptr, const int32_t *__restrict__ anc_idx,
-    const double *__restrict__ yhat, const double *__restrict__ part,
-    const int32_t *__restrict__ part_ptr, const int32_t *__restrict__ part_idx,
-    const double *__restrict__ yt, const int64_t *__restrict__ perm, int nrhs,
-    double *__restrict__ Y, int64_t ldy) {
-  __shared__ double Ls[kMaxDim][64][kMaxCheb];
-  __shared__ double yh[4096];
-  __shared__ double cu[kMaxCheb], cw[kMaxCheb];
-  const int leaf = blockIdx.x;
-  const int c0 = blockIdx.y * NC;
-  const int tid = threadIdx.x;
-  const int64_t s0 = leaf_off[leaf], m = leaf_off[leaf + 1] - s0;
-  const int i = tid & 63, cg = tid >> 6;
-  constexpr int PER = (NC + 3) / 4;
-  double acc[PER];
-  for (int q = 0; q < PER; ++q) acc[q] = 0.0;
-  for (int e = anc_ptr[leaf]; e < anc_ptr[leaf + 1]; ++e) {
-    const FarCluster c = fc[anc_idx[e]];
-    const int p = c.p, pd = c.pd;
-    __syncthreads();
-    if (tid < p) {
-      cu[tid] = cheb[p * 2 * kMaxCheb + tid];
-      cw[tid] = cheb[p * 2 * kMaxCheb + kMaxCheb + tid];
-    }
-    __syncthreads();
-    if (tid < 64 * d) {
-      int ii = tid & 63, k = tid >> 6;
-      if (ii < m) {
-        double x = pts[k * n + s0 + ii];
-        double z = c.hw[k] > 0 ? (x - c.ctr[k]) / c.hw[k] : 0.0;
-        lagrange_dev(p, cu, cw, z, Ls[k][ii]);
-      }
-    }
-    for (int q = tid; q < pd * NC; q += 256) {
-      int a = q % pd, cc = q / pd;
-      yh[q] = (c0 + cc < nrhs) ? yhat[c.coef_off * nrhs + a + (int64_t)pd * (c0 + cc)] : 0.0;
-    }
-    __syncthreads();
-    if (i < m) {
-      for (int q = 0; q < PER; ++q) {
-        int cc = cg + 4 * q;
-        if (cc >= NC) break;
-        double s = 0;
-        for (int a = 0; a < pd; ++a) {
-          int a0 = a % p, a1 = (a / p) % p, a2 = a / (p * p);
-          double u = Ls[0][i][a0] * Ls[1][i][a1];
-          if (d == 3) u *= Ls[2][i][a2];
-          s = fma(u, yh[a + pd * cc], s);
-        }
-        acc[q] += s;
-      }
-    }
-  }
-  if (i < m) {
-    for (int q = 0; q < PER; ++q) {
-      int cc = cg + 4 * q;
-      if (cc >= NC || c0 + cc >= nrhs) break;
-      double v = acc[q];
-      if (part) {
-        for (int e = part_ptr[leaf]; e < part_ptr[leaf + 1]; ++e) {
-          int code = part_idx[e];
-          v += part[(int64_t)(code >> 1) * 128 + (code & 1) * 64 + i];
-        }
-      } else {
-        v += yt[s0 + i + n * (c0 + cc)];
-      }
-      Y[perm[s0 + i] + ldy * (c0 + cc)] = v;
-    }
-  }
-}
-
 
 // ------------------------------------------------ one-column far field ---
 // Lagrange basis with compile-time bound PM (loops fully unrolled so that L
@@ -637,7 +500,7 @@ __global__ void __launch_bounds__(256) k_up_reduce(const FarCluster *__restrict_
 // part_pair (yhat_s part first, then yhat_t part).
 constexpr int kKTile = 2048;
 
-template <int D>
+template <int D, bool F32>
 __global__ void __launch_bounds__(256) k_couple1(const PairItem *__restrict__ pairs,
                                                  const FarCluster *__restrict__ fc,
                                                  const double *__restrict__ cheb, int kind,
@@ -697,13 +560,7 @@ __global__ void __launch_bounds__(256) k_couple1(const PairItem *__restrict__ pa
             dx = xi_s[k][a] - xb[k];
             t2 = fma(dx, dx, t2);
           }
-          const double t = sqrt_pos(t2);
-          const double ex = exp_nonpos(-t);
-          const double kv = kind == FKF_MATERN_12
-                                ? ex
-                                : (kind == FKF_MATERN_32 ? fma(t, ex, ex)
-                                                         : fma(fma(t, 1.0 / 3.0, 1.0) * t, ex, ex));
-          Kt[rw * pdt + b] = theta * kv;
+          Kt[rw * pdt + b] = kernel_t2<F32>(t2, kind, theta);
         }
       }
     }
@@ -744,7 +601,7 @@ __global__ void __launch_bounds__(256) k_couple1(const PairItem *__restrict__ pa
 // accumulates (K^T xhat_s)[b] in a register and keeps the 64 row terms
 // K[a][b] xhat_t[b]; a butterfly reduce-scatter over the wavefront (63
 // shuffles) leaves (K xhat_t)[l] on lane l.
-template <int D>
+template <int D, bool F32>
 __global__ void __launch_bounds__(256) k_couple_small(const PairItem *__restrict__ pairs,
                                                       int64_t n_pairs,
                                                       const FarCluster *__restrict__ fc,
@@ -799,13 +656,7 @@ __global__ void __launch_bounds__(256) k_couple_small(const PairItem *__restrict
         dx = xi[w][k][a] - xb[k];
         t2 = fma(dx, dx, t2);
       }
-      const double t = sqrt_pos(t2);
-      const double ex = exp_nonpos(-t);
-      double kv = kind == FKF_MATERN_12
-                      ? ex
-                      : (kind == FKF_MATERN_32 ? fma(t, ex, ex)
-                                               : fma(fma(t, 1.0 / 3.0, 1.0) * t, ex, ex));
-      kv = col_ok ? theta * kv : 0.0;
+      double kv = col_ok ? kernel_t2<F32>(t2, kind, theta) : 0.0;
       v[a] = kv * xtb;
       cacc = fma(kv, xsv[w][a], cacc);
     }
@@ -1049,7 +900,7 @@ __global__ void __launch_bounds__(256) k_up_reduce_m(const FarCluster *__restric
 // Couplings: Yhat_s = sum over admissible t of K(xi_s, xi_t) Xhat_t.  The
 // kernel entries are evaluated in registers directly as MFMA A operands; B is
 // a 64-row chunk of Xhat_t staged in LDS.
-template <int D, int NCB, int RBW>
+template <int D, int NCB, int RBW, bool F32>
 __global__ void __launch_bounds__(256) k_couple_mfma(const FarCluster *__restrict__ fc,
                                                      const int32_t *__restrict__ far_ptr,
                                                      const int32_t *__restrict__ far_col,
@@ -1130,13 +981,7 @@ __global__ void __launch_bounds__(256) k_couple_mfma(const FarCluster *__restric
               dx = xa[q][k] - xb[k];
               t2 = fma(dx, dx, t2);
             }
-            const double t = sqrt_pos(t2);
-            const double ex = exp_nonpos(-t);
-            double kv = kind == FKF_MATERN_12
-                            ? ex
-                            : (kind == FKF_MATERN_32 ? fma(t, ex, ex)
-                                                     : fma(fma(t, 1.0 / 3.0, 1.0) * t, ex, ex));
-            kv = (aval[q] && kb < cnt) ? theta * kv : 0.0;
+            double kv = (aval[q] && kb < cnt) ? kernel_t2<F32>(t2, kind, theta) : 0.0;
 #pragma unroll
             for (int j = 0; j < NCB; ++j) acc[q][j] = mfma4(kv, b[j], acc[q][j]);
           }
@@ -1159,9 +1004,9 @@ __global__ void __launch_bounds__(256) k_couple_mfma(const FarCluster *__restric
 
 // Near field + downward pass + scatter for one leaf and NC columns:
 // Y_s = sum_{t near s} Gamma_st X_t + sum_{far ancestors c} U_c|_s Yhat_c.
-template <int D, int NCB>
+template <int D, int NCB, typename TT>
 __global__ void __launch_bounds__(256) k_down_mfma(
-    const double *__restrict__ blk, const int32_t *__restrict__ near_ptr,
+    const TT *__restrict__ blk, const int32_t *__restrict__ near_ptr,
     const int32_t *__restrict__ near_idx, const int32_t *__restrict__ bs,
     const int32_t *__restrict__ bt, const int64_t *__restrict__ leaf_off,
     const double *__restrict__ pts, int64_t n, const double *__restrict__ cheb,
@@ -1192,17 +1037,33 @@ __global__ void __launch_bounds__(256) k_down_mfma(
     const int t = trans ? bs[b] : bt[b];
     const int64_t t0 = leaf_off[t], mt = leaf_off[t + 1] - t0;
     __syncthreads();
-    const v2d *src = reinterpret_cast<const v2d *>(blk + b * 4096);
-    for (int q = tid; q < 2048; q += 256) {
-      int k = q >> 6, lane = q & 63;
-      int i = 8 * (lane & 7) + (k >> 2), j = 8 * (lane >> 3) + 2 * (k & 3);
-      v2d v = src[q];
-      if (!trans) {
-        As[i][j] = v.x;
-        As[i][j + 1] = v.y;
-      } else {
-        As[j][i] = v.x;
-        As[j + 1][i] = v.y;
+    if (sizeof(TT) == 8) {
+      const v2d *src = reinterpret_cast<const v2d *>(blk + b * 4096);
+      for (int q = tid; q < 2048; q += 256) {
+        int k = q >> 6, lane = q & 63;
+        int i = 8 * (lane & 7) + (k >> 2), j = 8 * (lane >> 3) + 2 * (k & 3);
+        v2d v = src[q];
+        if (!trans) {
+          As[i][j] = v.x;
+          As[i][j + 1] = v.y;
+        } else {
+          As[j][i] = v.x;
+          As[j + 1][i] = v.y;
+        }
+      }
+    } else {
+      const float4 *src = reinterpret_cast<const float4 *>(blk + b * 4096);
+      for (int q = tid; q < 1024; q += 256) {
+        int k = q >> 6, lane = q & 63;
+        int i = 8 * (lane & 7) + (k >> 1), j = 8 * (lane >> 3) + 4 * (k & 1);
+        float4 v = src[q];
+        const double vv[4] = {v.x, v.y, v.z, v.w};
+        for (int h = 0; h < 4; ++h) {
+          if (!trans)
+            As[i][j + h] = vv[h];
+          else
+            As[j + h][i] = vv[h];
+        }
       }
     }
     for (int q = tid; q < 64 * NC; q += 256) {
@@ -1308,7 +1169,8 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
                                        hp->cheb_order_max <= kMaxCheb),
                 "fkf_cov_build: cheb_order_max in cheb_order..16");
     FKF_REQUIRE(hp->eta > 0, "fkf_cov_build: eta must be > 0");
-    FKF_REQUIRE(hp->precision == FKF_FP64, "fkf_cov_build: only FP64 precision");
+    FKF_REQUIRE(hp->precision == FKF_FP64 || hp->precision == FKF_MIXED,
+                "fkf_cov_build: unknown precision");
     for (int64_t i = 0; i < n * d; ++i)
       FKF_REQUIRE(std::isfinite(pts_host[i]), "fkf_cov_build: non-finite coordinate");
     hipStream_t st = as_stream(stream);
@@ -1393,11 +1255,20 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
     cov->part_idx.upload(pi, st);
     cov->near_ptr.upload(np_, st);
     cov->near_idx.upload(ni, st);
-    cov->blk.alloc((size_t)cov->n_blk * 4096);
-    if (cov->n_blk > 0)
-      hipLaunchKernelGGL(k_near_assemble, dim3((unsigned)cov->n_blk), dim3(64), 0, st,
-                         cov->pts.p, n, d, cov->leaf_off.p, cov->blk_s.p, cov->blk_t.p,
-                         cov->kind, 1.0 / cov->ell, cov->theta, cov->blk.p);
+    cov->mixed = hp->precision == FKF_MIXED;
+    if (cov->mixed) {
+      cov->blk32.alloc((size_t)cov->n_blk * 4096);
+      if (cov->n_blk > 0)
+        hipLaunchKernelGGL(k_near_assemble32, dim3((unsigned)cov->n_blk), dim3(64), 0, st,
+                           cov->pts.p, n, d, cov->leaf_off.p, cov->blk_s.p, cov->blk_t.p,
+                           cov->kind, 1.0 / cov->ell, cov->theta, cov->blk32.p);
+    } else {
+      cov->blk.alloc((size_t)cov->n_blk * 4096);
+      if (cov->n_blk > 0)
+        hipLaunchKernelGGL(k_near_assemble, dim3((unsigned)cov->n_blk), dim3(64), 0, st,
+                           cov->pts.p, n, d, cov->leaf_off.p, cov->blk_s.p, cov->blk_t.p,
+                           cov->kind, 1.0 / cov->ell, cov->theta, cov->blk.p);
+    }
     FKF_CHECK_HIP(hipGetLastError());
 
     // far clusters
@@ -1545,7 +1416,11 @@ void apply_one(fkf_cov *cov, double *Y, hipStream_t st) {
   FKF_CHECK_HIP(hipStreamWaitEvent(cov->side, cov->ev_fork, 0));
   {
     FKF_TRACE("hmat_near_1rhs", cov->side);
-    if (cov->n_blk)
+    if (cov->n_blk && cov->mixed)
+      hipLaunchKernelGGL(k_near_sym1_32, dim3((unsigned)((cov->n_blk + 3) / 4)), dim3(256), 0,
+                         cov->side, cov->blk32.p, cov->blk_s.p, cov->blk_t.p, cov->leaf_off.p,
+                         cov->xt.p, cov->n_blk, cov->part.p);
+    else if (cov->n_blk)
       hipLaunchKernelGGL(k_near_sym1, dim3((unsigned)((cov->n_blk + 3) / 4)), dim3(256), 0,
                          cov->side, cov->blk.p, cov->blk_s.p, cov->blk_t.p, cov->leaf_off.p,
                          cov->xt.p, cov->n_blk, cov->part.p);
@@ -1573,28 +1448,24 @@ void apply_one(fkf_cov *cov, double *Y, hipStream_t st) {
     {
       FKF_TRACE("hmat_far_couple_1rhs", st);
       const int64_t nl = cov->n_pairs_large, ns = cov->n_pairs - cov->n_pairs_large;
-      if (nl > 0) {
-        if (d3)
-          hipLaunchKernelGGL(k_couple1<3>, dim3((unsigned)nl), dim3(256), 0, st, cov->pairs.p,
-                             cov->fc.p, cov->cheb.p, cov->kind, 1.0 / cov->ell, cov->theta,
-                             cov->xhat.p, cov->part_pair.p);
-        else
-          hipLaunchKernelGGL(k_couple1<2>, dim3((unsigned)nl), dim3(256), 0, st, cov->pairs.p,
-                             cov->fc.p, cov->cheb.p, cov->kind, 1.0 / cov->ell, cov->theta,
-                             cov->xhat.p, cov->part_pair.p);
-      }
-      if (ns > 0) {
-        const PairItem *sp = cov->pairs.p + nl;
-        const unsigned g = (unsigned)((ns + 3) / 4);
-        if (d3)
-          hipLaunchKernelGGL(k_couple_small<3>, dim3(g), dim3(256), 0, st, sp, ns, cov->fc.p,
+      auto launch = [&](auto k1, auto ksmall) {
+        if (nl > 0)
+          hipLaunchKernelGGL(k1, dim3((unsigned)nl), dim3(256), 0, st, cov->pairs.p, cov->fc.p,
                              cov->cheb.p, cov->kind, 1.0 / cov->ell, cov->theta, cov->xhat.p,
                              cov->part_pair.p);
-        else
-          hipLaunchKernelGGL(k_couple_small<2>, dim3(g), dim3(256), 0, st, sp, ns, cov->fc.p,
-                             cov->cheb.p, cov->kind, 1.0 / cov->ell, cov->theta, cov->xhat.p,
-                             cov->part_pair.p);
-      }
+        if (ns > 0)
+          hipLaunchKernelGGL(ksmall, dim3((unsigned)((ns + 3) / 4)), dim3(256), 0, st,
+                             cov->pairs.p + nl, ns, cov->fc.p, cov->cheb.p, cov->kind,
+                             1.0 / cov->ell, cov->theta, cov->xhat.p, cov->part_pair.p);
+      };
+      if (d3 && cov->mixed)
+        launch(k_couple1<3, true>, k_couple_small<3, true>);
+      else if (d3)
+        launch(k_couple1<3, false>, k_couple_small<3, false>);
+      else if (cov->mixed)
+        launch(k_couple1<2, true>, k_couple_small<2, true>);
+      else
+        launch(k_couple1<2, false>, k_couple_small<2, false>);
       hipLaunchKernelGGL(k_couple_reduce, dim3(cov->n_fc), dim3(256), 0, st, cov->fc.p,
                          cov->cp_ptr.p, cov->cp_off.p, cov->part_pair.p, cov->yhat.p);
     }
@@ -1617,7 +1488,7 @@ void apply_one(fkf_cov *cov, double *Y, hipStream_t st) {
 
 // Several columns on the FP64 matrix cores: upward chunks + reduction,
 // couplings per target cluster, then near field + downward + scatter per leaf.
-template <int D, int NCB, int RBW>
+template <int D, int NCB, int RBW, bool F32>
 void apply_multi_t(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t st) {
   constexpr int NC = NCB * 16;
   const int64_t n = cov->n;
@@ -1636,25 +1507,35 @@ void apply_multi_t(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t s
     }
     {
       FKF_TRACE("hmat_far_couple_multi", st);
-      hipLaunchKernelGGL((k_couple_mfma<D, NCB, RBW>), dim3(cov->n_fc, gy), dim3(256), 0, st,
+      hipLaunchKernelGGL((k_couple_mfma<D, NCB, RBW, F32>), dim3(cov->n_fc, gy), dim3(256), 0, st,
                          cov->fc.p, cov->far_ptr.p, cov->far_col.p, cov->cheb.p, cov->kind,
                          1.0 / cov->ell, cov->theta, cov->xhat.p, nrhs, cov->yhat.p);
     }
   }
   FKF_TRACE("hmat_near_down_multi", st);
-  hipLaunchKernelGGL((k_down_mfma<D, NCB>), dim3(cov->n_leaves, gy), dim3(256), 0, st, cov->blk.p,
-                     cov->near_ptr.p, cov->near_idx.p, cov->blk_s.p, cov->blk_t.p,
-                     cov->leaf_off.p, cov->pts.p, n, cov->cheb.p, cov->fc.p, cov->anc_ptr.p,
-                     cov->anc_idx.p, cov->xt.p, cov->yhat.p, cov->perm.p, nrhs, Y, ldy);
+  if (F32)
+    hipLaunchKernelGGL((k_down_mfma<D, NCB, float>), dim3(cov->n_leaves, gy), dim3(256), 0, st,
+                       cov->blk32.p, cov->near_ptr.p, cov->near_idx.p, cov->blk_s.p, cov->blk_t.p,
+                       cov->leaf_off.p, cov->pts.p, n, cov->cheb.p, cov->fc.p, cov->anc_ptr.p,
+                       cov->anc_idx.p, cov->xt.p, cov->yhat.p, cov->perm.p, nrhs, Y, ldy);
+  else
+    hipLaunchKernelGGL((k_down_mfma<D, NCB, double>), dim3(cov->n_leaves, gy), dim3(256), 0, st,
+                       cov->blk.p, cov->near_ptr.p, cov->near_idx.p, cov->blk_s.p, cov->blk_t.p,
+                       cov->leaf_off.p, cov->pts.p, n, cov->cheb.p, cov->fc.p, cov->anc_ptr.p,
+                       cov->anc_idx.p, cov->xt.p, cov->yhat.p, cov->perm.p, nrhs, Y, ldy);
 }
 
 void apply_multi(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t st) {
+  const bool m = cov->mixed;
   if (cov->d == 2)
-    apply_multi_t<2, 4, 4>(cov, nrhs, Y, ldy, st);
+    m ? apply_multi_t<2, 4, 4, true>(cov, nrhs, Y, ldy, st)
+      : apply_multi_t<2, 4, 4, false>(cov, nrhs, Y, ldy, st);
   else if (cov->max_pd <= 256)
-    apply_multi_t<3, 4, 4>(cov, nrhs, Y, ldy, st);
+    m ? apply_multi_t<3, 4, 4, true>(cov, nrhs, Y, ldy, st)
+      : apply_multi_t<3, 4, 4, false>(cov, nrhs, Y, ldy, st);
   else
-    apply_multi_t<3, 1, 16>(cov, nrhs, Y, ldy, st);
+    m ? apply_multi_t<3, 1, 16, true>(cov, nrhs, Y, ldy, st)
+      : apply_multi_t<3, 1, 16, false>(cov, nrhs, Y, ldy, st);
 }
 
 }  // namespace
@@ -1695,7 +1576,7 @@ extern "C" fkf_status fkf_cov_info(const fkf_cov *cov, fkf_cov_info_t *info) {
     info->n_near_blocks = cov->n_blk;
     info->n_near_pairs = cov->n_near_pairs;
     info->n_far_pairs = cov->n_far_pairs;
-    info->near_bytes = cov->n_blk * 4096 * (int64_t)sizeof(double);
+    info->near_bytes = cov->n_blk * 4096 * (int64_t)(cov->mixed ? sizeof(float) : sizeof(double));
     info->far_coef_per_rhs = cov->n_coef;
     for (int l = 0; l < 32 && l < (int)cov->level_p.size(); ++l) info->cheb_p[l] = cov->level_p[l];
     info->covered_entries = cov->covered;
@@ -1724,6 +1605,8 @@ extern "C" fkf_status fkf_cov_plan(const double *pts_host, int64_t n, int32_t d,
     FKF_REQUIRE(hp->leaf_size >= 1 && hp->leaf_size <= kTile, "fkf_cov_plan: leaf_size in 1..64");
     FKF_REQUIRE(hp->cheb_order >= 2 && hp->cheb_order <= kMaxCheb, "fkf_cov_plan: cheb_order");
     FKF_REQUIRE(hp->eta > 0, "fkf_cov_plan: eta must be > 0");
+    FKF_REQUIRE(hp->precision == FKF_FP64 || hp->precision == FKF_MIXED,
+                "fkf_cov_plan: unknown precision");
     Tree t = build_tree(pts_host, n, d, hp->leaf_size);
     std::vector<std::pair<int, int>> near, far;
     partition(t, hp->eta, near, far);
@@ -1745,7 +1628,8 @@ extern "C" fkf_status fkf_cov_plan(const double *pts_host, int64_t n, int32_t d,
     info->n_near_blocks = nb;
     info->n_near_pairs = (int64_t)near.size();
     info->n_far_pairs = (int64_t)far.size();
-    info->near_bytes = nb * 4096 * (int64_t)sizeof(double);
+    info->near_bytes =
+        nb * 4096 * (int64_t)(hp->precision == FKF_MIXED ? sizeof(float) : sizeof(double));
     info->covered_entries = cov;
     for (int l = 0; l < 32 && l < (int)lp.size(); ++l) info->cheb_p[l] = lp[l];
   });
@@ -1753,5 +1637,6 @@ extern "C" fkf_status fkf_cov_plan(const double *pts_host, int64_t n, int32_t d,
 
 namespace fkf {
 double cov_variance(const fkf_cov *cov) { return cov->theta; }
+bool cov_mixed(const fkf_cov *cov) { return cov->mixed; }
 int64_t cov_n(const fkf_cov *cov) { return cov->n; }
 }  // namespace fkf

@@ -64,21 +64,6 @@ __global__ void k_jacobi_init(const double *__restrict__ A, int64_t lda, int n, 
   V[e] = (i == j) ? 1.0 : 0.0;
 }
 
-__global__ void __launch_bounds__(1024) k_frob(const double *__restrict__ A, int64_t len,
-                                               double *__restrict__ out) {
-  __shared__ double red[16];
-  double s = 0;
-  for (int64_t e = threadIdx.x; e < len; e += 1024) s += A[e] * A[e];
-  s = wave_sum(s);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0;
-    for (int w = 0; w < 16; ++w) t += red[w];
-    out[0] = sqrt(t);
-  }
-}
-
 __global__ void k_set_int(int *p, int v) { *p = v; }
 
 // Off-diagonal sum of squares: one workgroup per column (partials), then

@@ -58,6 +58,11 @@ def test_headline_grid_partition_is_the_3x3_leaf_neighbourhood():
     # interior leaves have 9 near neighbours, edges 6, corners 4
     assert info["n_near_pairs"] == 30 * 30 * 9 + 4 * 30 * 6 + 4 * 4
     assert info["n_near_blocks"] == (info["n_near_pairs"] + 1024) // 2
+    assert info["near_bytes"] == info["n_near_blocks"] * 64 * 64 * 8
+    mixed = fkf.plan(wl.points(), nu=wl.nu, length=wl.length, variance=wl.variance,
+                     precision="mixed")
+    assert mixed["near_bytes"] * 2 == info["near_bytes"]
+    assert mixed["cheb_p"] == info["cheb_p"]
 
 
 @pytest.mark.parametrize("shape,nsrc,nrcv", [((32, 32), 8, 8), ((128, 128), 16, 15),
@@ -92,5 +97,7 @@ def test_host_entry_points_reject_bad_arguments():
     with pytest.raises(fkf.FkfError) as e:
         fkf.plan(np.zeros((10, 2)), leaf_size=100)
     assert e.value.name == "FKF_E_ARG"
+    with pytest.raises(ValueError):
+        fkf.plan(np.zeros((10, 2)), precision="bf16")
     with pytest.raises(fkf.FkfError):
         fkf.rays_host((4, 4), np.array([[0.0, 2.0]]), np.array([[1.0, 0.5]]))

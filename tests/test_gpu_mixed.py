@@ -1,0 +1,141 @@
+"""GPU parity of the mixed-precision mode (FP32 near-field storage and
+far-field kernel evaluation, FP32 filter basis, FP64 accumulation and FP64
+eigenproblem / Cholesky / orthogonalisation) against the FP64 oracle.
+
+Bar: the one the mixed mode is held to, 1e-6 relative, for the covariance
+product, the state estimate and the variances; the measured error is printed
+per result.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import direct, kalman, rays
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-6
+REF = os.path.join(os.path.dirname(__file__), "golden", "headline_reference.npz")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _dev(a):
+    import torch
+    a = np.asarray(a, dtype=np.float64)
+    if a.ndim == 1:
+        return torch.from_numpy(a.copy()).cuda()
+    return torch.from_numpy(np.asfortranarray(a).T.copy()).cuda().t()
+
+
+def _host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+CASES = {
+    "exp-32x32": dict(pts=lambda: W.grid_points((32, 32)), nu=0.5, ell=0.3, theta=1.0, leaf=64),
+    "m32-128x128": dict(pts=lambda: W.grid_points((128, 128)), nu=1.5, ell=0.2, theta=1e-4, leaf=64),
+    "m52-jitter-40x31": dict(pts=lambda: W.grid_points((40, 31)) + np.random.default_rng(8).uniform(
+        -0.004, 0.004, (1240, 2)), nu=2.5, ell=0.25, theta=1.0, leaf=48),
+    "exp-3d-16": dict(pts=lambda: W.grid_points((16, 16, 16)), nu=0.5, ell=0.3, theta=1.0, leaf=64),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("nrhs", [1, 40])
+def test_mixed_hmatvec_matches_direct(name, nrhs):
+    import paper_1405_2276_amd as fkf
+    c = CASES[name]
+    pts = c["pts"]()
+    _say(f"[mixed] case={name} nrhs={nrhs} n={len(pts)}")
+    cov = fkf.Cov(pts, nu=c["nu"], length=c["ell"], variance=c["theta"], leaf_size=c["leaf"],
+                  precision="mixed")
+    X = np.random.default_rng(11).standard_normal((len(pts), nrhs))
+    want = direct.cov_matvec(pts, X, c["nu"], c["ell"], c["theta"])
+    got = _host(cov.apply(_dev(X if nrhs > 1 else X[:, 0]))).reshape(want.shape)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    _say(f"[mixed] case={name} nrhs={nrhs} relerr={err:.3e}")
+    assert err <= TOL
+
+
+def test_mixed_storage_and_agreement_with_fp64():
+    import paper_1405_2276_amd as fkf
+    pts = W.grid_points((96, 80))
+    kw = dict(nu=1.5, length=0.15, variance=1.0)
+    c64 = fkf.Cov(pts, **kw)
+    c32 = fkf.Cov(pts, precision="mixed", **kw)
+    i64, i32 = c64.info(), c32.info()
+    assert i32["near_bytes"] * 2 == i64["near_bytes"]
+    assert i32["n_near_pairs"] == i64["n_near_pairs"] and i32["cheb_p"] == i64["cheb_p"]
+    X = _dev(np.random.default_rng(5).standard_normal((len(pts), 7)))
+    a, b = _host(c64.apply(X)), _host(c32.apply(X))
+    err = np.linalg.norm(a - b) / np.linalg.norm(a)
+    _say(f"[mixed] fp64 vs mixed relerr={err:.3e}")
+    assert 0 < err <= TOL
+    # one column of the block product equals the single-column product
+    one = _host(c32.apply(X[:, 3].contiguous()))
+    assert np.linalg.norm(one - b[:, 3]) <= 1e-12 * np.linalg.norm(b[:, 3])
+
+
+def test_mixed_medium_filter_matches_cross_covariance_kf():
+    import paper_1405_2276_amd as fkf
+    wl = W.MEDIUM
+    _say(f"[mixed] medium n={wl.n}")
+    pts = wl.points()
+    cov = fkf.Cov(pts, nu=wl.nu, length=wl.length, variance=wl.variance,
+                  leaf_size=wl.leaf_size, precision="mixed")
+    src, rcv = wl.rays()
+    obs = fkf.Obs.from_rays(wl.shape, src, rcv, wl.noise_var)
+    H = rays.ray_operator(wl.shape, src, rcv)
+    R = np.full(H.shape[0], wl.noise_var)
+    ys = W.observations(wl)
+    P = direct.cross_cov(pts, H, wl.nu, wl.length, wl.variance)
+    ref = kalman.xcov_kf(P, H, R, ys, wl.variance)
+    f = fkf.Filter(cov)
+    worst_s = worst_v = 0.0
+    for k in range(wl.steps):
+        f.step(obs, ys[k])
+        if k in (0, 4, wl.steps - 1):
+            s, v = _host(f.mean()), _host(f.variance())
+            es = np.linalg.norm(s - ref[k]["s"]) / np.linalg.norm(ref[k]["s"])
+            ev = np.max(np.abs(v - ref[k]["var"])) / np.max(np.abs(ref[k]["var"]))
+            worst_s, worst_v = max(worst_s, es), max(worst_v, ev)
+            _say(f"[mixed] medium step={k + 1} state_err={es:.2e} var_err={ev:.2e}")
+    f.status()
+    assert worst_s <= TOL and worst_v <= TOL
+
+
+def test_mixed_headline_matches_oracle_at_sampled_cells():
+    import torch
+    import paper_1405_2276_amd as fkf
+    if not os.path.exists(REF):
+        pytest.skip("reference file not generated")
+    ref = np.load(REF)
+    wl = W.LARGE
+    _say(f"[mixed] headline n={wl.n} steps={wl.steps}")
+    cov = fkf.Cov(wl.points(), nu=wl.nu, length=wl.length, variance=wl.variance,
+                  leaf_size=wl.leaf_size, precision="mixed")
+    src, rcv = wl.rays()
+    obs = fkf.Obs.from_rays(wl.shape, src, rcv, wl.noise_var)
+    ys = torch.from_numpy(W.observations(wl)).cuda()
+    f = fkf.Filter(cov)
+    idx = ref["idx"]
+    check = set(ref["steps"].tolist())
+    for k in range(1, wl.steps + 1):
+        f.step(obs, ys[k - 1])
+        if k in check:
+            s, v = _host(f.mean()), _host(f.variance())
+            es = np.linalg.norm(s[idx] - ref[f"s{k}"]) / np.linalg.norm(ref[f"s{k}"])
+            ev = np.abs(v[idx] - ref[f"v{k}"]).max() / ref[f"v{k}_max"]
+            en = abs(np.linalg.norm(s) - ref[f"s{k}_norm"]) / ref[f"s{k}_norm"]
+            _say(f"[mixed] headline step={k} state err={es:.2e} var err={ev:.2e} "
+                 f"norm err={en:.2e}")
+            assert es <= TOL and ev <= TOL and en <= TOL
+    f.status()
