@@ -91,6 +91,9 @@ typedef struct {
   double eta;             /* admissibility parameter, > 0 */
   double block_tol;       /* per-level block tolerance, or <= 0 */
   int32_t precision;      /* fkf_precision */
+  int32_t far_eval;       /* 0: store the coupling matrices K(xi_s, xi_t) at build when they
+                             take at most 8 GiB (faster one-column products); 1: evaluate
+                             them in every product (no coupling storage) */
 } fkf_hmat_params;
 
 typedef struct {
@@ -112,6 +115,9 @@ typedef struct {
   int64_t far_coef_per_rhs;  /* sum over far clusters of p^dim */
   int32_t cheb_p[32];        /* Chebyshev nodes per dimension at each level */
   int64_t covered_entries;   /* sum of |s|*|t| over all blocks (= n*n for a partition) */
+  int64_t far_bytes;         /* bytes of the stored coupling matrices K(xi_s, xi_t), one per
+                                unordered admissible pair; 0 when they are evaluated on the
+                                fly (kept only up to 8 GiB) */
 } fkf_cov_info_t;
 
 typedef struct fkf_cov fkf_cov;

@@ -50,7 +50,7 @@ class HmatParams(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("leaf_size", ctypes.c_int32),
                 ("cheb_order", ctypes.c_int32), ("cheb_order_max", ctypes.c_int32),
                 ("eta", ctypes.c_double), ("block_tol", ctypes.c_double),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("far_eval", ctypes.c_int32)]
 
 
 class FilterParams(ctypes.Structure):
@@ -63,7 +63,8 @@ class CovInfo(ctypes.Structure):
                 ("n_levels", ctypes.c_int32), ("n_near_blocks", ctypes.c_int64),
                 ("n_near_pairs", ctypes.c_int64), ("n_far_pairs", ctypes.c_int64),
                 ("near_bytes", ctypes.c_int64), ("far_coef_per_rhs", ctypes.c_int64),
-                ("cheb_p", ctypes.c_int32 * 32), ("covered_entries", ctypes.c_int64)]
+                ("cheb_p", ctypes.c_int32 * 32), ("covered_entries", ctypes.c_int64),
+                ("far_bytes", ctypes.c_int64)]
 
 
 def _sig(name, res, args):
@@ -174,14 +175,14 @@ PRECISION = {"fp64": 0, "mixed": 1}
 
 
 def _params(nu, length, variance, leaf_size, cheb_order, cheb_order_max, eta, block_tol,
-            precision="fp64"):
+            precision="fp64", far_eval=False):
     if nu not in MATERN:
         raise ValueError("nu must be 0.5, 1.5 or 2.5")
     if precision not in PRECISION:
         raise ValueError("precision must be 'fp64' or 'mixed'")
     kp = KernelParams(ctypes.sizeof(KernelParams), MATERN[nu], variance, length)
     hp = HmatParams(ctypes.sizeof(HmatParams), leaf_size, cheb_order, cheb_order_max,
-                    eta, block_tol, PRECISION[precision])
+                    eta, block_tol, PRECISION[precision], int(bool(far_eval)))
     return kp, hp
 
 
@@ -192,11 +193,11 @@ def _info_dict(inf: CovInfo) -> dict:
 
 
 def plan(points, nu=1.5, length=0.1, variance=1.0, leaf_size=64, cheb_order=6,
-         cheb_order_max=16, eta=1.5, block_tol=1e-7, precision="fp64") -> dict:
+         cheb_order_max=16, eta=1.5, block_tol=1e-7, precision="fp64", far_eval=False) -> dict:
     """Host-only H-matrix plan (tree, partition, Chebyshev orders); no GPU."""
     pts = np.ascontiguousarray(points, dtype=np.float64)
     kp, hp = _params(nu, length, variance, leaf_size, cheb_order, cheb_order_max, eta, block_tol,
-                     precision)
+                     precision, far_eval)
     inf = CovInfo()
     _check(_lib.fkf_cov_plan(pts.ctypes.data_as(_c_dbl_p), pts.shape[0], pts.shape[1],
                              ctypes.byref(kp), ctypes.byref(hp), ctypes.byref(inf)))
@@ -226,19 +227,20 @@ class Cov:
 
     precision: "fp64", or "mixed" (FP32 near-field storage and far-field kernel
     evaluation, FP64 accumulation; filters built on it stream their basis in
-    FP32)."""
+    FP32).  far_eval: evaluate the far-field coupling matrices in every product
+    instead of storing them at build."""
 
     def __init__(self, points, nu: float = 1.5, length: float = 0.1, variance: float = 1.0,
                  leaf_size: int = 64, cheb_order: int = 6, cheb_order_max: int = 16,
                  eta: float = 1.5, block_tol: float = 1e-7, precision: str = "fp64",
-                 stream=None):
+                 far_eval: bool = False, stream=None):
         pts = np.ascontiguousarray(points, dtype=np.float64)
         if pts.ndim != 2:
             raise ValueError("points must be (N, d)")
         self.n, self.d = pts.shape
         self.nu, self.length, self.variance = nu, length, variance
         kp, hp = _params(nu, length, variance, leaf_size, cheb_order, cheb_order_max, eta,
-                         block_tol, precision)
+                         block_tol, precision, far_eval)
         self.precision = precision
         h = ctypes.c_void_p()
         _check(_lib.fkf_cov_build(pts.ctypes.data_as(_c_dbl_p), self.n, self.d,

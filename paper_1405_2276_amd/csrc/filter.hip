@@ -267,8 +267,12 @@ __global__ void k_to_f32(const double *__restrict__ src, float *__restrict__ dst
 
 // s[i] += sum_seg part[seg][i]
 __global__ void k_seg_add(const double *__restrict__ part, int nseg, int64_t n,
-                          double *__restrict__ s) {
+                          double *__restrict__ s, const int *__restrict__ err,
+                          int *__restrict__ err_mirror) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // one thread mirrors the latched device error flag into pinned host memory
+  // (read by the next host call without a copy of its own)
+  if (err_mirror != nullptr && i == 0) *err_mirror = *err;
   if (i >= n) return;
   double a = 0;
   for (int g = 0; g < nseg; ++g) a += part[(int64_t)g * n + i];
@@ -811,9 +815,8 @@ extern "C" fkf_status fkf_filter_step(fkf_filter *f, const fkf_obs *o, const dou
     {
       int nseg = (nm + kSegCols - 1) / kSegCols;
       hipLaunchKernelGGL(k_seg_add, dim3(blocks(f->n)), dim3(256), 0, st, f->part.p, nseg, f->n,
-                         f->s.p);
+                         f->s.p, f->err.p, f->err_host);
     }
-    FKF_CHECK_HIP(hipMemcpyAsync(f->err_host, f->err.p, sizeof(int), hipMemcpyDeviceToHost, st));
     FKF_CHECK_HIP(hipGetLastError());
     f->alpha = alpha_new;
     f->k += 1;

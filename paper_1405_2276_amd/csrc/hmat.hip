@@ -18,6 +18,7 @@
 #include <cstring>
 #include <memory>
 #include <numeric>
+#include <type_traits>
 
 #include "common.h"
 #include "kernels.h"
@@ -42,12 +43,39 @@ struct UpItem {
   int64_t poff;     // offset of this item's partial in the upward partial buffer
 };
 
-// Unordered admissible pair {s, t} (s < t) with the offset of its partials:
-// [off, off + pd_s) for s, then [off + pd_s, off + pd_s + pd_t) for t.
+// Unordered admissible pair {s, t} (s < t) with the offset of its partials,
+// ncb = ceil(pd_t / 64) vectors of length pd_s for s followed by
+// nrb = ceil(pd_s / 32) vectors of length pd_t for t, and the offset koff of
+// its stored coupling matrix K(xi_s, xi_t) (pd_s x pd_t, row-major) when
+// couplings are stored.
 struct PairItem {
   int32_t s, t;
   int64_t off;
+  int64_t koff;
 };
+
+// Rows of K per coupling sub-block (columns: 64, one per lane).
+constexpr int kRowBlk = 32;
+
+// One kRowBlk x 64 (at most) sub-block (rb, cb) of the couplings of a pair.
+struct CoupleItem {
+  int32_t pair;
+  int16_t rb, cb;
+};
+
+// A sub-block of stored couplings with every offset resolved at build, so a
+// wavefront needs one (scalar) descriptor load before streaming K.
+struct CoupleItemSt {
+  int64_t koff;            // K[r0][c0] in the stored couplings
+  int64_t xs_off, xt_off;  // xhat_s[r0], xhat_t[c0]
+  int64_t ys_off, yt_off;  // row-sum and column-sum outputs in the pair partials
+  int32_t rows, cols, ldk; // sub-block extent, row stride of K (= pd_t)
+  int32_t pad;
+};
+
+// Couplings are stored (evaluated once at build) when they take at most this
+// many bytes; otherwise every product evaluates them again.
+constexpr int64_t kMaxCouplingBytes = int64_t(8) << 30;
 
 }  // namespace fkf
 
@@ -80,7 +108,13 @@ struct fkf_cov {
   fkf::DevBuf<fkf::UpItem> up_items;
   fkf::DevBuf<int32_t> up_ptr;               // items of each far cluster
   fkf::DevBuf<fkf::PairItem> pairs;          // unordered admissible pairs (large first)
-  int64_t n_pairs_large = 0;                 // pairs with a side of more than 64 nodes
+  int64_t n_kst = 0;                         // entries of all coupling matrices
+  fkf::DevBuf<double> kst;                   // stored couplings (FP64 mode)
+  fkf::DevBuf<float> kst32;                  // stored couplings (mixed mode)
+  bool stored = false;
+  fkf::DevBuf<fkf::CoupleItem> citems;       // 64 x 64 coupling sub-blocks
+  fkf::DevBuf<fkf::CoupleItemSt> citems_st;  // the same sub-blocks, stored couplings
+  int64_t n_citems = 0;
   fkf::DevBuf<int32_t> cp_ptr;               // pair partials of each far cluster
   fkf::DevBuf<int64_t> cp_off;
   int64_t n_up_items = 0, n_part_up = 0, n_pairs = 0, n_part_pair = 0;
@@ -478,177 +512,115 @@ __global__ void __launch_bounds__(64) k_up1(const UpItem *__restrict__ items,
 }
 
 // Sum the chunk partials of each far cluster (fixed order).
-__global__ void __launch_bounds__(256) k_up_reduce(const FarCluster *__restrict__ fc,
+__global__ void __launch_bounds__(256) k_up_reduce(const FarCluster *__restrict__ fc, int n_fc,
                                                    const int32_t *__restrict__ item_ptr,
                                                    const UpItem *__restrict__ items,
                                                    const double *__restrict__ part_up,
                                                    double *__restrict__ xhat) {
-  const FarCluster c = fc[blockIdx.x];
-  const int i0 = item_ptr[blockIdx.x], i1 = item_ptr[blockIdx.x + 1];
-  for (int a = threadIdx.x; a < c.pd; a += 256) {
+  // one wavefront per far cluster; the cluster's chunk partials are
+  // consecutive (stride pd), summed in chunk order with the loads of eight
+  // chunks in flight
+  const int c = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (c >= n_fc) return;
+  const int l = threadIdx.x & 63;
+  const FarCluster f = fc[c];
+  const int i0 = item_ptr[c], cnt = item_ptr[c + 1] - i0;
+  const int pd = f.pd;
+  const double *src = part_up + items[i0].poff;
+  for (int a = l; a < pd; a += 64) {
     double s = 0;
-    for (int it = i0; it < i1; ++it) s += part_up[items[it].poff + a];
-    xhat[c.coef_off + a] = s;
+    int k = 0;
+    for (; k + 8 <= cnt; k += 8) {
+      double t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = src[(int64_t)(k + u) * pd + a];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += t[u];
+    }
+    for (; k < cnt; ++k) s += src[(int64_t)k * pd + a];
+    xhat[f.coef_off + a] = s;
   }
 }
 
-// Couplings over unordered admissible pairs {s, t}: every entry of
-// K(xi_s, xi_t) is evaluated once and used for both yhat_s += K xhat_t and
-// yhat_t += K^T xhat_s.  K is produced in LDS row blocks of at most kKTile
-// entries (all threads evaluate, balanced), then the block's row sums
-// (K xhat_t) and column sums (K^T xhat_s) are taken from LDS.  Results go to
-// part_pair (yhat_s part first, then yhat_t part).
-constexpr int kKTile = 2048;
+// Row sums of a 32 x 64 block held as v[a] = term of row a on every lane:
+// afterwards lane l (and l ^ 32) holds the sum over all 64 lanes of row
+// l & 31 in v[0] (a fold of the two half-waves, then a butterfly
+// reduce-scatter, 63 shuffles in all).  A macro, so that v stays in registers.
+#define FKF_ROW_SUMS_32(v, l)                                         \
+  do {                                                                \
+    _Pragma("unroll") for (int i_ = 0; i_ < 32; ++i_) v[i_] += __shfl_xor(v[i_], 32); \
+    _Pragma("unroll") for (int m_ = 16; m_ >= 1; m_ >>= 1) {          \
+      const bool up_ = ((l) & m_) != 0;                               \
+      _Pragma("unroll") for (int i_ = 0; i_ < m_; ++i_) {             \
+        const double keep_ = up_ ? v[i_ + m_] : v[i_];                \
+        const double send_ = up_ ? v[i_] : v[i_ + m_];                \
+        v[i_] = keep_ + __shfl_xor(send_, m_);                        \
+      }                                                               \
+    }                                                                 \
+  } while (0)
 
+// Couplings over unordered admissible pairs {s, t}, evaluated in every
+// product, in sub-blocks of at most 32 x 64 entries of K(xi_s, xi_t) (rows:
+// nodes of s, columns: nodes of t), one wavefront per sub-block and four per
+// workgroup.  Lane b owns column b of the sub-block: it evaluates K[a][b] for
+// every row a, accumulates (K^T xhat_s)[b] in a register and keeps the 32 row
+// terms K[a][b] xhat_t[b], reduced across the wavefront by row_sums_32.
+// Sub-block (rb, cb) writes its row sums into the cb-th partial vector of s
+// and its column sums into the rb-th partial vector of t (every entry of
+// every partial is written by exactly one sub-block).
 template <int D, bool F32>
-__global__ void __launch_bounds__(256) k_couple1(const PairItem *__restrict__ pairs,
-                                                 const FarCluster *__restrict__ fc,
-                                                 const double *__restrict__ cheb, int kind,
-                                                 double inv_ell, double theta,
-                                                 const double *__restrict__ xhat,
-                                                 double *__restrict__ part_pair) {
-  constexpr int PDM = D == 2 ? kMaxCheb * kMaxCheb : 1024;   // max p^D
-  __shared__ double Kt[kKTile];
-  __shared__ double xi_s[D][PDM];                    // nodes of s (scaled by the kernel rate)
-  __shared__ double xs_s[PDM], xs_t[PDM];
-  __shared__ double yt[PDM];
-  const PairItem pr = pairs[blockIdx.x];
-  const FarCluster cs = fc[pr.s], ct = fc[pr.t];
-  const int ps = cs.p, pt = ct.p, pds = cs.pd, pdt = ct.pd;
-  const int tid = threadIdx.x;
-  const double sq = kind == FKF_MATERN_12 ? 1.0 : (kind == FKF_MATERN_32 ? 1.7320508075688772
-                                                                          : 2.2360679774997896);
-  const double scale = sq * inv_ell;   // t = scale * r
-  const double *us = cheb + ps * 2 * kMaxCheb, *ut = cheb + pt * 2 * kMaxCheb;
-  for (int a = tid; a < pds; a += 256) {
-    xs_s[a] = xhat[cs.coef_off + a];
-    int r = a;
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      xi_s[k][a] = scale * (cs.ctr[k] + cs.hw[k] * us[r % ps]);
-      r /= ps;
-    }
-  }
-  for (int c = tid; c < pdt; c += 256) {
-    xs_t[c] = xhat[ct.coef_off + c];
-    yt[c] = 0.0;
-  }
-  __syncthreads();
-  // thread -> fixed column(s) b = bb (+256...), rows rr, rr + nrp, ...
-  const int pdt_c = min(pdt, 256);
-  const int nrp = 256 / pdt_c;
-  const int bb = tid % pdt_c, rr = tid / pdt_c;
-  const bool active = rr < nrp;
-  const int rb = max(1, min(pds, kKTile / pdt));      // rows per LDS block
-  for (int A0 = 0; A0 < pds; A0 += rb) {
-    const int rows = min(rb, pds - A0);
-    if (active) {
-      for (int b = bb; b < pdt; b += 256) {
-        double xb[D];
-        int r = b;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-          xb[k] = scale * (ct.ctr[k] + ct.hw[k] * ut[r % pt]);
-          r /= pt;
-        }
-        for (int rw = rr; rw < rows; rw += nrp) {
-          const int a = A0 + rw;
-          double dx = xi_s[0][a] - xb[0];
-          double t2 = dx * dx;
-#pragma unroll
-          for (int k = 1; k < D; ++k) {
-            dx = xi_s[k][a] - xb[k];
-            t2 = fma(dx, dx, t2);
-          }
-          Kt[rw * pdt + b] = kernel_t2<F32>(t2, kind, theta);
-        }
-      }
-    }
-    __syncthreads();
-    // row sums (K xhat_t)[A0 + r]: four lanes per row, combined by shuffles
-    for (int r0 = 0; r0 < rows; r0 += 64) {
-      const int r = r0 + (tid >> 2), q0 = tid & 3;
-      double s = 0;
-      if (r < rows) {
-        const double *kr = Kt + r * pdt;
-#pragma unroll 4
-        for (int q = q0; q < pdt; q += 4) s = fma(kr[q], xs_t[q], s);
-      }
-      s += __shfl_xor(s, 1);
-      s += __shfl_xor(s, 2);
-      if (r < rows && q0 == 0) part_pair[pr.off + A0 + r] = s;
-    }
-    // column sums (K^T xhat_s)[c], accumulated over row blocks
-    for (int c0 = 0; c0 < pdt; c0 += 64) {
-      const int c = c0 + (tid >> 2), r1 = tid & 3;
-      double s = 0;
-      if (c < pdt) {
-#pragma unroll 4
-        for (int r = r1; r < rows; r += 4) s = fma(Kt[r * pdt + c], xs_s[A0 + r], s);
-      }
-      s += __shfl_xor(s, 1);
-      s += __shfl_xor(s, 2);
-      if (c < pdt && r1 == 0) yt[c] += s;
-    }
-    __syncthreads();
-  }
-  for (int c = tid; c < pdt; c += 256) part_pair[pr.off + pds + c] = yt[c];
-}
-
-// Couplings for pairs whose clusters both have at most 64 nodes (the fine
-// levels, which carry most pairs): one wavefront per pair, four pairs per
-// workgroup.  Lane b owns column b of K: it evaluates K[a][b] for every row a,
-// accumulates (K^T xhat_s)[b] in a register and keeps the 64 row terms
-// K[a][b] xhat_t[b]; a butterfly reduce-scatter over the wavefront (63
-// shuffles) leaves (K xhat_t)[l] on lane l.
-template <int D, bool F32>
-__global__ void __launch_bounds__(256) k_couple_small(const PairItem *__restrict__ pairs,
-                                                      int64_t n_pairs,
-                                                      const FarCluster *__restrict__ fc,
-                                                      const double *__restrict__ cheb, int kind,
-                                                      double inv_ell, double theta,
-                                                      const double *__restrict__ xhat,
-                                                      double *__restrict__ part_pair) {
+__global__ void __launch_bounds__(256) k_couple_blk(const CoupleItem *__restrict__ items,
+                                                    int64_t n_items,
+                                                    const PairItem *__restrict__ pairs,
+                                                    const FarCluster *__restrict__ fc,
+                                                    const double *__restrict__ cheb, int kind,
+                                                    double inv_ell, double theta,
+                                                    const double *__restrict__ xhat,
+                                                    double *__restrict__ part_pair) {
   __shared__ double xi[4][D][64];
   __shared__ double xsv[4][64];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
   const int64_t q = (int64_t)blockIdx.x * 4 + w;
-  if (q >= n_pairs) return;   // whole wavefront leaves together
-  const PairItem pr = pairs[q];
+  if (q >= n_items) return;   // whole wavefront leaves together
+  const CoupleItem it = items[q];
+  const PairItem pr = pairs[it.pair];
   const FarCluster cs = fc[pr.s], ct = fc[pr.t];
   const int ps = cs.p, pt = ct.p, pds = cs.pd, pdt = ct.pd;
+  const int r0 = kRowBlk * it.rb, c0 = 64 * it.cb;
+  const int rows = min(kRowBlk, pds - r0), cols = min(64, pdt - c0);
+  const int ncb = (pdt + 63) >> 6;
   const double sq = kind == FKF_MATERN_12 ? 1.0 : (kind == FKF_MATERN_32 ? 1.7320508075688772
                                                                           : 2.2360679774997896);
   const double scale = sq * inv_ell;
   const double *us = cheb + ps * 2 * kMaxCheb, *ut = cheb + pt * 2 * kMaxCheb;
-  if (l < pds) {
-    int r = l;
+  if (l < rows) {
+    int r = r0 + l;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       xi[w][k][l] = scale * (cs.ctr[k] + cs.hw[k] * us[r % ps]);
       r /= ps;
     }
-    xsv[w][l] = xhat[cs.coef_off + l];
+    xsv[w][l] = xhat[cs.coef_off + r0 + l];
   }
+  const bool col_ok = l < cols;
   double xb[D];
   {
-    int r = l < pdt ? l : 0;
+    int r = col_ok ? c0 + l : 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       xb[k] = scale * (ct.ctr[k] + ct.hw[k] * ut[r % pt]);
       r /= pt;
     }
   }
-  const double xtb = l < pdt ? xhat[ct.coef_off + l] : 0.0;
-  const bool col_ok = l < pdt;
+  const double xtb = col_ok ? xhat[ct.coef_off + c0 + l] : 0.0;
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
-  double v[64];
+  double v[kRowBlk];
   double cacc = 0.0;
 #pragma unroll
-  for (int a = 0; a < 64; ++a) {
+  for (int a = 0; a < kRowBlk; ++a) {
     v[a] = 0.0;
-    if (a < pds) {
+    if (a < rows) {
       double dx = xi[w][0][a] - xb[0];
       double t2 = dx * dx;
 #pragma unroll
@@ -656,38 +628,113 @@ __global__ void __launch_bounds__(256) k_couple_small(const PairItem *__restrict
         dx = xi[w][k][a] - xb[k];
         t2 = fma(dx, dx, t2);
       }
-      double kv = col_ok ? kernel_t2<F32>(t2, kind, theta) : 0.0;
+      const double kv = col_ok ? kernel_t2<F32>(t2, kind, theta) : 0.0;
       v[a] = kv * xtb;
       cacc = fma(kv, xsv[w][a], cacc);
     }
   }
-  // reduce-scatter: after the step with mask m, v[i] holds row i + (bits of l above m)
+  FKF_ROW_SUMS_32(v, l);
+  if (l < rows) part_pair[pr.off + (int64_t)it.cb * pds + r0 + l] = v[0];
+  if (col_ok) part_pair[pr.off + (int64_t)ncb * pds + (int64_t)it.rb * pdt + c0 + l] = cacc;
+}
+
+// Stored-coupling variant of k_couple_blk: the same sub-block product with
+// all offsets taken from one descriptor; the 32 row loads of K are issued
+// together from clamped (in-block) addresses and out-of-block entries are
+// zeroed afterwards.
+template <typename KT>
+__global__ void __launch_bounds__(256) k_couple_st(const CoupleItemSt *__restrict__ items,
+                                                   int64_t n_items, const KT *__restrict__ kst,
+                                                   const double *__restrict__ xhat,
+                                                   double *__restrict__ part_pair) {
+  __shared__ double xsv[4][kRowBlk];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
+  const int64_t q = (int64_t)blockIdx.x * 4 + w;
+  if (q >= n_items) return;   // whole wavefront leaves together
+  const CoupleItemSt it = items[q];
+  const int rows = it.rows, cols = it.cols, ldk = it.ldk;
+  const bool col_ok = l < cols;
+  const KT *src = kst + it.koff + (col_ok ? l : 0);
+  KT kv[kRowBlk];
 #pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    const bool up = (l & m) != 0;
+  for (int a = 0; a < kRowBlk; ++a) kv[a] = src[min(a, rows - 1) * ldk];
+  if (l < kRowBlk) xsv[w][l] = l < rows ? xhat[it.xs_off + l] : 0.0;
+  const double xtb = col_ok ? xhat[it.xt_off + l] : 0.0;
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_wave_barrier();
+  double v[kRowBlk];
+  double cacc = 0.0;
 #pragma unroll
-    for (int i = 0; i < m; ++i) {
-      const double keep = up ? v[i + m] : v[i];
-      const double send = up ? v[i] : v[i + m];
-      v[i] = keep + __shfl_xor(send, m);
-    }
+  for (int a = 0; a < kRowBlk; ++a) {
+    const double k = (a < rows && col_ok) ? (double)kv[a] : 0.0;
+    v[a] = k * xtb;
+    cacc = fma(k, xsv[w][a], cacc);
   }
-  if (l < pds) part_pair[pr.off + l] = v[0];
-  if (col_ok) part_pair[pr.off + pds + l] = cacc;
+  FKF_ROW_SUMS_32(v, l);
+  if (l < rows) part_pair[it.ys_off + l] = v[0];
+  if (col_ok) part_pair[it.yt_off + l] = cacc;
+}
+
+// Build-time evaluation of the coupling matrices K(xi_s, xi_t) of every
+// unordered admissible pair (one workgroup per pair), with the same entry
+// formula as the product kernels.
+template <int D, bool F32>
+__global__ void __launch_bounds__(256) k_couple_store(const PairItem *__restrict__ pairs,
+                                                      const FarCluster *__restrict__ fc,
+                                                      const double *__restrict__ cheb, int kind,
+                                                      double inv_ell, double theta,
+                                                      void *__restrict__ kst) {
+  typedef typename std::conditional<F32, float, double>::type KT;
+  const PairItem pr = pairs[blockIdx.x];
+  const FarCluster cs = fc[pr.s], ct = fc[pr.t];
+  const int ps = cs.p, pt = ct.p, pds = cs.pd, pdt = ct.pd;
+  const double sq = kind == FKF_MATERN_12 ? 1.0 : (kind == FKF_MATERN_32 ? 1.7320508075688772
+                                                                          : 2.2360679774997896);
+  const double scale = sq * inv_ell;
+  const double *us = cheb + ps * 2 * kMaxCheb, *ut = cheb + pt * 2 * kMaxCheb;
+  KT *dst = reinterpret_cast<KT *>(kst) + pr.koff;
+  for (int64_t e = threadIdx.x; e < (int64_t)pds * pdt; e += 256) {
+    int ra = (int)(e / pdt), rb = (int)(e % pdt);
+    double t2 = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const double xa = scale * (cs.ctr[k] + cs.hw[k] * us[ra % ps]);
+      const double xb = scale * (ct.ctr[k] + ct.hw[k] * ut[rb % pt]);
+      ra /= ps;
+      rb /= pt;
+      const double dx = xa - xb;
+      t2 = k == 0 ? dx * dx : fma(dx, dx, t2);
+    }
+    dst[e] = (KT)kernel_t2<F32>(t2, kind, theta);
+  }
 }
 
 // yhat_c = sum of the pair partials that belong to far cluster c (fixed order).
 __global__ void __launch_bounds__(256) k_couple_reduce(const FarCluster *__restrict__ fc,
+                                                       int n_fc,
                                                        const int32_t *__restrict__ cp_ptr,
                                                        const int64_t *__restrict__ cp_off,
                                                        const double *__restrict__ part_pair,
                                                        double *__restrict__ yhat) {
-  const FarCluster c = fc[blockIdx.x];
-  const int e0 = cp_ptr[blockIdx.x], e1 = cp_ptr[blockIdx.x + 1];
-  for (int a = threadIdx.x; a < c.pd; a += 256) {
+  // one wavefront per far cluster, partials summed in list order with eight
+  // loads in flight
+  const int c = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (c >= n_fc) return;
+  const int l = threadIdx.x & 63;
+  const FarCluster f = fc[c];
+  const int e0 = cp_ptr[c], e1 = cp_ptr[c + 1];
+  for (int a = l; a < f.pd; a += 64) {
     double s = 0;
-    for (int e = e0; e < e1; ++e) s += part_pair[cp_off[e] + a];
-    yhat[c.coef_off + a] = s;
+    int e = e0;
+    for (; e + 8 <= e1; e += 8) {
+      double t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = part_pair[cp_off[e + u] + a];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += t[u];
+    }
+    for (; e < e1; ++e) s += part_pair[cp_off[e] + a];
+    yhat[f.coef_off + a] = s;
   }
 }
 
@@ -1171,6 +1218,7 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
     FKF_REQUIRE(hp->eta > 0, "fkf_cov_build: eta must be > 0");
     FKF_REQUIRE(hp->precision == FKF_FP64 || hp->precision == FKF_MIXED,
                 "fkf_cov_build: unknown precision");
+    FKF_REQUIRE(hp->far_eval == 0 || hp->far_eval == 1, "fkf_cov_build: far_eval must be 0 or 1");
     for (int64_t i = 0; i < n * d; ++i)
       FKF_REQUIRE(std::isfinite(pts_host[i]), "fkf_cov_build: non-finite coordinate");
     hipStream_t st = as_stream(stream);
@@ -1274,6 +1322,8 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
     // far clusters
     std::vector<int> fidx(t.nodes.size(), -1);
     std::vector<FarCluster> fcs;
+    std::vector<PairItem> prs;     // unordered admissible pairs
+    std::vector<CoupleItem> cis;   // their coupling sub-blocks
     auto far_id = [&](int node) {
       if (fidx[node] >= 0) return fidx[node];
       const Node &nd = t.nodes[node];
@@ -1356,32 +1406,37 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
       cov->n_part_up_m = poffm;
       cov->up_items_m.upload(upm, st);
       cov->up_ptr_m.upload(uptrm, st);
-      std::vector<PairItem> prs;
       std::vector<std::vector<int64_t>> cpl(cov->n_fc);
-      int64_t off = 0, n_lt = 0, n_gt = 0;
+      int64_t off = 0, n_lt = 0, n_gt = 0, koff = 0;
       for (auto &pr : fpairs) {
         if (pr.first < pr.second) {
           ++n_lt;
+          const int pds = fcs[pr.first].pd, pdt = fcs[pr.second].pd;
+          const int nrb = (pds + kRowBlk - 1) / kRowBlk, ncb = (pdt + 63) / 64;
           PairItem q{};
           q.s = pr.first;
           q.t = pr.second;
           q.off = off;
-          cpl[pr.first].push_back(off);
-          cpl[pr.second].push_back(off + fcs[pr.first].pd);
-          off += fcs[pr.first].pd + fcs[pr.second].pd;
+          q.koff = koff;
+          for (int cb = 0; cb < ncb; ++cb) cpl[pr.first].push_back(off + (int64_t)cb * pds);
+          for (int rb = 0; rb < nrb; ++rb)
+            cpl[pr.second].push_back(off + (int64_t)ncb * pds + (int64_t)rb * pdt);
+          for (int rb = 0; rb < nrb; ++rb)
+            for (int cb = 0; cb < ncb; ++cb)
+              cis.push_back(CoupleItem{(int32_t)prs.size(), (int16_t)rb, (int16_t)cb});
+          off += (int64_t)ncb * pds + (int64_t)nrb * pdt;
+          koff += (int64_t)pds * pdt;
           prs.push_back(q);
         } else {
           ++n_gt;
         }
       }
       if (n_lt != n_gt) throw Error{FKF_E_ARG, "fkf_cov_build: admissible pairs are not symmetric"};
-      std::stable_partition(prs.begin(), prs.end(), [&](const PairItem &q) {
-        return fcs[q.s].pd > 64 || fcs[q.t].pd > 64;
-      });
-      cov->n_pairs_large = 0;
-      for (auto &q : prs) cov->n_pairs_large += (fcs[q.s].pd > 64 || fcs[q.t].pd > 64);
+      cov->n_kst = koff;
       cov->n_pairs = (int64_t)prs.size();
       cov->n_part_pair = off;
+      cov->n_citems = (int64_t)cis.size();
+      cov->citems.upload(cis, st);
       cov->pairs.upload(prs, st);
       std::vector<int32_t> cptr(1, 0);
       std::vector<int64_t> coff;
@@ -1395,6 +1450,45 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
     std::vector<double> ch((kMaxCheb + 1) * 2 * kMaxCheb, 0.0);
     for (int p = 1; p <= kMaxCheb; ++p) cheb_nodes(p, &ch[p * 2 * kMaxCheb], &ch[p * 2 * kMaxCheb + kMaxCheb]);
     cov->cheb.upload(ch, st);
+    const int64_t kbytes = cov->n_kst * (int64_t)(cov->mixed ? sizeof(float) : sizeof(double));
+    if (cov->n_pairs > 0 && kbytes <= kMaxCouplingBytes && hp->far_eval == 0) {
+      void *dst;
+      if (cov->mixed) {
+        cov->kst32.alloc((size_t)cov->n_kst);
+        dst = cov->kst32.p;
+      } else {
+        cov->kst.alloc((size_t)cov->n_kst);
+        dst = cov->kst.p;
+      }
+      auto store = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3((unsigned)cov->n_pairs), dim3(256), 0, st, cov->pairs.p,
+                           cov->fc.p, cov->cheb.p, cov->kind, 1.0 / cov->ell, cov->theta, dst);
+      };
+      if (d == 3)
+        cov->mixed ? store(k_couple_store<3, true>) : store(k_couple_store<3, false>);
+      else
+        cov->mixed ? store(k_couple_store<2, true>) : store(k_couple_store<2, false>);
+      cov->stored = true;
+      std::vector<CoupleItemSt> cst;
+      cst.reserve(cis.size());
+      for (const CoupleItem &ci : cis) {
+        const PairItem &q = prs[ci.pair];
+        const int pds = fcs[q.s].pd, pdt = fcs[q.t].pd;
+        const int ncb = (pdt + 63) / 64;
+        const int r0 = kRowBlk * ci.rb, c0 = 64 * ci.cb;
+        CoupleItemSt e{};
+        e.koff = q.koff + (int64_t)r0 * pdt + c0;
+        e.xs_off = fcs[q.s].coef_off + r0;
+        e.xt_off = fcs[q.t].coef_off + c0;
+        e.ys_off = q.off + (int64_t)ci.cb * pds + r0;
+        e.yt_off = q.off + (int64_t)ncb * pds + (int64_t)ci.rb * pdt + c0;
+        e.rows = std::min(kRowBlk, pds - r0);
+        e.cols = std::min(64, pdt - c0);
+        e.ldk = pdt;
+        cst.push_back(e);
+      }
+      cov->citems_st.upload(cst, st);
+    }
     FKF_CHECK_HIP(hipStreamSynchronize(st));
     *out = cov.release();
   });
@@ -1442,32 +1536,38 @@ void apply_one(fkf_cov *cov, double *Y, hipStream_t st) {
         hipLaunchKernelGGL(k_up1<2>, dim3((unsigned)cov->n_up_items), dim3(64), 0, st,
                            cov->up_items.p, cov->fc.p, cov->pts.p, n, cov->cheb.p, cov->xt.p,
                            cov->part_up.p);
-      hipLaunchKernelGGL(k_up_reduce, dim3(cov->n_fc), dim3(256), 0, st, cov->fc.p, cov->up_ptr.p,
+      hipLaunchKernelGGL(k_up_reduce, dim3((cov->n_fc + 3) / 4), dim3(256), 0, st, cov->fc.p,
+                         cov->n_fc, cov->up_ptr.p,
                          cov->up_items.p, cov->part_up.p, cov->xhat.p);
     }
     {
       FKF_TRACE("hmat_far_couple_1rhs", st);
-      const int64_t nl = cov->n_pairs_large, ns = cov->n_pairs - cov->n_pairs_large;
-      auto launch = [&](auto k1, auto ksmall) {
-        if (nl > 0)
-          hipLaunchKernelGGL(k1, dim3((unsigned)nl), dim3(256), 0, st, cov->pairs.p, cov->fc.p,
-                             cov->cheb.p, cov->kind, 1.0 / cov->ell, cov->theta, cov->xhat.p,
-                             cov->part_pair.p);
-        if (ns > 0)
-          hipLaunchKernelGGL(ksmall, dim3((unsigned)((ns + 3) / 4)), dim3(256), 0, st,
-                             cov->pairs.p + nl, ns, cov->fc.p, cov->cheb.p, cov->kind,
-                             1.0 / cov->ell, cov->theta, cov->xhat.p, cov->part_pair.p);
+      auto launch = [&](auto kern) {
+        if (cov->n_citems > 0)
+          hipLaunchKernelGGL(kern, dim3((unsigned)((cov->n_citems + 3) / 4)), dim3(256), 0, st,
+                           cov->citems.p, cov->n_citems, cov->pairs.p, cov->fc.p, cov->cheb.p,
+                           cov->kind, 1.0 / cov->ell, cov->theta, cov->xhat.p,
+                           cov->part_pair.p);
       };
-      if (d3 && cov->mixed)
-        launch(k_couple1<3, true>, k_couple_small<3, true>);
-      else if (d3)
-        launch(k_couple1<3, false>, k_couple_small<3, false>);
-      else if (cov->mixed)
-        launch(k_couple1<2, true>, k_couple_small<2, true>);
-      else
-        launch(k_couple1<2, false>, k_couple_small<2, false>);
-      hipLaunchKernelGGL(k_couple_reduce, dim3(cov->n_fc), dim3(256), 0, st, cov->fc.p,
-                         cov->cp_ptr.p, cov->cp_off.p, cov->part_pair.p, cov->yhat.p);
+      const unsigned gc = (unsigned)((cov->n_citems + 3) / 4);
+      if (cov->stored && cov->n_citems > 0) {
+        if (cov->mixed)
+          hipLaunchKernelGGL(k_couple_st<float>, dim3(gc), dim3(256), 0, st, cov->citems_st.p,
+                             cov->n_citems, cov->kst32.p, cov->xhat.p, cov->part_pair.p);
+        else
+          hipLaunchKernelGGL(k_couple_st<double>, dim3(gc), dim3(256), 0, st, cov->citems_st.p,
+                             cov->n_citems, cov->kst.p, cov->xhat.p, cov->part_pair.p);
+      } else {
+        const int sel = (d3 ? 2 : 0) + (cov->mixed ? 1 : 0);
+        switch (sel) {
+          case 0: launch(k_couple_blk<2, false>); break;
+          case 1: launch(k_couple_blk<2, true>); break;
+          case 2: launch(k_couple_blk<3, false>); break;
+          default: launch(k_couple_blk<3, true>); break;
+        }
+      }
+      hipLaunchKernelGGL(k_couple_reduce, dim3((cov->n_fc + 3) / 4), dim3(256), 0, st, cov->fc.p,
+                         cov->n_fc, cov->cp_ptr.p, cov->cp_off.p, cov->part_pair.p, cov->yhat.p);
     }
   }
   FKF_CHECK_HIP(hipStreamWaitEvent(st, cov->ev_join, 0));
@@ -1577,6 +1677,8 @@ extern "C" fkf_status fkf_cov_info(const fkf_cov *cov, fkf_cov_info_t *info) {
     info->n_near_pairs = cov->n_near_pairs;
     info->n_far_pairs = cov->n_far_pairs;
     info->near_bytes = cov->n_blk * 4096 * (int64_t)(cov->mixed ? sizeof(float) : sizeof(double));
+    info->far_bytes =
+        cov->stored ? cov->n_kst * (int64_t)(cov->mixed ? sizeof(float) : sizeof(double)) : 0;
     info->far_coef_per_rhs = cov->n_coef;
     for (int l = 0; l < 32 && l < (int)cov->level_p.size(); ++l) info->cheb_p[l] = cov->level_p[l];
     info->covered_entries = cov->covered;
@@ -1607,6 +1709,7 @@ extern "C" fkf_status fkf_cov_plan(const double *pts_host, int64_t n, int32_t d,
     FKF_REQUIRE(hp->eta > 0, "fkf_cov_plan: eta must be > 0");
     FKF_REQUIRE(hp->precision == FKF_FP64 || hp->precision == FKF_MIXED,
                 "fkf_cov_plan: unknown precision");
+    FKF_REQUIRE(hp->far_eval == 0 || hp->far_eval == 1, "fkf_cov_plan: far_eval must be 0 or 1");
     Tree t = build_tree(pts_host, n, d, hp->leaf_size);
     std::vector<std::pair<int, int>> near, far;
     partition(t, hp->eta, near, far);
@@ -1624,7 +1727,20 @@ extern "C" fkf_status fkf_cov_plan(const double *pts_host, int64_t n, int32_t d,
       if (t.nodes[pr.first].leaf <= t.nodes[pr.second].leaf) ++nb;
       cov += t.nodes[pr.first].size() * t.nodes[pr.second].size();
     }
-    for (auto &pr : far) cov += t.nodes[pr.first].size() * t.nodes[pr.second].size();
+    int64_t nk = 0;
+    for (auto &pr : far) {
+      cov += t.nodes[pr.first].size() * t.nodes[pr.second].size();
+      if (pr.first < pr.second) {
+        int64_t a = 1, b = 1;
+        for (int k = 0; k < d; ++k) {
+          a *= lp[t.nodes[pr.first].level];
+          b *= lp[t.nodes[pr.second].level];
+        }
+        nk += a * b;
+      }
+    }
+    const int64_t kb = nk * (int64_t)(hp->precision == FKF_MIXED ? sizeof(float) : sizeof(double));
+    info->far_bytes = (kb <= kMaxCouplingBytes && hp->far_eval == 0) ? kb : 0;
     info->n_near_blocks = nb;
     info->n_near_pairs = (int64_t)near.size();
     info->n_far_pairs = (int64_t)far.size();

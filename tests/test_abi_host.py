@@ -63,6 +63,12 @@ def test_headline_grid_partition_is_the_3x3_leaf_neighbourhood():
                      precision="mixed")
     assert mixed["near_bytes"] * 2 == info["near_bytes"]
     assert mixed["cheb_p"] == info["cheb_p"]
+    # stored couplings: one pd_s x pd_t matrix per unordered admissible pair,
+    # at least the smallest order's p^4 entries per pair
+    assert info["far_bytes"] == 2 * mixed["far_bytes"] > 0
+    assert info["far_bytes"] >= 8 * (info["n_far_pairs"] // 2) * min(info["cheb_p"]) ** 4
+    ev = fkf.plan(wl.points(), nu=wl.nu, length=wl.length, variance=wl.variance, far_eval=True)
+    assert ev["far_bytes"] == 0 and ev["near_bytes"] == info["near_bytes"]
 
 
 @pytest.mark.parametrize("shape,nsrc,nrcv", [((32, 32), 8, 8), ((128, 128), 16, 15),
