@@ -186,13 +186,16 @@ def hmatvec_bench(fkf, torch, cov, info, reps):
     fkf.trace_enable(False)
     del flush
     cold_us = float(np.mean(cold))
-    mv_bytes = info["near_bytes"] + 8 * n + 8 * n + 8 * 2 * n   # near tiles, x, y, coordinates
+    # algorithmic bytes of one product: stored near-field tiles, stored
+    # far-field couplings, x, y and the point coordinates
+    mv_bytes = info["near_bytes"] + info["far_bytes"] + 8 * n + 8 * n + 8 * 2 * n
     near_bytes = info["near_bytes"] + 8 * n
     c_near, ms_near = tr_cold.get("hmat_near_1rhs", (1, float("nan")))
     c_nw, ms_nw = tr_warm.get("hmat_near_1rhs", (1, float("nan")))
     cold_near_us, warm_near_us = ms_near * 1e3 / c_near, ms_nw * 1e3 / c_nw
     return {"cold_us": cold_us, "warm_us": warm_us,
-            "alg_bytes": mv_bytes, "cold_gbs": mv_bytes / cold_us * 1e-3,
+            "alg_bytes": mv_bytes, "near_bytes": info["near_bytes"], "far_bytes": info["far_bytes"],
+            "cold_gbs": mv_bytes / cold_us * 1e-3,
             "warm_gbs": mv_bytes / warm_us * 1e-3,
             "near_kernel_cold_us": cold_near_us, "near_kernel_warm_us": warm_near_us,
             "near_kernel_cold_gbs": near_bytes / cold_near_us * 1e-3,

@@ -34,7 +34,7 @@ struct FarCluster {
 };
 
 // Upward work item: a chunk of <= kUpChunk points of one far cluster.
-constexpr int64_t kUpChunk = 128;
+constexpr int64_t kUpChunk = 256;
 constexpr int64_t kUpChunkM = 1024;   // chunk for the several-column path
 struct UpItem {
   int32_t fc;       // far cluster
@@ -518,7 +518,7 @@ __global__ void __launch_bounds__(256) k_up_reduce(const FarCluster *__restrict_
                                                    const double *__restrict__ part_up,
                                                    double *__restrict__ xhat) {
   // one wavefront per far cluster; the cluster's chunk partials are
-  // consecutive (stride pd), summed in chunk order with the loads of eight
+  // consecutive (stride pd), summed in chunk order with the loads of sixteen
   // chunks in flight
   const int c = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (c >= n_fc) return;
@@ -530,12 +530,12 @@ __global__ void __launch_bounds__(256) k_up_reduce(const FarCluster *__restrict_
   for (int a = l; a < pd; a += 64) {
     double s = 0;
     int k = 0;
-    for (; k + 8 <= cnt; k += 8) {
-      double t[8];
+    for (; k + 16 <= cnt; k += 16) {
+      double t[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) t[u] = src[(int64_t)(k + u) * pd + a];
+      for (int u = 0; u < 16; ++u) t[u] = src[(int64_t)(k + u) * pd + a];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) s += t[u];
+      for (int u = 0; u < 16; ++u) s += t[u];
     }
     for (; k < cnt; ++k) s += src[(int64_t)k * pd + a];
     xhat[f.coef_off + a] = s;
@@ -738,6 +738,30 @@ __global__ void __launch_bounds__(256) k_couple_reduce(const FarCluster *__restr
   }
 }
 
+// Sum, in list order, of the near-field partials of point i of a leaf
+// (entries e0..e1 of part_idx: block * 2 + side); the loads of eight entries
+// are issued together.
+__device__ __forceinline__ double near_partials(const double *__restrict__ part, int e0, int e1,
+                                                const int32_t *__restrict__ part_idx, int i) {
+  double v = 0;
+  int e = e0;
+  for (; e + 8 <= e1; e += 8) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int code = part_idx[e + u];
+      t[u] = part[(int64_t)(code >> 1) * 128 + (code & 1) * 64 + i];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += t[u];
+  }
+  for (; e < e1; ++e) {
+    const int code = part_idx[e];
+    v += part[(int64_t)(code >> 1) * 128 + (code & 1) * 64 + i];
+  }
+  return v;
+}
+
 // Downward pass + near-field partials + scatter, one column.  Four waves split
 // the far ancestors of the leaf; lane i owns point i; the tensor Lagrange
 // contraction is factorised per axis.
@@ -808,10 +832,7 @@ __global__ void __launch_bounds__(256) k_final1(
   __syncthreads();
   if (w == 0 && i < m) {
     double v = wsum[0][i] + wsum[1][i] + wsum[2][i] + wsum[3][i];
-    for (int e = part_ptr[leaf]; e < part_ptr[leaf + 1]; ++e) {
-      int code = part_idx[e];
-      v += part[(int64_t)(code >> 1) * 128 + (code & 1) * 64 + i];
-    }
+    v += near_partials(part, part_ptr[leaf], part_ptr[leaf + 1], part_idx, i);
     Y[perm[s0 + i]] = v;
   }
 }
@@ -829,6 +850,158 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ v4d mfma4(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+
+// Barycentric Lagrange values at p <= 16 Chebyshev nodes (L[a] = 0 for
+// a >= p), with Newton-refined hardware reciprocals in place of divisions.
+__device__ __forceinline__ void lagrange16(int p, const double *__restrict__ u,
+                                           const double *__restrict__ w, double x, double (&L)[16]) {
+  double s = 0;
+  int exact = -1;
+#pragma unroll
+  for (int a = 0; a < 16; ++a) {
+    L[a] = 0.0;
+    if (a < p) {
+      const double dx = x - u[a];
+      if (dx == 0.0) exact = a;
+      const double q = w[a] * rcp_nr(dx == 0.0 ? 1.0 : dx);
+      L[a] = q;
+      s += q;
+    }
+  }
+  if (exact >= 0) {
+#pragma unroll
+    for (int a = 0; a < 16; ++a) L[a] = (a == exact) ? 1.0 : 0.0;
+  } else {
+    const double is = rcp_nr(s);
+#pragma unroll
+    for (int a = 0; a < 16; ++a) L[a] *= is;
+  }
+}
+
+// Upward pass, one column, two dimensions, on the FP64 matrix cores: for one
+// chunk of <= kUpChunk points of a far cluster, Xhat[a0][a1] =
+// sum_i L0_i[a0] (x_i L1_i[a1]) is a 16 x 16 product accumulated over the
+// points four at a time (v_mfma_f64_16x16x4f64).  One wavefront per chunk;
+// lane l evaluates the Lagrange values of point l of each 64-point block
+// into LDS.
+__global__ void __launch_bounds__(64) k_up1_mfma2(const UpItem *__restrict__ items,
+                                                  const FarCluster *__restrict__ fc,
+                                                  const double *__restrict__ pts, int64_t n,
+                                                  const double *__restrict__ cheb,
+                                                  const double *__restrict__ xt,
+                                                  double *__restrict__ part_up) {
+  __shared__ double L0s[64][17], L1s[64][17];
+  const UpItem it = items[blockIdx.x];
+  const FarCluster c = fc[it.fc];
+  const int p = c.p;
+  const int l = threadIdx.x, lr = l & 15, lk = l >> 4;
+  const double *cu = cheb + p * 2 * kMaxCheb;
+  v4d acc = {0, 0, 0, 0};
+  for (int64_t i0 = it.begin; i0 < it.end; i0 += 64) {
+    const int64_t i = i0 + l;
+    double L0[16], L1[16];
+    if (i < it.end) {
+      const double x0 = pts[i], x1 = pts[n + i], xv = xt[i];
+      lagrange16(p, cu, cu + kMaxCheb, c.hw[0] > 0 ? (x0 - c.ctr[0]) / c.hw[0] : 0.0, L0);
+      lagrange16(p, cu, cu + kMaxCheb, c.hw[1] > 0 ? (x1 - c.ctr[1]) / c.hw[1] : 0.0, L1);
+#pragma unroll
+      for (int a = 0; a < 16; ++a) L1[a] *= xv;
+    } else {
+#pragma unroll
+      for (int a = 0; a < 16; ++a) L0[a] = L1[a] = 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 16; ++a) {
+      L0s[l][a] = L0[a];
+      L1s[l][a] = L1[a];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const int k = 4 * kk + lk;
+      acc = mfma4(L0s[k][lr], L1s[k][lr], acc);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int a0 = lk + 4 * r, a1 = lr;
+    if (a0 < p && a1 < p) part_up[it.poff + a0 + p * a1] = acc[r];
+  }
+}
+
+// Downward pass + near-field partials + scatter, one column, two dimensions:
+// for every far ancestor c of the leaf, y_i += L0_i^T Yhat_c L1_i, formed as
+// C = Yhat_c L1^T on the matrix cores (16 points per tile) and contracted
+// with L0 per point.  Four waves split the ancestors; lane l owns point l.
+__global__ void __launch_bounds__(256) k_final1_mfma2(
+    const int64_t *__restrict__ leaf_off, const double *__restrict__ pts, int64_t n,
+    const double *__restrict__ cheb, const FarCluster *__restrict__ fc,
+    const int32_t *__restrict__ anc_ptr, const int32_t *__restrict__ anc_idx,
+    const double *__restrict__ yhat, const double *__restrict__ part,
+    const int32_t *__restrict__ part_ptr, const int32_t *__restrict__ part_idx,
+    const int64_t *__restrict__ perm, double *__restrict__ Y) {
+  __shared__ double L0s[4][64][17], L1s[4][64][17];
+  __shared__ double wsum[4][64];
+  const int leaf = blockIdx.x;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
+  const int64_t s0 = leaf_off[leaf], m = leaf_off[leaf + 1] - s0;
+  double x0 = 0, x1 = 0;
+  if (l < m) {
+    x0 = pts[s0 + l];
+    x1 = pts[n + s0 + l];
+  }
+  double yacc = 0;
+  for (int e = anc_ptr[leaf] + w; e < anc_ptr[leaf + 1]; e += 4) {
+    const FarCluster c = fc[__builtin_amdgcn_readfirstlane(anc_idx[e])];
+    const int p = c.p;
+    const double *cu = cheb + p * 2 * kMaxCheb;
+    const double *yh = yhat + c.coef_off;
+    double L0[16], L1[16];
+    if (l < m) {
+      lagrange16(p, cu, cu + kMaxCheb, c.hw[0] > 0 ? (x0 - c.ctr[0]) / c.hw[0] : 0.0, L0);
+      lagrange16(p, cu, cu + kMaxCheb, c.hw[1] > 0 ? (x1 - c.ctr[1]) / c.hw[1] : 0.0, L1);
+    } else {
+#pragma unroll
+      for (int a = 0; a < 16; ++a) L0[a] = L1[a] = 0.0;
+    }
+    double yv[4];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int a0 = lr, a1 = 4 * kk + lk;
+      yv[kk] = (a0 < p && a1 < p) ? yh[a0 + p * a1] : 0.0;
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int a = 0; a < 16; ++a) {
+      L0s[w][l][a] = L0[a];
+      L1s[w][l][a] = L1[a];
+    }
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): LDS writes done
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt) {
+      v4d acc = {0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) acc = mfma4(yv[kk], L1s[w][16 * jt + lr][4 * kk + lk], acc);
+      double sv = 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sv = fma(L0s[w][16 * jt + lr][lk + 4 * r], acc[r], sv);
+      sv += __shfl_xor(sv, 16);
+      sv += __shfl_xor(sv, 32);
+      if (lk == jt) yacc += sv;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  wsum[w][l] = yacc;
+  __syncthreads();
+  if (w == 0 && l < m) {
+    double v = wsum[0][l] + wsum[1][l] + wsum[2][l] + wsum[3][l];
+    v += near_partials(part, part_ptr[leaf], part_ptr[leaf + 1], part_idx, l);
+    Y[perm[s0 + l]] = v;
+  }
+}
+
 
 // Upward: partial Xhat_c = U_c^T X_c over one chunk of <= kUpChunkM points.
 // A[a][i] = prod_k L_k(x_i)[a_k] is formed from per-point Lagrange values in
@@ -1533,7 +1706,7 @@ void apply_one(fkf_cov *cov, double *Y, hipStream_t st) {
                            cov->up_items.p, cov->fc.p, cov->pts.p, n, cov->cheb.p, cov->xt.p,
                            cov->part_up.p);
       else
-        hipLaunchKernelGGL(k_up1<2>, dim3((unsigned)cov->n_up_items), dim3(64), 0, st,
+        hipLaunchKernelGGL(k_up1_mfma2, dim3((unsigned)cov->n_up_items), dim3(64), 0, st,
                            cov->up_items.p, cov->fc.p, cov->pts.p, n, cov->cheb.p, cov->xt.p,
                            cov->part_up.p);
       hipLaunchKernelGGL(k_up_reduce, dim3((cov->n_fc + 3) / 4), dim3(256), 0, st, cov->fc.p,
@@ -1579,7 +1752,7 @@ void apply_one(fkf_cov *cov, double *Y, hipStream_t st) {
                          cov->yhat.p, cov->part.p, cov->part_ptr.p, cov->part_idx.p, cov->perm.p,
                          Y);
     else
-      hipLaunchKernelGGL(k_final1<2>, dim3(cov->n_leaves), dim3(256), 0, st, cov->leaf_off.p,
+      hipLaunchKernelGGL(k_final1_mfma2, dim3(cov->n_leaves), dim3(256), 0, st, cov->leaf_off.p,
                          cov->pts.p, n, cov->cheb.p, cov->fc.p, cov->anc_ptr.p, cov->anc_idx.p,
                          cov->yhat.p, cov->part.p, cov->part_ptr.p, cov->part_idx.p, cov->perm.p,
                          Y);
