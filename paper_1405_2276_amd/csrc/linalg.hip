@@ -10,14 +10,15 @@
 namespace fkf {
 
 // ===================================================== block Jacobi eigen ===
-// Two-sided block Jacobi.  The padded matrix (np = multiple of 32) is split
-// into nb = np/16 blocks of 16 indices.  A round pairs the blocks by a
-// round-robin tournament; each pair's 32 x 32 principal submatrix gets one
-// cyclic (parallel-ordered) Jacobi sweep in LDS, giving an orthogonal J_k,
-// and then every 32 x 32 tile of A is updated as J_k1^T A J_k2 and V as V J_k.
-// A sweep visits every block pair once; the iteration stops when the
-// off-diagonal Frobenius norm falls below 1e-12 ||A||_F (or nothing rotates).
-// Padding indices carry zero rows/columns and are never rotated.
+// Cyclic two-sided Jacobi in a block-parallel order.  The padded matrix
+// (np = multiple of 32) is split into nb = np/16 blocks of 16 indices.  A
+// round pairs the blocks by a round-robin tournament; in each pair's 32 x 32
+// principal submatrix (in LDS) the rotations of the round are applied,
+// giving an orthogonal J_k, and then every 32 x 32 tile of A is updated as
+// J_k1^T A J_k2 and V as V J_k.  A sweep (nb - 1 rounds) rotates every index
+// pair once; the iteration stops when the off-diagonal Frobenius norm falls
+// below 1e-12 ||A||_F (or a sweep rotates nothing).  Padding indices carry
+// zero rows/columns and are never rotated.
 
 constexpr int kJB = 16;   // block size
 constexpr int kJT = 32;   // tile (pair) size
@@ -31,28 +32,25 @@ __device__ __forceinline__ int pair_index(int k, int i, int round, int nb) {
   return i < kJB ? P * kJB + i : Q * kJB + (i - kJB);
 }
 
+// Rotation (c, s) that annihilates apq in the 2 x 2 symmetric block
+// [app apq; apq aqq]: with zeta = aqq - app and eta = 2 apq,
+// t = sign(zeta) eta / (|zeta| + sqrt(zeta^2 + eta^2)) is the smaller root of
+// t^2 + 2 tau t - 1 = 0 (tau = zeta / eta), c = 1 / sqrt(1 + t^2), s = t c.
+// Branch-free (the skip test selects the identity), so two rotations of one
+// thread are evaluated as independent instruction streams.  Skipped when
+// |apq| <= max(tol_rel sqrt|app aqq|, tol_abs) (compared in squares).
 __device__ __forceinline__ bool jacobi_rotation(double app, double aqq, double apq, double tol_rel,
                                                 double tol_abs, double &c, double &s) {
-  double thr = fmax(tol_rel * sqrt(fabs(app * aqq)), tol_abs);
-  if (!(fabs(apq) > thr)) {
-    c = 1.0;
-    s = 0.0;
-    return false;
-  }
-  // tau = (aqq - app) / (2 apq); t = sign(tau) / (|tau| + sqrt(1 + tau^2)) is the
-  // smaller root of t^2 + 2 tau t - 1 = 0; c = 1/sqrt(1 + t^2), s = t c.
-  double tau = (aqq - app) * rcp_nr(2.0 * apq);
-  double t;
-  if (fabs(tau) > 1e150) {
-    t = 0.5 * rcp_nr(tau);
-  } else {
-    double q = 1.0 + tau * tau;
-    double sq = q * rsq_nr(q);
-    t = (tau >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(tau) + sq);
-  }
-  c = rsq_nr(1.0 + t * t);
-  s = t * c;
-  return true;
+  const double a2 = apq * apq;
+  const bool rot = a2 > tol_rel * tol_rel * fabs(app * aqq) && a2 > tol_abs * tol_abs;
+  const double zeta = aqq - app, eta = 2.0 * apq;
+  const double q = fma(zeta, zeta, eta * eta);
+  const double r = q * rsq_nr(rot ? q : 1.0);
+  const double t = copysign(1.0, zeta) * eta * rcp_nr(rot ? fabs(zeta) + r : 1.0);
+  const double cc = rsq_nr(fma(t, t, 1.0));
+  c = rot ? cc : 1.0;
+  s = rot ? t * cc : 0.0;
+  return rot;
 }
 
 __global__ void k_jacobi_init(const double *__restrict__ A, int64_t lda, int n, int np,
@@ -98,73 +96,84 @@ __global__ void __launch_bounds__(256) k_offnorm_final(const double *__restrict_
   }
 }
 
+// Rotations of one round on the 32 x 32 principal submatrix of block pair k
+// (local indices 0..15: block P, 16..31: block Q).  Every index pair (i, j)
+// of the matrix is rotated exactly once per sweep, so a sweep is one cyclic
+// Jacobi sweep in a block-parallel order: the round visits the 256 cross
+// pairs (i in P, j in Q) in 16 sub-rounds of 16 disjoint rotations (i with
+// 16 + (i + u) mod 16), and the first round of a sweep also visits the pairs
+// within each block beforehand (15 sub-rounds, round-robin within P and Q).
+// The tile is double-buffered in LDS: in a sub-round every thread reads the
+// current tile, computes the two rotations of its 2 x 2 pair block itself
+// and writes its four entries of the next tile; rows of J = prod R are
+// updated in place; one barrier per sub-round.
+__device__ __forceinline__ void sub_round_pair(int u, bool first, int k, int &p, int &q) {
+  if (first && u < kJB - 1) {
+    const int base = k < kJB / 2 ? 0 : kJB, kk = k & (kJB / 2 - 1);
+    p = base + rr_player(kk, u, kJB);
+    q = base + rr_player(kJB - 1 - kk, u, kJB);
+  } else {
+    const int sr = first ? u - (kJB - 1) : u;
+    p = k;
+    q = kJB + ((k + sr) & (kJB - 1));
+  }
+}
+
 __global__ void __launch_bounds__(256) k_jacobi_solve(const double *__restrict__ A, int np, int nb,
                                                       int round, const double *__restrict__ fro,
-                                                      int max_inner, double *__restrict__ Jout,
-                                                      int *cnt) {
-  __shared__ double S[kJT][kJT + 1];
+                                                      double *__restrict__ Jout, int *cnt) {
+  __shared__ double S[2][kJT][kJT + 1];
   __shared__ double Jm[kJT][kJT + 1];
-  __shared__ double rc[kJB], rs[kJB];
-  __shared__ int pp[kJB], qq[kJB], rotp[kJB];
-  __shared__ int rot_sweep, rot_any;
+  __shared__ int rot_any;
   const int k = blockIdx.x, tid = threadIdx.x;
   for (int e = tid; e < kJT * kJT; e += 256) {
     int i = e & 31, j = e >> 5;
     int gi = pair_index(k, i, round, nb), gj = pair_index(k, j, round, nb);
-    S[i][j] = A[gi + (int64_t)np * gj];
+    S[0][i][j] = A[gi + (int64_t)np * gj];
     Jm[i][j] = (i == j) ? 1.0 : 0.0;
   }
   if (tid == 0) rot_any = 0;
   const double tol_abs = 1e-15 * fro[0], tol_rel = 1e-15;
+  const int P1 = tid >> 4, P2 = tid & 15;
+  const int jr = tid >> 4;   // J rows jr and jr + 16, column pair P2
+  const bool first = round == 0;
+  const int nsub = first ? 2 * kJB - 1 : kJB;
+  int cur = 0;
   __syncthreads();
-  for (int sw = 0; sw < max_inner; ++sw) {
-    if (tid == 0) rot_sweep = 0;
-    __syncthreads();
-    for (int ir = 0; ir < kJT - 1; ++ir) {
-      if (tid < kJB) {
-        int p = rr_player(tid, ir, kJT), q = rr_player(kJT - 1 - tid, ir, kJT);
-        double c, s;
-        bool r = jacobi_rotation(S[p][p], S[q][q], S[p][q], tol_rel, tol_abs, c, s);
-        pp[tid] = p;
-        qq[tid] = q;
-        rc[tid] = c;
-        rs[tid] = s;
-        rotp[tid] = r;
-        if (r) rot_sweep = 1;
-      }
-      __syncthreads();
-      {
-        int P1 = tid >> 4, P2 = tid & 15;
-        int p1 = pp[P1], q1 = qq[P1], p2 = pp[P2], q2 = qq[P2];
-        double c1 = rc[P1], s1 = rs[P1], c2 = rc[P2], s2 = rs[P2];
-        double b11 = S[p1][p2], b12 = S[p1][q2], b21 = S[q1][p2], b22 = S[q1][q2];
-        double t11 = c2 * b11 - s2 * b12, t12 = s2 * b11 + c2 * b12;
-        double t21 = c2 * b21 - s2 * b22, t22 = s2 * b21 + c2 * b22;
-        double n11 = c1 * t11 - s1 * t21, n12 = c1 * t12 - s1 * t22;
-        double n21 = s1 * t11 + c1 * t21, n22 = s1 * t12 + c1 * t22;
-        if (P1 == P2 && rotp[P1]) {
-          n12 = 0.0;
-          n21 = 0.0;
-        }
-        S[p1][p2] = n11;
-        S[p1][q2] = n12;
-        S[q1][p2] = n21;
-        S[q1][q2] = n22;
-      }
-      for (int e = tid; e < kJT * kJB; e += 256) {
-        int row = e >> 4, P = e & 15;
-        int p = pp[P], q = qq[P];
-        double c = rc[P], s = rs[P];
-        double jp = Jm[row][p], jq = Jm[row][q];
-        Jm[row][p] = c * jp - s * jq;
-        Jm[row][q] = s * jp + c * jq;
-      }
-      __syncthreads();
+  for (int u = 0; u < nsub; ++u) {
+    int p1, q1, p2, q2;
+    sub_round_pair(u, first, P1, p1, q1);
+    sub_round_pair(u, first, P2, p2, q2);
+    const double a11 = S[cur][p1][p1], a12 = S[cur][q1][q1], a13 = S[cur][p1][q1];
+    const double a21 = S[cur][p2][p2], a22 = S[cur][q2][q2], a23 = S[cur][p2][q2];
+    const double b11 = S[cur][p1][p2], b12 = S[cur][p1][q2];
+    const double b21 = S[cur][q1][p2], b22 = S[cur][q1][q2];
+    double c1, s1, c2, s2;
+    const bool r1 = jacobi_rotation(a11, a12, a13, tol_rel, tol_abs, c1, s1);
+    const bool r2 = jacobi_rotation(a21, a22, a23, tol_rel, tol_abs, c2, s2);
+    if (r2 && P1 == 0) rot_any = 1;
+    const double t11 = c2 * b11 - s2 * b12, t12 = s2 * b11 + c2 * b12;
+    const double t21 = c2 * b21 - s2 * b22, t22 = s2 * b21 + c2 * b22;
+    double n11 = c1 * t11 - s1 * t21, n12 = c1 * t12 - s1 * t22;
+    double n21 = s1 * t11 + c1 * t21, n22 = s1 * t12 + c1 * t22;
+    if (P1 == P2 && r1) {
+      n12 = 0.0;
+      n21 = 0.0;
     }
-    bool any = rot_sweep != 0;
+    const int nx = cur ^ 1;
+    S[nx][p1][p2] = n11;
+    S[nx][p1][q2] = n12;
+    S[nx][q1][p2] = n21;
+    S[nx][q1][q2] = n22;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int row = jr + 16 * h;
+      const double jp = Jm[row][p2], jq = Jm[row][q2];
+      Jm[row][p2] = c2 * jp - s2 * jq;
+      Jm[row][q2] = s2 * jp + c2 * jq;
+    }
+    cur = nx;
     __syncthreads();
-    if (!any) break;
-    if (tid == 0) rot_any = 1;
   }
   double *Jo = Jout + (int64_t)k * kJT * kJT;
   for (int e = tid; e < kJT * kJT; e += 256) {
@@ -174,12 +183,21 @@ __global__ void __launch_bounds__(256) k_jacobi_solve(const double *__restrict__
   if (tid == 0 && rot_any) atomicAdd(cnt, 1);
 }
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Apply the round's rotations: every 32 x 32 tile of A (rows of block pair
+// k1, columns of pair k2) becomes J_k1^T A J_k2, and every 32-row tile of V
+// becomes V J_k2.  Both products run on the FP64 matrix cores, one 16 x 16
+// output quarter per wavefront (v_mfma_f64_16x16x4f64: lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16]; result register r is
+// D[l / 16 + 4 r][l % 16]).
 __global__ void __launch_bounds__(256) k_jacobi_update(double *__restrict__ A, double *__restrict__ V,
                                                        int np, int nb, int round,
                                                        const double *__restrict__ Jbuf) {
   __shared__ double Tl[kJT][kJT + 1];
   __shared__ double J1[kJT][kJT + 1];
   __shared__ double J2[kJT][kJT + 1];
+  __shared__ double Tm[kJT][kJT + 1];
   const int npair = nb / 2;
   const int tilesA = npair * npair;
   int w = blockIdx.x;
@@ -208,35 +226,33 @@ __global__ void __launch_bounds__(256) k_jacobi_update(double *__restrict__ A, d
     J2[i][j] = Jbuf[(int64_t)k2 * kJT * kJT + i + kJT * j];
   }
   __syncthreads();
-  double t[4];
+  const int wv = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
+  const int ti = wv >> 1, tj = wv & 1;   // this wave's 16 x 16 output quarter
+  v4d acc = {0, 0, 0, 0};
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int e = tid + 256 * q, i = e & 31, j = e >> 5;
-    double s = 0;
-#pragma unroll 8
-    for (int m = 0; m < kJT; ++m) s = fma(Tl[i][m], J2[m][j], s);
-    t[q] = s;
-  }
-  __syncthreads();
+  for (int kk = 0; kk < 8; ++kk)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Tl[16 * ti + lr][4 * kk + lk],
+                                               J2[4 * kk + lk][16 * tj + lr], acc, 0, 0, 0);
+  if (!isA) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int e = tid + 256 * q, i = e & 31, j = e >> 5;
-    Tl[i][j] = t[q];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int e = tid + 256 * q, i = e & 31, j = e >> 5;
-    int gj = pair_index(k2, j, round, nb);
-    if (isA) {
-      double s = 0;
-#pragma unroll 8
-      for (int m = 0; m < kJT; ++m) s = fma(J1[m][i], Tl[m][j], s);
-      int gi = pair_index(k1, i, round, nb);
-      A[gi + (int64_t)np * gj] = s;
-    } else {
-      V[rc0 + i + (int64_t)np * gj] = Tl[i][j];
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * ti + lk + 4 * r, j = 16 * tj + lr;
+      V[rc0 + i + (int64_t)np * pair_index(k2, j, round, nb)] = acc[r];
     }
+    return;
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) Tm[16 * ti + lk + 4 * r][16 * tj + lr] = acc[r];
+  __syncthreads();
+  acc = v4d{0, 0, 0, 0};
+#pragma unroll
+  for (int kk = 0; kk < 8; ++kk)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(J1[4 * kk + lk][16 * ti + lr],
+                                               Tm[4 * kk + lk][16 * tj + lr], acc, 0, 0, 0);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = 16 * ti + lk + 4 * r, j = 16 * tj + lr;
+    A[pair_index(k1, i, round, nb) + (int64_t)np * pair_index(k2, j, round, nb)] = acc[r];
   }
 }
 
@@ -293,7 +309,7 @@ int sym_eig(const double *A, int64_t lda, int n, double *w, double *W, int64_t l
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, ws.cnt.p, 0);
     for (int r = 0; r < nb - 1; ++r) {
       hipLaunchKernelGGL(k_jacobi_solve, dim3(npair), dim3(256), 0, st, ws.A.p, np, nb, r,
-                         ws.fro.p, 1, ws.J.p, ws.cnt.p);
+                         ws.fro.p, ws.J.p, ws.cnt.p);
       hipLaunchKernelGGL(k_jacobi_update, dim3(grid_upd), dim3(256), 0, st, ws.A.p, ws.V.p, np, nb,
                          r, ws.J.p);
     }
