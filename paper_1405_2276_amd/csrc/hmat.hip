@@ -1236,10 +1236,14 @@ __global__ void __launch_bounds__(256) k_down_mfma(
     double *__restrict__ Y, int64_t ldy) {
   constexpr int PM = PMax<D>::v;
   constexpr int NC = NCB * 16;
-  __shared__ double As[64][65];
+  // the near tile (near-field phase) and the Lagrange values (far-field
+  // phase) share one LDS region, so that two workgroups fit on a CU
+  static_assert(D * 64 * (PM + 1) <= 64 * 65, "Lagrange table exceeds the shared region");
+  __shared__ double As_raw[64 * 65];
   __shared__ double Bs[64][NC + 1];
-  __shared__ double Ls[D][64][PM + 1];
   __shared__ int32_t aidx[D == 2 ? 256 : 1024];   // packed per-axis node indices
+  double(*As)[65] = reinterpret_cast<double(*)[65]>(As_raw);
+  double(*Ls)[64][PM + 1] = reinterpret_cast<double(*)[64][PM + 1]>(As_raw);
   const int s = blockIdx.x;
   const int c0 = blockIdx.y * NC;
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
