@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--matvec-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
+    ap.add_argument("--varying-steps", type=int, default=4,
+                    help="steps with a new measurement operator each (0: skip)")
     return ap.parse_args()
 
 
@@ -202,6 +204,35 @@ def hmatvec_bench(fkf, torch, cov, info, reps):
             "kernel_us": {k: v[1] * 1e3 / max(v[0], 1) for k, v in tr_cold.items()}}
 
 
+def varying_h(fkf, torch, cov, wl, ys, n_steps=4, rank_rtol=1e-5):
+    """Steps with a new measurement operator every step: the crosswell rays
+    and the same rays with x and y swapped (bottom-to-top), alternating.  Each
+    step runs the cross covariance Gamma H_k^T, the rank update of the
+    low-rank term and the innovation solve.  Returns per-step times (ms) and
+    ranks; the observation vectors are the workload's own (timing only)."""
+    src, rcv = wl.rays()
+    obs = [fkf.Obs.from_rays(wl.shape, src, rcv, wl.noise_var),
+           fkf.Obs.from_rays(wl.shape, np.ascontiguousarray(src[:, ::-1]),
+                             np.ascontiguousarray(rcv[:, ::-1]), wl.noise_var)]
+    st = torch.cuda.current_stream()
+    f = fkf.Filter(cov, rank_rtol=rank_rtol)
+    times, ranks = [], []
+    for k in range(n_steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        f.step(obs[k % 2], ys[k])
+        e1.record(st)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+        ranks.append(f.info()["rank"])
+    f.status()
+    f.close()
+    for o in obs:
+        o.close()
+    return {"step_ms": times, "rank": ranks, "rank_rtol": rank_rtol,
+            "steady_steps_per_s": 1e3 / float(np.mean(times[1:])) if n_steps > 1 else None}
+
+
 def accuracy(wl, res, ref64):
     """Per-result error of a pass: against the oracle's stored values at
     sampled cells (when the workload has them) and against the FP64 GPU form
@@ -268,6 +299,10 @@ def main():
     log(f"[bench] fp64 phases {phases} accuracy {acc64}")
     hmatvec = hmatvec_bench(fkf, torch, cov, info, args.matvec_reps)
     log(f"[bench] hmatvec fp64 {hmatvec}")
+    vary = None
+    if args.varying_steps > 0:
+        vary = varying_h(fkf, torch, cov, wl, ys, args.varying_steps)
+        log(f"[bench] varying-H steps {vary}")
 
     # ---- mixed form (FP32 storage / kernel evaluation, FP64 accumulation)
     mixed = None
@@ -296,11 +331,15 @@ def main():
 
     # ---- roofline of the dominant kernel of the FP64 pass
     per = {k: (c, ms) for k, (c, ms) in trace.items()}
+    # entries of the coupling matrices over all ordered admissible pairs
+    k_entries = 2.0 * info["far_bytes"] / 8.0
     models = {
         # site: (bound, algorithmic units per launch, unit)
         "filter_gemv": ("hbm", 8.0 * n * n_m + 16.0 * n_m, "GB/s"),
         "filter_gemv_sq": ("hbm", 8.0 * n * n_m + 16.0 * n_m, "GB/s"),
-        "hmat_near_multi": ("alu", 2.0 * n_m * info["n_near_pairs"] * 4096, "TFLOP/s"),
+        # far-field couplings of the n_m-column product: one FMA per coupling
+        # entry and column, on the FP64 matrix cores
+        "hmat_far_couple_multi": ("mfma", 2.0 * n_m * k_entries, "TFLOP/s"),
         "gep_basis_gemm": ("alu", 2.0 * n * n_m * n_m, "TFLOP/s"),
     }
     leaf_sites = [k for k in per if k not in ("gep_total", "gep_cross_cov", "filter_step")]
@@ -345,6 +384,7 @@ def main():
             "hmatvec_1rhs": hmatvec,
             "constant_h_step_us": step_us,
             "constant_h_steps_per_s": 1e6 / step_us,
+            "varying_h": vary,
             "phases_ms": phases,
             "errors": acc64,
             "dominant_site": dom,

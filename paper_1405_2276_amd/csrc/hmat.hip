@@ -438,6 +438,35 @@ __device__ __forceinline__ void lagrange_reg(int p, const double *__restrict__ u
   }
 }
 
+// Barycentric Lagrange values at p <= PM Chebyshev nodes (L[a] = 0 for
+// a >= p) with Newton-refined hardware reciprocals in place of divisions.
+template <int PM>
+__device__ __forceinline__ void lagrange_any(int p, const double *__restrict__ u,
+                                             const double *__restrict__ w, double x,
+                                             double (&L)[PM]) {
+  double s = 0;
+  int exact = -1;
+#pragma unroll
+  for (int a = 0; a < PM; ++a) {
+    L[a] = 0.0;
+    if (a < p) {
+      const double dx = x - u[a];
+      if (dx == 0.0) exact = a;
+      const double q = w[a] * rcp_nr(dx == 0.0 ? 1.0 : dx);
+      L[a] = q;
+      s += q;
+    }
+  }
+  if (exact >= 0) {
+#pragma unroll
+    for (int a = 0; a < PM; ++a) L[a] = (a == exact) ? 1.0 : 0.0;
+  } else {
+    const double is = rcp_nr(s);
+#pragma unroll
+    for (int a = 0; a < PM; ++a) L[a] *= is;
+  }
+}
+
 template <int D> struct PMax { static constexpr int v = D == 2 ? kMaxCheb : 10; };
 
 // Upward: one wavefront per chunk of <= kUpChunk points of a far cluster; the
@@ -851,33 +880,6 @@ __device__ __forceinline__ v4d mfma4(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Barycentric Lagrange values at p <= 16 Chebyshev nodes (L[a] = 0 for
-// a >= p), with Newton-refined hardware reciprocals in place of divisions.
-__device__ __forceinline__ void lagrange16(int p, const double *__restrict__ u,
-                                           const double *__restrict__ w, double x, double (&L)[16]) {
-  double s = 0;
-  int exact = -1;
-#pragma unroll
-  for (int a = 0; a < 16; ++a) {
-    L[a] = 0.0;
-    if (a < p) {
-      const double dx = x - u[a];
-      if (dx == 0.0) exact = a;
-      const double q = w[a] * rcp_nr(dx == 0.0 ? 1.0 : dx);
-      L[a] = q;
-      s += q;
-    }
-  }
-  if (exact >= 0) {
-#pragma unroll
-    for (int a = 0; a < 16; ++a) L[a] = (a == exact) ? 1.0 : 0.0;
-  } else {
-    const double is = rcp_nr(s);
-#pragma unroll
-    for (int a = 0; a < 16; ++a) L[a] *= is;
-  }
-}
-
 // Upward pass, one column, two dimensions, on the FP64 matrix cores: for one
 // chunk of <= kUpChunk points of a far cluster, Xhat[a0][a1] =
 // sum_i L0_i[a0] (x_i L1_i[a1]) is a 16 x 16 product accumulated over the
@@ -902,8 +904,8 @@ __global__ void __launch_bounds__(64) k_up1_mfma2(const UpItem *__restrict__ ite
     double L0[16], L1[16];
     if (i < it.end) {
       const double x0 = pts[i], x1 = pts[n + i], xv = xt[i];
-      lagrange16(p, cu, cu + kMaxCheb, c.hw[0] > 0 ? (x0 - c.ctr[0]) / c.hw[0] : 0.0, L0);
-      lagrange16(p, cu, cu + kMaxCheb, c.hw[1] > 0 ? (x1 - c.ctr[1]) / c.hw[1] : 0.0, L1);
+      lagrange_any<16>(p, cu, cu + kMaxCheb, c.hw[0] > 0 ? (x0 - c.ctr[0]) / c.hw[0] : 0.0, L0);
+      lagrange_any<16>(p, cu, cu + kMaxCheb, c.hw[1] > 0 ? (x1 - c.ctr[1]) / c.hw[1] : 0.0, L1);
 #pragma unroll
       for (int a = 0; a < 16; ++a) L1[a] *= xv;
     } else {
@@ -959,8 +961,8 @@ __global__ void __launch_bounds__(256) k_final1_mfma2(
     const double *yh = yhat + c.coef_off;
     double L0[16], L1[16];
     if (l < m) {
-      lagrange16(p, cu, cu + kMaxCheb, c.hw[0] > 0 ? (x0 - c.ctr[0]) / c.hw[0] : 0.0, L0);
-      lagrange16(p, cu, cu + kMaxCheb, c.hw[1] > 0 ? (x1 - c.ctr[1]) / c.hw[1] : 0.0, L1);
+      lagrange_any<16>(p, cu, cu + kMaxCheb, c.hw[0] > 0 ? (x0 - c.ctr[0]) / c.hw[0] : 0.0, L0);
+      lagrange_any<16>(p, cu, cu + kMaxCheb, c.hw[1] > 0 ? (x1 - c.ctr[1]) / c.hw[1] : 0.0, L1);
     } else {
 #pragma unroll
       for (int a = 0; a < 16; ++a) L0[a] = L1[a] = 0.0;
@@ -1046,22 +1048,20 @@ __global__ void __launch_bounds__(256) k_up_mfma(const UpItem *__restrict__ item
   const int nrb = (pd + 15) / 16;
   for (int64_t i0 = it.begin; i0 < it.end; i0 += 64) {
     const int cnt = (int)min((int64_t)64, it.end - i0);
-    if (tid < 64) {
-      const int i = tid;
+    if (tid < D * 64) {
+      // one (axis, point) per thread
+      const int i = tid & 63, k = tid >> 6;
+      double L[PM];
+      if (i < cnt) {
+        double x = pts[k * n + i0 + i];
+        double z = c.hw[k] > 0 ? (x - c.ctr[k]) / c.hw[k] : 0.0;
+        lagrange_any<PM>(p, cu, cu + kMaxCheb, z, L);
+      } else {
 #pragma unroll
-      for (int k = 0; k < D; ++k) {
-        double L[PM];
-        if (i < cnt) {
-          double x = pts[k * n + i0 + i];
-          double z = c.hw[k] > 0 ? (x - c.ctr[k]) / c.hw[k] : 0.0;
-          lagrange_reg<PM>(p, cu, cu + kMaxCheb, z, L);
-        } else {
-#pragma unroll
-          for (int a = 0; a < PM; ++a) L[a] = 0.0;
-        }
-#pragma unroll
-        for (int a = 0; a < PM; ++a) Ls[k][i][a] = L[a];
+        for (int a = 0; a < PM; ++a) L[a] = 0.0;
       }
+#pragma unroll
+      for (int a = 0; a < PM; ++a) Ls[k][i][a] = L[a];
     }
     for (int e = tid; e < 64 * NC; e += 256) {
       int i = e & 63, cc = e >> 6;
@@ -1318,22 +1318,20 @@ __global__ void __launch_bounds__(256) k_down_mfma(
       }
       aidx[a] = code;
     }
-    if (tid < 64) {
-      const int i = tid;
+    if (tid < D * 64) {
+      // one (axis, point) per thread
+      const int i = tid & 63, k = tid >> 6;
+      double L[PM];
+      if (i < ms) {
+        double x = pts[k * n + s0 + i];
+        double z = c.hw[k] > 0 ? (x - c.ctr[k]) / c.hw[k] : 0.0;
+        lagrange_any<PM>(p, cu, cu + kMaxCheb, z, L);
+      } else {
 #pragma unroll
-      for (int k = 0; k < D; ++k) {
-        double L[PM];
-        if (i < ms) {
-          double x = pts[k * n + s0 + i];
-          double z = c.hw[k] > 0 ? (x - c.ctr[k]) / c.hw[k] : 0.0;
-          lagrange_reg<PM>(p, cu, cu + kMaxCheb, z, L);
-        } else {
-#pragma unroll
-          for (int a = 0; a < PM; ++a) L[a] = 0.0;
-        }
-#pragma unroll
-        for (int a = 0; a < PM; ++a) Ls[k][i][a] = L[a];
+        for (int a = 0; a < PM; ++a) L[a] = 0.0;
       }
+#pragma unroll
+      for (int a = 0; a < PM; ++a) Ls[k][i][a] = L[a];
     }
     for (int a0 = 0; a0 < pd; a0 += 64) {
       const int cnt = min(64, pd - a0);
