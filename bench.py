@@ -48,6 +48,12 @@ def parse():
     ap.add_argument("--matvec-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from two counter runs and exit")
+    ap.add_argument("--matvec-only", choices=["fp64", "mixed"],
+                    help="20 one-column products only (for profiler runs)")
+    ap.add_argument("--profile", action="store_true",
+                    help="one FP64 pass and a calibration copy only (for counter runs)")
     ap.add_argument("--varying-steps", type=int, default=4,
                     help="steps with a new measurement operator each (0: skip)")
     return ap.parse_args()
@@ -100,7 +106,8 @@ def cpu_baseline(wl, H, n_panels=4, n_steps=5):
 
 def time_passes(fkf, torch, cov, obs, ys, g, steps_per_pass, warmup, reps):
     """Mean wall time of one hot-path pass over `reps` timed passes, and the
-    per-site trace (HIP events on the launching streams) of those passes."""
+    per-site trace (HIP events on the launching streams) of one further
+    instrumented pass."""
     var_out = torch.empty(cov.n, dtype=torch.float64, device="cuda")
     real_out = fkf.fortran_empty(cov.n, g.shape[1])
 
@@ -115,13 +122,15 @@ def time_passes(fkf, torch, cov, obs, ys, g, steps_per_pass, warmup, reps):
     for _ in range(warmup):
         one_pass()
     torch.cuda.synchronize()
-    fkf.trace_enable(True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
         one_pass()
     torch.cuda.synchronize()
     t_pass = (time.perf_counter() - t0) / reps
+    # one more pass with per-site event timing (not part of the timed region)
+    fkf.trace_enable(True)
+    one_pass()
+    torch.cuda.synchronize()
     trace = fkf.trace_report()
     fkf.trace_enable(False)
     return t_pass, trace
@@ -233,6 +242,84 @@ def varying_h(fkf, torch, cov, wl, ys, n_steps=4, rank_rtol=1e-5):
             "steady_steps_per_s": 1e3 / float(np.mean(times[1:])) if n_steps > 1 else None}
 
 
+# kernel (name prefix in the counter output) -> launch site of the trace
+TRAFFIC_KERNELS = {
+    "fkf::k_jacobi_solve": "eig_jacobi_solve",
+    "fkf::k_jacobi_update": "eig_jacobi_update",
+    "void fkf::k_couple_mfma<2, 4, 4, false>": "hmat_far_couple_multi",
+    "void fkf::k_down_mfma<2, 4, double>": "hmat_near_down_multi",
+    "void fkf::k_up_mfma<2, 4, 4>": "hmat_far_up_multi",
+    "void fkf::k_gemv_seg<false>": "filter_gemv",
+    "fkf::k_gemm_nn": "gep_basis_gemm",
+}
+TRAFFIC_SOURCES = ["paper_1405_2276_amd/csrc/common.h", "paper_1405_2276_amd/csrc/kernels.h",
+                   "paper_1405_2276_amd/csrc/hmat.hip", "paper_1405_2276_amd/csrc/linalg.hip",
+                   "paper_1405_2276_amd/csrc/filter.hip"]
+
+
+def _sources_sha256(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(files):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def write_traffic(fetch_csv, write_csv):
+    """profiles/traffic.json from two counter runs of `bench.py --profile`
+    (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, --output-format csv): the
+    mean KiB per dispatch of each traced kernel, and the factors that map the
+    counters of the calibration copy (2^25 doubles read after a cache flush,
+    2^25 written) onto its true bytes."""
+    import csv
+    sites, calib = {}, {}
+    for path, ctr in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
+        vals = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != ctr:
+                continue
+            name = r["Kernel_Name"]
+            if "AUnaryFunctor" in name and int(r["Grid_Size"]) == (1 << 23):
+                calib[ctr] = float(r["Counter_Value"])
+            for pref, site in TRAFFIC_KERNELS.items():
+                if name.startswith(pref):
+                    vals.setdefault(site, []).append(float(r["Counter_Value"]))
+        for site, v in vals.items():
+            sites.setdefault(site, {})["fetch_kib" if ctr == "FETCH_SIZE" else "write_kib"] = \
+                float(np.mean(v))
+    true_kib = (8 << 25) / 1024.0
+    rec = {"fetch_factor": true_kib / calib["FETCH_SIZE"],
+           "write_factor": true_kib / calib["WRITE_SIZE"],
+           "calibration_kib": {"fetch": calib["FETCH_SIZE"], "write": calib["WRITE_SIZE"],
+                               "true_each_way": true_kib},
+           "sites": sites, "sources": TRAFFIC_SOURCES,
+           "sources_sha256": _sources_sha256(TRAFFIC_SOURCES)}
+    out = os.path.join(ROOT, "profiles", "traffic.json")
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=1, sort_keys=True)
+        fh.write("\n")
+    print(out)
+
+
+def traffic_for(site):
+    """HBM bytes per launch of a kernel site from the committed counter runs
+    (profiles/traffic.json: FETCH_SIZE and WRITE_SIZE per dispatch, scaled by
+    what the counters read for a copy kernel of known size), or None when
+    absent or taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if _sources_sha256(rec.get("sources", [])) != rec.get("sources_sha256"):
+        return None
+    k = rec.get("sites", {}).get(site)
+    if k is None:
+        return None
+    return (k["fetch_kib"] * rec["fetch_factor"] + k["write_kib"] * rec["write_factor"]) * 1024.0
+
+
 def accuracy(wl, res, ref64):
     """Per-result error of a pass: against the oracle's stored values at
     sampled cells (when the workload has them) and against the FP64 GPU form
@@ -262,6 +349,9 @@ def accuracy(wl, res, ref64):
 
 def main():
     args = parse()
+    if args.traffic_from:
+        write_traffic(*args.traffic_from)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -289,6 +379,33 @@ def main():
     ys = torch.from_numpy(W.observations(wl)).to(dev)             # (steps, n_m), resident
     g = fkf.to_device(W.normals(wl, W.STREAM_DRAWS, (wl.n, args.realizations)))
     log(f"[bench] built Gamma in {t_build:.2f} s: {info}")
+    if args.matvec_only:
+        # profiler runs of the one-column product alone: 20 products in the
+        # given precision
+        c = cov if args.matvec_only == "fp64" else fkf.Cov(
+            pts, nu=wl.nu, length=wl.length, variance=wl.variance, leaf_size=wl.leaf_size,
+            precision="mixed")
+        x = torch.randn(wl.n, dtype=torch.float64, device=dev)
+        yv = torch.empty_like(x)
+        for _ in range(20):
+            c.apply(x, out=yv)
+        torch.cuda.synchronize()
+        print(json.dumps({"matvec_only": args.matvec_only, "products": 20}), flush=True)
+        return
+    if args.profile:
+        # counter runs: one FP64 pass and a plain copy of known size whose
+        # FETCH_SIZE / WRITE_SIZE calibrate the counters (2^25 doubles read
+        # from HBM after a cache flush, 2^25 written, by one elementwise kernel)
+        a = torch.ones(1 << 25, dtype=torch.float64, device=dev)
+        flush = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB > Infinity Cache
+        flush.fill_(0.0)
+        b = a * 2.0
+        torch.cuda.synchronize()
+        del flush
+        t_pass, _ = time_passes(fkf, torch, cov, obs, ys, g, wl.steps, 0, 1)
+        print(json.dumps({"profile_pass_ms": t_pass * 1e3, "copy_bytes_each_way": 8 << 25,
+                          "check": float(b[0].item())}), flush=True)
+        return
 
     # ---- FP64 form: the timed passes (the headline value)
     t_pass, trace = time_passes(fkf, torch, cov, obs, ys, g, wl.steps, args.warmup, args.steps)
@@ -326,39 +443,51 @@ def main():
                  "constant_h_step_us": step_us_m, "phases_ms": phases_m,
                  "hmatvec_1rhs": hmv_m, "gamma_build_s": t_build_m,
                  "near_bytes": info_m["near_bytes"], "errors": acc_m,
-                 "sites_ms_per_pass": {k: v[1] / args.steps for k, v in trace_m.items()}}
+                 "sites_ms_per_pass": {k: v[1] for k, v in trace_m.items()}}
         cov_m.close()
 
     # ---- roofline of the dominant kernel of the FP64 pass
     per = {k: (c, ms) for k, (c, ms) in trace.items()}
     # entries of the coupling matrices over all ordered admissible pairs
     k_entries = 2.0 * info["far_bytes"] / 8.0
+    npad = -(-n_m // 32) * 32          # eigensolver: padded order
+    ntile = npad // 32                 # block pairs per round = 32-row tiles per column
     models = {
         # site: (bound, algorithmic units per launch, unit)
         "filter_gemv": ("hbm", 8.0 * n * n_m + 16.0 * n_m, "GB/s"),
         "filter_gemv_sq": ("hbm", 8.0 * n * n_m + 16.0 * n_m, "GB/s"),
-        # far-field couplings of the n_m-column product: one FMA per coupling
-        # entry and column, on the FP64 matrix cores
+        # n_m-column H-matrix product on the FP64 matrix cores, one FMA per
+        # entry and column: couplings of the ordered admissible pairs; the
+        # near-field tiles plus the downward interpolation; the upward one
         "hmat_far_couple_multi": ("mfma", 2.0 * n_m * k_entries, "TFLOP/s"),
+        "hmat_near_down_multi": ("mfma", 2.0 * n_m * (info["n_near_pairs"] * 4096.0
+                                                      + info["far_interp_entries"]), "TFLOP/s"),
+        "hmat_far_up_multi": ("mfma", 2.0 * n_m * info["far_interp_entries"], "TFLOP/s"),
         "gep_basis_gemm": ("alu", 2.0 * n * n_m * n_m, "TFLOP/s"),
+        # Jacobi round: tiles of A become J^T A J and tiles of V become V J
+        # (32 x 32 x 32 products, 2 flops per FMA)
+        "eig_jacobi_update": ("mfma", 2.0 * 32 ** 3 * 3 * ntile ** 2, "TFLOP/s"),
+        # Jacobi round, tile rotations: per sub-round 16 rotations applied to
+        # the rows and columns of a 32 x 32 tile and to J (6 flops per pair of
+        # entries); 16 sub-rounds (31 in the first round of a sweep, counted as 16)
+        "eig_jacobi_solve": ("alu", ntile * 16 * (2 * 32 * 16 * 6 + 32 * 16 * 6), "TFLOP/s"),
     }
-    leaf_sites = [k for k in per if k not in ("gep_total", "gep_cross_cov", "filter_step")]
+    # single-kernel sites (composite sites excluded)
+    leaf_sites = [k for k in per if k not in ("gep_total", "gep_cross_cov", "gep_eig",
+                                               "filter_step")]
     dom = max(leaf_sites, key=lambda k: per[k][1])
-    modelled = [k for k in leaf_sites if k in models]
-    dom_m = max(modelled, key=lambda k: per[k][1]) if modelled else None
     roof = None
-    if dom_m is not None:
-        bound, units, unit = models[dom_m]
-        c, ms = per[dom_m]
+    if dom in models:
+        bound, units, unit = models[dom]
+        c, ms = per[dom]
         avg_s = ms / c * 1e-3
         if unit == "GB/s":
             ach, peak = units / avg_s * 1e-9, HBM_PEAK_GBS
         else:
             ach, peak = units / avg_s * 1e-12, FP64_PEAK_TFLOPS
         roof = {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
-                "traffic": None, "kernel": dom_m, "avg_launch_us": avg_s * 1e6,
-                "launches_per_pass": c / args.steps,
-                "share_of_pass": ms / args.steps / (t_pass * 1e3)}
+                "traffic": traffic_for(dom), "kernel": dom, "avg_launch_us": avg_s * 1e6,
+                "launches_per_pass": c, "share_of_pass": ms / (t_pass * 1e3)}
     result = {
         "metric": METRIC,
         "value": wl.steps / t_pass,
@@ -388,7 +517,7 @@ def main():
             "phases_ms": phases,
             "errors": acc64,
             "dominant_site": dom,
-            "sites_ms_per_pass": {k: v[1] / args.steps for k, v in per.items()},
+            "sites_ms_per_pass": {k: v[1] for k, v in per.items()},
             "gamma_build_s": t_build,
             "mixed": mixed,
             "mixed_vs_fp64_speedup": (t_pass * 1e3 / mixed["pass_ms"]) if mixed else None,

@@ -115,6 +115,8 @@ typedef struct {
   int64_t far_coef_per_rhs;  /* sum over far clusters of p^dim */
   int32_t cheb_p[32];        /* Chebyshev nodes per dimension at each level */
   int64_t covered_entries;   /* sum of |s|*|t| over all blocks (= n*n for a partition) */
+  int64_t far_interp_entries; /* sum over far clusters c of |c| * p_c^dim: interpolation-basis
+                                  entries one upward (or downward) pass touches per column */
   int64_t far_bytes;         /* bytes of the stored coupling matrices K(xi_s, xi_t), one per
                                 unordered admissible pair; 0 when they are evaluated on the
                                 fly (kept only up to 8 GiB) */

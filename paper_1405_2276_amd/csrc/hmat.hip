@@ -89,6 +89,7 @@ struct fkf_cov {
   std::vector<int> level_p;
   int n_leaves = 0;
   int64_t n_blk = 0, n_near_pairs = 0, n_far_pairs = 0, n_coef = 0, covered = 0;
+  int64_t n_interp = 0;   // sum over far clusters of |c| * p^d
   int n_fc = 0;
   int max_pd = 1;
   fkf::DevBuf<int64_t> perm;
@@ -1526,6 +1527,8 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
       cov->max_pd = std::max(cov->max_pd, c.pd);
     }
     cov->n_coef = off;
+    cov->n_interp = 0;
+    for (auto &c : fcs) cov->n_interp += (c.end - c.begin) * (int64_t)c.pd;
     std::vector<std::vector<int32_t>> flist(cov->n_fc);
     for (auto &pr : fpairs) flist[pr.first].push_back(pr.second);
     std::vector<int32_t> fp, fcol;
@@ -1855,6 +1858,7 @@ extern "C" fkf_status fkf_cov_info(const fkf_cov *cov, fkf_cov_info_t *info) {
     info->far_bytes =
         cov->stored ? cov->n_kst * (int64_t)(cov->mixed ? sizeof(float) : sizeof(double)) : 0;
     info->far_coef_per_rhs = cov->n_coef;
+    info->far_interp_entries = cov->n_interp;
     for (int l = 0; l < 32 && l < (int)cov->level_p.size(); ++l) info->cheb_p[l] = cov->level_p[l];
     info->covered_entries = cov->covered;
   });
@@ -1913,6 +1917,20 @@ extern "C" fkf_status fkf_cov_plan(const double *pts_host, int64_t n, int32_t d,
         }
         nk += a * b;
       }
+    }
+    {
+      std::vector<char> is_far(t.nodes.size(), 0);
+      for (auto &pr : far) is_far[pr.first] = is_far[pr.second] = 1;
+      int64_t coef = 0, interp = 0;
+      for (size_t nd = 0; nd < t.nodes.size(); ++nd)
+        if (is_far[nd]) {
+          int64_t pd = 1;
+          for (int k = 0; k < d; ++k) pd *= lp[t.nodes[nd].level];
+          coef += pd;
+          interp += t.nodes[nd].size() * pd;
+        }
+      info->far_coef_per_rhs = coef;
+      info->far_interp_entries = interp;
     }
     const int64_t kb = nk * (int64_t)(hp->precision == FKF_MIXED ? sizeof(float) : sizeof(double));
     info->far_bytes = (kb <= kMaxCouplingBytes && hp->far_eval == 0) ? kb : 0;

@@ -6,6 +6,7 @@
 
 #include "kernels.h"
 #include "linalg.h"
+#include "trace.h"
 
 namespace fkf {
 
@@ -308,10 +309,16 @@ int sym_eig(const double *A, int64_t lda, int n, double *w, double *W, int64_t l
   for (int sw = 0; sw < 40; ++sw) {
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, ws.cnt.p, 0);
     for (int r = 0; r < nb - 1; ++r) {
-      hipLaunchKernelGGL(k_jacobi_solve, dim3(npair), dim3(256), 0, st, ws.A.p, np, nb, r,
-                         ws.fro.p, ws.J.p, ws.cnt.p);
-      hipLaunchKernelGGL(k_jacobi_update, dim3(grid_upd), dim3(256), 0, st, ws.A.p, ws.V.p, np, nb,
-                         r, ws.J.p);
+      {
+        FKF_TRACE("eig_jacobi_solve", st);
+        hipLaunchKernelGGL(k_jacobi_solve, dim3(npair), dim3(256), 0, st, ws.A.p, np, nb, r,
+                           ws.fro.p, ws.J.p, ws.cnt.p);
+      }
+      {
+        FKF_TRACE("eig_jacobi_update", st);
+        hipLaunchKernelGGL(k_jacobi_update, dim3(grid_upd), dim3(256), 0, st, ws.A.p, ws.V.p, np,
+                           nb, r, ws.J.p);
+      }
     }
     hipLaunchKernelGGL(k_offnorm_cols, dim3(np), dim3(256), 0, st, ws.A.p, np, ws.fro.p + 2, 0);
     hipLaunchKernelGGL(k_offnorm_final, dim3(1), dim3(256), 0, st, ws.fro.p + 2, np, ws.fro.p,
