@@ -244,8 +244,7 @@ def varying_h(fkf, torch, cov, wl, ys, n_steps=4, rank_rtol=1e-5):
 
 # kernel (name prefix in the counter output) -> launch site of the trace
 TRAFFIC_KERNELS = {
-    "fkf::k_jacobi_solve": "eig_jacobi_solve",
-    "fkf::k_jacobi_update": "eig_jacobi_update",
+    "fkf::k_jacobi_round": "eig_jacobi_round",
     "void fkf::k_couple_mfma<2, 4, 4, false>": "hmat_far_couple_multi",
     "void fkf::k_down_mfma<2, 4, double>": "hmat_near_down_multi",
     "void fkf::k_up_mfma<2, 4, 4>": "hmat_far_up_multi",
@@ -464,13 +463,14 @@ def main():
                                                       + info["far_interp_entries"]), "TFLOP/s"),
         "hmat_far_up_multi": ("mfma", 2.0 * n_m * info["far_interp_entries"], "TFLOP/s"),
         "gep_basis_gemm": ("alu", 2.0 * n * n_m * n_m, "TFLOP/s"),
-        # Jacobi round: tiles of A become J^T A J and tiles of V become V J
-        # (32 x 32 x 32 products, 2 flops per FMA)
-        "eig_jacobi_update": ("mfma", 2.0 * 32 ** 3 * 3 * ntile ** 2, "TFLOP/s"),
-        # Jacobi round, tile rotations: per sub-round 16 rotations applied to
-        # the rows and columns of a 32 x 32 tile and to J (6 flops per pair of
-        # entries); 16 sub-rounds (31 in the first round of a sweep, counted as 16)
-        "eig_jacobi_solve": ("alu", ntile * 16 * (2 * 32 * 16 * 6 + 32 * 16 * 6), "TFLOP/s"),
+        # Jacobi round (one launch): the update part turns every 32 x 32 tile
+        # of A into J^T A J and every tile of V into V J (3 tile products per
+        # tile pair), the solve part forms its 15 pair tiles as J'^T A' J'
+        # (4 blocks of 16 x 32 x 32 + 16 x 16 x 32 each); 2 flops per FMA.
+        # The rotations themselves (~2.4 MFLOP) are not counted.
+        "eig_jacobi_round": ("mfma", 2.0 * (3 * ntile ** 2 * 32 ** 3
+                                            + ntile * 4 * (16 * 32 * 32 + 16 * 16 * 32)),
+                             "TFLOP/s"),
     }
     # single-kernel sites (composite sites excluded)
     leaf_sites = [k for k in per if k not in ("gep_total", "gep_cross_cov", "gep_eig",

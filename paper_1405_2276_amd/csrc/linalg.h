@@ -7,9 +7,12 @@ namespace fkf {
 
 // Workspace of the symmetric eigensolver (grown on demand).
 struct EigWork {
-  DevBuf<double> A, V, J, fro;
+  DevBuf<double> A, A2, V, J, J2, fro;   // A, J double-buffered across rounds
   DevBuf<int> cnt;
-  int *cnt_host = nullptr;   // pinned host scratch (8 bytes)
+  DevBuf<int32_t> pidx;       // pair index table of the rounds
+  int pidx_np = -1;
+  int *cnt_host = nullptr;   // pinned host scratch (4 ints; [2]: convergence flag)
+  hipEvent_t ev = nullptr;   // marks the convergence test of the last sweep
   ~EigWork();
 };
 

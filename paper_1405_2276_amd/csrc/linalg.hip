@@ -3,6 +3,7 @@
 // Gram matrix and its eigen-decomposition (the projected eigenproblem of the
 // generalized eigenvalue problem, Section 2.2.2), and tall GEMMs.
 #include <algorithm>
+#include <vector>
 
 #include "kernels.h"
 #include "linalg.h"
@@ -33,24 +34,34 @@ __device__ __forceinline__ int pair_index(int k, int i, int round, int nb) {
   return i < kJB ? P * kJB + i : Q * kJB + (i - kJB);
 }
 
-// Rotation (c, s) that annihilates apq in the 2 x 2 symmetric block
-// [app apq; apq aqq]: with zeta = aqq - app and eta = 2 apq,
-// t = sign(zeta) eta / (|zeta| + sqrt(zeta^2 + eta^2)) is the smaller root of
-// t^2 + 2 tau t - 1 = 0 (tau = zeta / eta), c = 1 / sqrt(1 + t^2), s = t c.
-// Branch-free (the skip test selects the identity), so two rotations of one
-// thread are evaluated as independent instruction streams.  Skipped when
+// Rotation (c, s) for the 2 x 2 symmetric block [app apq; apq aqq]: with
+// zeta = aqq - app and eta = 2 apq, t = sign(zeta) eta / (|zeta| + sqrt(zeta^2
+// + eta^2)) is the smaller root of t^2 + 2 tau t - 1 = 0 (tau = zeta / eta).
+// The angle is evaluated in FP32 on (zeta, eta) scaled to [-1, 1] (a short
+// dependency chain of single-precision operations); c = 1 / sqrt(1 + t^2)
+// (FP32 seed and two FP64 Newton steps) and s = t c make the applied rotation
+// orthogonal to FP64 rounding, so the entry apq is reduced by the angle's
+// relative error (~1e-7) rather than zeroed, and the next sweep removes the
+// remainder.  Branch-free; skipped (identity) when
 // |apq| <= max(tol_rel sqrt|app aqq|, tol_abs) (compared in squares).
 __device__ __forceinline__ bool jacobi_rotation(double app, double aqq, double apq, double tol_rel,
                                                 double tol_abs, double &c, double &s) {
   const double a2 = apq * apq;
   const bool rot = a2 > tol_rel * tol_rel * fabs(app * aqq) && a2 > tol_abs * tol_abs;
-  const double zeta = aqq - app, eta = 2.0 * apq;
-  const double q = fma(zeta, zeta, eta * eta);
-  const double r = q * rsq_nr(rot ? q : 1.0);
-  const double t = copysign(1.0, zeta) * eta * rcp_nr(rot ? fabs(zeta) + r : 1.0);
-  const double cc = rsq_nr(fma(t, t, 1.0));
-  c = rot ? cc : 1.0;
-  s = rot ? t * cc : 0.0;
+  const float z = (float)(aqq - app), e = (float)(2.0 * apq);
+  const float m = fmaxf(fabsf(z), fabsf(e));
+  const float sc = __builtin_amdgcn_rcpf(rot ? m : 1.0f);
+  const float zs = z * sc, es = e * sc;
+  const float r = __fsqrt_rn(fmaf(zs, zs, es * es));
+  const float tf = copysignf(1.0f, zs) * es * __builtin_amdgcn_rcpf(rot ? fabsf(zs) + r : 1.0f);
+  const double t = (double)tf;
+  const double q = fma(t, t, 1.0);
+  double y = (double)__builtin_amdgcn_rsqf((float)q);
+  const double h = 0.5 * q;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  c = rot ? y : 1.0;
+  s = rot ? t * y : 0.0;
   return rot;
 }
 
@@ -64,6 +75,15 @@ __global__ void k_jacobi_init(const double *__restrict__ A, int64_t lda, int n, 
 }
 
 __global__ void k_set_int(int *p, int v) { *p = v; }
+
+// Convergence flag of a sweep: relative off-diagonal norm <= tol, or no
+// workgroup rotated anything.
+__global__ void k_eig_converged(const double *__restrict__ rel_off, const int *__restrict__ cnt,
+                                double tol, int *__restrict__ done, int *__restrict__ done_host) {
+  const int d = (rel_off[0] <= tol || cnt[0] == 0) ? 1 : 0;
+  done[0] = d;
+  done_host[0] = d;
+}
 
 // Off-diagonal sum of squares: one workgroup per column (partials), then
 // off[0] = sqrt(sum of partials) / fro in a fixed order.
@@ -97,6 +117,31 @@ __global__ void __launch_bounds__(256) k_offnorm_final(const double *__restrict_
   }
 }
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Position of block B in the pairing of round r: pair index k and half h
+// (0: first block of the pair, 1: second).  Inverse of rr_player.
+__device__ __forceinline__ void block_slot(int B, int r, int nb, int &k, int &h) {
+  if (B == 0) {
+    k = 0;
+    h = 0;
+    return;
+  }
+  const int m = nb - 1;
+  const int pos = ((B - 1 - r) % m + m) % m + 1;
+  if (pos < nb / 2) {
+    k = pos;
+    h = 0;
+  } else {
+    k = nb - 1 - pos;
+    h = 1;
+  }
+}
+
 // Rotations of one round on the 32 x 32 principal submatrix of block pair k
 // (local indices 0..15: block P, 16..31: block Q).  Every index pair (i, j)
 // of the matrix is rotated exactly once per sweep, so a sweep is one cyclic
@@ -104,10 +149,6 @@ __global__ void __launch_bounds__(256) k_offnorm_final(const double *__restrict_
 // pairs (i in P, j in Q) in 16 sub-rounds of 16 disjoint rotations (i with
 // 16 + (i + u) mod 16), and the first round of a sweep also visits the pairs
 // within each block beforehand (15 sub-rounds, round-robin within P and Q).
-// The tile is double-buffered in LDS: in a sub-round every thread reads the
-// current tile, computes the two rotations of its 2 x 2 pair block itself
-// and writes its four entries of the next tile; rows of J = prod R are
-// updated in place; one barrier per sub-round.
 __device__ __forceinline__ void sub_round_pair(int u, bool first, int k, int &p, int &q) {
   if (first && u < kJB - 1) {
     const int base = k < kJB / 2 ? 0 : kJB, kk = k & (kJB / 2 - 1);
@@ -120,52 +161,126 @@ __device__ __forceinline__ void sub_round_pair(int u, bool first, int k, int &p,
   }
 }
 
-__global__ void __launch_bounds__(256) k_jacobi_solve(const double *__restrict__ A, int np, int nb,
-                                                      int round, const double *__restrict__ fro,
-                                                      double *__restrict__ Jout, int *cnt) {
-  __shared__ double S[2][kJT][kJT + 1];
-  __shared__ double Jm[kJT][kJT + 1];
+constexpr int kTS = kJT * (kJT + 1);   // doubles in one padded 32 x 32 LDS tile
+// LDS of a round: solve part = 2 tiles + J (rotation phase), or 4 products
+// M (32 x 16) over tiles 1-2, 4 tiles of A and 2 halves of J' (formation);
+// update part = 4 tiles
+constexpr int kRoundSmem = 7 * kTS + 2 * kJT * 17;
+
+// Solve part of a round (one workgroup per block pair k of round r).  The
+// pair's tile is either read from A (no rotations pending) or formed from the
+// previous round's state: with the previous round's rotations J' pending,
+// block (X, Y) of the tile is J'_X^T A'[X', Y'] J'_Y, where X' is the previous
+// pair tile holding block X and J'_X its 16 columns for X; each wave forms one
+// of the four 16 x 16 blocks on the FP64 matrix cores.  Then the rotations of
+// the round: the tile is double-buffered in LDS; in a sub-round every thread
+// reads the current tile, computes the two rotations of its 2 x 2 pair block
+// itself (branch-free) and writes its four entries of the next tile; rows of
+// J = prod R are updated in place; one barrier per sub-round.
+__device__ void jacobi_solve_part(double *smem, const double *__restrict__ A, int np, int nb,
+                                  const int32_t *__restrict__ pidx, int k, int r, int rprev,
+                                  const double *__restrict__ Jprev,
+                                  const double *__restrict__ fro, double *__restrict__ Jout,
+                                  int *cnt) {
+  // pidx[(round * npair + pair) * 32 + i]: global index of local index i
+  const int npair = nb / 2;
+  const int32_t *ix = pidx + ((int64_t)r * npair + k) * kJT;
+  double(*S0)[kJT + 1] = reinterpret_cast<double(*)[kJT + 1]>(smem);
+  double(*S1)[kJT + 1] = reinterpret_cast<double(*)[kJT + 1]>(smem + kTS);
+  double(*Jm)[kJT + 1] = reinterpret_cast<double(*)[kJT + 1]>(smem + 2 * kTS);
   __shared__ int rot_any;
-  const int k = blockIdx.x, tid = threadIdx.x;
+  const int tid = threadIdx.x;
+  if (rprev < 0) {
+    for (int e = tid; e < kJT * kJT; e += 256) {
+      int i = e & 31, j = e >> 5;
+      S0[i][j] = A[ix[i] + (int64_t)np * ix[j]];
+    }
+  } else {
+    // regions: M (4 x 32 x 16) over S1 and Jm; T (4 tiles) and the J' halves after them
+    double *Mb = smem + kTS;
+    double *Tb = smem + 3 * kTS;
+    double *Jh = smem + 7 * kTS;   // [2][32][17]
+    const int wv = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
+    const int blk[2] = {rr_player(k, r, nb), rr_player(nb - 1 - k, r, nb)};
+    int kp[2], hp[2];
+    block_slot(blk[0], rprev, nb, kp[0], hp[0]);
+    block_slot(blk[1], rprev, nb, kp[1], hp[1]);
+    for (int e = tid; e < 2 * kJT * kJB; e += 256) {
+      const int x = e / (kJT * kJB), a = (e >> 4) & 31, c = e & 15;
+      Jh[(x * kJT + a) * 17 + c] = Jprev[(int64_t)kp[x] * kJT * kJT + a + kJT * (hp[x] * kJB + c)];
+    }
+    // wave wv: block (X, Y) = (wv >> 1, wv & 1); its previous tile (kp[X], kp[Y])
+    const int X = wv >> 1, Y = wv & 1;
+    double *T = Tb + wv * kTS;
+    {
+      const int32_t *px = pidx + ((int64_t)rprev * npair + kp[X]) * kJT;
+      const int32_t *py = pidx + ((int64_t)rprev * npair + kp[Y]) * kJT;
+      const int gi = px[l & 31];
+      double v[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) v[q] = A[gi + (int64_t)np * py[(l >> 5) + 2 * q]];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) T[(l & 31) * (kJT + 1) + (l >> 5) + 2 * q] = v[q];
+    }
+    __syncthreads();
+    // M (32 x 16) = T (32 x 32) J'_Y (32 x 16)
+    double *M = Mb + wv * (kJT * kJB);
+    const double *JY = Jh + Y * kJT * 17, *JX = Jh + X * kJT * 17;
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti) {
+      v4d acc = {0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk)
+        acc = mfma_f64(T[(16 * ti + lr) * (kJT + 1) + 4 * kk + lk], JY[(4 * kk + lk) * 17 + lr],
+                       acc);
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) M[(16 * ti + lk + 4 * rr) * kJB + lr] = acc[rr];
+    }
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): this wave's LDS writes are done
+    __builtin_amdgcn_wave_barrier();
+    // block (16 x 16) = J'_X^T (16 x 32) M (32 x 16)
+    v4d acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk)
+      acc = mfma_f64(JX[(4 * kk + lk) * 17 + lr], M[(4 * kk + lk) * kJB + lr], acc);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) S0[kJB * X + lk + 4 * rr][kJB * Y + lr] = acc[rr];
+    __syncthreads();
+  }
   for (int e = tid; e < kJT * kJT; e += 256) {
     int i = e & 31, j = e >> 5;
-    int gi = pair_index(k, i, round, nb), gj = pair_index(k, j, round, nb);
-    S[0][i][j] = A[gi + (int64_t)np * gj];
     Jm[i][j] = (i == j) ? 1.0 : 0.0;
   }
   if (tid == 0) rot_any = 0;
   const double tol_abs = 1e-15 * fro[0], tol_rel = 1e-15;
   const int P1 = tid >> 4, P2 = tid & 15;
   const int jr = tid >> 4;   // J rows jr and jr + 16, column pair P2
-  const bool first = round == 0;
+  const bool first = r == 0;
   const int nsub = first ? 2 * kJB - 1 : kJB;
-  int cur = 0;
+  double(*Sc)[kJT + 1] = S0;
+  double(*Sn)[kJT + 1] = S1;
   __syncthreads();
   for (int u = 0; u < nsub; ++u) {
     int p1, q1, p2, q2;
     sub_round_pair(u, first, P1, p1, q1);
     sub_round_pair(u, first, P2, p2, q2);
-    const double a11 = S[cur][p1][p1], a12 = S[cur][q1][q1], a13 = S[cur][p1][q1];
-    const double a21 = S[cur][p2][p2], a22 = S[cur][q2][q2], a23 = S[cur][p2][q2];
-    const double b11 = S[cur][p1][p2], b12 = S[cur][p1][q2];
-    const double b21 = S[cur][q1][p2], b22 = S[cur][q1][q2];
+    const double a11 = Sc[p1][p1], a12 = Sc[q1][q1], a13 = Sc[p1][q1];
+    const double a21 = Sc[p2][p2], a22 = Sc[q2][q2], a23 = Sc[p2][q2];
+    const double b11 = Sc[p1][p2], b12 = Sc[p1][q2];
+    const double b21 = Sc[q1][p2], b22 = Sc[q1][q2];
     double c1, s1, c2, s2;
     const bool r1 = jacobi_rotation(a11, a12, a13, tol_rel, tol_abs, c1, s1);
     const bool r2 = jacobi_rotation(a21, a22, a23, tol_rel, tol_abs, c2, s2);
     if (r2 && P1 == 0) rot_any = 1;
     const double t11 = c2 * b11 - s2 * b12, t12 = s2 * b11 + c2 * b12;
     const double t21 = c2 * b21 - s2 * b22, t22 = s2 * b21 + c2 * b22;
-    double n11 = c1 * t11 - s1 * t21, n12 = c1 * t12 - s1 * t22;
-    double n21 = s1 * t11 + c1 * t21, n22 = s1 * t12 + c1 * t22;
-    if (P1 == P2 && r1) {
-      n12 = 0.0;
-      n21 = 0.0;
-    }
-    const int nx = cur ^ 1;
-    S[nx][p1][p2] = n11;
-    S[nx][p1][q2] = n12;
-    S[nx][q1][p2] = n21;
-    S[nx][q1][q2] = n22;
+    const double n11 = c1 * t11 - s1 * t21, n12 = c1 * t12 - s1 * t22;
+    const double n21 = s1 * t11 + c1 * t21, n22 = s1 * t12 + c1 * t22;
+    (void)r1;
+    Sn[p1][p2] = n11;
+    Sn[p1][q2] = n12;
+    Sn[q1][p2] = n21;
+    Sn[q1][q2] = n22;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int row = jr + 16 * h;
@@ -173,7 +288,9 @@ __global__ void __launch_bounds__(256) k_jacobi_solve(const double *__restrict__
       Jm[row][p2] = c2 * jp - s2 * jq;
       Jm[row][q2] = s2 * jp + c2 * jq;
     }
-    cur = nx;
+    double(*t)[kJT + 1] = Sc;
+    Sc = Sn;
+    Sn = t;
     __syncthreads();
   }
   double *Jo = Jout + (int64_t)k * kJT * kJT;
@@ -184,26 +301,25 @@ __global__ void __launch_bounds__(256) k_jacobi_solve(const double *__restrict__
   if (tid == 0 && rot_any) atomicAdd(cnt, 1);
 }
 
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-// Apply the round's rotations: every 32 x 32 tile of A (rows of block pair
-// k1, columns of pair k2) becomes J_k1^T A J_k2, and every 32-row tile of V
-// becomes V J_k2.  Both products run on the FP64 matrix cores, one 16 x 16
-// output quarter per wavefront (v_mfma_f64_16x16x4f64: lane l holds
-// A[l % 16][l / 16] and B[l / 16][l % 16]; result register r is
-// D[l / 16 + 4 r][l % 16]).
-__global__ void __launch_bounds__(256) k_jacobi_update(double *__restrict__ A, double *__restrict__ V,
-                                                       int np, int nb, int round,
-                                                       const double *__restrict__ Jbuf) {
-  __shared__ double Tl[kJT][kJT + 1];
-  __shared__ double J1[kJT][kJT + 1];
-  __shared__ double J2[kJT][kJT + 1];
-  __shared__ double Tm[kJT][kJT + 1];
+// Update part of a round (one workgroup per output tile): with the round's
+// rotations J (pairs of round r), every 32 x 32 tile of A (rows of pair k1,
+// columns of pair k2) becomes J_k1^T A J_k2 (read from Acur, written to
+// Anext) and every 32-row tile of V becomes V J_k2 (in place).  Both products
+// run on the FP64 matrix cores, one 16 x 16 output quarter per wavefront
+// (v_mfma_f64_16x16x4f64: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16];
+// result register r is D[l / 16 + 4 r][l % 16]).
+__device__ void jacobi_update_part(double *smem, int w, const double *__restrict__ Acur,
+                                   double *__restrict__ Anext, double *__restrict__ V, int np,
+                                   int nb, const int32_t *__restrict__ pidx, int r,
+                                   const double *__restrict__ Jbuf) {
+  double(*Tl)[kJT + 1] = reinterpret_cast<double(*)[kJT + 1]>(smem);
+  double(*J1)[kJT + 1] = reinterpret_cast<double(*)[kJT + 1]>(smem + kTS);
+  double(*J2)[kJT + 1] = reinterpret_cast<double(*)[kJT + 1]>(smem + 2 * kTS);
+  double(*Tm)[kJT + 1] = reinterpret_cast<double(*)[kJT + 1]>(smem + 3 * kTS);
   const int npair = nb / 2;
   const int tilesA = npair * npair;
-  int w = blockIdx.x;
   const int tid = threadIdx.x;
-  bool isA = w < tilesA;
+  const bool isA = w < tilesA;
   int k1, k2, rc0 = 0;
   if (isA) {
     k1 = w / npair;
@@ -214,12 +330,13 @@ __global__ void __launch_bounds__(256) k_jacobi_update(double *__restrict__ A, d
     k1 = -1;
     k2 = w % npair;
   }
+  const int32_t *i1 = pidx + ((int64_t)r * npair + (isA ? k1 : 0)) * kJT;
+  const int32_t *i2 = pidx + ((int64_t)r * npair + k2) * kJT;
   for (int e = tid; e < kJT * kJT; e += 256) {
     int i = e & 31, j = e >> 5;
-    int gj = pair_index(k2, j, round, nb);
+    int gj = i2[j];
     if (isA) {
-      int gi = pair_index(k1, i, round, nb);
-      Tl[i][j] = A[gi + (int64_t)np * gj];
+      Tl[i][j] = Acur[i1[i] + (int64_t)np * gj];
       J1[i][j] = Jbuf[(int64_t)k1 * kJT * kJT + i + kJT * j];
     } else {
       Tl[i][j] = V[rc0 + i + (int64_t)np * gj];
@@ -232,29 +349,50 @@ __global__ void __launch_bounds__(256) k_jacobi_update(double *__restrict__ A, d
   v4d acc = {0, 0, 0, 0};
 #pragma unroll
   for (int kk = 0; kk < 8; ++kk)
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Tl[16 * ti + lr][4 * kk + lk],
-                                               J2[4 * kk + lk][16 * tj + lr], acc, 0, 0, 0);
+    acc = mfma_f64(Tl[16 * ti + lr][4 * kk + lk], J2[4 * kk + lk][16 * tj + lr], acc);
   if (!isA) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = 16 * ti + lk + 4 * r, j = 16 * tj + lr;
-      V[rc0 + i + (int64_t)np * pair_index(k2, j, round, nb)] = acc[r];
+    for (int q = 0; q < 4; ++q) {
+      const int i = 16 * ti + lk + 4 * q, j = 16 * tj + lr;
+      V[rc0 + i + (int64_t)np * i2[j]] = acc[q];
     }
     return;
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r) Tm[16 * ti + lk + 4 * r][16 * tj + lr] = acc[r];
+  for (int q = 0; q < 4; ++q) Tm[16 * ti + lk + 4 * q][16 * tj + lr] = acc[q];
   __syncthreads();
   acc = v4d{0, 0, 0, 0};
 #pragma unroll
   for (int kk = 0; kk < 8; ++kk)
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(J1[4 * kk + lk][16 * ti + lr],
-                                               Tm[4 * kk + lk][16 * tj + lr], acc, 0, 0, 0);
+    acc = mfma_f64(J1[4 * kk + lk][16 * ti + lr], Tm[4 * kk + lk][16 * tj + lr], acc);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int i = 16 * ti + lk + 4 * r, j = 16 * tj + lr;
-    A[pair_index(k1, i, round, nb) + (int64_t)np * pair_index(k2, j, round, nb)] = acc[r];
+  for (int q = 0; q < 4; ++q) {
+    const int i = 16 * ti + lk + 4 * q, j = 16 * tj + lr;
+    Anext[i1[i] + (int64_t)np * i2[j]] = acc[q];
   }
+}
+
+// One launch per round: workgroups [0, npair) solve the pairs of round r
+// (when solve_on), the rest apply the pending rotations of round rprev (when
+// rprev >= 0) to A (Acur -> Anext) and V.  The two parts only read Acur, so
+// they run concurrently; one LDS region serves either part.
+__global__ void __launch_bounds__(256) k_jacobi_round(const double *__restrict__ Acur,
+                                                      double *__restrict__ Anext,
+                                                      double *__restrict__ V, int np, int nb,
+                                                      const int32_t *__restrict__ pidx,
+                                                      int r, int solve_on, int rprev,
+                                                      const double *__restrict__ Jprev,
+                                                      double *__restrict__ Jcur,
+                                                      const double *__restrict__ fro, int *cnt,
+                                                      const int *__restrict__ done) {
+  __shared__ double smem[kRoundSmem];
+  if (*done) return;   // converged at the previous sweep: the whole launch is empty
+  const int npair = nb / 2;
+  const int nsolve = solve_on ? npair : 0;
+  if ((int)blockIdx.x < nsolve)
+    jacobi_solve_part(smem, Acur, np, nb, pidx, blockIdx.x, r, rprev, Jprev, fro, Jcur, cnt);
+  else
+    jacobi_update_part(smem, blockIdx.x - nsolve, Acur, Anext, V, np, nb, pidx, rprev, Jprev);
 }
 
 // Eigenvalues from the diagonal, ranked in descending order (ties by index).
@@ -281,6 +419,7 @@ __global__ void k_eig_vecs(const double *__restrict__ V, int np, int n, const in
 
 EigWork::~EigWork() {
   if (cnt_host) (void)hipHostFree(cnt_host);
+  if (ev) (void)hipEventDestroy(ev);
 }
 
 int sym_eig(const double *A, int64_t lda, int n, double *w, double *W, int64_t ldw,
@@ -290,11 +429,28 @@ int sym_eig(const double *A, int64_t lda, int n, double *w, double *W, int64_t l
   const int nb = np / kJB;
   const int npair = nb / 2;
   ws.A.reserve((size_t)np * np);
+  ws.A2.reserve((size_t)np * np);
   ws.V.reserve((size_t)np * np);
   ws.J.reserve((size_t)npair * kJT * kJT);
+  ws.J2.reserve((size_t)npair * kJT * kJT);
   ws.fro.reserve(2 + np);   // ||A||_F, relative off-diagonal norm, column partials
-  ws.cnt.reserve(1 + np);   // counter + rank scratch
-  if (!ws.cnt_host) FKF_CHECK_HIP(hipHostMalloc((void **)&ws.cnt_host, sizeof(double)));
+  ws.cnt.reserve(2 + np);   // counter, rank scratch, convergence flag
+  if (!ws.cnt_host) FKF_CHECK_HIP(hipHostMalloc((void **)&ws.cnt_host, 4 * sizeof(int)));
+  if (!ws.ev) FKF_CHECK_HIP(hipEventCreateWithFlags(&ws.ev, hipEventDisableTiming));
+  if (ws.pidx_np != np) {
+    // global index of local index i of pair k in round r (round-robin tournament)
+    std::vector<int32_t> t((size_t)(nb - 1) * npair * kJT);
+    auto player = [&](int pos, int r) { return pos == 0 ? 0 : 1 + ((pos - 1 + r) % (nb - 1)); };
+    for (int r = 0; r < nb - 1; ++r)
+      for (int k = 0; k < npair; ++k)
+        for (int i = 0; i < kJT; ++i) {
+          const int P = player(k, r), Q = player(nb - 1 - k, r);
+          t[((size_t)r * npair + k) * kJT + i] = i < kJB ? P * kJB + i : Q * kJB + (i - kJB);
+        }
+    ws.pidx.upload(t, st);
+    FKF_CHECK_HIP(hipStreamSynchronize(st));   // t is a host temporary
+    ws.pidx_np = np;
+  }
   int64_t tot = (int64_t)np * np;
   hipLaunchKernelGGL(k_jacobi_init, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, A, lda,
                      n, np, ws.A.p, ws.V.p);
@@ -302,36 +458,61 @@ int sym_eig(const double *A, int64_t lda, int n, double *w, double *W, int64_t l
   hipLaunchKernelGGL(k_offnorm_final, dim3(1), dim3(256), 0, st, ws.fro.p + 2, np,
                      (const double *)nullptr, ws.fro.p);
   const unsigned grid_upd = (unsigned)(npair * npair + (np / kJT) * npair);
-  // Stop when the relative off-diagonal norm is below 1e-12 (a perturbation of
-  // at most 1e-12 ||A||_F on the eigenvalues) or a sweep rotates nothing.
-  int sweeps = 0;
-  double *off_host = reinterpret_cast<double *>(ws.cnt_host);
+  // Rounds are launched as k_jacobi_round: the solve of round r runs next to
+  // the update of round r - 1 (A double-buffered, J double-buffered); the last
+  // update of a sweep runs alone before the convergence test.  Stop when the
+  // relative off-diagonal norm is below 1e-12 (a perturbation of at most
+  // 1e-12 ||A||_F on the eigenvalues) or a sweep rotates nothing.
+  double *Ab[2] = {ws.A.p, ws.A2.p};
+  double *Jb[2] = {ws.J.p, ws.J2.p};
+  int ca = 0, cj = 0;   // current A buffer; J buffer written by the next solve
+  int *done = ws.cnt.p + 1 + np;    // device convergence flag
+  volatile int *done_host = ws.cnt_host + 2;
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, done, 0);
+  // The convergence test of sweep s is read on the host while sweep s + 1 is
+  // already queued (no idle GPU during the host round trip); kernels of a
+  // sweep that follows convergence exit at once, leaving A and V untouched.
+  int sweeps = 0, ca_prev = 0;
   for (int sw = 0; sw < 40; ++sw) {
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, ws.cnt.p, 0);
-    for (int r = 0; r < nb - 1; ++r) {
+    int rprev = -1;
+    for (int r = 0; r <= nb - 1; ++r) {
+      const bool solve = r < nb - 1;
+      const unsigned grid = (solve ? npair : 0) + (rprev >= 0 ? grid_upd : 0);
       {
-        FKF_TRACE("eig_jacobi_solve", st);
-        hipLaunchKernelGGL(k_jacobi_solve, dim3(npair), dim3(256), 0, st, ws.A.p, np, nb, r,
-                           ws.fro.p, ws.J.p, ws.cnt.p);
+        FKF_TRACE("eig_jacobi_round", st);
+        hipLaunchKernelGGL(k_jacobi_round, dim3(grid), dim3(256), 0, st, Ab[ca], Ab[ca ^ 1], ws.V.p,
+                           np, nb, ws.pidx.p, r, solve ? 1 : 0, rprev, Jb[cj ^ 1], Jb[cj],
+                           ws.fro.p, ws.cnt.p, done);
       }
-      {
-        FKF_TRACE("eig_jacobi_update", st);
-        hipLaunchKernelGGL(k_jacobi_update, dim3(grid_upd), dim3(256), 0, st, ws.A.p, ws.V.p, np,
-                           nb, r, ws.J.p);
+      if (rprev >= 0) ca ^= 1;   // the update wrote the other A buffer
+      if (solve) {
+        cj ^= 1;                 // this solve's rotations are pending now
+        rprev = r;
       }
     }
-    hipLaunchKernelGGL(k_offnorm_cols, dim3(np), dim3(256), 0, st, ws.A.p, np, ws.fro.p + 2, 0);
+    hipLaunchKernelGGL(k_offnorm_cols, dim3(np), dim3(256), 0, st, Ab[ca], np, ws.fro.p + 2, 0);
     hipLaunchKernelGGL(k_offnorm_final, dim3(1), dim3(256), 0, st, ws.fro.p + 2, np, ws.fro.p,
                        ws.fro.p + 1);
-    FKF_CHECK_HIP(hipMemcpyAsync(off_host, ws.fro.p + 1, sizeof(double), hipMemcpyDeviceToHost, st));
-    int rotated = 0;
-    FKF_CHECK_HIP(hipMemcpyAsync(&rotated, ws.cnt.p, sizeof(int), hipMemcpyDeviceToHost, st));
-    FKF_CHECK_HIP(hipStreamSynchronize(st));
+    // wait for the previous sweep's flag (this sweep is queued behind it)
+    if (sw > 0) {
+      FKF_CHECK_HIP(hipEventSynchronize(ws.ev));
+      if (*done_host) {
+        ca = ca_prev;   // this sweep's launches were empty
+        break;
+      }
+    }
     ++sweeps;
-    if (*off_host <= 1e-12 || rotated == 0) break;
+    *done_host = 0;
+    hipLaunchKernelGGL(k_eig_converged, dim3(1), dim3(1), 0, st, ws.fro.p + 1, ws.cnt.p, 1e-12,
+                       done, (int *)done_host);
+    FKF_CHECK_HIP(hipEventRecord(ws.ev, st));
+    ca_prev = ca;
+    if (sw == 39) FKF_CHECK_HIP(hipEventSynchronize(ws.ev));
   }
+  const double *Af = Ab[ca];
   int *rank = ws.cnt.p + 1;
-  hipLaunchKernelGGL(k_eig_rank, dim3(1), dim3(1024), 0, st, ws.A.p, np, n, w, rank);
+  hipLaunchKernelGGL(k_eig_rank, dim3(1), dim3(1024), 0, st, Af, np, n, w, rank);
   hipLaunchKernelGGL(k_eig_vecs, dim3(n, (unsigned)((n + 255) / 256)), dim3(256), 0, st, ws.V.p,
                      np, n, rank, W, ldw);
   FKF_CHECK_HIP(hipGetLastError());
