@@ -246,7 +246,8 @@ def varying_h(fkf, torch, cov, wl, ys, n_steps=4, rank_rtol=1e-5):
 TRAFFIC_KERNELS = {
     "fkf::k_jacobi_round": "eig_jacobi_round",
     "void fkf::k_couple_mfma<2, 4, 4, false>": "hmat_far_couple_multi",
-    "void fkf::k_down_mfma<2, 4, double>": "hmat_near_down_multi",
+    "void fkf::k_down_mfma<2, 4, double, 1>": "hmat_near_multi",
+    "void fkf::k_down_mfma<2, 4, double, 2>": "hmat_down_multi",
     "void fkf::k_up_mfma<2, 4, 4>": "hmat_far_up_multi",
     "void fkf::k_gemv_seg<false>": "filter_gemv",
     "fkf::k_gemm_nn": "gep_basis_gemm",
@@ -459,8 +460,8 @@ def main():
         # entry and column: couplings of the ordered admissible pairs; the
         # near-field tiles plus the downward interpolation; the upward one
         "hmat_far_couple_multi": ("mfma", 2.0 * n_m * k_entries, "TFLOP/s"),
-        "hmat_near_down_multi": ("mfma", 2.0 * n_m * (info["n_near_pairs"] * 4096.0
-                                                      + info["far_interp_entries"]), "TFLOP/s"),
+        "hmat_near_multi": ("mfma", 2.0 * n_m * info["n_near_pairs"] * 4096.0, "TFLOP/s"),
+        "hmat_down_multi": ("mfma", 2.0 * n_m * info["far_interp_entries"], "TFLOP/s"),
         "hmat_far_up_multi": ("mfma", 2.0 * n_m * info["far_interp_entries"], "TFLOP/s"),
         "gep_basis_gemm": ("alu", 2.0 * n * n_m * n_m, "TFLOP/s"),
         # Jacobi round (one launch): the update part turns every 32 x 32 tile

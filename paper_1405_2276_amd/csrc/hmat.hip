@@ -1225,7 +1225,9 @@ __global__ void __launch_bounds__(256) k_couple_mfma(const FarCluster *__restric
 
 // Near field + downward pass + scatter for one leaf and NC columns:
 // Y_s = sum_{t near s} Gamma_st X_t + sum_{far ancestors c} U_c|_s Yhat_c.
-template <int D, int NCB, typename TT>
+// MODE 0: near field and downward pass, Y = result; MODE 1: near field only,
+// Y = near part; MODE 2: downward pass only, Y += far part.
+template <int D, int NCB, typename TT, int MODE>
 __global__ void __launch_bounds__(256) k_down_mfma(
     const TT *__restrict__ blk, const int32_t *__restrict__ near_ptr,
     const int32_t *__restrict__ near_idx, const int32_t *__restrict__ bs,
@@ -1255,7 +1257,7 @@ __global__ void __launch_bounds__(256) k_down_mfma(
 #pragma unroll
   for (int j = 0; j < NCB; ++j) acc[j] = v4d{0, 0, 0, 0};
   // near field
-  for (int e = near_ptr[s]; e < near_ptr[s + 1]; ++e) {
+  for (int e = MODE == 2 ? 0 : near_ptr[s]; e < (MODE == 2 ? 0 : near_ptr[s + 1]); ++e) {
     const int code = near_idx[e];
     const int64_t b = code >> 1;
     const bool trans = code & 1;
@@ -1305,7 +1307,7 @@ __global__ void __launch_bounds__(256) k_down_mfma(
     }
   }
   // far field: U_c restricted to the leaf's points times Yhat_c
-  for (int e = anc_ptr[s]; e < anc_ptr[s + 1]; ++e) {
+  for (int e = MODE == 1 ? 0 : anc_ptr[s]; e < (MODE == 1 ? 0 : anc_ptr[s + 1]); ++e) {
     const FarCluster c = fc[anc_idx[e]];
     const int p = c.p, pd = c.pd;
     const double *cu = cheb + p * 2 * kMaxCheb;
@@ -1363,7 +1365,10 @@ __global__ void __launch_bounds__(256) k_down_mfma(
     for (int r = 0; r < 4; ++r) {
       int i = w * 16 + lk + 4 * r;
       int cc = c0 + j * 16 + lr;
-      if (i < ms && cc < nrhs) Y[perm[s0 + i] + ldy * cc] = acc[j][r];
+      if (i < ms && cc < nrhs) {
+        double *y = Y + perm[s0 + i] + ldy * cc;
+        *y = MODE == 2 ? *y + acc[j][r] : acc[j][r];
+      }
     }
 }
 
@@ -1676,13 +1681,19 @@ namespace {
 
 // One column: near field (HBM-bound) on a forked stream, far field (ALU-bound)
 // on the caller's stream, joined before the final pass.
-void apply_one(fkf_cov *cov, double *Y, hipStream_t st) {
-  const int64_t n = cov->n;
+// Second stream (default priority) and fork/join events of a covariance
+// operator, created on first use.
+static void ensure_side_stream(fkf_cov *cov) {
   if (!cov->side) {
     FKF_CHECK_HIP(hipStreamCreateWithFlags(&cov->side, hipStreamNonBlocking));
     FKF_CHECK_HIP(hipEventCreateWithFlags(&cov->ev_fork, hipEventDisableTiming));
     FKF_CHECK_HIP(hipEventCreateWithFlags(&cov->ev_join, hipEventDisableTiming));
   }
+}
+
+void apply_one(fkf_cov *cov, double *Y, hipStream_t st) {
+  const int64_t n = cov->n;
+  ensure_side_stream(cov);
   cov->part.reserve((size_t)std::max<int64_t>(cov->n_blk, 1) * 128);
   FKF_CHECK_HIP(hipEventRecord(cov->ev_fork, st));
   FKF_CHECK_HIP(hipStreamWaitEvent(cov->side, cov->ev_fork, 0));
@@ -1775,6 +1786,21 @@ void apply_multi_t(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t s
     cov->xhat.reserve((size_t)cov->n_coef * nrhs);
     cov->yhat.reserve((size_t)cov->n_coef * nrhs);
     cov->part_up_m.reserve((size_t)cov->n_part_up_m * nrhs);
+    // near field on the side stream, concurrent with the far-field chain;
+    // the downward pass then adds to its result
+    ensure_side_stream(cov);
+    FKF_CHECK_HIP(hipEventRecord(cov->ev_fork, st));
+    FKF_CHECK_HIP(hipStreamWaitEvent(cov->side, cov->ev_fork, 0));
+    {
+      FKF_TRACE("hmat_near_multi", cov->side);
+      typedef typename std::conditional<F32, float, double>::type TTn;
+      hipLaunchKernelGGL((k_down_mfma<D, NCB, TTn, 1>), dim3(cov->n_leaves, gy), dim3(256), 0,
+                         cov->side, F32 ? (const TTn *)cov->blk32.p : (const TTn *)cov->blk.p,
+                         cov->near_ptr.p, cov->near_idx.p, cov->blk_s.p, cov->blk_t.p,
+                         cov->leaf_off.p, cov->pts.p, n, cov->cheb.p, cov->fc.p, cov->anc_ptr.p,
+                         cov->anc_idx.p, cov->xt.p, cov->yhat.p, cov->perm.p, nrhs, Y, ldy);
+    }
+    FKF_CHECK_HIP(hipEventRecord(cov->ev_join, cov->side));
     {
       FKF_TRACE("hmat_far_up_multi", st);
       hipLaunchKernelGGL((k_up_mfma<D, NCB, RBW>), dim3((unsigned)cov->n_up_items_m, gy), dim3(256),
@@ -1790,17 +1816,22 @@ void apply_multi_t(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t s
                          1.0 / cov->ell, cov->theta, cov->xhat.p, nrhs, cov->yhat.p);
     }
   }
-  FKF_TRACE("hmat_near_down_multi", st);
-  if (F32)
-    hipLaunchKernelGGL((k_down_mfma<D, NCB, float>), dim3(cov->n_leaves, gy), dim3(256), 0, st,
-                       cov->blk32.p, cov->near_ptr.p, cov->near_idx.p, cov->blk_s.p, cov->blk_t.p,
-                       cov->leaf_off.p, cov->pts.p, n, cov->cheb.p, cov->fc.p, cov->anc_ptr.p,
-                       cov->anc_idx.p, cov->xt.p, cov->yhat.p, cov->perm.p, nrhs, Y, ldy);
-  else
-    hipLaunchKernelGGL((k_down_mfma<D, NCB, double>), dim3(cov->n_leaves, gy), dim3(256), 0, st,
-                       cov->blk.p, cov->near_ptr.p, cov->near_idx.p, cov->blk_s.p, cov->blk_t.p,
-                       cov->leaf_off.p, cov->pts.p, n, cov->cheb.p, cov->fc.p, cov->anc_ptr.p,
-                       cov->anc_idx.p, cov->xt.p, cov->yhat.p, cov->perm.p, nrhs, Y, ldy);
+  typedef typename std::conditional<F32, float, double>::type TT;
+  const TT *blk = F32 ? (const TT *)cov->blk32.p : (const TT *)cov->blk.p;
+  auto down = [&](auto kern, hipStream_t s) {
+    hipLaunchKernelGGL(kern, dim3(cov->n_leaves, gy), dim3(256), 0, s, blk, cov->near_ptr.p,
+                       cov->near_idx.p, cov->blk_s.p, cov->blk_t.p, cov->leaf_off.p, cov->pts.p, n,
+                       cov->cheb.p, cov->fc.p, cov->anc_ptr.p, cov->anc_idx.p, cov->xt.p,
+                       cov->yhat.p, cov->perm.p, nrhs, Y, ldy);
+  };
+  if (cov->n_fc == 0) {
+    FKF_TRACE("hmat_near_multi", st);
+    down(k_down_mfma<D, NCB, TT, 1>, st);
+    return;
+  }
+  FKF_TRACE("hmat_down_multi", st);
+  FKF_CHECK_HIP(hipStreamWaitEvent(st, cov->ev_join, 0));
+  down(k_down_mfma<D, NCB, TT, 2>, st);
 }
 
 void apply_multi(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t st) {
