@@ -54,6 +54,8 @@ def parse():
                     help="20 one-column products only (for profiler runs)")
     ap.add_argument("--profile", action="store_true",
                     help="one FP64 pass and a calibration copy only (for counter runs)")
+    ap.add_argument("--batched-filters", type=int, default=64,
+                    help="independent filters of uneven size stepped together (0: skip)")
     ap.add_argument("--varying-steps", type=int, default=4,
                     help="steps with a new measurement operator each (0: skip)")
     return ap.parse_args()
@@ -320,6 +322,57 @@ def traffic_for(site):
     return (k["fetch_kib"] * rec["fetch_factor"] + k["write_kib"] * rec["write_factor"]) * 1024.0
 
 
+def many_filters(fkf, torch, count, reps=2):
+    """Independent filters of uneven size (workloads.batch): every filter
+    built and resident, then timed passes of `steps` steps of all filters,
+    (a) together through fkf_filter_step_many (the bases' projected
+    eigenproblems solved as one batch) and (b) one filter at a time.  Returns
+    filter steps per second for both."""
+    import workloads as W
+    wls = W.batch(count)
+    t0 = time.perf_counter()
+    covs, obss, yss = [], [], []
+    for wl in wls:
+        covs.append(fkf.Cov(wl.points(), nu=wl.nu, length=wl.length, variance=wl.variance,
+                            leaf_size=wl.leaf_size))
+        src, rcv = wl.rays()
+        obss.append(fkf.Obs.from_rays(wl.shape, src, rcv, wl.noise_var))
+        yss.append(torch.from_numpy(W.observations(wl)).cuda())
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    steps = wls[0].steps
+
+    def run(together):
+        fs = [fkf.Filter(c) for c in covs]
+        for k in range(steps):
+            if together:
+                fkf.step_many(fs, obss, [y[k] for y in yss])
+            else:
+                for f, o, y in zip(fs, obss, yss):
+                    f.step(o, y[k])
+        torch.cuda.synchronize()
+        for f in fs:
+            f.status()
+            f.close()
+
+    out = {"filters": count, "steps_each": steps, "n_total": int(sum(w.n for w in wls)),
+           "n_m_range": [min(w.n_src * w.n_rcv for w in wls), max(w.n_src * w.n_rcv for w in wls)],
+           "setup_s": t_setup}
+    for name, together in (("together", True), ("one_by_one", False)):
+        run(together)                               # warm-up
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            run(together)
+        dt = (time.perf_counter() - t0) / reps
+        out[name] = {"pass_s": dt, "filter_steps_per_s": count * steps / dt}
+    out["speedup_together"] = out["one_by_one"]["pass_s"] / out["together"]["pass_s"]
+    for o in obss:
+        o.close()
+    for c in covs:
+        c.close()
+    return out
+
+
 def accuracy(wl, res, ref64):
     """Per-result error of a pass: against the oracle's stored values at
     sampled cells (when the workload has them) and against the FP64 GPU form
@@ -416,6 +469,10 @@ def main():
     log(f"[bench] fp64 phases {phases} accuracy {acc64}")
     hmatvec = hmatvec_bench(fkf, torch, cov, info, args.matvec_reps)
     log(f"[bench] hmatvec fp64 {hmatvec}")
+    many = None
+    if args.batched_filters > 0:
+        many = many_filters(fkf, torch, args.batched_filters)
+        log(f"[bench] many filters {many}")
     vary = None
     if args.varying_steps > 0:
         vary = varying_h(fkf, torch, cov, wl, ys, args.varying_steps)
@@ -515,6 +572,7 @@ def main():
             "constant_h_step_us": step_us,
             "constant_h_steps_per_s": 1e6 / step_us,
             "varying_h": vary,
+            "many_filters": many,
             "phases_ms": phases,
             "errors": acc64,
             "dominant_site": dom,

@@ -221,6 +221,20 @@ fkf_status fkf_filter_create(fkf_cov *cov, const double *s0_dev, double alpha0,
 fkf_status fkf_filter_step(fkf_filter *f, const fkf_obs *obs, const double *y_dev,
                            void *stream);
 
+/* One step of count independent filters: the same as calling
+ * fkf_filter_step(filters[i], obs[i], y[i]) for i = 0..count-1 in order,
+ * except that the projected eigenproblems (Section 2.2.2) of all filters that
+ * build their constant-H basis in this step are solved together, as one
+ * batch of eigenproblems in one sequence of launches (the many-filter form of
+ * the method: independent filters of uneven size share the latency-bound
+ * eigensolver rounds).  filters, obs and y are host arrays of count handles /
+ * device pointers (each y[i] of length obs[i]'s n_m); a filter may appear
+ * only once.  The argument and state checks of fkf_filter_step are made for
+ * every filter before any work is queued, so such an error leaves every
+ * filter unchanged. */
+fkf_status fkf_filter_step_many(fkf_filter *const *filters, const fkf_obs *const *obs,
+                                const double *const *y, int32_t count, void *stream);
+
 /* Synchronise `stream` and return the latched device-side status. */
 fkf_status fkf_filter_status(fkf_filter *f, void *stream);
 

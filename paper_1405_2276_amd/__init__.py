@@ -98,6 +98,8 @@ _sig("fkf_obs_destroy", None, [_vp])
 _sig("fkf_filter_create", _i, [_vp, _vp, ctypes.c_double, ctypes.POINTER(FilterParams), _vp,
                                ctypes.POINTER(_vp)])
 _sig("fkf_filter_step", _i, [_vp, _vp, _vp, _vp])
+_sig("fkf_filter_step_many", _i, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                  ctypes.c_int32, _vp])
 _sig("fkf_filter_status", _i, [_vp, _vp])
 _sig("fkf_filter_mean", _i, [_vp, _vp, _vp])
 _sig("fkf_filter_variance", _i, [_vp, _vp, _vp])
@@ -131,6 +133,22 @@ def trace_report() -> dict:
         _check(_lib.fkf_trace_query(name.encode(), ctypes.byref(c), ctypes.byref(ms)))
         out[name] = (c.value, ms.value)
     return out
+
+
+def step_many(filters, obs, ys, stream=None):
+    """One step of several independent filters (fkf_filter_step_many): the
+    projected eigenproblems of filters that build their basis now are solved
+    as one batch."""
+    n = len(filters)
+    if len(obs) != n or len(ys) != n:
+        raise ValueError("filters, obs and ys must have the same length")
+    yd = [to_device(y) for y in ys]
+    fa = (_vp * n)(*[f._h.value for f in filters])
+    oa = (_vp * n)(*[o.handle.value for o in obs])
+    ya = (_vp * n)(*[y.data_ptr() for y in yd])
+    for f, y in zip(filters, yd):
+        f._y = y     # keep alive until the stream consumes it
+    _check(_lib.fkf_filter_step_many(fa, oa, ya, n, _stream(stream)))
 
 
 def version() -> str:

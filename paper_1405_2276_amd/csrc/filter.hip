@@ -397,43 +397,89 @@ static void compute_gep(fkf_filter *f, const fkf_obs *o, DevBuf<double> &Ht, Dev
 
 // Constant-H basis U0 = P R^-1/2 W_e (the generalized eigenvectors times
 // Lambda^1/2), Ve = R^-1/2 W_e, lambda; delta = D / lambda starts at zero.
-static void build_basis(fkf_filter *f, const fkf_obs *o, hipStream_t st) {
+// Constant-H bases of count filters (filter i with operator obs[i]): the
+// cross covariances, innovation Grams and, after one batched eigensolve of
+// the projected problems, the bases and carriers.
+struct BasisWork {
+  DevBuf<double> P, G, A;
+};
+
+static void build_bases(fkf_filter *const *fs, const fkf_obs *const *os, int count,
+                        hipStream_t st) {
   FKF_TRACE("gep_total", st);
-  const int64_t n = f->n;
-  const int nm = o->n_m;
-  DevBuf<double> Ht, P, G, A;
-  compute_gep(f, o, Ht, P, G, A, f->lam, f->Ve, st);
-  scale_rows(nm, nm, o->inv_sqrt_noise.p, f->Ve.p, nm, st);
-  f->ldu = (n + 63) / 64 * 64;
-  f->U0.alloc((size_t)f->ldu * nm);
-  fill(f->U0.p, f->ldu * nm, 0.0, st);
+  std::vector<BasisWork> bw(count);
+  std::vector<EigProblem> probs(count);
+  for (int i = 0; i < count; ++i) {
+    fkf_filter *f = fs[i];
+    const fkf_obs *o = os[i];
+    const int64_t n = f->n;
+    const int nm = o->n_m;
+    DevBuf<double> Ht;
+    Ht.reserve((size_t)n * nm);
+    bw[i].P.reserve((size_t)n * nm);
+    bw[i].G.reserve((size_t)nm * nm);
+    bw[i].A.reserve((size_t)nm * nm);
+    f->lam.alloc(nm);
+    f->Ve.alloc((size_t)nm * nm);
+    dense_ht(o->rowptr.p, o->col.p, o->val.p, nm, n, Ht.p, st);
+    {
+      FKF_TRACE("gep_cross_cov", st);
+      fkf_status rc = fkf_cov_apply(f->cov, Ht.p, n, nm, bw[i].P.p, n, (void *)st);
+      if (rc != FKF_OK) throw Error{rc, std::string("covariance product failed: ") + fkf_last_error()};
+    }
+    innovation_gram(o->rowptr.p, o->col.p, o->val.p, nm, n, bw[i].P.p, o->noise.p, bw[i].G.p,
+                    bw[i].A.p, st);
+    FKF_CHECK_HIP(hipStreamSynchronize(st));   // Ht is released at the end of this iteration
+    probs[i] = EigProblem{bw[i].A.p, nm, nm, 0, f->lam.p, f->Ve.p, nm};
+  }
   {
-    FKF_TRACE("gep_basis_gemm", st);
-    gemm_nn(n, nm, nm, P.p, n, f->Ve.p, nm, f->U0.p, f->ldu, st);
+    FKF_TRACE("gep_eig", st);
+    sym_eig_batched(probs.data(), count, st, fs[0]->eig);
   }
-  if (f->mixed) {
-    f->U0f.alloc((size_t)f->ldu * nm);
-    const int64_t len = f->ldu * (int64_t)nm;
-    if (len > 0) hipLaunchKernelGGL(k_to_f32, dim3(blocks(len)), dim3(256), 0, st, f->U0.p, f->U0f.p, len);
+  for (int i = 0; i < count; ++i) {
+    fkf_filter *f = fs[i];
+    const fkf_obs *o = os[i];
+    const int64_t n = f->n;
+    const int nm = o->n_m;
+    hipLaunchKernelGGL(k_clamp_nonneg, dim3(blocks(nm)), dim3(256), 0, st, f->lam.p, nm);
+    scale_rows(nm, nm, o->inv_sqrt_noise.p, f->Ve.p, nm, st);
+    f->ldu = (n + 63) / 64 * 64;
+    f->U0.alloc((size_t)f->ldu * nm);
+    fill(f->U0.p, f->ldu * nm, 0.0, st);
+    {
+      FKF_TRACE("gep_basis_gemm", st);
+      gemm_nn(n, nm, nm, bw[i].P.p, n, f->Ve.p, nm, f->U0.p, f->ldu, st);
+    }
+    if (f->mixed) {
+      f->U0f.alloc((size_t)f->ldu * nm);
+      const int64_t len = f->ldu * (int64_t)nm;
+      if (len > 0)
+        hipLaunchKernelGGL(k_to_f32, dim3(blocks(len)), dim3(256), 0, st, f->U0.p, f->U0f.p, len);
+    }
+    f->delta.alloc(nm);
+    fill(f->delta.p, nm, 0.0, st);
+    f->nu.alloc(nm);
+    f->zp.alloc(nm);
+    f->tmp.alloc(nm);
+    int nseg = (nm + kSegCols - 1) / kSegCols;
+    f->part.alloc((size_t)nseg * n);
+    f->b_rowptr.upload(o->rowptr_h, st);
+    f->b_col.upload(o->col_h, st);
+    f->b_val.upload(o->val_h, st);
+    // eta = Ve^T H s for the current estimate
+    f->eta.alloc(nm);
+    spmv(o->rowptr.p, o->col.p, o->val.p, nm, f->s.p, f->nu.p, st);
+    hipLaunchKernelGGL(k_vet, dim3(blocks(nm, 4)), dim3(256), 0, st, f->Ve.p, nm, f->nu.p,
+                       f->eta.p);
+    f->n_m = nm;
+    f->mode = 1;
+    f->basis_gen = o->gen;
   }
-  f->delta.alloc(nm);
-  fill(f->delta.p, nm, 0.0, st);
-  f->nu.alloc(nm);
-  f->zp.alloc(nm);
-  f->tmp.alloc(nm);
-  int nseg = (nm + kSegCols - 1) / kSegCols;
-  f->part.alloc((size_t)nseg * n);
-  f->b_rowptr.upload(o->rowptr_h, st);
-  f->b_col.upload(o->col_h, st);
-  f->b_val.upload(o->val_h, st);
-  // eta = Ve^T H s for the current estimate
-  f->eta.alloc(nm);
-  spmv(o->rowptr.p, o->col.p, o->val.p, nm, f->s.p, f->nu.p, st);
-  hipLaunchKernelGGL(k_vet, dim3(blocks(nm, 4)), dim3(256), 0, st, f->Ve.p, nm, f->nu.p, f->eta.p);
-  f->n_m = nm;
-  f->mode = 1;
-  f->basis_gen = o->gen;
-  FKF_CHECK_HIP(hipStreamSynchronize(st));   // P, Ht, G, A are released on return
+  FKF_CHECK_HIP(hipStreamSynchronize(st));   // P, G, A are released on return
+}
+
+static void build_basis(fkf_filter *f, const fkf_obs *o, hipStream_t st) {
+  build_bases(&f, &o, 1, st);
 }
 
 static std::vector<double> to_host(const double *p, size_t n, hipStream_t st) {
@@ -782,44 +828,75 @@ extern "C" fkf_status fkf_filter_create(fkf_cov *cov, const double *s0, double a
   });
 }
 
+// Argument and state checks of one filter step (throws).
+static void check_step(fkf_filter *f, const fkf_obs *o, const double *y, const char *who) {
+  if (!(f && o && y)) throw Error{FKF_E_ARG, std::string(who) + ": NULL argument"};
+  if (f->failed != FKF_OK) throw Error{FKF_E_ORDER, std::string(who) + ": filter has failed earlier"};
+  if (*f->err_host != 0) {
+    f->failed = (fkf_status)*f->err_host;
+    throw Error{f->failed, std::string(who) + ": a previous step produced non-finite values"};
+  }
+  if (o->n != f->n) throw Error{FKF_E_ARG, std::string(who) + ": operator size does not match the state"};
+}
+
+// The step after the basis (if any) is in place: prediction and update.
+static void step_after_basis(fkf_filter *f, const fkf_obs *o, const double *y, hipStream_t st) {
+  if (f->mode == 1 && o->gen != f->basis_gen) to_general(f, st);
+  if (f->mode == 2) {
+    step_general(f, o, y, st);
+    FKF_CHECK_HIP(hipMemcpyAsync(f->err_host, f->err.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    FKF_CHECK_HIP(hipGetLastError());
+    f->alpha += 1.0;
+    f->k += 1;
+    return;
+  }
+  const double alpha_new = f->alpha + 1.0;   // prediction (F = I)
+  const int nm = f->n_m;
+  FKF_TRACE("filter_step", st);
+  hipLaunchKernelGGL(k_modes_step_eta, dim3(blocks(nm, 4)), dim3(256), 0, st, f->Ve.p, nm, y,
+                     f->lam.p, f->delta.p, f->eta.p, alpha_new, f->zp.p, f->err.p);
+  gemv_seg(f, f->zp.p, false, st);
+  {
+    int nseg = (nm + kSegCols - 1) / kSegCols;
+    hipLaunchKernelGGL(k_seg_add, dim3(blocks(f->n)), dim3(256), 0, st, f->part.p, nseg, f->n,
+                       f->s.p, f->err.p, f->err_host);
+  }
+  FKF_CHECK_HIP(hipGetLastError());
+  f->alpha = alpha_new;
+  f->k += 1;
+}
+
 extern "C" fkf_status fkf_filter_step(fkf_filter *f, const fkf_obs *o, const double *y,
                                       void *stream) {
   return guarded([&] {
-    FKF_REQUIRE(f && o && y, "fkf_filter_step: NULL argument");
-    if (f->failed != FKF_OK) throw Error{FKF_E_ORDER, "fkf_filter_step: filter has failed earlier"};
-    if (*f->err_host != 0) {
-      f->failed = (fkf_status)*f->err_host;
-      throw Error{f->failed, "fkf_filter_step: a previous step produced non-finite values"};
-    }
-    FKF_REQUIRE(o->n == f->n, "fkf_filter_step: operator size does not match the state");
+    check_step(f, o, y, "fkf_filter_step");
     hipStream_t st = as_stream(stream);
-    if (f->mode == 0) {
-      build_basis(f, o, st);
-    } else if (f->mode == 1 && o->gen != f->basis_gen) {
-      to_general(f, st);
+    if (f->mode == 0) build_basis(f, o, st);
+    step_after_basis(f, o, y, st);
+  });
+}
+
+extern "C" fkf_status fkf_filter_step_many(fkf_filter *const *filters, const fkf_obs *const *obs,
+                                           const double *const *y, int32_t count, void *stream) {
+  return guarded([&] {
+    FKF_REQUIRE(count >= 0, "fkf_filter_step_many: count < 0");
+    if (count == 0) return;
+    FKF_REQUIRE(filters && obs && y, "fkf_filter_step_many: NULL array");
+    for (int i = 0; i < count; ++i) {
+      check_step(filters[i], obs[i], y[i], "fkf_filter_step_many");
+      for (int j = 0; j < i; ++j)
+        FKF_REQUIRE(filters[j] != filters[i], "fkf_filter_step_many: a filter appears twice");
     }
-    if (f->mode == 2) {
-      step_general(f, o, y, st);
-      FKF_CHECK_HIP(hipMemcpyAsync(f->err_host, f->err.p, sizeof(int), hipMemcpyDeviceToHost, st));
-      FKF_CHECK_HIP(hipGetLastError());
-      f->alpha += 1.0;
-      f->k += 1;
-      return;
-    }
-    const double alpha_new = f->alpha + 1.0;   // prediction (F = I)
-    const int nm = f->n_m;
-    FKF_TRACE("filter_step", st);
-    hipLaunchKernelGGL(k_modes_step_eta, dim3(blocks(nm, 4)), dim3(256), 0, st, f->Ve.p, nm, y,
-                       f->lam.p, f->delta.p, f->eta.p, alpha_new, f->zp.p, f->err.p);
-    gemv_seg(f, f->zp.p, false, st);
-    {
-      int nseg = (nm + kSegCols - 1) / kSegCols;
-      hipLaunchKernelGGL(k_seg_add, dim3(blocks(f->n)), dim3(256), 0, st, f->part.p, nseg, f->n,
-                         f->s.p, f->err.p, f->err_host);
-    }
-    FKF_CHECK_HIP(hipGetLastError());
-    f->alpha = alpha_new;
-    f->k += 1;
+    hipStream_t st = as_stream(stream);
+    std::vector<fkf_filter *> nf;
+    std::vector<const fkf_obs *> no;
+    for (int i = 0; i < count; ++i)
+      if (filters[i]->mode == 0) {
+        nf.push_back(filters[i]);
+        no.push_back(obs[i]);
+      }
+    if (!nf.empty()) build_bases(nf.data(), no.data(), (int)nf.size(), st);
+    for (int i = 0; i < count; ++i) step_after_basis(filters[i], obs[i], y[i], st);
   });
 }
 

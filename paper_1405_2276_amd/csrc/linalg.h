@@ -5,11 +5,23 @@
 
 namespace fkf {
 
+// One symmetric eigenproblem of a batch: A (n x n, column-major, lda) in,
+// eigenvalues w (n, descending) and eigenvectors W (n x n, ldw) out.
+struct EigProblem {
+  const double *A;
+  int64_t lda;
+  int32_t n, pad;
+  double *w;
+  double *W;
+  int64_t ldw;
+};
+
 // Workspace of the symmetric eigensolver (grown on demand).
 struct EigWork {
   DevBuf<double> A, A2, V, J, J2, fro;   // A, J double-buffered across rounds
   DevBuf<int> cnt;
   DevBuf<int32_t> pidx;       // pair index table of the rounds
+  DevBuf<EigProblem> probs;   // descriptors of the batch
   int pidx_np = -1;
   int *cnt_host = nullptr;   // pinned host scratch (4 ints; [2]: convergence flag)
   hipEvent_t ev = nullptr;   // marks the convergence test of the last sweep
@@ -22,6 +34,11 @@ struct EigWork {
 // the stream once per sweep to test convergence.
 int sym_eig(const double *A, int64_t lda, int n, double *w, double *W, int64_t ldw,
             hipStream_t st, EigWork &ws);
+
+// The same for count independent problems in one sequence of launches (all
+// padded to the largest order, one convergence flag each).  Returns the
+// number of sweeps of the slowest problem.
+int sym_eig_batched(const EigProblem *probs, int count, hipStream_t st, EigWork &ws);
 
 // y (n_m) = H x for CSR H.
 void spmv(const int64_t *rowptr, const int32_t *col, const double *val, int n_m,

@@ -65,55 +65,88 @@ __device__ __forceinline__ bool jacobi_rotation(double app, double aqq, double a
   return rot;
 }
 
-__global__ void k_jacobi_init(const double *__restrict__ A, int64_t lda, int n, int np,
-                              double *__restrict__ Ap, double *__restrict__ V) {
+// Batched form: blockIdx.y (or .z) selects problem b; problem b's padded
+// matrices start at b * np * np, its rotations at b * npair * 32 * 32, its
+// norms at b * (2 + np) (fro[0] = ||A||_F, fro[1] = relative off-diagonal
+// norm, fro[2..] column partials) and its counters at b * (3 + np)
+// (cnt[0] = workgroups that rotated in the sweep, cnt[1..np] rank scratch,
+// cnt[1 + np] = convergence flag, cnt[2 + np] = A buffer holding the
+// converged matrix, or -1).
+__global__ void k_jacobi_init(const EigProblem *__restrict__ pr, int np, double *__restrict__ Ap,
+                              double *__restrict__ V) {
+  const int b = blockIdx.y;
+  const EigProblem q = pr[b];
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)np * np) return;
   int i = (int)(e % np), j = (int)(e / np);
-  Ap[e] = (i < n && j < n) ? A[i + lda * j] : 0.0;
-  V[e] = (i == j) ? 1.0 : 0.0;
+  const int64_t o = (int64_t)b * np * np;
+  Ap[o + e] = (i < q.n && j < q.n) ? q.A[i + q.lda * j] : 0.0;
+  V[o + e] = (i == j) ? 1.0 : 0.0;
 }
 
 __global__ void k_set_int(int *p, int v) { *p = v; }
 
-// Convergence flag of a sweep: relative off-diagonal norm <= tol, or no
-// workgroup rotated anything.
-__global__ void k_eig_converged(const double *__restrict__ rel_off, const int *__restrict__ cnt,
-                                double tol, int *__restrict__ done, int *__restrict__ done_host) {
-  const int d = (rel_off[0] <= tol || cnt[0] == 0) ? 1 : 0;
-  done[0] = d;
-  done_host[0] = d;
+// cnt[b * stride] = v for every problem b
+__global__ void k_set_int_strided(int *p, int64_t stride, int count, int v) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < count) p[b * stride] = v;
 }
 
-// Off-diagonal sum of squares: one workgroup per column (partials), then
-// off[0] = sqrt(sum of partials) / fro in a fixed order.
+// Convergence flags after a sweep: problem b has converged when its relative
+// off-diagonal norm is <= tol or none of its workgroups rotated anything (a
+// converged problem stays converged).  done_host[0] = 1 when all have.
+__global__ void k_eig_converged(const double *__restrict__ fro, int *__restrict__ cnt, int np,
+                                int count, double tol, int cur_buf, int *__restrict__ done_host) {
+  __shared__ int all;
+  if (threadIdx.x == 0) all = 1;
+  __syncthreads();
+  for (int b = threadIdx.x; b < count; b += blockDim.x) {
+    const double *f = fro + (int64_t)b * (2 + np);
+    int *c = cnt + (int64_t)b * (3 + np);
+    const int was = c[1 + np];
+    const int d = (was != 0 || f[1] <= tol || c[0] == 0) ? 1 : 0;
+    if (d && !was) c[2 + np] = cur_buf;   // later launches leave this problem's A there
+    c[1 + np] = d;
+    if (!d) all = 0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) done_host[0] = all;
+}
+
+// Off-diagonal sum of squares: one workgroup per (column, problem)
+// (partials), then one workgroup per problem sums them in a fixed order.
 __global__ void __launch_bounds__(256) k_offnorm_cols(const double *__restrict__ A, int np,
-                                                      double *__restrict__ part, int with_diag) {
+                                                      double *__restrict__ fro, int with_diag) {
   __shared__ double red[4];
-  const int j = blockIdx.x;
+  const int j = blockIdx.x, b = blockIdx.y;
+  const double *Ab = A + (int64_t)b * np * np;
   double s = 0;
   for (int i = threadIdx.x; i < np; i += 256) {
-    double v = A[i + (int64_t)np * j];
+    double v = Ab[i + (int64_t)np * j];
     if (i != j || with_diag) s = fma(v, v, s);
   }
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) part[j] = red[0] + red[1] + red[2] + red[3];
+  if (threadIdx.x == 0) fro[(int64_t)b * (2 + np) + 2 + j] = red[0] + red[1] + red[2] + red[3];
 }
 
-__global__ void __launch_bounds__(256) k_offnorm_final(const double *__restrict__ part, int np,
-                                                       const double *__restrict__ fro,
-                                                       double *__restrict__ off) {
+// initial: fro[0] = sqrt(sum); else fro[1] = sqrt(sum) / fro[0]
+__global__ void __launch_bounds__(256) k_offnorm_final(double *__restrict__ fro, int np,
+                                                       int initial) {
   __shared__ double red[4];
+  double *f = fro + (int64_t)blockIdx.x * (2 + np);
   double s = 0;
-  for (int j = threadIdx.x; j < np; j += 256) s += part[j];
+  for (int j = threadIdx.x; j < np; j += 256) s += f[2 + j];
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
     double t = red[0] + red[1] + red[2] + red[3];
-    off[0] = fro ? (fro[0] > 0 ? sqrt(t) / fro[0] : 0.0) : sqrt(t);
+    if (initial)
+      f[0] = sqrt(t);
+    else
+      f[1] = f[0] > 0 ? sqrt(t) / f[0] : 0.0;
   }
 }
 
@@ -372,10 +405,12 @@ __device__ void jacobi_update_part(double *smem, int w, const double *__restrict
   }
 }
 
-// One launch per round: workgroups [0, npair) solve the pairs of round r
-// (when solve_on), the rest apply the pending rotations of round rprev (when
-// rprev >= 0) to A (Acur -> Anext) and V.  The two parts only read Acur, so
-// they run concurrently; one LDS region serves either part.
+// One launch per round for every problem of the batch (blockIdx.y):
+// workgroups [0, npair) solve the pairs of round r (when solve_on), the rest
+// apply the pending rotations of round rprev (when rprev >= 0) to A
+// (Acur -> Anext) and V.  The two parts only read Acur, so they run
+// concurrently; one LDS region serves either part.  A problem that has
+// converged skips the launch entirely.
 __global__ void __launch_bounds__(256) k_jacobi_round(const double *__restrict__ Acur,
                                                       double *__restrict__ Anext,
                                                       double *__restrict__ V, int np, int nb,
@@ -383,38 +418,55 @@ __global__ void __launch_bounds__(256) k_jacobi_round(const double *__restrict__
                                                       int r, int solve_on, int rprev,
                                                       const double *__restrict__ Jprev,
                                                       double *__restrict__ Jcur,
-                                                      const double *__restrict__ fro, int *cnt,
-                                                      const int *__restrict__ done) {
+                                                      const double *__restrict__ fro, int *cnt) {
   __shared__ double smem[kRoundSmem];
-  if (*done) return;   // converged at the previous sweep: the whole launch is empty
+  const int b = blockIdx.y;
+  int *c = cnt + (int64_t)b * (3 + np);
+  if (c[1 + np]) return;   // converged: this problem's part of the launch is empty
   const int npair = nb / 2;
+  const int64_t oa = (int64_t)b * np * np, oj = (int64_t)b * npair * kJT * kJT;
   const int nsolve = solve_on ? npair : 0;
   if ((int)blockIdx.x < nsolve)
-    jacobi_solve_part(smem, Acur, np, nb, pidx, blockIdx.x, r, rprev, Jprev, fro, Jcur, cnt);
+    jacobi_solve_part(smem, Acur + oa, np, nb, pidx, blockIdx.x, r, rprev, Jprev + oj,
+                      fro + (int64_t)b * (2 + np), Jcur + oj, c);
   else
-    jacobi_update_part(smem, blockIdx.x - nsolve, Acur, Anext, V, np, nb, pidx, rprev, Jprev);
+    jacobi_update_part(smem, blockIdx.x - nsolve, Acur + oa, Anext + oa, V + oa, np, nb, pidx,
+                       rprev, Jprev + oj);
 }
 
-// Eigenvalues from the diagonal, ranked in descending order (ties by index).
-__global__ void __launch_bounds__(1024) k_eig_rank(const double *__restrict__ Ap, int np, int n,
-                                                   double *__restrict__ w, int *__restrict__ rank) {
-  for (int i = threadIdx.x; i < n; i += 1024) {
+// Eigenvalues from the diagonal, ranked in descending order (ties by index),
+// one workgroup per problem.
+__global__ void __launch_bounds__(1024) k_eig_rank(const EigProblem *__restrict__ pr,
+                                                   const double *__restrict__ A0,
+                                                   const double *__restrict__ A1, int last_buf,
+                                                   int np, int *__restrict__ cnt) {
+  const int b = blockIdx.x;
+  const EigProblem q = pr[b];
+  int *c = cnt + (int64_t)b * (3 + np);
+  const int buf = c[2 + np] >= 0 ? c[2 + np] : last_buf;
+  const double *Ap = (buf ? A1 : A0) + (int64_t)b * np * np;
+  int *rank = c + 1;
+  for (int i = threadIdx.x; i < q.n; i += 1024) {
     double li = Ap[i + (int64_t)np * i];
     int r = 0;
-    for (int j = 0; j < n; ++j) {
+    for (int j = 0; j < q.n; ++j) {
       double lj = Ap[j + (int64_t)np * j];
       r += (lj > li) || (lj == li && j < i);
     }
-    w[r] = li;
+    q.w[r] = li;
     rank[i] = r;
   }
 }
 
-__global__ void k_eig_vecs(const double *__restrict__ V, int np, int n, const int *__restrict__ rank,
-                           double *__restrict__ W, int64_t ldw) {
+__global__ void k_eig_vecs(const EigProblem *__restrict__ pr, const double *__restrict__ V, int np,
+                           const int *__restrict__ cnt) {
+  const int b = blockIdx.z;
+  const EigProblem q = pr[b];
   int r = blockIdx.y * blockDim.x + threadIdx.x;
   int i = blockIdx.x;
-  if (r < n) W[r + ldw * rank[i]] = V[r + (int64_t)np * i];
+  if (i >= q.n || r >= q.n) return;
+  const int *rank = cnt + (int64_t)b * (3 + np) + 1;
+  q.W[r + q.ldw * rank[i]] = V[(int64_t)b * np * np + r + (int64_t)np * i];
 }
 
 EigWork::~EigWork() {
@@ -422,19 +474,21 @@ EigWork::~EigWork() {
   if (ev) (void)hipEventDestroy(ev);
 }
 
-int sym_eig(const double *A, int64_t lda, int n, double *w, double *W, int64_t ldw,
-            hipStream_t st, EigWork &ws) {
-  if (n <= 0) return 0;
-  const int np = (n + kJT - 1) / kJT * kJT;
+int sym_eig_batched(const EigProblem *probs, int count, hipStream_t st, EigWork &ws) {
+  int nmax = 0;
+  for (int b = 0; b < count; ++b) nmax = std::max(nmax, probs[b].n);
+  if (count <= 0 || nmax <= 0) return 0;
+  const int np = (nmax + kJT - 1) / kJT * kJT;
   const int nb = np / kJB;
   const int npair = nb / 2;
-  ws.A.reserve((size_t)np * np);
-  ws.A2.reserve((size_t)np * np);
-  ws.V.reserve((size_t)np * np);
-  ws.J.reserve((size_t)npair * kJT * kJT);
-  ws.J2.reserve((size_t)npair * kJT * kJT);
-  ws.fro.reserve(2 + np);   // ||A||_F, relative off-diagonal norm, column partials
-  ws.cnt.reserve(2 + np);   // counter, rank scratch, convergence flag
+  const size_t sq = (size_t)np * np * count;
+  ws.A.reserve(sq);
+  ws.A2.reserve(sq);
+  ws.V.reserve(sq);
+  ws.J.reserve((size_t)npair * kJT * kJT * count);
+  ws.J2.reserve((size_t)npair * kJT * kJT * count);
+  ws.fro.reserve((size_t)(2 + np) * count);
+  ws.cnt.reserve((size_t)(3 + np) * count);
   if (!ws.cnt_host) FKF_CHECK_HIP(hipHostMalloc((void **)&ws.cnt_host, 4 * sizeof(int)));
   if (!ws.ev) FKF_CHECK_HIP(hipEventCreateWithFlags(&ws.ev, hipEventDisableTiming));
   if (ws.pidx_np != np) {
@@ -451,39 +505,45 @@ int sym_eig(const double *A, int64_t lda, int n, double *w, double *W, int64_t l
     FKF_CHECK_HIP(hipStreamSynchronize(st));   // t is a host temporary
     ws.pidx_np = np;
   }
+  std::vector<EigProblem> hp(probs, probs + count);
+  ws.probs.upload(hp, st);
+  FKF_CHECK_HIP(hipStreamSynchronize(st));     // hp is a host temporary
+  const int64_t cstride = 3 + np;
   int64_t tot = (int64_t)np * np;
-  hipLaunchKernelGGL(k_jacobi_init, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, A, lda,
-                     n, np, ws.A.p, ws.V.p);
-  hipLaunchKernelGGL(k_offnorm_cols, dim3(np), dim3(256), 0, st, ws.A.p, np, ws.fro.p + 2, 1);
-  hipLaunchKernelGGL(k_offnorm_final, dim3(1), dim3(256), 0, st, ws.fro.p + 2, np,
-                     (const double *)nullptr, ws.fro.p);
+  hipLaunchKernelGGL(k_jacobi_init, dim3((unsigned)((tot + 255) / 256), count), dim3(256), 0, st,
+                     ws.probs.p, np, ws.A.p, ws.V.p);
+  hipLaunchKernelGGL(k_offnorm_cols, dim3(np, count), dim3(256), 0, st, ws.A.p, np, ws.fro.p, 1);
+  hipLaunchKernelGGL(k_offnorm_final, dim3(count), dim3(256), 0, st, ws.fro.p, np, 1);
+  hipLaunchKernelGGL(k_set_int_strided, dim3((count + 255) / 256), dim3(256), 0, st,
+                     ws.cnt.p + 1 + np, cstride, count, 0);
+  hipLaunchKernelGGL(k_set_int_strided, dim3((count + 255) / 256), dim3(256), 0, st,
+                     ws.cnt.p + 2 + np, cstride, count, -1);
   const unsigned grid_upd = (unsigned)(npair * npair + (np / kJT) * npair);
   // Rounds are launched as k_jacobi_round: the solve of round r runs next to
   // the update of round r - 1 (A double-buffered, J double-buffered); the last
-  // update of a sweep runs alone before the convergence test.  Stop when the
-  // relative off-diagonal norm is below 1e-12 (a perturbation of at most
-  // 1e-12 ||A||_F on the eigenvalues) or a sweep rotates nothing.
+  // update of a sweep runs alone before the convergence test.  A problem has
+  // converged when its relative off-diagonal norm is below 1e-12 (a
+  // perturbation of at most 1e-12 ||A||_F on the eigenvalues) or a sweep
+  // rotates nothing; the batch stops when all have.  The test of sweep s is
+  // read on the host while sweep s + 1 is already queued (no idle GPU during
+  // the host round trip); launches of a converged problem are empty.
   double *Ab[2] = {ws.A.p, ws.A2.p};
   double *Jb[2] = {ws.J.p, ws.J2.p};
   int ca = 0, cj = 0;   // current A buffer; J buffer written by the next solve
-  int *done = ws.cnt.p + 1 + np;    // device convergence flag
   volatile int *done_host = ws.cnt_host + 2;
-  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, done, 0);
-  // The convergence test of sweep s is read on the host while sweep s + 1 is
-  // already queued (no idle GPU during the host round trip); kernels of a
-  // sweep that follows convergence exit at once, leaving A and V untouched.
   int sweeps = 0, ca_prev = 0;
   for (int sw = 0; sw < 40; ++sw) {
-    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, ws.cnt.p, 0);
+    hipLaunchKernelGGL(k_set_int_strided, dim3((count + 255) / 256), dim3(256), 0, st, ws.cnt.p,
+                       cstride, count, 0);
     int rprev = -1;
     for (int r = 0; r <= nb - 1; ++r) {
       const bool solve = r < nb - 1;
       const unsigned grid = (solve ? npair : 0) + (rprev >= 0 ? grid_upd : 0);
       {
         FKF_TRACE("eig_jacobi_round", st);
-        hipLaunchKernelGGL(k_jacobi_round, dim3(grid), dim3(256), 0, st, Ab[ca], Ab[ca ^ 1], ws.V.p,
-                           np, nb, ws.pidx.p, r, solve ? 1 : 0, rprev, Jb[cj ^ 1], Jb[cj],
-                           ws.fro.p, ws.cnt.p, done);
+        hipLaunchKernelGGL(k_jacobi_round, dim3(grid, count), dim3(256), 0, st, Ab[ca],
+                           Ab[ca ^ 1], ws.V.p, np, nb, ws.pidx.p, r, solve ? 1 : 0, rprev,
+                           Jb[cj ^ 1], Jb[cj], ws.fro.p, ws.cnt.p);
       }
       if (rprev >= 0) ca ^= 1;   // the update wrote the other A buffer
       if (solve) {
@@ -491,10 +551,9 @@ int sym_eig(const double *A, int64_t lda, int n, double *w, double *W, int64_t l
         rprev = r;
       }
     }
-    hipLaunchKernelGGL(k_offnorm_cols, dim3(np), dim3(256), 0, st, Ab[ca], np, ws.fro.p + 2, 0);
-    hipLaunchKernelGGL(k_offnorm_final, dim3(1), dim3(256), 0, st, ws.fro.p + 2, np, ws.fro.p,
-                       ws.fro.p + 1);
-    // wait for the previous sweep's flag (this sweep is queued behind it)
+    hipLaunchKernelGGL(k_offnorm_cols, dim3(np, count), dim3(256), 0, st, Ab[ca], np, ws.fro.p, 0);
+    hipLaunchKernelGGL(k_offnorm_final, dim3(count), dim3(256), 0, st, ws.fro.p, np, 0);
+    // wait for the previous sweep's flags (this sweep is queued behind them)
     if (sw > 0) {
       FKF_CHECK_HIP(hipEventSynchronize(ws.ev));
       if (*done_host) {
@@ -504,19 +563,25 @@ int sym_eig(const double *A, int64_t lda, int n, double *w, double *W, int64_t l
     }
     ++sweeps;
     *done_host = 0;
-    hipLaunchKernelGGL(k_eig_converged, dim3(1), dim3(1), 0, st, ws.fro.p + 1, ws.cnt.p, 1e-12,
-                       done, (int *)done_host);
+    hipLaunchKernelGGL(k_eig_converged, dim3(1), dim3(256), 0, st, ws.fro.p, ws.cnt.p, np, count,
+                       1e-12, ca, (int *)done_host);
     FKF_CHECK_HIP(hipEventRecord(ws.ev, st));
     ca_prev = ca;
     if (sw == 39) FKF_CHECK_HIP(hipEventSynchronize(ws.ev));
   }
-  const double *Af = Ab[ca];
-  int *rank = ws.cnt.p + 1;
-  hipLaunchKernelGGL(k_eig_rank, dim3(1), dim3(1024), 0, st, Af, np, n, w, rank);
-  hipLaunchKernelGGL(k_eig_vecs, dim3(n, (unsigned)((n + 255) / 256)), dim3(256), 0, st, ws.V.p,
-                     np, n, rank, W, ldw);
+  hipLaunchKernelGGL(k_eig_rank, dim3(count), dim3(1024), 0, st, ws.probs.p, Ab[0], Ab[1], ca, np,
+                     ws.cnt.p);
+  hipLaunchKernelGGL(k_eig_vecs, dim3(np, (unsigned)((np + 255) / 256), count), dim3(256), 0, st,
+                     ws.probs.p, ws.V.p, np, ws.cnt.p);
   FKF_CHECK_HIP(hipGetLastError());
   return sweeps;
+}
+
+int sym_eig(const double *A, int64_t lda, int n, double *w, double *W, int64_t ldw,
+            hipStream_t st, EigWork &ws) {
+  if (n <= 0) return 0;
+  EigProblem p{A, lda, n, 0, w, W, ldw};
+  return sym_eig_batched(&p, 1, st, ws);
 }
 
 // ========================================================= sparse products ===

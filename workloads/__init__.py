@@ -126,6 +126,24 @@ CUBE = Workload("crosswell-64^3", 5, (64, 64, 64), 0.5, 0.15, 1e-4, (4, 8), (8, 
 WORKLOADS = {w.name: w for w in (SMALL, MEDIUM, LARGE, CUBE)}
 
 
+def batch(count: int = 64, steps: int = 10):
+    """Independent filters of uneven size for the many-filter form: square
+    grids with side uniform on {64, 72, ..., 256} (N = 4096 ... 65536),
+    Matern nu in {1/2, 3/2} (fair coin), length uniform on [0.1, 0.3],
+    variance 1e-4, crosswell rays with n_src uniform on {8..24} and n_rcv on
+    {8..20} (64 ... 480 rays), R = 1e-4 I, `steps` steps each."""
+    g = np.random.default_rng(np.random.SeedSequence([ROOT_SEED, 4, 0]))
+    out = []
+    for i in range(count):
+        side = int(g.choice(np.arange(64, 257, 8)))
+        nu = float(g.choice([0.5, 1.5]))
+        ell = float(g.uniform(0.1, 0.3))
+        ns, nr = int(g.integers(8, 25)), int(g.integers(8, 21))
+        out.append(Workload(f"batch-{i}-{side}x{side}", 400 + i, (side, side), nu, ell, 1e-4,
+                            ns, nr, 1e-4, steps, 0.01))
+    return out
+
+
 def tiny(shape=(8, 8), nu=0.5, length=0.3, variance=1.0, n_src=3, n_rcv=4,
          noise_var=1e-2, steps=4, drift_sigma=1.0, cfg_id=100, leaf_size=16,
          cheb_order=6) -> Workload:
