@@ -27,7 +27,9 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <map>
 #include <memory>
+#include <mutex>
 
 #include "kernels.h"
 #include "linalg.h"
@@ -397,11 +399,65 @@ static void compute_gep(fkf_filter *f, const fkf_obs *o, DevBuf<double> &Ht, Dev
 
 // Constant-H basis U0 = P R^-1/2 W_e (the generalized eigenvectors times
 // Lambda^1/2), Ve = R^-1/2 W_e, lambda; delta = D / lambda starts at zero.
+// Streams (default priority) over which the work of independent filters is
+// spread, and the fork/join between them and the caller's stream: lane c of
+// a fork runs on pool stream c after everything queued on the caller's
+// stream so far; the join makes the caller's stream wait for every lane.
+constexpr int kLanes = 4;
+struct LanePool {
+  hipStream_t s[kLanes] = {};
+  hipEvent_t fork = nullptr, join[kLanes] = {};
+};
+
+static LanePool &lane_pool() {
+  static std::mutex mu;
+  static std::map<int, LanePool> pools;   // per device
+  int dev = 0;
+  FKF_CHECK_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  LanePool &p = pools[dev];
+  if (!p.fork) {
+    for (int c = 0; c < kLanes; ++c) {
+      FKF_CHECK_HIP(hipStreamCreateWithFlags(&p.s[c], hipStreamNonBlocking));
+      FKF_CHECK_HIP(hipEventCreateWithFlags(&p.join[c], hipEventDisableTiming));
+    }
+    FKF_CHECK_HIP(hipEventCreateWithFlags(&p.fork, hipEventDisableTiming));
+  }
+  return p;
+}
+
+static void lanes_fork(LanePool &p, hipStream_t st) {
+  FKF_CHECK_HIP(hipEventRecord(p.fork, st));
+  for (int c = 0; c < kLanes; ++c) FKF_CHECK_HIP(hipStreamWaitEvent(p.s[c], p.fork, 0));
+}
+
+static void lanes_join(LanePool &p, hipStream_t st) {
+  for (int c = 0; c < kLanes; ++c) {
+    FKF_CHECK_HIP(hipEventRecord(p.join[c], p.s[c]));
+    FKF_CHECK_HIP(hipStreamWaitEvent(st, p.join[c], 0));
+  }
+}
+
+// Lane of each filter: filters that share a covariance operator (whose
+// product workspace is not reentrant) share a lane.
+static std::vector<int> lanes_of(fkf_filter *const *fs, int count) {
+  std::map<const fkf_cov *, int> m;
+  std::vector<int> lane(count);
+  for (int i = 0; i < count; ++i) {
+    auto it = m.find(fs[i]->cov);
+    if (it == m.end()) it = m.emplace(fs[i]->cov, (int)m.size() % kLanes).first;
+    lane[i] = it->second;
+  }
+  return lane;
+}
+
 // Constant-H bases of count filters (filter i with operator obs[i]): the
 // cross covariances, innovation Grams and, after one batched eigensolve of
-// the projected problems, the bases and carriers.
+// the projected problems, the bases and carriers.  With several filters the
+// per-filter work runs on kLanes streams (joined before the eigensolve and
+// at the end).
 struct BasisWork {
-  DevBuf<double> P, G, A;
+  DevBuf<double> Ht, P, G, A;
 };
 
 static void build_bases(fkf_filter *const *fs, const fkf_obs *const *os, int count,
@@ -409,73 +465,82 @@ static void build_bases(fkf_filter *const *fs, const fkf_obs *const *os, int cou
   FKF_TRACE("gep_total", st);
   std::vector<BasisWork> bw(count);
   std::vector<EigProblem> probs(count);
+  const bool multi = count > 1;
+  LanePool *lp = multi ? &lane_pool() : nullptr;
+  const std::vector<int> lane = lanes_of(fs, count);
+  auto sti = [&](int i) { return multi ? lp->s[lane[i]] : st; };
+  if (multi) lanes_fork(*lp, st);
   for (int i = 0; i < count; ++i) {
     fkf_filter *f = fs[i];
     const fkf_obs *o = os[i];
     const int64_t n = f->n;
     const int nm = o->n_m;
-    DevBuf<double> Ht;
+    hipStream_t si = sti(i);
+    DevBuf<double> &Ht = bw[i].Ht;
     Ht.reserve((size_t)n * nm);
     bw[i].P.reserve((size_t)n * nm);
     bw[i].G.reserve((size_t)nm * nm);
     bw[i].A.reserve((size_t)nm * nm);
     f->lam.alloc(nm);
     f->Ve.alloc((size_t)nm * nm);
-    dense_ht(o->rowptr.p, o->col.p, o->val.p, nm, n, Ht.p, st);
+    dense_ht(o->rowptr.p, o->col.p, o->val.p, nm, n, Ht.p, si);
     {
-      FKF_TRACE("gep_cross_cov", st);
-      fkf_status rc = fkf_cov_apply(f->cov, Ht.p, n, nm, bw[i].P.p, n, (void *)st);
+      FKF_TRACE("gep_cross_cov", si);
+      fkf_status rc = fkf_cov_apply(f->cov, Ht.p, n, nm, bw[i].P.p, n, (void *)si);
       if (rc != FKF_OK) throw Error{rc, std::string("covariance product failed: ") + fkf_last_error()};
     }
     innovation_gram(o->rowptr.p, o->col.p, o->val.p, nm, n, bw[i].P.p, o->noise.p, bw[i].G.p,
-                    bw[i].A.p, st);
-    FKF_CHECK_HIP(hipStreamSynchronize(st));   // Ht is released at the end of this iteration
+                    bw[i].A.p, si);
     probs[i] = EigProblem{bw[i].A.p, nm, nm, 0, f->lam.p, f->Ve.p, nm};
   }
+  if (multi) lanes_join(*lp, st);
   {
     FKF_TRACE("gep_eig", st);
     sym_eig_batched(probs.data(), count, st, fs[0]->eig);
   }
+  if (multi) lanes_fork(*lp, st);
   for (int i = 0; i < count; ++i) {
     fkf_filter *f = fs[i];
     const fkf_obs *o = os[i];
     const int64_t n = f->n;
     const int nm = o->n_m;
-    hipLaunchKernelGGL(k_clamp_nonneg, dim3(blocks(nm)), dim3(256), 0, st, f->lam.p, nm);
-    scale_rows(nm, nm, o->inv_sqrt_noise.p, f->Ve.p, nm, st);
+    hipStream_t si = sti(i);
+    hipLaunchKernelGGL(k_clamp_nonneg, dim3(blocks(nm)), dim3(256), 0, si, f->lam.p, nm);
+    scale_rows(nm, nm, o->inv_sqrt_noise.p, f->Ve.p, nm, si);
     f->ldu = (n + 63) / 64 * 64;
     f->U0.alloc((size_t)f->ldu * nm);
-    fill(f->U0.p, f->ldu * nm, 0.0, st);
+    fill(f->U0.p, f->ldu * nm, 0.0, si);
     {
-      FKF_TRACE("gep_basis_gemm", st);
-      gemm_nn(n, nm, nm, bw[i].P.p, n, f->Ve.p, nm, f->U0.p, f->ldu, st);
+      FKF_TRACE("gep_basis_gemm", si);
+      gemm_nn(n, nm, nm, bw[i].P.p, n, f->Ve.p, nm, f->U0.p, f->ldu, si);
     }
     if (f->mixed) {
       f->U0f.alloc((size_t)f->ldu * nm);
       const int64_t len = f->ldu * (int64_t)nm;
       if (len > 0)
-        hipLaunchKernelGGL(k_to_f32, dim3(blocks(len)), dim3(256), 0, st, f->U0.p, f->U0f.p, len);
+        hipLaunchKernelGGL(k_to_f32, dim3(blocks(len)), dim3(256), 0, si, f->U0.p, f->U0f.p, len);
     }
     f->delta.alloc(nm);
-    fill(f->delta.p, nm, 0.0, st);
+    fill(f->delta.p, nm, 0.0, si);
     f->nu.alloc(nm);
     f->zp.alloc(nm);
     f->tmp.alloc(nm);
     int nseg = (nm + kSegCols - 1) / kSegCols;
     f->part.alloc((size_t)nseg * n);
-    f->b_rowptr.upload(o->rowptr_h, st);
-    f->b_col.upload(o->col_h, st);
-    f->b_val.upload(o->val_h, st);
+    f->b_rowptr.upload(o->rowptr_h, si);
+    f->b_col.upload(o->col_h, si);
+    f->b_val.upload(o->val_h, si);
     // eta = Ve^T H s for the current estimate
     f->eta.alloc(nm);
-    spmv(o->rowptr.p, o->col.p, o->val.p, nm, f->s.p, f->nu.p, st);
-    hipLaunchKernelGGL(k_vet, dim3(blocks(nm, 4)), dim3(256), 0, st, f->Ve.p, nm, f->nu.p,
+    spmv(o->rowptr.p, o->col.p, o->val.p, nm, f->s.p, f->nu.p, si);
+    hipLaunchKernelGGL(k_vet, dim3(blocks(nm, 4)), dim3(256), 0, si, f->Ve.p, nm, f->nu.p,
                        f->eta.p);
     f->n_m = nm;
     f->mode = 1;
     f->basis_gen = o->gen;
   }
-  FKF_CHECK_HIP(hipStreamSynchronize(st));   // P, G, A are released on return
+  if (multi) lanes_join(*lp, st);
+  FKF_CHECK_HIP(hipStreamSynchronize(st));   // Ht, P, G, A are released on return
 }
 
 static void build_basis(fkf_filter *f, const fkf_obs *o, hipStream_t st) {
@@ -896,7 +961,16 @@ extern "C" fkf_status fkf_filter_step_many(fkf_filter *const *filters, const fkf
         no.push_back(obs[i]);
       }
     if (!nf.empty()) build_bases(nf.data(), no.data(), (int)nf.size(), st);
-    for (int i = 0; i < count; ++i) step_after_basis(filters[i], obs[i], y[i], st);
+    if (count == 1) {
+      step_after_basis(filters[0], obs[0], y[0], st);
+      return;
+    }
+    // the steps of independent filters run on the stream lanes
+    LanePool &lp = lane_pool();
+    const std::vector<int> lane = lanes_of(filters, count);
+    lanes_fork(lp, st);
+    for (int i = 0; i < count; ++i) step_after_basis(filters[i], obs[i], y[i], lp.s[lane[i]]);
+    lanes_join(lp, st);
   });
 }
 
