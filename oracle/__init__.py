@@ -21,6 +21,9 @@ and a low-rank perturbative approach"):
                 (Section 2.2.2, eqs. ghep and geneigendecomposition) and the
                 closed-form per-mode recursion it implies for constant H
                 (Section 2.3, Algorithm 3).
+* ``ekf``       the extended Kalman filter for the Box-Cox observation model
+                (the numerical experiments' extended filter, Algorithm 4,
+                transform of eq. nonlinear).
 * ``sampling``  conditional realizations s = s_hat + L s_u with L L^T = Sigma
                 (Section 3.3).
 """
