@@ -221,6 +221,27 @@ fkf_status fkf_filter_create(fkf_cov *cov, const double *s0_dev, double alpha0,
 fkf_status fkf_filter_step(fkf_filter *f, const fkf_obs *obs, const double *y_dev,
                            void *stream);
 
+/* One step of the extended Kalman filter for the Box-Cox observation model
+ * (numerical experiments, Extended Kalman Filter; Algorithm 4).  The filter's
+ * state is the transformed field x; the physical field is
+ * s = g(x) = ((x + a)/a)^a with a = bc_alpha, the inverse of the Box-Cox
+ * transform x = a (s^(1/a) - 1) (eq. nonlinear), and y_dev (n_m values) are
+ * measurements y = H g(x) + v of obs's operator H and noise.  Prediction as
+ * in fkf_filter_step.  The update linearises h(x) = H g(x) about the
+ * predicted estimate, H_k = H diag(g'(x)) with g'(x) = ((x + a)/a)^(a-1), and
+ * is the update of fkf_filter_step for H_k with the innovation y - H g(x)
+ * (one linearisation per step).  Below the transform's domain (x < -a) the
+ * base (x + a)/a is taken as 0: g = 0 and g' is its one-sided limit at the
+ * edge (1 for a = 1, else 0).  H_k changes from step to step, so the first
+ * step builds the constant-H basis of H_0 and every later step takes the
+ * update of Section 2.4; fkf_filter_params.rank_rtol truncates the low-rank
+ * term there (the paper uses 1e-5).  bc_alpha must be finite and > 0
+ * (FKF_E_ARG).  fkf_filter_mean and fkf_filter_variance report x and its
+ * variances.  The linearised operator and data are held by the filter (n_m
+ * + nnz doubles, reused while obs is the same). */
+fkf_status fkf_filter_step_boxcox(fkf_filter *f, const fkf_obs *obs, double bc_alpha,
+                                  const double *y_dev, void *stream);
+
 /* One step of count independent filters: the same as calling
  * fkf_filter_step(filters[i], obs[i], y[i]) for i = 0..count-1 in order,
  * except that the projected eigenproblems (Section 2.2.2) of all filters that

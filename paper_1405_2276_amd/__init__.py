@@ -98,6 +98,7 @@ _sig("fkf_obs_destroy", None, [_vp])
 _sig("fkf_filter_create", _i, [_vp, _vp, ctypes.c_double, ctypes.POINTER(FilterParams), _vp,
                                ctypes.POINTER(_vp)])
 _sig("fkf_filter_step", _i, [_vp, _vp, _vp, _vp])
+_sig("fkf_filter_step_boxcox", _i, [_vp, _vp, ctypes.c_double, _vp, _vp])
 _sig("fkf_filter_step_many", _i, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                   ctypes.c_int32, _vp])
 _sig("fkf_filter_status", _i, [_vp, _vp])
@@ -406,6 +407,14 @@ class Filter:
         y = to_device(y)
         self._y = y     # keep alive until the stream consumes it
         _check(_lib.fkf_filter_step(self._h, obs.handle, y.data_ptr(), _stream(stream)))
+
+    def step_boxcox(self, obs: Obs, y, bc_alpha: float, stream=None):
+        """One extended-filter step for measurements y = H g(x) + v, with
+        g(x) = ((x + a)/a)^a, a = bc_alpha (fkf_filter_step_boxcox)."""
+        y = to_device(y)
+        self._y = y     # keep alive until the stream consumes it
+        _check(_lib.fkf_filter_step_boxcox(self._h, obs.handle, float(bc_alpha), y.data_ptr(),
+                                           _stream(stream)))
 
     def status(self, stream=None):
         _check(_lib.fkf_filter_status(self._h, _stream(stream)))

@@ -87,6 +87,12 @@ struct DevBuf {
     alloc(v.size());
     upload(v.data(), v.size(), s);
   }
+  // device-to-device copy of count elements of src (stream-ordered)
+  void copy_from(const T *src, size_t count, hipStream_t s) {
+    alloc(count);
+    if (count)
+      FKF_CHECK_HIP(hipMemcpyAsync(p, src, count * sizeof(T), hipMemcpyDeviceToDevice, s));
+  }
 };
 
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }

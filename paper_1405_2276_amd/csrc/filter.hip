@@ -72,6 +72,12 @@ struct fkf_filter {
   int rg = 0;
   // scratch reused across general steps
   fkf::DevBuf<double> gP, gHt, gG, gA, gWe, glam, gwork, gtmp;
+  // extended filter (Box-Cox model): operator H_k linearised about the
+  // estimate (same sparsity as the source operator, whose generation is
+  // lin_src) and the data of the equivalent linear step
+  std::unique_ptr<fkf_obs> lin;
+  uint64_t lin_src = 0;
+  fkf::DevBuf<double> ytil;
   ~fkf_filter() {
     if (err_host) (void)hipHostFree(err_host);
   }
@@ -324,6 +330,43 @@ __global__ void __launch_bounds__(256) k_spmv_f(const int64_t *__restrict__ rowp
   if (l == 0) h[m] = acc;
 }
 
+// Linearisation of the Box-Cox measurement model h(x) = H g(x) about the
+// estimate x (extended filter, Algorithm 4; transform of eq. nonlinear):
+// g(x) = t^a, g'(x) = t^(a-1), t = (x + a)/a, with t < 0 taken as 0 (g = 0,
+// g' its one-sided limit: 1 for a = 1, else 0).  One wavefront per row m
+// writes the row of H_k = H diag(g'(x)) (the sparsity of H) and
+// ytil_m = y_m - sum_e H_e (g - g' x)_col(e), the data for which the linear
+// update with H_k has innovation ytil - H_k x = y - h(x).  A non-finite
+// estimate propagates into ytil and latches FKF_E_NONFINITE.
+__global__ void __launch_bounds__(256) k_boxcox_linearize(const int64_t *__restrict__ rowptr,
+                                                          const int32_t *__restrict__ col,
+                                                          const double *__restrict__ val, int n_m,
+                                                          const double *__restrict__ x, double a,
+                                                          const double *__restrict__ y,
+                                                          double *__restrict__ val_k,
+                                                          double *__restrict__ ytil, int *err) {
+  int m = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (m >= n_m) return;
+  int l = threadIdx.x & 63;
+  const double edge = a == 1.0 ? 1.0 : 0.0;
+  double acc = 0;
+  for (int64_t e = rowptr[m] + l; e < rowptr[m + 1]; e += 64) {
+    const double xi = x[col[e]];
+    double t = (xi + a) / a;
+    if (t < 0.0) t = 0.0;                      // NaN passes through
+    const double gp = t > 0.0 ? pow(t, a - 1.0) : edge;
+    const double g = t * gp;
+    val_k[e] = val[e] * gp;
+    acc = fma(val[e], g - gp * xi, acc);
+  }
+  acc = wave_sum(acc);
+  if (l == 0) {
+    double v = y[m] - acc;
+    if (!isfinite(v)) atomicExch(err, (int)FKF_E_NONFINITE);
+    ytil[m] = v;
+  }
+}
+
 __global__ void k_set_flag(int *p, int v) { *p = v; }
 
 __global__ void k_clamp_nonneg(double *__restrict__ x, int n) {
@@ -527,9 +570,9 @@ static void build_bases(fkf_filter *const *fs, const fkf_obs *const *os, int cou
     f->tmp.alloc(nm);
     int nseg = (nm + kSegCols - 1) / kSegCols;
     f->part.alloc((size_t)nseg * n);
-    f->b_rowptr.upload(o->rowptr_h, si);
-    f->b_col.upload(o->col_h, si);
-    f->b_val.upload(o->val_h, si);
+    f->b_rowptr.copy_from(o->rowptr.p, (size_t)nm + 1, si);
+    f->b_col.copy_from(o->col.p, (size_t)o->nnz, si);
+    f->b_val.copy_from(o->val.p, (size_t)o->nnz, si);
     // eta = Ve^T H s for the current estimate
     f->eta.alloc(nm);
     spmv(o->rowptr.p, o->col.p, o->val.p, nm, f->s.p, f->nu.p, si);
@@ -938,6 +981,52 @@ extern "C" fkf_status fkf_filter_step(fkf_filter *f, const fkf_obs *o, const dou
     hipStream_t st = as_stream(stream);
     if (f->mode == 0) build_basis(f, o, st);
     step_after_basis(f, o, y, st);
+  });
+}
+
+// The linearised operator H_k of the extended filter about the current
+// estimate and the data ytil of the equivalent linear step (both held by the
+// filter; the sparsity pattern is copied once per source operator).  H_k gets
+// a fresh generation every step: it is a different operator each time.
+static const fkf_obs *boxcox_linearize(fkf_filter *f, const fkf_obs *o, double a,
+                                       const double *y, hipStream_t st) {
+  if (!f->lin || f->lin_src != o->gen) {
+    auto L = std::make_unique<fkf_obs>();
+    L->n_m = o->n_m;
+    L->n = o->n;
+    L->nnz = o->nnz;
+    L->noise_h = o->noise_h;
+    L->rowptr.copy_from(o->rowptr.p, (size_t)o->n_m + 1, st);
+    L->col.copy_from(o->col.p, (size_t)o->nnz, st);
+    L->noise.copy_from(o->noise.p, (size_t)o->n_m, st);
+    L->inv_sqrt_noise.copy_from(o->inv_sqrt_noise.p, (size_t)o->n_m, st);
+    L->val.alloc((size_t)o->nnz);
+    f->lin = std::move(L);
+    f->lin_src = o->gen;
+  }
+  f->ytil.reserve((size_t)o->n_m);
+  hipLaunchKernelGGL(k_boxcox_linearize, dim3(blocks(o->n_m, 4)), dim3(256), 0, st, o->rowptr.p,
+                     o->col.p, o->val.p, o->n_m, f->s.p, a, y, f->lin->val.p, f->ytil.p,
+                     f->err.p);
+  FKF_CHECK_HIP(hipGetLastError());
+  f->lin->gen = g_obs_gen.fetch_add(1);
+  return f->lin.get();
+}
+
+extern "C" fkf_status fkf_filter_step_boxcox(fkf_filter *f, const fkf_obs *o, double bc_alpha,
+                                             const double *y, void *stream) {
+  return guarded([&] {
+    check_step(f, o, y, "fkf_filter_step_boxcox");
+    FKF_REQUIRE(std::isfinite(bc_alpha) && bc_alpha > 0,
+                "fkf_filter_step_boxcox: bc_alpha must be finite and positive");
+    hipStream_t st = as_stream(stream);
+    const fkf_obs *lin;
+    {
+      FKF_TRACE("boxcox_linearize", st);
+      lin = boxcox_linearize(f, o, bc_alpha, y, st);
+    }
+    if (f->mode == 0) build_basis(f, lin, st);
+    step_after_basis(f, lin, f->ytil.p, st);
   });
 }
 

@@ -210,11 +210,14 @@ class Truth:
         return L * (vals @ wq)
 
 
-def observations(wl: Workload) -> np.ndarray:
+def observations(wl: Workload, positive: bool = False) -> np.ndarray:
     """Noisy travel times y_k for k = 1..steps, shape (steps, n_m).
 
     Same values as Truth.travel_times(k) plus noise; the drift fields are
     evaluated once at the quadrature points and accumulated step by step.
+    With positive=True the integrated field is exp(Truth.value), a strictly
+    positive field around 1 (the truth for the non-negative observation
+    model of the extended filter).
     """
     tr = Truth(wl)
     g = rng(wl.cfg_id, STREAM_NOISE)
@@ -234,6 +237,8 @@ def observations(wl: Workload) -> np.ndarray:
             drift = drift + wl.drift_sigma * tr.fields[k - 1](pts)
         w = 0.05 + 0.15 * min(k / K, 1.0)
         vals = tr.amp * min(k / K, 1.0) * np.exp(-r2 / (2 * w * w)) + drift
+        if positive:
+            vals = np.exp(vals)
         y = L * (vals.reshape(len(src), -1) @ wq)
         ys.append(y + math.sqrt(wl.noise_var) * g.standard_normal(len(y)))
     return np.array(ys)
