@@ -72,6 +72,7 @@ struct fkf_filter {
   int rg = 0;
   // scratch reused across general steps
   fkf::DevBuf<double> gP, gHt, gG, gA, gWe, glam, gwork, gtmp;
+  fkf::DevBuf<int> chol_flag;
   // extended filter (Box-Cox model): operator H_k linearised about the
   // estimate (same sparsity as the source operator, whose generation is
   // lin_src) and the data of the equivalent linear step
@@ -672,7 +673,10 @@ static void step_general(fkf_filter *f, const fkf_obs *o, const double *y, hipSt
   const int r = f->rg;
   const double a1 = f->alpha + 1.0;
   DevBuf<double> &P = f->gP, &Ht = f->gHt, &G = f->gG, &A = f->gA, &We = f->gWe, &lam = f->glam;
-  compute_gep(f, o, Ht, P, G, A, lam, We, st);
+  {
+    FKF_TRACE("general_gep", st);
+    compute_gep(f, o, Ht, P, G, A, lam, We, st);
+  }
   // eigenpairs with lambda > 1e-13 lambda_max: Z = R^-1/2 We Lambda^-1/2, U = P Z, Ud = H^T Z
   std::vector<double> lh = to_host(lam.p, nm, st);
   const int rk = count_above(lh, 1e-13 * (lh.empty() ? 0.0 : lh[0]));
@@ -706,7 +710,8 @@ static void step_general(fkf_filter *f, const fkf_obs *o, const double *y, hipSt
   // state: c = S^-1 (y - H s), s += F c
   hipLaunchKernelGGL(k_innov, dim3(blocks(nm, 4)), dim3(256), 0, st, o->rowptr.p, o->col.p,
                      o->val.p, nm, f->s.p, y, c.p, f->err.p);
-  chol_solve(S.p, nm, c.p, f->err.p, st);
+  f->chol_flag.reserve(1);
+  chol_solve(S.p, nm, c.p, f->chol_flag.p, f->err.p, st);
   gemm(false, false, n, 1, nm, 1.0, F.p, n, c.p, nm, 1.0, f->s.p, n, st, nullptr);
   // covariance: Dbar = D / (a1 (a1 - D)); AddLowRank(W, Dbar, U, Lambda; Gamma^-1)
   std::vector<double> dh = to_host(f->Dg.p, r, st);
@@ -727,7 +732,10 @@ static void step_general(fkf_filter *f, const fkf_obs *o, const double *y, hipSt
       Q((size_t)std::max(rk, 1) * std::max(rk, 1));
   gemm(true, false, rk, rk, n, 1.0, Vtd.p, ldu, Vt.p, ldu, 0.0, Gm.p, rk, st, &f->gwork);
   symmetrize(Gm.p, rk, st);
-  sym_eig(Gm.p, rk, rk, th.p, Q.p, rk, st, f->eig);
+  {
+    FKF_TRACE("general_gram_eig", st);
+    sym_eig(Gm.p, rk, rk, th.p, Q.p, rk, st, f->eig);
+  }
   std::vector<double> thh = to_host(th.p, rk, st);
   const int rp = count_above(thh, 1e-12);
   std::vector<double> ith(rp);
@@ -760,7 +768,10 @@ static void step_general(fkf_filter *f, const fkf_obs *o, const double *y, hipSt
   hipLaunchKernelGGL(k_add_diag, dim3(blocks(rt)), dim3(256), 0, st, M.p, rt, s_df.p);
   symmetrize(M.p, rt, st);
   DevBuf<double> mu(std::max(rt, 1)), Sm((size_t)std::max(rt, 1) * std::max(rt, 1));
-  sym_eig(M.p, rt, rt, mu.p, Sm.p, rt, st, f->eig);
+  {
+    FKF_TRACE("general_addlowrank_eig", st);
+    sym_eig(M.p, rt, rt, mu.p, Sm.p, rt, st, f->eig);
+  }
   std::vector<double> muh = to_host(mu.p, rt, st);
   const double mmax = muh.empty() ? 0.0 : muh[0];
   const double rtol = f->params.rank_rtol > 0 ? f->params.rank_rtol : 1e-14;

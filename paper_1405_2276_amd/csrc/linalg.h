@@ -73,9 +73,11 @@ void gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double alpha, const
 void sp_dense(const int64_t *rowptr, const int32_t *col, const double *val, int n_m,
               const double *X, int64_t ldx, int cols, double *out, hipStream_t st);
 
-// In-place Cholesky of the SPD m x m matrix S (ld m) and solve S x = b (b
-// overwritten).  Sets *err = FKF_E_NOT_SPD on a non-positive pivot.
-void chol_solve(double *S, int m, double *b, int *err, hipStream_t st);
+// In-place Cholesky of the SPD m x m matrix S (ld m, lower triangle used;
+// the upper triangle is overwritten) and solve S x = b (b overwritten).
+// flag: one device int of scratch.  Sets *err = FKF_E_NOT_SPD on a
+// non-positive pivot and then leaves b unchanged.
+void chol_solve(double *S, int m, double *b, int *flag, int *err, hipStream_t st);
 
 void scale_cols(int64_t m, int n, const double *s, double *A, int64_t lda, hipStream_t st);
 void symmetrize(double *A, int m, hipStream_t st);

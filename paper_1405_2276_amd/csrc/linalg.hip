@@ -850,8 +850,10 @@ void gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double alpha, const
   }
   const int64_t tm = (m + 63) / 64, tn = (n + 63) / 64;
   int splits = 1;
-  if (work && tm * tn < 256 && k >= 1024) {
-    splits = (int)std::min<int64_t>((256 + tm * tn - 1) / (tm * tn), k / 512);
+  if (work && tm * tn < 1024 && k >= 1024) {
+    // long reductions with a small output (W^T U and the like): enough
+    // k-slices for about 2048 workgroups
+    splits = (int)std::min<int64_t>((2048 + tm * tn - 1) / (tm * tn), k / 256);
     splits = std::max(splits, 1);
   }
   int64_t kslice = (k + splits - 1) / splits;
@@ -899,71 +901,155 @@ void sp_dense(const int64_t *rowptr, const int32_t *col, const double *val, int 
 }
 
 // ======================================================== Cholesky solve ===
-// S (m x m, ld m) = L L^T in place (lower), then x = S^-1 b overwriting b.
-// One workgroup; right-looking, column by column.  A non-positive pivot sets
+// S (m x m, ld m) = L L^T in place (lower triangle), then x = S^-1 b
+// overwriting b.  Blocked right-looking factorization over panels of
+// kCholNB columns: one launch factors the panel's diagonal block, one solves
+// the block column below it, the plain GEMM updates the trailing matrix, and
+// one workgroup finally runs the two triangular solves.  A non-positive (or
+// non-finite) pivot is recorded in *flag; the solve then sets
 // *err = FKF_E_NOT_SPD and leaves b unchanged.
-__global__ void __launch_bounds__(1024) k_chol_solve(double *__restrict__ S, int m,
-                                                     double *__restrict__ b, int *err) {
-  __shared__ double piv;
-  __shared__ int bad;
-  const int tid = threadIdx.x;
-  if (tid == 0) bad = 0;
+constexpr int kCholNB = 32;
+
+// Panel p, diagonal block: one wavefront factors the nb x nb block (already
+// updated by the panels to its left) in LDS, lane l owning row l, writes L_pp
+// back (lower triangle) and records a bad pivot in *flag.
+__global__ void __launch_bounds__(64) k_chol_diag(double *__restrict__ S, int m, int p,
+                                                  int *__restrict__ flag) {
+  __shared__ double D[kCholNB][kCholNB + 1];
+  const int l = threadIdx.x;
+  const int nb = min(kCholNB, m - p);
+  if (l < nb)
+    for (int c = 0; c <= l; ++c) D[l][c] = S[(p + l) + (int64_t)m * (p + c)];
   __syncthreads();
-  for (int j = 0; j < m; ++j) {
-    if (tid == 0) {
-      double d = S[j + (int64_t)m * j];
-      if (!(d > 0.0) || !isfinite(d)) {
-        bad = 1;
-        piv = 1.0;
-      } else {
-        piv = sqrt(d);
-      }
-      S[j + (int64_t)m * j] = piv;
-    }
+  int bad = 0;
+  for (int j = 0; j < nb; ++j) {
+    const double d = D[j][j];
+    const bool ok = d > 0.0 && isfinite(d);
+    bad |= !ok;
+    const double piv = ok ? sqrt(d) : 1.0;
     __syncthreads();
-    if (bad) break;
-    const double ip = 1.0 / piv;
-    for (int i = j + 1 + tid; i < m; i += 1024) S[i + (int64_t)m * j] *= ip;
+    if (l == j) D[j][j] = piv;
+    if (l > j && l < nb) D[l][j] /= piv;
     __syncthreads();
-    // trailing update of the lower triangle
-    const int r = m - j - 1;
-    const int64_t tot = (int64_t)r * (r + 1) / 2;
-    for (int64_t e = tid; e < tot; e += 1024) {
-      // e -> (i, k) with 0 <= k <= i < r, column-wise packing
-      int64_t kk = (int64_t)((sqrt(8.0 * (double)e + 1.0) - 1.0) / 2.0);
-      while (kk * (kk + 1) / 2 > e) --kk;
-      while ((kk + 1) * (kk + 2) / 2 <= e) ++kk;
-      int64_t i = kk, c = e - kk * (kk + 1) / 2;   // row index i >= column index c
-      int gi = j + 1 + (int)i, gc = j + 1 + (int)c;
-      S[gi + (int64_t)m * gc] -= S[gi + (int64_t)m * j] * S[gc + (int64_t)m * j];
+    if (l > j && l < nb) {
+      const double lj = D[l][j];
+      for (int c = j + 1; c <= l; ++c) D[l][c] -= lj * D[c][j];
     }
     __syncthreads();
   }
-  if (bad) {
-    if (tid == 0) atomicExch(err, (int)FKF_E_NOT_SPD);
+  if (l < nb)
+    for (int c = 0; c <= l; ++c) S[(p + l) + (int64_t)m * (p + c)] = D[l][c];
+  if (l == 0) {
+    if (p == 0) *flag = bad;
+    else if (bad) *flag = 1;
+  }
+}
+
+// Panel p, block column: X L_pp^T = A for the rows below the diagonal block,
+// one row per lane, 64 rows per workgroup (L_pp read from S after
+// k_chol_diag has written it).
+__global__ void __launch_bounds__(64) k_chol_panel(double *__restrict__ S, int m, int p) {
+  __shared__ double D[kCholNB][kCholNB + 1];
+  const int l = threadIdx.x;
+  const int nb = min(kCholNB, m - p);
+  if (l < nb)
+    for (int c = 0; c <= l; ++c) D[l][c] = S[(p + l) + (int64_t)m * (p + c)];
+  __syncthreads();
+  const int i = p + nb + 64 * blockIdx.x + l;
+  if (i >= m) return;
+  double x[kCholNB];
+#pragma unroll
+  for (int c = 0; c < kCholNB; ++c) x[c] = c < nb ? S[i + (int64_t)m * (p + c)] : 0.0;
+#pragma unroll
+  for (int c = 0; c < kCholNB; ++c) {
+    if (c < nb) {
+      double v = x[c];
+#pragma unroll
+      for (int q = 0; q < c; ++q) v -= x[q] * D[c][q];
+      x[c] = v / D[c][c];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < kCholNB; ++c)
+    if (c < nb) S[i + (int64_t)m * (p + c)] = x[c];
+}
+
+// Forward (L y = b) and backward (L^T x = y) substitution by one workgroup,
+// panel by panel: wavefront 0 solves the nb x nb triangle with lane l owning
+// entry l; the other rows are updated by the whole workgroup (forward: row
+// updates, coalesced down the panel's columns; backward: one wavefront-wide
+// dot product per panel column).
+__global__ void __launch_bounds__(1024) k_chol_trsv(const double *__restrict__ S, int m,
+                                                    double *__restrict__ b,
+                                                    const int *__restrict__ flag, int *err) {
+  __shared__ double xs[kCholNB];
+  if (*flag) {
+    if (threadIdx.x == 0) atomicExch(err, (int)FKF_E_NOT_SPD);
     return;
   }
-  // forward: L y = b
-  for (int j = 0; j < m; ++j) {
-    if (tid == 0) b[j] /= S[j + (int64_t)m * j];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  for (int p = 0; p < m; p += kCholNB) {
+    const int nb = min(kCholNB, m - p);
+    if (w == 0) {
+      double v = l < nb ? b[p + l] : 0.0;
+      const double dg = l < nb ? S[(p + l) + (int64_t)m * (p + l)] : 1.0;
+      for (int c = 0; c < nb; ++c) {
+        const double xc = __shfl(v / dg, c);
+        if (l == c) v = xc;
+        else if (l > c && l < nb) v -= S[(p + l) + (int64_t)m * (p + c)] * xc;
+      }
+      if (l < nb) {
+        xs[l] = v;
+        b[p + l] = v;
+      }
+    }
     __syncthreads();
-    const double yj = b[j];
-    for (int i = j + 1 + tid; i < m; i += 1024) b[i] -= S[i + (int64_t)m * j] * yj;
+    for (int i = p + nb + tid; i < m; i += 1024) {
+      double acc = b[i];
+      for (int c = 0; c < nb; ++c) acc -= S[i + (int64_t)m * (p + c)] * xs[c];
+      b[i] = acc;
+    }
     __syncthreads();
   }
-  // backward: L^T x = y
-  for (int j = m - 1; j >= 0; --j) {
-    if (tid == 0) b[j] /= S[j + (int64_t)m * j];
+  const int last = (m - 1) / kCholNB * kCholNB;
+  for (int p = last; p >= 0; p -= kCholNB) {
+    const int nb = min(kCholNB, m - p);
+    for (int c = w; c < nb; c += 16) {
+      double acc = 0.0;
+      for (int i = p + nb + l; i < m; i += 64) acc = fma(S[i + (int64_t)m * (p + c)], b[i], acc);
+      acc = wave_sum(acc);
+      if (l == 0) xs[c] = b[p + c] - acc;
+    }
     __syncthreads();
-    const double xj = b[j];
-    for (int i = tid; i < j; i += 1024) b[i] -= S[j + (int64_t)m * i] * xj;
+    if (w == 0) {
+      double v = l < nb ? xs[l] : 0.0;
+      const double dg = l < nb ? S[(p + l) + (int64_t)m * (p + l)] : 1.0;
+      for (int c = nb - 1; c >= 0; --c) {
+        const double xc = __shfl(v / dg, c);
+        if (l == c) v = xc;
+        else if (l < c) v -= S[(p + c) + (int64_t)m * (p + l)] * xc;
+      }
+      if (l < nb) b[p + l] = v;
+    }
     __syncthreads();
   }
 }
 
-void chol_solve(double *S, int m, double *b, int *err, hipStream_t st) {
+void chol_solve(double *S, int m, double *b, int *flag, int *err, hipStream_t st) {
   if (m <= 0) return;
-  hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), 0, st, S, m, b, err);
+  for (int p = 0; p < m; p += kCholNB) {
+    const int nb = std::min(kCholNB, m - p);
+    const int below = m - p - nb;
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(64), 0, st, S, m, p, flag);
+    if (below > 0) {
+      hipLaunchKernelGGL(k_chol_panel, dim3((unsigned)((below + 63) / 64)), dim3(64), 0, st, S, m,
+                         p);
+      double *L21 = S + (p + nb) + (int64_t)m * p;
+      double *A22 = S + (p + nb) + (int64_t)m * (p + nb);
+      gemm(false, true, below, below, nb, -1.0, L21, m, L21, m, 1.0, A22, m, st, nullptr);
+    }
+  }
+  hipLaunchKernelGGL(k_chol_trsv, dim3(1), dim3(1024), 0, st, S, m, b, flag, err);
 }
 
 // Scale column j of a column-major m x n matrix by s[j] (in place).
