@@ -221,6 +221,23 @@ fkf_status fkf_filter_create(fkf_cov *cov, const double *s0_dev, double alpha0,
 fkf_status fkf_filter_step(fkf_filter *f, const fkf_obs *obs, const double *y_dev,
                            void *stream);
 
+/* Innovation log-likelihood of the steps taken so far,
+ *   ll = sum_k -(nu_k^T S_k^-1 nu_k + log det S_k + n_m log 2 pi) / 2,
+ * with innovation nu_k = y_k - H_k s_{k|k-1} (for the extended filter,
+ * y_k - h(s_{k|k-1})) and S_k = H_k Sigma_{k|k-1} H_k^T + R_k: the Gaussian
+ * likelihood of y_1..y_k under the model of Section 2.1 in prediction-error
+ * form (a quantity the paper does not compute; it is what parameter
+ * estimation of theta, length and the noise level differentiates).  *ll
+ * receives it (0 before the first step).  dll_dlog_theta and dll_dlog_noise
+ * (each may be NULL) receive its exact derivatives with respect to log theta
+ * (Gamma scaled as a whole) and log sigma^2 (every R_k scaled as a whole),
+ * carried in forward mode through the scalar recursions that the constant-H
+ * eigenbasis decouples the filter into; they are available while every step
+ * so far was a constant-H step (FKF_E_UNSUPPORTED after a step of Section
+ * 2.4 or a second extended-filter step).  Synchronises `stream`. */
+fkf_status fkf_filter_loglik(const fkf_filter *f, double *ll, double *dll_dlog_theta,
+                             double *dll_dlog_noise, void *stream);
+
 /* One step of the extended Kalman filter for the Box-Cox observation model
  * (numerical experiments, Extended Kalman Filter; Algorithm 4).  The filter's
  * state is the transformed field x; the physical field is

@@ -68,8 +68,9 @@ def dense_ekf(Gamma: np.ndarray, H, R, ys, a: float, alpha0: float = 0.0, x0=Non
 
     R is the diagonal of the measurement-noise covariance.  Returns per step
     a dict with the estimate ``x`` of the filtered field, its covariance
-    ``Sigma`` and variances ``var``, and the linearization used (``Hk``,
-    innovation ``nu``).
+    ``Sigma`` and variances ``var``, the linearization used (``Hk``,
+    innovation ``nu``) and the innovation log-likelihood of the steps so far
+    (``ll``: the sum of -(nu^T S^-1 nu + log det S + n_m log 2 pi)/2).
     """
     H = _dense(H)
     R = np.asarray(R, dtype=np.float64)
@@ -77,6 +78,7 @@ def dense_ekf(Gamma: np.ndarray, H, R, ys, a: float, alpha0: float = 0.0, x0=Non
     x = np.zeros(N) if x0 is None else np.array(x0, dtype=np.float64)
     Sigma = alpha0 * Gamma.copy()
     out = []
+    ll = 0.0
     for k, y in enumerate(ys, start=1):
         Sp = Sigma + Gamma                           # prediction (F = I)
         Hk = H * boxcox_inverse_deriv(x, a)[None, :]  # H diag(g'(x))
@@ -84,9 +86,11 @@ def dense_ekf(Gamma: np.ndarray, H, R, ys, a: float, alpha0: float = 0.0, x0=Non
         C = Sp @ Hk.T                                # Sigma_{k|k-1} H_k^T
         S = Hk @ C + np.diag(R)
         cf = sla.cho_factor(S)
+        ll -= 0.5 * (nu @ sla.cho_solve(cf, nu) + 2 * np.sum(np.log(np.diag(cf[0])))
+                     + len(nu) * np.log(2 * np.pi))
         x = x + C @ sla.cho_solve(cf, nu)
         Sigma = Sp - C @ sla.cho_solve(cf, C.T)
         Sigma = 0.5 * (Sigma + Sigma.T)
         out.append({"x": x.copy(), "Sigma": Sigma.copy(), "var": np.diag(Sigma).copy(),
-                    "alpha": alpha0 + k, "Hk": Hk, "nu": nu})
+                    "alpha": alpha0 + k, "Hk": Hk, "nu": nu, "ll": ll})
     return out

@@ -120,3 +120,15 @@ def innovation_loglik(Gamma, Hs, Rs, ys, alpha0=0.0):
         Sigma = Sp - C @ sla.cho_solve(cf, C.T)
         Sigma = 0.5 * (Sigma + Sigma.T)
     return ll
+
+
+def loglik_log_derivatives_fd(Gamma, Hs, Rs, ys, alpha0=0.0, h=1e-4):
+    """Central differences of ``innovation_loglik`` in log theta (Gamma scaled
+    by e^t) and in log sigma^2 (every R_k scaled by e^t), step h."""
+    def ll(a, s):
+        return innovation_loglik(a * Gamma, Hs, [s * np.asarray(R, dtype=np.float64) for R in Rs],
+                                 ys, alpha0)
+    e, ie = np.exp(h), np.exp(-h)
+    d_theta = (ll(e, 1.0) - ll(ie, 1.0)) / (2 * h)
+    d_noise = (ll(1.0, e) - ll(1.0, ie)) / (2 * h)
+    return d_theta, d_noise

@@ -99,6 +99,7 @@ _sig("fkf_filter_create", _i, [_vp, _vp, ctypes.c_double, ctypes.POINTER(FilterP
                                ctypes.POINTER(_vp)])
 _sig("fkf_filter_step", _i, [_vp, _vp, _vp, _vp])
 _sig("fkf_filter_step_boxcox", _i, [_vp, _vp, ctypes.c_double, _vp, _vp])
+_sig("fkf_filter_loglik", _i, [_vp, _c_dbl_p, _c_dbl_p, _c_dbl_p, _vp])
 _sig("fkf_filter_step_many", _i, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                   ctypes.c_int32, _vp])
 _sig("fkf_filter_status", _i, [_vp, _vp])
@@ -150,6 +151,56 @@ def step_many(filters, obs, ys, stream=None):
     for f, y in zip(filters, yd):
         f._y = y     # keep alive until the stream consumes it
     _check(_lib.fkf_filter_step_many(fa, oa, ya, n, _stream(stream)))
+
+
+_LL_FUNCTION = None
+
+
+def _loglik_function():
+    """The torch.autograd.Function behind ``innovation_loglik`` (built on
+    first use, so that importing the package does not import torch)."""
+    global _LL_FUNCTION
+    if _LL_FUNCTION is None:
+        torch = _torch()
+
+        class InnovationLogLik(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, theta, noise_var, points, make_obs, ys, cov_kw, alpha0):
+                th, nv = float(theta), float(noise_var)
+                cov = Cov(points, variance=th, **cov_kw)
+                obs = make_obs(nv)
+                f = Filter(cov, alpha0=alpha0)
+                try:
+                    for y in ys:
+                        f.step(obs, y)
+                    ll, d_th, d_nv = f.loglik()
+                finally:
+                    f.close()
+                    obs.close()
+                    cov.close()
+                # d/d theta = (d/d log theta) / theta, likewise for the noise
+                ctx.grads = (d_th / th, d_nv / nv)
+                return torch.tensor(ll, dtype=torch.float64, device=theta.device)
+
+            @staticmethod
+            def backward(ctx, g):
+                gt, gn = ctx.grads
+                return g * gt, g * gn, None, None, None, None, None
+
+        _LL_FUNCTION = InnovationLogLik
+    return _LL_FUNCTION
+
+
+def innovation_loglik(theta, noise_var, points, make_obs, ys, alpha0: float = 0.0, **cov_kw):
+    """Innovation log-likelihood of observations ys (steps x n_m) under the
+    random-walk model with Gamma of variance ``theta`` (a 0-d float64 tensor)
+    and noise ``noise_var`` (a 0-d tensor; make_obs(noise_var) builds the
+    observation operator with that noise variance), as a differentiable torch
+    function of (theta, noise_var).  The forward pass runs the constant-H
+    filter on the GPU; the backward pass uses the exact derivatives the
+    filter carries (fkf_filter_loglik).  cov_kw go to Cov (nu, length,
+    leaf_size, precision, ...)."""
+    return _loglik_function().apply(theta, noise_var, points, make_obs, ys, cov_kw, alpha0)
 
 
 def version() -> str:
@@ -415,6 +466,15 @@ class Filter:
         self._y = y     # keep alive until the stream consumes it
         _check(_lib.fkf_filter_step_boxcox(self._h, obs.handle, float(bc_alpha), y.data_ptr(),
                                            _stream(stream)))
+
+    def loglik(self, grad: bool = True, stream=None):
+        """Innovation log-likelihood of the steps so far (fkf_filter_loglik);
+        with grad, (ll, d ll / d log theta, d ll / d log sigma^2)."""
+        ll, a, s = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(_lib.fkf_filter_loglik(self._h, ctypes.byref(ll),
+                                      ctypes.byref(a) if grad else None,
+                                      ctypes.byref(s) if grad else None, _stream(stream)))
+        return (ll.value, a.value, s.value) if grad else ll.value
 
     def status(self, stream=None):
         _check(_lib.fkf_filter_status(self._h, _stream(stream)))

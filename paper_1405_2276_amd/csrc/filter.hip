@@ -45,6 +45,7 @@ struct fkf_obs {
   fkf::DevBuf<int64_t> rowptr;
   fkf::DevBuf<int32_t> col;
   fkf::DevBuf<double> val, noise, inv_sqrt_noise;
+  double ll_const = 0.0;   // -(sum log R + n_m log 2 pi) / 2
 };
 
 struct fkf_filter {
@@ -73,6 +74,13 @@ struct fkf_filter {
   // scratch reused across general steps
   fkf::DevBuf<double> gP, gHt, gG, gA, gWe, glam, gwork, gtmp;
   fkf::DevBuf<int> chol_flag;
+  // innovation log-likelihood: per-mode terms and tangents of the constant-H
+  // steps (llq), the sum over general steps (ll_gen, device), the whitening
+  // constants of the constant-H steps (host), and whether a general step
+  // has been taken (its log-likelihood has no tangents)
+  fkf::DevBuf<double> llq, ll_gen;
+  double ll_const = 0.0;
+  bool ll_general = false;
   // extended filter (Box-Cox model): operator H_k linearised about the
   // estimate (same sparsity as the source operator, whose generation is
   // lin_src) and the data of the equivalent linear step
@@ -117,16 +125,60 @@ __global__ void __launch_bounds__(256) k_innov(const int64_t *__restrict__ rowpt
   }
 }
 
+// Innovation log-likelihood of the constant-H filter, mode by mode.  In the
+// whitened eigenbasis (u = Ve^T y) the data-space filter decouples into n_m
+// scalar random walks: mode j has predicted variance p- = (alpha - D_j)
+// lambda_j, innovation variance S = p- + 1 and innovation z_j, and
+// contributes -(z^2/S + log S)/2 per step (the whitening's -(sum log R +
+// n_m log 2 pi)/2 is added on the host).  Scaling Gamma by A and R by s
+// changes only the scalar recursions (p- = p + A lambda, S = p- + s), so the
+// derivatives with respect to log theta and log sigma^2 at A = s = 1 follow
+// by carrying the tangents of the mode's posterior variance p and mean m
+// (forward mode).  Per mode: q = [dp/dA, dp/ds, dm/dA, dm/ds, ll, dll/dA,
+// dll/ds, unused].
+constexpr int kLLStride = 8;
+
+__device__ __forceinline__ void loglik_mode_step(double *__restrict__ q, double pm, double lj,
+                                                 double z) {
+  const double S = pm + 1.0;
+  const double iS = 1.0 / S;
+  const double pmA = q[0] + lj, pmS = q[1];
+  const double SA = pmA, SS = pmS + 1.0;
+  const double eA = -q[2], eS = -q[3];
+  const double e2 = z * z * iS;
+  q[4] += -0.5 * (e2 + log(S));
+  q[5] += -0.5 * ((2.0 * z * eA - e2 * SA + SA) * iS);
+  q[6] += -0.5 * ((2.0 * z * eS - e2 * SS + SS) * iS);
+  const double G = pm * iS;                       // gain of the mode's mean
+  const double GA = (pmA - G * SA) * iS, GS = (pmS - G * SS) * iS;
+  q[2] += GA * z + G * eA;
+  q[3] += GS * z + G * eS;
+  q[0] = GA;                                      // posterior p = s p- / S
+  q[1] = G + GS;
+}
+
+// Tangent state at the basis build: p = alpha lambda_j (so dp/dA = p), the
+// rest zero.
+__global__ void k_loglik_init(double *__restrict__ q, const double *__restrict__ lam, int n_m,
+                              double alpha) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_m) return;
+  double *r = q + (int64_t)kLLStride * j;
+  r[0] = alpha * lam[j];
+  for (int c = 1; c < kLLStride; ++c) r[c] = 0.0;
+}
+
 // One wavefront per mode j of the constant-H step: z_j = Ve[:, j] . y - eta_j
 // (eta = Ve^T H s is carried in data space: H U0 = H P Ve and
 // Ve^T H P Ve = Lambda, so the update s += U0 zp moves eta by Lambda zp),
-// then the per-mode gain and D update.
+// then the per-mode gain and D update, and the mode's log-likelihood terms.
 __global__ void __launch_bounds__(256) k_modes_step_eta(const double *__restrict__ Ve, int n_m,
                                                         const double *__restrict__ y,
                                                         const double *__restrict__ lam,
                                                         double *__restrict__ delta,
                                                         double *__restrict__ eta, double alpha,
-                                                        double *__restrict__ zp, int *err) {
+                                                        double *__restrict__ zp,
+                                                        double *__restrict__ llq, int *err) {
   int j = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= n_m) return;
   int l = threadIdx.x & 63;
@@ -144,6 +196,7 @@ __global__ void __launch_bounds__(256) k_modes_step_eta(const double *__restrict
     zp[j] = zpj;
     delta[j] = dj + a * g;               // D_{k+1} / lambda
     eta[j] += lj * zpj;
+    loglik_mode_step(llq + (int64_t)kLLStride * j, a * lj, lj, z);
     if (!isfinite(zpj) || !isfinite(delta[j])) atomicExch(err, (int)FKF_E_NONFINITE);
   }
 }
@@ -550,6 +603,9 @@ static void build_bases(fkf_filter *const *fs, const fkf_obs *const *os, int cou
     const int nm = o->n_m;
     hipStream_t si = sti(i);
     hipLaunchKernelGGL(k_clamp_nonneg, dim3(blocks(nm)), dim3(256), 0, si, f->lam.p, nm);
+    f->llq.alloc((size_t)kLLStride * nm);
+    hipLaunchKernelGGL(k_loglik_init, dim3(blocks(nm)), dim3(256), 0, si, f->llq.p, f->lam.p, nm,
+                       f->alpha);
     scale_rows(nm, nm, o->inv_sqrt_noise.p, f->Ve.p, nm, si);
     f->ldu = (n + 63) / 64 * 64;
     f->U0.alloc((size_t)f->ldu * nm);
@@ -711,7 +767,12 @@ static void step_general(fkf_filter *f, const fkf_obs *o, const double *y, hipSt
   hipLaunchKernelGGL(k_innov, dim3(blocks(nm, 4)), dim3(256), 0, st, o->rowptr.p, o->col.p,
                      o->val.p, nm, f->s.p, y, c.p, f->err.p);
   f->chol_flag.reserve(1);
-  chol_solve(S.p, nm, c.p, f->chol_flag.p, f->err.p, st);
+  if (!f->ll_gen.p) {
+    f->ll_gen.alloc(1);
+    fill(f->ll_gen.p, 1, 0.0, st);
+  }
+  chol_solve(S.p, nm, c.p, f->chol_flag.p, f->err.p, st, f->ll_gen.p);
+  f->ll_general = true;
   gemm(false, false, n, 1, nm, 1.0, F.p, n, c.p, nm, 1.0, f->s.p, n, st, nullptr);
   // covariance: Dbar = D / (a1 (a1 - D)); AddLowRank(W, Dbar, U, Lambda; Gamma^-1)
   std::vector<double> dh = to_host(f->Dg.p, r, st);
@@ -799,6 +860,12 @@ static void step_general(fkf_filter *f, const fkf_obs *o, const double *y, hipSt
 using namespace fkf;
 
 // ========================================================== observations ===
+static double obs_ll_const(const std::vector<double> &noise) {
+  double s = 0.0;
+  for (double r : noise) s += std::log(r);
+  return -0.5 * (s + (double)noise.size() * std::log(2.0 * M_PI));
+}
+
 static void obs_finish(fkf_obs *o, hipStream_t st) {
   o->rowptr.upload(o->rowptr_h, st);
   o->col.upload(o->col_h, st);
@@ -807,6 +874,7 @@ static void obs_finish(fkf_obs *o, hipStream_t st) {
   std::vector<double> isr(o->noise_h.size());
   for (size_t i = 0; i < isr.size(); ++i) isr[i] = 1.0 / std::sqrt(o->noise_h[i]);
   o->inv_sqrt_noise.upload(isr, st);
+  o->ll_const = obs_ll_const(o->noise_h);
   o->gen = g_obs_gen.fetch_add(1);
   FKF_CHECK_HIP(hipStreamSynchronize(st));
 }
@@ -973,7 +1041,8 @@ static void step_after_basis(fkf_filter *f, const fkf_obs *o, const double *y, h
   const int nm = f->n_m;
   FKF_TRACE("filter_step", st);
   hipLaunchKernelGGL(k_modes_step_eta, dim3(blocks(nm, 4)), dim3(256), 0, st, f->Ve.p, nm, y,
-                     f->lam.p, f->delta.p, f->eta.p, alpha_new, f->zp.p, f->err.p);
+                     f->lam.p, f->delta.p, f->eta.p, alpha_new, f->zp.p, f->llq.p, f->err.p);
+  f->ll_const += o->ll_const;
   gemv_seg(f, f->zp.p, false, st);
   {
     int nseg = (nm + kSegCols - 1) / kSegCols;
@@ -1007,6 +1076,7 @@ static const fkf_obs *boxcox_linearize(fkf_filter *f, const fkf_obs *o, double a
     L->n = o->n;
     L->nnz = o->nnz;
     L->noise_h = o->noise_h;
+    L->ll_const = o->ll_const;
     L->rowptr.copy_from(o->rowptr.p, (size_t)o->n_m + 1, st);
     L->col.copy_from(o->col.p, (size_t)o->nnz, st);
     L->noise.copy_from(o->noise.p, (size_t)o->n_m, st);
@@ -1176,6 +1246,31 @@ extern "C" fkf_status fkf_filter_info(const fkf_filter *f, int64_t *k, double *a
     if (k) *k = f->k;
     if (alpha) *alpha = f->alpha;
     if (rank) *rank = f->mode == 0 ? 0 : (f->mode == 1 ? f->n_m : f->rg);
+  });
+}
+
+extern "C" fkf_status fkf_filter_loglik(const fkf_filter *f, double *ll, double *dll_dlog_theta,
+                                        double *dll_dlog_noise, void *stream) {
+  return guarded([&] {
+    FKF_REQUIRE(f && ll, "fkf_filter_loglik: NULL argument");
+    if ((dll_dlog_theta || dll_dlog_noise) && f->ll_general)
+      throw Error{FKF_E_UNSUPPORTED,
+                  "fkf_filter_loglik: derivatives are available while every step is a constant-H "
+                  "step"};
+    hipStream_t st = as_stream(stream);
+    double tot = f->ll_const, ga = 0.0, gs = 0.0;
+    if (f->llq.p) {
+      const std::vector<double> q = to_host(f->llq.p, f->llq.n, st);
+      for (size_t j = 0; j + kLLStride <= q.size(); j += kLLStride) {
+        tot += q[j + 4];
+        ga += q[j + 5];
+        gs += q[j + 6];
+      }
+    }
+    if (f->ll_gen.p) tot += to_host(f->ll_gen.p, 1, st)[0];
+    *ll = tot;
+    if (dll_dlog_theta) *dll_dlog_theta = ga;
+    if (dll_dlog_noise) *dll_dlog_noise = gs;
   });
 }
 

@@ -76,8 +76,11 @@ void sp_dense(const int64_t *rowptr, const int32_t *col, const double *val, int 
 // In-place Cholesky of the SPD m x m matrix S (ld m, lower triangle used;
 // the upper triangle is overwritten) and solve S x = b (b overwritten).
 // flag: one device int of scratch.  Sets *err = FKF_E_NOT_SPD on a
-// non-positive pivot and then leaves b unchanged.
-void chol_solve(double *S, int m, double *b, int *flag, int *err, hipStream_t st);
+// non-positive pivot and then leaves b unchanged.  With ll_acc (device),
+// adds the Gaussian log-density -(b^T S^-1 b + log det S + m log 2 pi)/2 of
+// the right-hand side to ll_acc[0].
+void chol_solve(double *S, int m, double *b, int *flag, int *err, hipStream_t st,
+                double *ll_acc = nullptr);
 
 void scale_cols(int64_t m, int n, const double *s, double *A, int64_t lda, hipStream_t st);
 void symmetrize(double *A, int m, hipStream_t st);

@@ -981,8 +981,10 @@ __global__ void __launch_bounds__(64) k_chol_panel(double *__restrict__ S, int m
 // dot product per panel column).
 __global__ void __launch_bounds__(1024) k_chol_trsv(const double *__restrict__ S, int m,
                                                     double *__restrict__ b,
-                                                    const int *__restrict__ flag, int *err) {
+                                                    const int *__restrict__ flag, int *err,
+                                                    double *__restrict__ ll_acc) {
   __shared__ double xs[kCholNB];
+  __shared__ double red[2][16];
   if (*flag) {
     if (threadIdx.x == 0) atomicExch(err, (int)FKF_E_NOT_SPD);
     return;
@@ -1011,6 +1013,31 @@ __global__ void __launch_bounds__(1024) k_chol_trsv(const double *__restrict__ S
     }
     __syncthreads();
   }
+  if (ll_acc) {
+    // Gaussian log-density of b: with y = L^-1 b (now in b),
+    // -(y^T y + 2 sum log L_ii + m log 2 pi) / 2
+    double q = 0.0, ld = 0.0;
+    for (int i = tid; i < m; i += 1024) {
+      q = fma(b[i], b[i], q);
+      ld += log(S[i + (int64_t)m * i]);
+    }
+    q = wave_sum(q);
+    ld = wave_sum(ld);
+    if (l == 0) {
+      red[0][w] = q;
+      red[1][w] = ld;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double qs = 0.0, ls = 0.0;
+      for (int v = 0; v < 16; ++v) {
+        qs += red[0][v];
+        ls += red[1][v];
+      }
+      ll_acc[0] += -0.5 * (qs + 2.0 * ls + (double)m * log(2.0 * M_PI));
+    }
+    __syncthreads();
+  }
   const int last = (m - 1) / kCholNB * kCholNB;
   for (int p = last; p >= 0; p -= kCholNB) {
     const int nb = min(kCholNB, m - p);
@@ -1035,7 +1062,8 @@ __global__ void __launch_bounds__(1024) k_chol_trsv(const double *__restrict__ S
   }
 }
 
-void chol_solve(double *S, int m, double *b, int *flag, int *err, hipStream_t st) {
+void chol_solve(double *S, int m, double *b, int *flag, int *err, hipStream_t st,
+                double *ll_acc) {
   if (m <= 0) return;
   for (int p = 0; p < m; p += kCholNB) {
     const int nb = std::min(kCholNB, m - p);
@@ -1049,7 +1077,7 @@ void chol_solve(double *S, int m, double *b, int *flag, int *err, hipStream_t st
       gemm(false, true, below, below, nb, -1.0, L21, m, L21, m, 1.0, A22, m, st, nullptr);
     }
   }
-  hipLaunchKernelGGL(k_chol_trsv, dim3(1), dim3(1024), 0, st, S, m, b, flag, err);
+  hipLaunchKernelGGL(k_chol_trsv, dim3(1), dim3(1024), 0, st, S, m, b, flag, err, ll_acc);
 }
 
 // Scale column j of a column-major m x n matrix by s[j] (in place).

@@ -82,7 +82,11 @@ def test_affine_case_is_the_linear_filter():
     out = ekf.dense_ekf(Gamma, H, R, ys, 1.0, alpha0=0.4)
     ref = kalman.dense_kf(Gamma, [H] * len(ys), [R] * len(ys), ys - H @ np.ones(H.shape[1]),
                           alpha0=0.4)
-    for o, r in zip(out, ref):
+    Hs, Rs = [H] * len(ys), [R] * len(ys)
+    for k, (o, r) in enumerate(zip(out, ref), start=1):
+        ll = kalman.innovation_loglik(Gamma, Hs[:k], Rs[:k], (ys - H @ np.ones(H.shape[1]))[:k],
+                                      alpha0=0.4)
+        assert abs(o["ll"] - ll) <= 1e-10 * abs(ll)
         assert o["x"].min() > -1.0
         np.testing.assert_allclose(o["x"], r["s"], rtol=1e-11, atol=1e-13)
         np.testing.assert_allclose(o["Sigma"], r["Sigma"], rtol=1e-10, atol=1e-14)

@@ -268,3 +268,21 @@ def test_innovation_loglik_equals_joint_gaussian_log_density():
     want = -0.5 * (y @ np.linalg.solve(Syy, y) + logdet + len(y) * np.log(2 * np.pi))
     assert sign > 0
     assert ll == pytest.approx(want, rel=1e-11)
+
+
+@pytest.mark.parametrize("alpha0", [0.0, 0.4])
+def test_loglik_derivatives_match_joint_gaussian_closed_form(alpha0):
+    # y (stacked) ~ N(0, C) with C = a C_G + s C_R (Gamma scaled by a, every R
+    # by s): d ll / d log a = -a (tr(C^-1 C_G) - y^T C^-1 C_G C^-1 y) / 2 at
+    # a = 1, and likewise for s; the oracle's central differences must agree
+    Gamma, Hs, Rs, ys = _tiny_problem(N=6, steps=3)
+    K = len(Hs)
+    CG = np.block([[(alpha0 + min(i, j) + 1) * Hs[i] @ Gamma @ Hs[j].T for j in range(K)]
+                   for i in range(K)])
+    CR = np.diag(np.concatenate(Rs))
+    C = CG + CR
+    y = np.concatenate(ys)
+    Ci_y = np.linalg.solve(C, y)
+    want = [-0.5 * (np.trace(np.linalg.solve(C, M)) - Ci_y @ M @ Ci_y) for M in (CG, CR)]
+    got = kalman.loglik_log_derivatives_fd(Gamma, Hs, Rs, ys, alpha0=alpha0)
+    np.testing.assert_allclose(got, want, rtol=1e-7, atol=1e-10)
