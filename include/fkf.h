@@ -53,8 +53,20 @@ typedef enum {
 } fkf_status;
 
 /* Matern smoothness nu = 1/2, 3/2, 5/2: the half-integer cases whose Bessel
- * form (eq. maternfamily) reduces to an exponential times a polynomial. */
-typedef enum { FKF_MATERN_12 = 0, FKF_MATERN_32 = 1, FKF_MATERN_52 = 2 } fkf_kernel;
+ * form (eq. maternfamily) reduces to an exponential times a polynomial.
+ * The *_DLENGTH kinds are the derivatives d/d length of those kernels,
+ * (variance / length) (-t C'(t)) with t = c r / length: operators for
+ * likelihood gradients (fkf_filter_track_length).  They are symmetric but not
+ * positive definite, have zero diagonal, and cannot be a filter's
+ * covariance. */
+typedef enum {
+  FKF_MATERN_12 = 0,
+  FKF_MATERN_32 = 1,
+  FKF_MATERN_52 = 2,
+  FKF_MATERN_12_DLENGTH = 3,
+  FKF_MATERN_32_DLENGTH = 4,
+  FKF_MATERN_52_DLENGTH = 5
+} fkf_kernel;
 
 /* FKF_FP64: every H-matrix entry and every filter array in FP64.
  * FKF_MIXED: near-field blocks stored in FP32 (half the HBM bytes of the
@@ -228,15 +240,30 @@ fkf_status fkf_filter_step(fkf_filter *f, const fkf_obs *obs, const double *y_de
  * likelihood of y_1..y_k under the model of Section 2.1 in prediction-error
  * form (a quantity the paper does not compute; it is what parameter
  * estimation of theta, length and the noise level differentiates).  *ll
- * receives it (0 before the first step).  dll_dlog_theta and dll_dlog_noise
- * (each may be NULL) receive its exact derivatives with respect to log theta
- * (Gamma scaled as a whole) and log sigma^2 (every R_k scaled as a whole),
- * carried in forward mode through the scalar recursions that the constant-H
- * eigenbasis decouples the filter into; they are available while every step
- * so far was a constant-H step (FKF_E_UNSUPPORTED after a step of Section
- * 2.4 or a second extended-filter step).  Synchronises `stream`. */
+ * receives it (0 before the first step).  dll_dlog_theta, dll_dlog_length
+ * and dll_dlog_noise (each may be NULL) receive its exact derivatives with
+ * respect to log theta (Gamma scaled as a whole), log length (the Matern
+ * length; requires fkf_filter_track_length, else FKF_E_ORDER) and
+ * log sigma^2 (every R_k scaled as a whole).  They are carried in forward
+ * mode through the recursion of the constant-H filter in the whitened
+ * eigenbasis of its operator, in which the data-space covariance is diagonal:
+ * theta and sigma^2 keep it diagonal (O(n_m) per step), the length tangent
+ * is a full n_m x n_m matrix (O(n_m^2) per step).  Derivatives are available
+ * while every step so far was a constant-H step (FKF_E_UNSUPPORTED after a
+ * step of Section 2.4 or a second extended-filter step).  Synchronises
+ * `stream`. */
 fkf_status fkf_filter_loglik(const fkf_filter *f, double *ll, double *dll_dlog_theta,
-                             double *dll_dlog_noise, void *stream);
+                             double *dll_dlog_length, double *dll_dlog_noise, void *stream);
+
+/* Track d ll / d log length in f (see fkf_filter_loglik): dcov is the
+ * operator dGamma/d length, built by fkf_cov_build on the same points with
+ * the same variance, length and H-matrix parameters and the kind
+ * FKF_MATERN_*_DLENGTH of f's kernel (only its kind, size and length are
+ * checked; FKF_E_ARG).  Must be called before the first step (FKF_E_ORDER).
+ * The basis build then costs one more n_m-column product with dcov and two
+ * N x n_m x n_m products; each constant-H step one O(n_m^2) update.  dcov is
+ * borrowed: it must outlive f's steps and log-likelihood queries. */
+fkf_status fkf_filter_track_length(fkf_filter *f, fkf_cov *dcov, void *stream);
 
 /* One step of the extended Kalman filter for the Box-Cox observation model
  * (numerical experiments, Extended Kalman Filter; Algorithm 4).  The filter's

@@ -10,14 +10,15 @@ import numpy as np
 from .kernels import cov_block
 
 
-def cov_matvec(pts: np.ndarray, X: np.ndarray, nu, ell, theta, panel: int = 1024):
-    """Y = Gamma X for X of shape (N,) or (N, k)."""
+def cov_matvec(pts: np.ndarray, X: np.ndarray, nu, ell, theta, panel: int = 1024,
+               dlength: bool = False):
+    """Y = Gamma X for X of shape (N,) or (N, k) (dlength: Y = dGamma/d ell X)."""
     X = np.asarray(X, dtype=np.float64)
     Y = np.empty_like(X)
     N = pts.shape[0]
     for i0 in range(0, N, panel):
         i1 = min(N, i0 + panel)
-        Y[i0:i1] = cov_block(pts[i0:i1], pts, nu, ell, theta) @ X
+        Y[i0:i1] = cov_block(pts[i0:i1], pts, nu, ell, theta, dlength) @ X
     return Y
 
 
@@ -37,6 +38,6 @@ def cross_cov(pts: np.ndarray, H, nu, ell, theta, panel: int = 1024):
     return P
 
 
-def dense_cov(pts: np.ndarray, nu, ell, theta):
-    """The full Gamma (small N only)."""
-    return cov_block(pts, pts, nu, ell, theta)
+def dense_cov(pts: np.ndarray, nu, ell, theta, dlength: bool = False):
+    """The full Gamma, or dGamma/d ell (small N only)."""
+    return cov_block(pts, pts, nu, ell, theta, dlength)

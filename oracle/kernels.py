@@ -43,8 +43,27 @@ def matern_bessel(r, nu: float, ell: float, theta: float = 1.0):
     return theta * out
 
 
-def cov_block(pts_a: np.ndarray, pts_b: np.ndarray, nu, ell, theta):
-    """Dense block Gamma[a, b] = theta C(|x_a - x_b|)."""
+def matern_dlength(r, nu: float, ell: float, theta: float = 1.0):
+    """d/d ell of ``matern``: with t = c r / ell (c = 1, sqrt 3, sqrt 5),
+    d/d ell theta C(t) = theta C'(t) (-t / ell), written out per closed form
+    (the operator whose products give the length derivative of the
+    likelihood; the paper has no parameter estimation)."""
+    r = np.asarray(r, dtype=np.float64)
+    if nu == 0.5:
+        t = r / ell
+        return theta / ell * t * np.exp(-t)              # C' = -e^-t
+    if nu == 1.5:
+        t = np.sqrt(3.0) * r / ell
+        return theta / ell * t * t * np.exp(-t)          # C' = -t e^-t
+    if nu == 2.5:
+        t = np.sqrt(5.0) * r / ell
+        return theta / ell * t * t * (1.0 + t) / 3.0 * np.exp(-t)   # C' = -t (1 + t) e^-t / 3
+    raise ValueError(f"unsupported smoothness nu={nu}")
+
+
+def cov_block(pts_a: np.ndarray, pts_b: np.ndarray, nu, ell, theta, dlength: bool = False):
+    """Dense block Gamma[a, b] = theta C(|x_a - x_b|) (or its length
+    derivative)."""
     d = pts_a[:, None, :] - pts_b[None, :, :]
     r = np.sqrt(np.sum(d * d, axis=-1))
-    return matern(r, nu, ell, theta)
+    return (matern_dlength if dlength else matern)(r, nu, ell, theta)

@@ -99,7 +99,8 @@ _sig("fkf_filter_create", _i, [_vp, _vp, ctypes.c_double, ctypes.POINTER(FilterP
                                ctypes.POINTER(_vp)])
 _sig("fkf_filter_step", _i, [_vp, _vp, _vp, _vp])
 _sig("fkf_filter_step_boxcox", _i, [_vp, _vp, ctypes.c_double, _vp, _vp])
-_sig("fkf_filter_loglik", _i, [_vp, _c_dbl_p, _c_dbl_p, _c_dbl_p, _vp])
+_sig("fkf_filter_loglik", _i, [_vp, _c_dbl_p, _c_dbl_p, _c_dbl_p, _c_dbl_p, _vp])
+_sig("fkf_filter_track_length", _i, [_vp, _vp, _vp])
 _sig("fkf_filter_step_many", _i, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                   ctypes.c_int32, _vp])
 _sig("fkf_filter_status", _i, [_vp, _vp])
@@ -165,42 +166,47 @@ def _loglik_function():
 
         class InnovationLogLik(torch.autograd.Function):
             @staticmethod
-            def forward(ctx, theta, noise_var, points, make_obs, ys, cov_kw, alpha0):
-                th, nv = float(theta), float(noise_var)
-                cov = Cov(points, variance=th, **cov_kw)
+            def forward(ctx, theta, length, noise_var, points, make_obs, ys, cov_kw, alpha0):
+                th, ln, nv = float(theta), float(length), float(noise_var)
+                cov = Cov(points, variance=th, length=ln, **cov_kw)
+                dcov = Cov(points, variance=th, length=ln, dlength=True, **cov_kw)
                 obs = make_obs(nv)
                 f = Filter(cov, alpha0=alpha0)
                 try:
+                    f.track_length(dcov)
                     for y in ys:
                         f.step(obs, y)
-                    ll, d_th, d_nv = f.loglik()
+                    ll, d_th, d_nv, d_ln = f.loglik()
                 finally:
                     f.close()
                     obs.close()
+                    dcov.close()
                     cov.close()
-                # d/d theta = (d/d log theta) / theta, likewise for the noise
-                ctx.grads = (d_th / th, d_nv / nv)
+                # d/d theta = (d/d log theta) / theta, likewise for the others
+                ctx.grads = (d_th / th, d_ln / ln, d_nv / nv)
                 return torch.tensor(ll, dtype=torch.float64, device=theta.device)
 
             @staticmethod
             def backward(ctx, g):
-                gt, gn = ctx.grads
-                return g * gt, g * gn, None, None, None, None, None
+                gt, gl, gn = ctx.grads
+                return g * gt, g * gl, g * gn, None, None, None, None, None
 
         _LL_FUNCTION = InnovationLogLik
     return _LL_FUNCTION
 
 
-def innovation_loglik(theta, noise_var, points, make_obs, ys, alpha0: float = 0.0, **cov_kw):
+def innovation_loglik(theta, length, noise_var, points, make_obs, ys, alpha0: float = 0.0,
+                      **cov_kw):
     """Innovation log-likelihood of observations ys (steps x n_m) under the
-    random-walk model with Gamma of variance ``theta`` (a 0-d float64 tensor)
-    and noise ``noise_var`` (a 0-d tensor; make_obs(noise_var) builds the
-    observation operator with that noise variance), as a differentiable torch
-    function of (theta, noise_var).  The forward pass runs the constant-H
-    filter on the GPU; the backward pass uses the exact derivatives the
-    filter carries (fkf_filter_loglik).  cov_kw go to Cov (nu, length,
-    leaf_size, precision, ...)."""
-    return _loglik_function().apply(theta, noise_var, points, make_obs, ys, cov_kw, alpha0)
+    random-walk model with a Matern Gamma of variance ``theta`` and length
+    ``length`` and measurement noise ``noise_var`` (0-d float64 tensors;
+    make_obs(noise_var) builds the observation operator with that noise
+    variance), as a differentiable torch function of the three.  The forward
+    pass runs the constant-H filter on the GPU with the length derivative
+    tracked; the backward pass uses the exact derivatives the filter carries
+    (fkf_filter_loglik).  cov_kw go to Cov (nu, leaf_size, precision, ...)."""
+    return _loglik_function().apply(theta, length, noise_var, points, make_obs, ys, cov_kw,
+                                    alpha0)
 
 
 def version() -> str:
@@ -298,12 +304,13 @@ class Cov:
     precision: "fp64", or "mixed" (FP32 near-field storage and far-field kernel
     evaluation, FP64 accumulation; filters built on it stream their basis in
     FP32).  far_eval: evaluate the far-field coupling matrices in every product
-    instead of storing them at build."""
+    instead of storing them at build.  dlength: the operator dGamma/d length
+    instead of Gamma (for likelihood gradients, Filter.track_length)."""
 
     def __init__(self, points, nu: float = 1.5, length: float = 0.1, variance: float = 1.0,
                  leaf_size: int = 64, cheb_order: int = 6, cheb_order_max: int = 16,
                  eta: float = 1.5, block_tol: float = 1e-7, precision: str = "fp64",
-                 far_eval: bool = False, stream=None):
+                 far_eval: bool = False, dlength: bool = False, stream=None):
         pts = np.ascontiguousarray(points, dtype=np.float64)
         if pts.ndim != 2:
             raise ValueError("points must be (N, d)")
@@ -311,6 +318,8 @@ class Cov:
         self.nu, self.length, self.variance = nu, length, variance
         kp, hp = _params(nu, length, variance, leaf_size, cheb_order, cheb_order_max, eta,
                          block_tol, precision, far_eval)
+        if dlength:
+            kp.kind += 3      # FKF_MATERN_*_DLENGTH
         self.precision = precision
         h = ctypes.c_void_p()
         _check(_lib.fkf_cov_build(pts.ctypes.data_as(_c_dbl_p), self.n, self.d,
@@ -467,14 +476,27 @@ class Filter:
         _check(_lib.fkf_filter_step_boxcox(self._h, obs.handle, float(bc_alpha), y.data_ptr(),
                                            _stream(stream)))
 
+    def track_length(self, dcov: "Cov", stream=None):
+        """Carry d ll / d log length (fkf_filter_track_length); dcov is the
+        length derivative of this filter's covariance (Cov(..., dlength=True))."""
+        self._dcov = dcov     # borrowed by the library
+        _check(_lib.fkf_filter_track_length(self._h, dcov.handle, _stream(stream)))
+
     def loglik(self, grad: bool = True, stream=None):
         """Innovation log-likelihood of the steps so far (fkf_filter_loglik);
-        with grad, (ll, d ll / d log theta, d ll / d log sigma^2)."""
-        ll, a, s = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        with grad, (ll, d ll / d log theta, d ll / d log sigma^2), plus
+        d ll / d log length after track_length."""
+        ll, a, g, s = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        want_len = grad and getattr(self, "_dcov", None) is not None
         _check(_lib.fkf_filter_loglik(self._h, ctypes.byref(ll),
                                       ctypes.byref(a) if grad else None,
+                                      ctypes.byref(g) if want_len else None,
                                       ctypes.byref(s) if grad else None, _stream(stream)))
-        return (ll.value, a.value, s.value) if grad else ll.value
+        if not grad:
+            return ll.value
+        if want_len:
+            return ll.value, a.value, s.value, g.value
+        return ll.value, a.value, s.value
 
     def status(self, stream=None):
         _check(_lib.fkf_filter_status(self._h, _stream(stream)))

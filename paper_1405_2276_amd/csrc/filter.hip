@@ -81,6 +81,10 @@ struct fkf_filter {
   fkf::DevBuf<double> llq, ll_gen;
   double ll_const = 0.0;
   bool ll_general = false;
+  // length derivative (fkf_filter_track_length): dGamma/d ell, the tangent
+  // operator Ad and the tangent covariance Cd in the whitened eigenbasis
+  fkf_cov *dcov = nullptr;
+  fkf::DevBuf<double> ll_Ad, ll_Cd;
   // extended filter (Box-Cox model): operator H_k linearised about the
   // estimate (same sparsity as the source operator, whose generation is
   // lin_src) and the data of the equivalent linear step
@@ -98,6 +102,8 @@ namespace fkf {
 double cov_variance(const fkf_cov *cov);
 int64_t cov_n(const fkf_cov *cov);
 bool cov_mixed(const fkf_cov *cov);
+int cov_kind(const fkf_cov *cov);
+double cov_length(const fkf_cov *cov);
 
 static std::atomic<uint64_t> g_obs_gen{1};
 
@@ -135,8 +141,9 @@ __global__ void __launch_bounds__(256) k_innov(const int64_t *__restrict__ rowpt
 // derivatives with respect to log theta and log sigma^2 at A = s = 1 follow
 // by carrying the tangents of the mode's posterior variance p and mean m
 // (forward mode).  Per mode: q = [dp/dA, dp/ds, dm/dA, dm/ds, ll, dll/dA,
-// dll/ds, unused].
-constexpr int kLLStride = 8;
+// dll/ds, p- and z of the latest step, dll/d ell (row sums, see
+// k_loglik_length_step), dm/d ell, unused].
+constexpr int kLLStride = 12;
 
 __device__ __forceinline__ void loglik_mode_step(double *__restrict__ q, double pm, double lj,
                                                  double z) {
@@ -155,6 +162,47 @@ __device__ __forceinline__ void loglik_mode_step(double *__restrict__ q, double 
   q[3] += GS * z + G * eS;
   q[0] = GA;                                      // posterior p = s p- / S
   q[1] = G + GS;
+  q[7] = pm;
+  q[8] = z;
+}
+
+// Derivative of the log-likelihood with respect to the length scale.  In
+// the whitened eigenbasis of the reference operator the data-space
+// covariance C of the filter is diagonal, but its tangent Cd under
+// Gamma -> Gamma + d ell dGamma/d ell is a full matrix: it starts at
+// alpha_0 Ad (Ad = Ve^T H (dGamma/d ell) H^T Ve) and per step
+//   Cd- = Cd + Ad,  S = diag(p- + 1),  g = p- / S,
+//   dll += -(tr(S^-1 Cd-) - 2 z^T S^-1 dm - (S^-1 z)^T Cd- (S^-1 z)) / 2,
+//   dm <- dm + (1 - g) o (Cd- S^-1 z) - g o dm,   Cd <- Cd- o (1 - g)(1 - g)^T
+// (the tangents of the innovation terms, of the gain update of the mean and
+// of C = C- - C- S^-1 C-), O(n_m^2) per step.  One wavefront per row i; the
+// symmetric Cd is stored whole and wavefront i reads and writes column i.
+__global__ void __launch_bounds__(256) k_loglik_length_step(int n_m, const double *__restrict__ Ad,
+                                                            double *__restrict__ Cd,
+                                                            double *__restrict__ q) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n_m) return;
+  const int l = threadIdx.x & 63;
+  double *qi = q + (int64_t)kLLStride * i;
+  const double si = 1.0 + qi[7], gi = qi[7] / si, zi = qi[8];
+  double r = 0.0, dii = 0.0;
+  double *col = Cd + (int64_t)n_m * i;
+  const double *acol = Ad + (int64_t)n_m * i;
+  for (int j = l; j < n_m; j += 64) {
+    const double *qj = q + (int64_t)kLLStride * j;
+    const double sj = 1.0 + qj[7], gj = qj[7] / sj;
+    const double cm = col[j] + acol[j];
+    r = fma(cm, qj[8] / sj, r);
+    if (j == i) dii = cm;
+    col[j] = cm * (1.0 - gi) * (1.0 - gj);
+  }
+  r = wave_sum(r);
+  dii = wave_sum(dii);
+  if (l == 0) {
+    const double dm = qi[10];
+    qi[9] += -0.5 * (dii / si - 2.0 * zi * dm / si - zi / si * r);
+    qi[10] = dm + (1.0 - gi) * r - gi * dm;
+  }
 }
 
 // Tangent state at the basis build: p = alpha lambda_j (so dp/dA = p), the
@@ -554,7 +602,7 @@ static std::vector<int> lanes_of(fkf_filter *const *fs, int count) {
 // per-filter work runs on kLanes streams (joined before the eigensolve and
 // at the end).
 struct BasisWork {
-  DevBuf<double> Ht, P, G, A;
+  DevBuf<double> Ht, P, G, A, X;
 };
 
 static void build_bases(fkf_filter *const *fs, const fkf_obs *const *os, int count,
@@ -613,6 +661,21 @@ static void build_bases(fkf_filter *const *fs, const fkf_obs *const *os, int cou
     {
       FKF_TRACE("gep_basis_gemm", si);
       gemm_nn(n, nm, nm, bw[i].P.p, n, f->Ve.p, nm, f->U0.p, f->ldu, si);
+    }
+    if (f->dcov) {
+      // Ad = X^T (dGamma/d ell) X with X = H^T Ve; Cd starts at alpha Ad
+      FKF_TRACE("loglik_length_setup", si);
+      bw[i].X.reserve((size_t)n * nm);
+      gemm_nn(n, nm, nm, bw[i].Ht.p, n, f->Ve.p, nm, bw[i].X.p, n, si);
+      fkf_status rc = fkf_cov_apply(f->dcov, bw[i].X.p, n, nm, bw[i].P.p, n, (void *)si);
+      if (rc != FKF_OK) throw Error{rc, std::string("derivative product failed: ") + fkf_last_error()};
+      f->ll_Ad.alloc((size_t)nm * nm);
+      f->ll_Cd.alloc((size_t)nm * nm);
+      gemm(true, false, nm, nm, n, 1.0, bw[i].X.p, n, bw[i].P.p, n, 0.0, f->ll_Ad.p, nm, si,
+           &f->gwork);
+      symmetrize(f->ll_Ad.p, nm, si);
+      copy2d(nm, nm, f->ll_Ad.p, nm, f->ll_Cd.p, nm, si);
+      scale2d(nm, nm, f->alpha, f->ll_Cd.p, nm, si);
     }
     if (f->mixed) {
       f->U0f.alloc((size_t)f->ldu * nm);
@@ -984,6 +1047,8 @@ extern "C" fkf_status fkf_filter_create(fkf_cov *cov, const double *s0, double a
     FKF_REQUIRE(out != nullptr, "fkf_filter_create: out is NULL");
     *out = nullptr;
     FKF_REQUIRE(cov != nullptr, "fkf_filter_create: NULL covariance");
+    FKF_REQUIRE(cov_kind(cov) < FKF_MATERN_12_DLENGTH,
+                "fkf_filter_create: a length-derivative operator is not a covariance");
     FKF_REQUIRE(alpha0 >= 0 && std::isfinite(alpha0), "fkf_filter_create: alpha0 must be >= 0");
     if (params) FKF_REQUIRE(params->struct_size == sizeof(fkf_filter_params),
                             "fkf_filter_create: params struct_size");
@@ -1043,6 +1108,9 @@ static void step_after_basis(fkf_filter *f, const fkf_obs *o, const double *y, h
   hipLaunchKernelGGL(k_modes_step_eta, dim3(blocks(nm, 4)), dim3(256), 0, st, f->Ve.p, nm, y,
                      f->lam.p, f->delta.p, f->eta.p, alpha_new, f->zp.p, f->llq.p, f->err.p);
   f->ll_const += o->ll_const;
+  if (f->dcov)
+    hipLaunchKernelGGL(k_loglik_length_step, dim3(blocks(nm, 4)), dim3(256), 0, st, nm,
+                       f->ll_Ad.p, f->ll_Cd.p, f->llq.p);
   gemv_seg(f, f->zp.p, false, st);
   {
     int nseg = (nm + kSegCols - 1) / kSegCols;
@@ -1249,27 +1317,48 @@ extern "C" fkf_status fkf_filter_info(const fkf_filter *f, int64_t *k, double *a
   });
 }
 
+extern "C" fkf_status fkf_filter_track_length(fkf_filter *f, fkf_cov *dcov, void *stream) {
+  (void)stream;
+  return guarded([&] {
+    FKF_REQUIRE(f && dcov, "fkf_filter_track_length: NULL argument");
+    if (f->mode != 0 || f->k != 0)
+      throw Error{FKF_E_ORDER, "fkf_filter_track_length: must be called before the first step"};
+    FKF_REQUIRE(cov_kind(dcov) == cov_kind(f->cov) + FKF_MATERN_12_DLENGTH,
+                "fkf_filter_track_length: dcov must be the length derivative of the filter's kernel");
+    FKF_REQUIRE(cov_n(dcov) == f->n, "fkf_filter_track_length: size mismatch");
+    FKF_REQUIRE(cov_length(dcov) == cov_length(f->cov),
+                "fkf_filter_track_length: length differs from the filter's covariance");
+    f->dcov = dcov;
+  });
+}
+
 extern "C" fkf_status fkf_filter_loglik(const fkf_filter *f, double *ll, double *dll_dlog_theta,
-                                        double *dll_dlog_noise, void *stream) {
+                                        double *dll_dlog_length, double *dll_dlog_noise,
+                                        void *stream) {
   return guarded([&] {
     FKF_REQUIRE(f && ll, "fkf_filter_loglik: NULL argument");
-    if ((dll_dlog_theta || dll_dlog_noise) && f->ll_general)
+    if ((dll_dlog_theta || dll_dlog_length || dll_dlog_noise) && f->ll_general)
       throw Error{FKF_E_UNSUPPORTED,
                   "fkf_filter_loglik: derivatives are available while every step is a constant-H "
                   "step"};
+    if (dll_dlog_length && !f->dcov)
+      throw Error{FKF_E_ORDER, "fkf_filter_loglik: length derivative not tracked "
+                               "(fkf_filter_track_length before the first step)"};
     hipStream_t st = as_stream(stream);
-    double tot = f->ll_const, ga = 0.0, gs = 0.0;
+    double tot = f->ll_const, ga = 0.0, gl = 0.0, gs = 0.0;
     if (f->llq.p) {
       const std::vector<double> q = to_host(f->llq.p, f->llq.n, st);
       for (size_t j = 0; j + kLLStride <= q.size(); j += kLLStride) {
         tot += q[j + 4];
         ga += q[j + 5];
         gs += q[j + 6];
+        gl += q[j + 9];
       }
     }
     if (f->ll_gen.p) tot += to_host(f->ll_gen.p, 1, st)[0];
     *ll = tot;
     if (dll_dlog_theta) *dll_dlog_theta = ga;
+    if (dll_dlog_length) *dll_dlog_length = f->dcov ? gl * cov_length(f->cov) : 0.0;
     if (dll_dlog_noise) *dll_dlog_noise = gs;
   });
 }

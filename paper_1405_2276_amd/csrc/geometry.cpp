@@ -165,13 +165,18 @@ void cheb_nodes(int p, double *u, double *w) {
 }
 
 double matern_host(double r, int kind, double ell, double theta) {
-  if (kind == FKF_MATERN_12) return theta * std::exp(-r / ell);
-  if (kind == FKF_MATERN_32) {
-    double t = std::sqrt(3.0) * r / ell;
-    return theta * (1.0 + t) * std::exp(-t);
+  const int b = kind % 3;
+  const double t = (b == 0 ? 1.0 : std::sqrt(b == 1 ? 3.0 : 5.0)) * r / ell;
+  const double ex = std::exp(-t);
+  switch (kind) {
+    case FKF_MATERN_12: return theta * ex;
+    case FKF_MATERN_32: return theta * (1.0 + t) * ex;
+    case FKF_MATERN_52: return theta * (1.0 + t + t * t / 3.0) * ex;
+    // d/d ell of theta C(t(ell)) = (theta / ell) (-t C'(t))
+    case FKF_MATERN_12_DLENGTH: return theta / ell * t * ex;
+    case FKF_MATERN_32_DLENGTH: return theta / ell * t * t * ex;
+    default: return theta / ell * t * t * (1.0 + t) * ex / 3.0;
   }
-  double t = std::sqrt(5.0) * r / ell;
-  return theta * (1.0 + t + t * t / 3.0) * std::exp(-t);
 }
 
 namespace {

@@ -84,6 +84,7 @@ struct fkf_cov {
   int d = 2;
   int kind = 0;
   double theta = 1, ell = 1;
+  double amp = 1;   // multiplier of the kernel shape: theta, or theta / ell for a length derivative
   fkf_hmat_params hp{};
   fkf::Tree tree;
   std::vector<int> level_p;
@@ -137,35 +138,46 @@ struct fkf_cov {
 namespace fkf {
 
 // ------------------------------------------------------------ device code ---
-__device__ __forceinline__ double matern_dev(double r, int kind, double inv_ell, double theta) {
-  if (kind == FKF_MATERN_12) return theta * exp(-r * inv_ell);
-  if (kind == FKF_MATERN_32) {
-    double t = 1.7320508075688772 * r * inv_ell;
-    return theta * (1.0 + t) * exp(-t);
-  }
-  double t = 2.2360679774997896 * r * inv_ell;
-  return theta * (1.0 + t + t * t * (1.0 / 3.0)) * exp(-t);
+// Scale c of the scaled distance t = c r / ell (c = 1, sqrt 3, sqrt 5 for
+// nu = 1/2, 3/2, 5/2; the length derivatives share their kernel's scale).
+__host__ __device__ __forceinline__ double kernel_c(int kind) {
+  const int b = kind % 3;
+  return b == 0 ? 1.0 : (b == 1 ? 1.7320508075688772 : 2.2360679774997896);
 }
 
-// Kernel entry theta C(t) at scaled distance t = c r / ell from its square t2
-// (c = 1, sqrt 3, sqrt 5 for nu = 1/2, 3/2, 5/2).  F32: evaluated with the
-// FP32 hardware square root and exponential (mixed precision).
+// Shape of the kernel as a function of t (eq. maternfamily, half-integer
+// closed forms) and, for the length-derivative kinds, -t C'(t): the factor
+// that, times variance / ell, gives d/d ell of variance C(c r / ell).
+template <typename T>
+__device__ __forceinline__ T kernel_shape(int kind, T t, T ex) {
+  switch (kind) {
+    case FKF_MATERN_12: return ex;
+    case FKF_MATERN_32: return t * ex + ex;
+    case FKF_MATERN_52: return (t * (T)(1.0 / 3.0) + (T)1) * t * ex + ex;
+    case FKF_MATERN_12_DLENGTH: return t * ex;
+    case FKF_MATERN_32_DLENGTH: return t * t * ex;
+    default: return t * t * ((T)1 + t) * ex * (T)(1.0 / 3.0);
+  }
+}
+
+// amp * shape at distance r (near-field assembly; amp is the variance, or
+// variance / ell for a length derivative).
+__device__ __forceinline__ double matern_dev(double r, int kind, double inv_ell, double amp) {
+  const double t = kernel_c(kind) * r * inv_ell;
+  return amp * kernel_shape<double>(kind, t, exp(-t));
+}
+
+// Kernel entry amp * shape(t) from the square t2 of the scaled distance.
+// F32: evaluated with the FP32 hardware square root and exponential (mixed
+// precision).
 template <bool F32>
-__device__ __forceinline__ double kernel_t2(double t2, int kind, double theta) {
+__device__ __forceinline__ double kernel_t2(double t2, int kind, double amp) {
   if (F32) {
     const float t = __fsqrt_rn((float)t2);
-    const float ex = __expf(-t);
-    float kv = kind == FKF_MATERN_12 ? ex
-                                     : (kind == FKF_MATERN_32 ? fmaf(t, ex, ex)
-                                                              : fmaf(fmaf(t, 1.0f / 3.0f, 1.0f) * t, ex, ex));
-    return theta * (double)kv;
+    return amp * (double)kernel_shape<float>(kind, t, __expf(-t));
   } else {
     const double t = sqrt_pos(t2);
-    const double ex = exp_nonpos(-t);
-    double kv = kind == FKF_MATERN_12 ? ex
-                                      : (kind == FKF_MATERN_32 ? fma(t, ex, ex)
-                                                               : fma(fma(t, 1.0 / 3.0, 1.0) * t, ex, ex));
-    return theta * kv;
+    return amp * kernel_shape<double>(kind, t, exp_nonpos(-t));
   }
 }
 
@@ -619,8 +631,7 @@ __global__ void __launch_bounds__(256) k_couple_blk(const CoupleItem *__restrict
   const int r0 = kRowBlk * it.rb, c0 = 64 * it.cb;
   const int rows = min(kRowBlk, pds - r0), cols = min(64, pdt - c0);
   const int ncb = (pdt + 63) >> 6;
-  const double sq = kind == FKF_MATERN_12 ? 1.0 : (kind == FKF_MATERN_32 ? 1.7320508075688772
-                                                                          : 2.2360679774997896);
+  const double sq = kernel_c(kind);
   const double scale = sq * inv_ell;
   const double *us = cheb + ps * 2 * kMaxCheb, *ut = cheb + pt * 2 * kMaxCheb;
   if (l < rows) {
@@ -718,8 +729,7 @@ __global__ void __launch_bounds__(256) k_couple_store(const PairItem *__restrict
   const PairItem pr = pairs[blockIdx.x];
   const FarCluster cs = fc[pr.s], ct = fc[pr.t];
   const int ps = cs.p, pt = ct.p, pds = cs.pd, pdt = ct.pd;
-  const double sq = kind == FKF_MATERN_12 ? 1.0 : (kind == FKF_MATERN_32 ? 1.7320508075688772
-                                                                          : 2.2360679774997896);
+  const double sq = kernel_c(kind);
   const double scale = sq * inv_ell;
   const double *us = cheb + ps * 2 * kMaxCheb, *ut = cheb + pt * 2 * kMaxCheb;
   KT *dst = reinterpret_cast<KT *>(kst) + pr.koff;
@@ -1138,8 +1148,7 @@ __global__ void __launch_bounds__(256) k_couple_mfma(const FarCluster *__restric
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int lr = l & 15, lk = l >> 4;
   const int ps = cs.p, pds = cs.pd;
-  const double sq = kind == FKF_MATERN_12 ? 1.0 : (kind == FKF_MATERN_32 ? 1.7320508075688772
-                                                                          : 2.2360679774997896);
+  const double sq = kernel_c(kind);
   const double scale = sq * inv_ell;
   const double *us = cheb + ps * 2 * kMaxCheb;
   double xa[RBW][D];
@@ -1389,7 +1398,7 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
     FKF_REQUIRE(d == 2 || d == 3, "fkf_cov_build: d must be 2 or 3");
     FKF_REQUIRE(kp->struct_size == sizeof(fkf_kernel_params), "fkf_cov_build: kernel struct_size");
     FKF_REQUIRE(hp->struct_size == sizeof(fkf_hmat_params), "fkf_cov_build: hmat struct_size");
-    FKF_REQUIRE(kp->kind >= 0 && kp->kind <= 2, "fkf_cov_build: unknown kernel kind");
+    FKF_REQUIRE(kp->kind >= 0 && kp->kind <= 5, "fkf_cov_build: unknown kernel kind");
     FKF_REQUIRE(kp->variance > 0 && kp->length > 0, "fkf_cov_build: variance and length must be > 0");
     FKF_REQUIRE(hp->leaf_size >= 1 && hp->leaf_size <= kTile, "fkf_cov_build: leaf_size in 1..64");
     FKF_REQUIRE(hp->cheb_order >= 2 && hp->cheb_order <= kMaxCheb, "fkf_cov_build: cheb_order in 2..16");
@@ -1410,6 +1419,7 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
     cov->kind = kp->kind;
     cov->theta = kp->variance;
     cov->ell = kp->length;
+    cov->amp = kp->kind >= FKF_MATERN_12_DLENGTH ? kp->variance / kp->length : kp->variance;
     cov->hp = *hp;
     Tree &t = cov->tree;
     t = build_tree(pts_host, n, d, hp->leaf_size);
@@ -1490,13 +1500,13 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
       if (cov->n_blk > 0)
         hipLaunchKernelGGL(k_near_assemble32, dim3((unsigned)cov->n_blk), dim3(64), 0, st,
                            cov->pts.p, n, d, cov->leaf_off.p, cov->blk_s.p, cov->blk_t.p,
-                           cov->kind, 1.0 / cov->ell, cov->theta, cov->blk32.p);
+                           cov->kind, 1.0 / cov->ell, cov->amp, cov->blk32.p);
     } else {
       cov->blk.alloc((size_t)cov->n_blk * 4096);
       if (cov->n_blk > 0)
         hipLaunchKernelGGL(k_near_assemble, dim3((unsigned)cov->n_blk), dim3(64), 0, st,
                            cov->pts.p, n, d, cov->leaf_off.p, cov->blk_s.p, cov->blk_t.p,
-                           cov->kind, 1.0 / cov->ell, cov->theta, cov->blk.p);
+                           cov->kind, 1.0 / cov->ell, cov->amp, cov->blk.p);
     }
     FKF_CHECK_HIP(hipGetLastError());
 
@@ -1645,7 +1655,7 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
       }
       auto store = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3((unsigned)cov->n_pairs), dim3(256), 0, st, cov->pairs.p,
-                           cov->fc.p, cov->cheb.p, cov->kind, 1.0 / cov->ell, cov->theta, dst);
+                           cov->fc.p, cov->cheb.p, cov->kind, 1.0 / cov->ell, cov->amp, dst);
       };
       if (d == 3)
         cov->mixed ? store(k_couple_store<3, true>) : store(k_couple_store<3, false>);
@@ -1735,7 +1745,7 @@ void apply_one(fkf_cov *cov, double *Y, hipStream_t st) {
         if (cov->n_citems > 0)
           hipLaunchKernelGGL(kern, dim3((unsigned)((cov->n_citems + 3) / 4)), dim3(256), 0, st,
                            cov->citems.p, cov->n_citems, cov->pairs.p, cov->fc.p, cov->cheb.p,
-                           cov->kind, 1.0 / cov->ell, cov->theta, cov->xhat.p,
+                           cov->kind, 1.0 / cov->ell, cov->amp, cov->xhat.p,
                            cov->part_pair.p);
       };
       const unsigned gc = (unsigned)((cov->n_citems + 3) / 4);
@@ -1813,7 +1823,7 @@ void apply_multi_t(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t s
       FKF_TRACE("hmat_far_couple_multi", st);
       hipLaunchKernelGGL((k_couple_mfma<D, NCB, RBW, F32>), dim3(cov->n_fc, gy), dim3(256), 0, st,
                          cov->fc.p, cov->far_ptr.p, cov->far_col.p, cov->cheb.p, cov->kind,
-                         1.0 / cov->ell, cov->theta, cov->xhat.p, nrhs, cov->yhat.p);
+                         1.0 / cov->ell, cov->amp, cov->xhat.p, nrhs, cov->yhat.p);
     }
   }
   typedef typename std::conditional<F32, float, double>::type TT;
@@ -1976,7 +1986,11 @@ extern "C" fkf_status fkf_cov_plan(const double *pts_host, int64_t n, int32_t d,
 }
 
 namespace fkf {
-double cov_variance(const fkf_cov *cov) { return cov->theta; }
+double cov_variance(const fkf_cov *cov) {
+  return cov->kind >= FKF_MATERN_12_DLENGTH ? 0.0 : cov->theta;   // diagonal of the operator
+}
+int cov_kind(const fkf_cov *cov) { return cov->kind; }
+double cov_length(const fkf_cov *cov) { return cov->ell; }
 bool cov_mixed(const fkf_cov *cov) { return cov->mixed; }
 int64_t cov_n(const fkf_cov *cov) { return cov->n; }
 }  // namespace fkf

@@ -1,9 +1,11 @@
 """GPU parity of the innovation log-likelihood the filter accumulates
-(fkf_filter_loglik) and of its derivatives with respect to log theta and
-log sigma^2, against the oracle: the dense prediction-error log-likelihood
-and its central differences (themselves pinned to the closed-form gradient of
-the joint Gaussian density).  Bars: 1e-6 relative for the log-likelihood,
-1e-5 relative for the derivatives.
+(fkf_filter_loglik) and of its derivatives with respect to log theta, log
+length and log sigma^2, against the oracle: the dense prediction-error
+log-likelihood and its central differences (themselves pinned to the
+closed-form gradients of the joint Gaussian density); and of the
+length-derivative operator dGamma/d length against direct products.  Bars:
+1e-6 relative for the log-likelihood and the derivative operator, 1e-5
+relative for the derivatives.
 """
 import sys
 
@@ -43,6 +45,46 @@ def _rel(a, b):
     return abs(a - b) / max(abs(b), 1e-300)
 
 
+def _fd_log_length(wl, H, R, ys, K, alpha0, h=1e-4):
+    """Central difference of the oracle's log-likelihood over log length."""
+    pts = wl.points()
+
+    def ll(e):
+        G = direct.dense_cov(pts, wl.nu, e, wl.variance)
+        return kalman.innovation_loglik(G, [H] * K, [R] * K, ys[:K], alpha0=alpha0)
+    return (ll(wl.length * np.exp(h)) - ll(wl.length * np.exp(-h))) / (2 * h)
+
+
+DPTS = {
+    "grid-48x40": lambda: W.grid_points((48, 40)),
+    "jitter-40x31": lambda: W.grid_points((40, 31)) + np.random.default_rng(8).uniform(
+        -0.004, 0.004, (1240, 2)),
+    "cube-14": lambda: W.grid_points((14, 14, 14)),
+}
+
+
+@pytest.mark.parametrize("pname", list(DPTS))
+@pytest.mark.parametrize("nu", [0.5, 1.5, 2.5])
+def test_length_derivative_operator_matches_direct(pname, nu):
+    import torch
+    import paper_1405_2276_amd as fkf
+    pts = DPTS[pname]()
+    ell, theta = 0.2, 0.7
+    _say(f"[loglik] dGamma/dl case={pname} nu={nu} n={len(pts)}")
+    cov = fkf.Cov(pts, nu=nu, length=ell, variance=theta, leaf_size=48, dlength=True)
+    X = np.random.default_rng(3).standard_normal((len(pts), 5))
+    want = direct.cov_matvec(pts, X, nu, ell, theta, dlength=True)
+    Xd = torch.from_numpy(np.asfortranarray(X).T.copy()).cuda().t()
+    got = cov.apply(Xd)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    _say(f"[loglik] dGamma/dl case={pname} nu={nu} relerr={err:.2e}")
+    assert err <= 1e-6
+    with pytest.raises(fkf.FkfError):
+        fkf.Filter(cov)                      # not a covariance
+
+
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("alpha0", [0.0, 0.5])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -56,20 +98,32 @@ def test_loglik_and_derivatives_constant_h(name, alpha0, precision):
                   leaf_size=wl.leaf_size, precision=precision)
     src, rcv = wl.rays()
     obs = fkf.Obs.from_rays(wl.shape, src, rcv, wl.noise_var)
+    dcov = fkf.Cov(pts, nu=wl.nu, length=wl.length, variance=wl.variance,
+                   leaf_size=wl.leaf_size, precision=precision, dlength=True)
     f = fkf.Filter(cov, alpha0=alpha0)
-    assert f.loglik() == (0.0, 0.0, 0.0)
+    f.track_length(dcov)
+    assert f.loglik() == (0.0, 0.0, 0.0, 0.0)
     for k in range(wl.steps):
         f.step(obs, ys[k])
-        ll, d_th, d_nv = f.loglik()
+        ll, d_th, d_nv, d_ln = f.loglik()
         K = k + 1
         want = kalman.innovation_loglik(Gamma, [H] * K, [R] * K, ys[:K], alpha0=alpha0)
         w_th, w_nv = kalman.loglik_log_derivatives_fd(Gamma, [H] * K, [R] * K, ys[:K],
                                                       alpha0=alpha0)
-        e, et, en = _rel(ll, want), _rel(d_th, w_th), _rel(d_nv, w_nv)
+        w_ln = _fd_log_length(wl, H, R, ys, K, alpha0)
+        e, et, en, el = _rel(ll, want), _rel(d_th, w_th), _rel(d_nv, w_nv), _rel(d_ln, w_ln)
         _say(f"[loglik] {name} {precision} step={K} ll={ll:.6e} err={e:.1e} "
-             f"dlogtheta={d_th:.4e} err={et:.1e} dlognoise={d_nv:.4e} err={en:.1e}")
-        assert e <= LL_TOL and et <= GRAD_TOL and en <= GRAD_TOL
+             f"dlogtheta={d_th:.4e} err={et:.1e} dlognoise={d_nv:.4e} err={en:.1e} "
+             f"dloglength={d_ln:.4e} err={el:.1e}")
+        assert e <= LL_TOL and et <= GRAD_TOL and en <= GRAD_TOL and el <= GRAD_TOL
     f.status()
+    with pytest.raises(fkf.FkfError) as e:
+        f.track_length(dcov)                 # only before the first step
+    assert e.value.name == "FKF_E_ORDER"
+    g = fkf.Filter(cov)
+    with pytest.raises(fkf.FkfError) as e:
+        g.track_length(cov)                  # not a length derivative
+    assert e.value.name == "FKF_E_ARG"
 
 
 def test_loglik_varying_h_and_extended_filter():
@@ -114,19 +168,22 @@ def test_autograd_function_matches_oracle_gradient():
     ys = W.observations(wl)
     src, rcv = wl.rays()
     theta = torch.tensor(wl.variance, dtype=torch.float64, requires_grad=True)
+    length = torch.tensor(wl.length, dtype=torch.float64, requires_grad=True)
     noise = torch.tensor(wl.noise_var, dtype=torch.float64, requires_grad=True)
-    ll = fkf.innovation_loglik(theta, noise, pts,
+    ll = fkf.innovation_loglik(theta, length, noise, pts,
                                lambda nv: fkf.Obs.from_rays(wl.shape, src, rcv, nv),
-                               [y for y in ys], nu=wl.nu, length=wl.length,
-                               leaf_size=wl.leaf_size)
+                               [y for y in ys], nu=wl.nu, leaf_size=wl.leaf_size)
     ll.backward()
     K = len(ys)
     want = kalman.innovation_loglik(Gamma, [H] * K, [R] * K, ys)
     w_th, w_nv = kalman.loglik_log_derivatives_fd(Gamma, [H] * K, [R] * K, ys)
-    g_th, g_nv = theta.grad.item(), noise.grad.item()
+    w_ln = _fd_log_length(wl, H, R, ys, K, 0.0)
+    g_th, g_ln, g_nv = theta.grad.item(), length.grad.item(), noise.grad.item()
     _say(f"[loglik] autograd ll err={_rel(ll.item(), want):.1e} "
          f"dtheta={g_th:.5e} err={_rel(g_th, w_th / wl.variance):.1e} "
+         f"dlength={g_ln:.5e} err={_rel(g_ln, w_ln / wl.length):.1e} "
          f"dnoise={g_nv:.5e} err={_rel(g_nv, w_nv / wl.noise_var):.1e}")
     assert _rel(ll.item(), want) <= LL_TOL
     assert _rel(g_th, w_th / wl.variance) <= GRAD_TOL
+    assert _rel(g_ln, w_ln / wl.length) <= GRAD_TOL
     assert _rel(g_nv, w_nv / wl.noise_var) <= GRAD_TOL

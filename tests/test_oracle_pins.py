@@ -286,3 +286,44 @@ def test_loglik_derivatives_match_joint_gaussian_closed_form(alpha0):
     want = [-0.5 * (np.trace(np.linalg.solve(C, M)) - Ci_y @ M @ Ci_y) for M in (CG, CR)]
     got = kalman.loglik_log_derivatives_fd(Gamma, Hs, Rs, ys, alpha0=alpha0)
     np.testing.assert_allclose(got, want, rtol=1e-7, atol=1e-10)
+
+
+@pytest.mark.parametrize("nu", [0.5, 1.5, 2.5])
+@pytest.mark.parametrize("ell", [0.1, 0.3])
+def test_matern_length_derivative_matches_central_differences_of_bessel_form(nu, ell):
+    # differentiate the Bessel form itself (an independent route to C)
+    r = np.geomspace(1e-4, 3.0, 120)
+    h = 1e-4 * ell
+    fd = (kernels.matern_bessel(r, nu, ell + h, 2.5) - kernels.matern_bessel(r, nu, ell - h, 2.5)) / (2 * h)
+    np.testing.assert_allclose(kernels.matern_dlength(r, nu, ell, 2.5), fd, rtol=1e-6, atol=1e-9)
+    assert kernels.matern_dlength(0.0, nu, ell, 2.5) == 0.0
+
+
+@pytest.mark.parametrize("alpha0", [0.0, 0.4])
+def test_loglik_length_derivative_matches_joint_gaussian_closed_form(alpha0):
+    # d ll / d log ell = ell * -(tr(C^-1 C') - y^T C^-1 C' C^-1 y)/2 with
+    # C' built from dGamma/d ell; against central differences of the oracle's
+    # prediction-error log-likelihood over log ell
+    g = np.random.default_rng(4)
+    pts = g.uniform(0, 1, (7, 2))
+    nu, ell, theta = 1.5, 0.4, 0.8
+    Hs = [g.standard_normal((2 + k % 2, 7)) for k in range(3)]
+    Rs = [g.uniform(0.1, 0.5, H.shape[0]) for H in Hs]
+    ys = [g.standard_normal(H.shape[0]) for H in Hs]
+    Gamma = kernels.cov_block(pts, pts, nu, ell, theta)
+    dG = kernels.cov_block(pts, pts, nu, ell, theta, dlength=True)
+    K = len(Hs)
+    C = np.block([[(alpha0 + min(i, j) + 1) * Hs[i] @ Gamma @ Hs[j].T for j in range(K)]
+                  for i in range(K)]) + np.diag(np.concatenate(Rs))
+    Cp = np.block([[(alpha0 + min(i, j) + 1) * Hs[i] @ dG @ Hs[j].T for j in range(K)]
+                   for i in range(K)])
+    y = np.concatenate(ys)
+    Ci_y = np.linalg.solve(C, y)
+    want = -0.5 * ell * (np.trace(np.linalg.solve(C, Cp)) - Ci_y @ Cp @ Ci_y)
+    hh = 1e-4
+
+    def ll(e):
+        return kalman.innovation_loglik(kernels.cov_block(pts, pts, nu, e, theta), Hs, Rs, ys,
+                                        alpha0=alpha0)
+    fd = (ll(ell * np.exp(hh)) - ll(ell * np.exp(-hh))) / (2 * hh)
+    assert fd == pytest.approx(want, rel=1e-7, abs=1e-10)
