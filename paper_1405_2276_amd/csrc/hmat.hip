@@ -63,6 +63,12 @@ struct CoupleItem {
   int16_t rb, cb;
 };
 
+// A 64-row block rb of the coefficients of far cluster s (several-column
+// couplings).
+struct CoupleMItem {
+  int32_t s, rb;
+};
+
 // A sub-block of stored couplings with every offset resolved at build, so a
 // wavefront needs one (scalar) descriptor load before streaming K.
 struct CoupleItemSt {
@@ -102,8 +108,15 @@ struct fkf_cov {
   bool mixed = false;
   fkf::DevBuf<int32_t> part_ptr, part_idx;   // per leaf: entries blk*2 + side
   fkf::DevBuf<int32_t> near_ptr, near_idx;   // per leaf: entries blk*2 + transposed
+  // tiles of the ordered near pairs (near_idx order) in FP64 MFMA A-operand
+  // order, for the several-column product (FP32 in the mixed mode)
+  fkf::DevBuf<double> frag;
+  fkf::DevBuf<float> frag32;
   fkf::DevBuf<fkf::FarCluster> fc;
   fkf::DevBuf<int32_t> far_ptr, far_col;     // partners per target far cluster
+  fkf::DevBuf<fkf::CoupleMItem> cm_items;     // several-column coupling blocks, costliest first
+  int64_t n_cm_items = 0;
+  bool cm_all = true;                         // every far cluster has a partner
   fkf::DevBuf<int32_t> anc_ptr, anc_idx;     // far-cluster ancestors of each leaf
   fkf::DevBuf<double> cheb;                  // [p][a] nodes and weights
   // one-column far field work lists
@@ -1232,10 +1245,276 @@ __global__ void __launch_bounds__(256) k_couple_mfma(const FarCluster *__restric
       }
 }
 
+// Couplings of the several-column product, Yhat_s = sum over admissible t of
+// K(xi_s, xi_t) Xhat_t, for one 64-row block of cluster s and 512 columns per
+// workgroup.  The workgroup evaluates each 64 x 16 chunk of K once into LDS
+// (double-buffered, one barrier per chunk); wavefront w multiplies it with
+// columns [64 w, 64 w + 64) of Xhat_t, whose B operands it reads straight from
+// global memory one chunk ahead (every 32-byte sector fully used).  Rows past
+// the cluster and coefficients past the partner are zero in K; only the
+// 16-row blocks inside the cluster are multiplied.
+__global__ void k_zero(double *__restrict__ p, int64_t len) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) p[i] = 0.0;
+}
+
+template <int D, bool F32>
+__global__ void __launch_bounds__(512) k_couple_mfma2(
+    const CoupleMItem *__restrict__ items, const FarCluster *__restrict__ fc,
+    const int32_t *__restrict__ far_ptr, const int32_t *__restrict__ far_col,
+    const double *__restrict__ cheb, int kind, double inv_ell, double amp,
+    const double *__restrict__ xhat, int nrhs, double *__restrict__ yhat) {
+  constexpr int KC = 16, LDK = 18;
+  __shared__ double Ks[2][64 * LDK];
+  const CoupleMItem it = items[blockIdx.x];
+  const FarCluster cs = fc[it.s];
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
+  const int lr = l & 15, lk = l >> 4;
+  const int r0 = 64 * it.rb;
+  const int rows = min(64, cs.pd - r0);
+  const int nrb = (rows + 15) >> 4;
+  const int c0 = blockIdx.y * 512 + 64 * w;
+  const double scale = kernel_c(kind) * inv_ell;
+  // K evaluation role of this thread: row er, chunk columns ek, ek + 1
+  const int er = tid >> 3, ek = 2 * (tid & 7);
+  double xs[D];
+  {
+    int r = er < rows ? r0 + er : 0;
+    const double *us = cheb + cs.p * 2 * kMaxCheb;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      xs[k] = scale * (cs.ctr[k] + cs.hw[k] * us[r % cs.p]);
+      r /= cs.p;
+    }
+  }
+  const int e0 = far_ptr[it.s], e1 = far_ptr[it.s + 1];
+  // chunk sequence: (partner e, first coefficient k0)
+  auto eval_chunk = [&](int e, int k0, int buf) {
+    const FarCluster ct = fc[far_col[e]];
+    const double *ut = cheb + ct.p * 2 * kMaxCheb;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int kb = k0 + ek + h;
+      int r = kb < ct.pd ? kb : 0;
+      double t2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        const double dx = xs[k] - scale * (ct.ctr[k] + ct.hw[k] * ut[r % ct.p]);
+        t2 = fma(dx, dx, t2);
+        r /= ct.p;
+      }
+      const double kv = kernel_t2<F32>(t2, kind, amp);
+      Ks[buf][er * LDK + ek + h] = (er < rows && kb < ct.pd) ? kv : 0.0;
+    }
+  };
+  auto load_b = [&](int e, int k0, double *b) {
+    const FarCluster ct = fc[far_col[e]];
+    const double *x = xhat + ct.coef_off * nrhs;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int kb = k0 + 4 * kk + lk;
+      const int kc = kb < ct.pd ? kb : 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int c = c0 + 16 * j + lr;
+        b[4 * kk + j] = x[kc + (int64_t)ct.pd * (c < nrhs ? c : 0)];
+      }
+    }
+  };
+  v4d acc[4][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[q][j] = v4d{0, 0, 0, 0};
+  double bcur[16], bnext[16];
+  int e = e0, k0 = 0, buf = 0;
+  if (e < e1) load_b(e, k0, bcur);
+  while (e < e1) {
+    eval_chunk(e, k0, buf);
+    // next chunk
+    int en = e, kn = k0 + KC;
+    if (kn >= fc[far_col[e]].pd) {
+      ++en;
+      kn = 0;
+    }
+    if (en < e1) load_b(en, kn, bnext);
+    __syncthreads();
+    const double *K = Ks[buf];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (q < nrb) {
+          const double a = K[(16 * q + lr) * LDK + 4 * kk + lk];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[q][j] = mfma4(a, bcur[4 * kk + j], acc[q][j]);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) bcur[i] = bnext[i];
+    e = en;
+    k0 = kn;
+    buf ^= 1;
+  }
+  double *o = yhat + cs.coef_off * nrhs;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = 16 * q + lk + 4 * r;
+        const int cc = c0 + 16 * j + lr;
+        if (a < rows && cc < nrhs) o[r0 + a + (int64_t)cs.pd * cc] = acc[q][j][r];
+      }
+}
+
 // Near field + downward pass + scatter for one leaf and NC columns:
 // Y_s = sum_{t near s} Gamma_st X_t + sum_{far ancestors c} U_c|_s Yhat_c.
 // MODE 0: near field and downward pass, Y = result; MODE 1: near field only,
 // Y = near part; MODE 2: downward pass only, Y += far part.
+// Tiles of the ordered near pairs in MFMA operand order.  Pair e (entry e of
+// near_idx: stored tile b, used as is or transposed) becomes 4096 entries
+// frag[e][w][kk][l] = A[16 w + l % 16][4 kk + l / 16] with A = tile or
+// tile^T: the A operand of step kk of the 16 x 16 x 4 FP64 MFMA for rows
+// 16w..16w+15, so that a wavefront loads its operands with coalesced
+// 64-lane loads.  One workgroup per ordered pair.
+template <typename TT>
+__global__ void __launch_bounds__(256) k_near_repack(const TT *__restrict__ blk,
+                                                     const int32_t *__restrict__ near_idx,
+                                                     TT *__restrict__ frag) {
+  __shared__ double As[64][65];
+  const int64_t e = blockIdx.x;
+  const int code = near_idx[e];
+  const int64_t b = code >> 1;
+  const bool trans = code & 1;
+  const int tid = threadIdx.x;
+  if (sizeof(TT) == 8) {
+    const v2d *src = reinterpret_cast<const v2d *>(blk + b * 4096);
+    for (int q = tid; q < 2048; q += 256) {
+      const int k = q >> 6, lane = q & 63;
+      const int i = 8 * (lane & 7) + (k >> 2), j = 8 * (lane >> 3) + 2 * (k & 3);
+      const v2d v = src[q];
+      if (!trans) {
+        As[i][j] = v.x;
+        As[i][j + 1] = v.y;
+      } else {
+        As[j][i] = v.x;
+        As[j + 1][i] = v.y;
+      }
+    }
+  } else {
+    const float4 *src = reinterpret_cast<const float4 *>(blk + b * 4096);
+    for (int q = tid; q < 1024; q += 256) {
+      const int k = q >> 6, lane = q & 63;
+      const int i = 8 * (lane & 7) + (k >> 1), j = 8 * (lane >> 3) + 4 * (k & 1);
+      const float4 v = src[q];
+      const double vv[4] = {v.x, v.y, v.z, v.w};
+      for (int h = 0; h < 4; ++h) {
+        if (!trans)
+          As[i][j + h] = vv[h];
+        else
+          As[j + h][i] = vv[h];
+      }
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < 4096; idx += 256) {
+    const int w = idx >> 10, kk = (idx >> 6) & 15, l = idx & 63;
+    frag[e * 4096 + idx] = (TT)As[16 * w + (l & 15)][4 * kk + (l >> 4)];
+  }
+}
+
+// Near field of the several-column product on the FP64 matrix cores,
+// Y[perm, c] = sum over the near pairs (s, t) of A_st X_t: one workgroup per
+// (target leaf s, block of 64 columns), one wavefront per 16 rows.  The A
+// operands come from the repacked tiles straight into registers (coalesced,
+// one pair ahead); the 64 x 64 block of X_t goes through LDS, stored
+// column-major with row stride 66 (conflict-free operand reads) and
+// double-buffered, so that a pair costs one barrier.  Rows of X_t beyond the
+// leaf and columns beyond nrhs are staged as zeros.
+template <typename TT>
+__global__ void __launch_bounds__(256) k_near_mfma(
+    const TT *__restrict__ frag, const int32_t *__restrict__ near_ptr,
+    const int32_t *__restrict__ near_idx, const int32_t *__restrict__ bs,
+    const int32_t *__restrict__ bt, const int64_t *__restrict__ leaf_off, int64_t n,
+    const double *__restrict__ xt, const int64_t *__restrict__ perm, int nrhs,
+    double *__restrict__ Y, int64_t ldy) {
+  constexpr int NC = 64, LDB = 66;
+  __shared__ double Bt[2][NC * LDB];
+  const int s = blockIdx.x;
+  const int c0 = blockIdx.y * NC;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int lr = l & 15, lk = l >> 4;
+  const int e0 = near_ptr[s], e1 = near_ptr[s + 1];
+  const int64_t s0 = leaf_off[s], ms = leaf_off[s + 1] - s0;
+  double breg[16], acur[16], anext[16];
+  // X_t block of pair e into registers: thread (k = l, columns w + 4q)
+  auto load_b = [&](int e) {
+    const int code = near_idx[e];
+    const int64_t b = code >> 1;
+    const int t = (code & 1) ? bs[b] : bt[b];
+    const int64_t t0 = leaf_off[t], mt = leaf_off[t + 1] - t0;
+    const bool row_ok = l < mt;
+    const int64_t r = t0 + (row_ok ? l : 0);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int c = c0 + w + 4 * q;
+      const double v = xt[r + n * (int64_t)(c < nrhs ? c : 0)];
+      breg[q] = (row_ok && c < nrhs) ? v : 0.0;
+    }
+  };
+  auto store_b = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) Bt[buf][(w + 4 * q) * LDB + l] = breg[q];
+  };
+  auto load_a = [&](int e, double *a) {
+    const TT *src = frag + (int64_t)e * 4096 + w * 1024 + l;
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) a[kk] = (double)src[kk * 64];
+  };
+  v4d acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j] = v4d{0, 0, 0, 0};
+  if (e1 > e0) {   // (every leaf is near itself; kept for safety)
+    load_b(e0);
+    load_a(e0, acur);
+    store_b(0);
+  }
+  __syncthreads();
+  for (int e = e0; e < e1; ++e) {
+    const int cur = (e - e0) & 1;
+    const bool more = e + 1 < e1;
+    if (more) {
+      load_b(e + 1);
+      load_a(e + 1, anext);
+    }
+    const double *B = Bt[cur];
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const int k = 4 * kk + lk;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[j] = mfma4(acur[kk], B[(16 * j + lr) * LDB + k], acc[j]);
+    }
+    if (more) {
+      store_b(cur ^ 1);
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) acur[kk] = anext[kk];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = w * 16 + lk + 4 * r;
+      const int cc = c0 + j * 16 + lr;
+      if (i < ms && cc < nrhs) Y[perm[s0 + i] + ldy * cc] = acc[j][r];
+    }
+}
+
 template <int D, int NCB, typename TT, int MODE>
 __global__ void __launch_bounds__(256) k_down_mfma(
     const TT *__restrict__ blk, const int32_t *__restrict__ near_ptr,
@@ -1509,6 +1788,18 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
                            cov->kind, 1.0 / cov->ell, cov->amp, cov->blk.p);
     }
     FKF_CHECK_HIP(hipGetLastError());
+    if (cov->n_near_pairs > 0) {
+      if (cov->mixed) {
+        cov->frag32.alloc((size_t)cov->n_near_pairs * 4096);
+        hipLaunchKernelGGL(k_near_repack<float>, dim3((unsigned)cov->n_near_pairs), dim3(256), 0,
+                           st, cov->blk32.p, cov->near_idx.p, cov->frag32.p);
+      } else {
+        cov->frag.alloc((size_t)cov->n_near_pairs * 4096);
+        hipLaunchKernelGGL(k_near_repack<double>, dim3((unsigned)cov->n_near_pairs), dim3(256), 0,
+                           st, cov->blk.p, cov->near_idx.p, cov->frag.p);
+      }
+      FKF_CHECK_HIP(hipGetLastError());
+    }
 
     // far clusters
     std::vector<int> fidx(t.nodes.size(), -1);
@@ -1557,6 +1848,29 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
     cov->fc.upload(fcs, st);
     cov->far_ptr.upload(fp, st);
     cov->far_col.upload(fcol, st);
+    {
+      // several-column coupling blocks: (cluster, 64-row block), ordered by
+      // decreasing work (rows x sum of the partners' coefficients)
+      std::vector<std::pair<int64_t, CoupleMItem>> cm;
+      for (int s = 0; s < cov->n_fc; ++s) {
+        int64_t kext = 0;
+        for (int e = fp[s]; e < fp[s + 1]; ++e) kext += fcs[fcol[e]].pd;
+        if (kext == 0) {
+          cov->cm_all = false;
+          continue;
+        }
+        for (int rb = 0; 64 * rb < fcs[s].pd; ++rb) {
+          const int rows = std::min(64, fcs[s].pd - 64 * rb);
+          cm.push_back({(int64_t)rows * kext, CoupleMItem{s, rb}});
+        }
+      }
+      std::stable_sort(cm.begin(), cm.end(),
+                       [](const auto &a, const auto &b) { return a.first > b.first; });
+      std::vector<CoupleMItem> cmi(cm.size());
+      for (size_t i = 0; i < cm.size(); ++i) cmi[i] = cm[i].second;
+      cov->n_cm_items = (int64_t)cmi.size();
+      cov->cm_items.upload(cmi, st);
+    }
     cov->anc_ptr.upload(ap, st);
     cov->anc_idx.upload(ai, st);
     // one-column work lists: upward chunks and unordered pairs
@@ -1785,6 +2099,16 @@ void apply_one(fkf_cov *cov, double *Y, hipStream_t st) {
   }
 }
 
+// Near field of the several-column product (written to Y in caller order).
+template <bool F32>
+void near_multi(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t s) {
+  typedef typename std::conditional<F32, float, double>::type TT;
+  const TT *frag = F32 ? (const TT *)cov->frag32.p : (const TT *)cov->frag.p;
+  hipLaunchKernelGGL(k_near_mfma<TT>, dim3(cov->n_leaves, (unsigned)((nrhs + 63) / 64)),
+                     dim3(256), 0, s, frag, cov->near_ptr.p, cov->near_idx.p, cov->blk_s.p,
+                     cov->blk_t.p, cov->leaf_off.p, cov->n, cov->xt.p, cov->perm.p, nrhs, Y, ldy);
+}
+
 // Several columns on the FP64 matrix cores: upward chunks + reduction,
 // couplings per target cluster, then near field + downward + scatter per leaf.
 template <int D, int NCB, int RBW, bool F32>
@@ -1803,12 +2127,7 @@ void apply_multi_t(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t s
     FKF_CHECK_HIP(hipStreamWaitEvent(cov->side, cov->ev_fork, 0));
     {
       FKF_TRACE("hmat_near_multi", cov->side);
-      typedef typename std::conditional<F32, float, double>::type TTn;
-      hipLaunchKernelGGL((k_down_mfma<D, NCB, TTn, 1>), dim3(cov->n_leaves, gy), dim3(256), 0,
-                         cov->side, F32 ? (const TTn *)cov->blk32.p : (const TTn *)cov->blk.p,
-                         cov->near_ptr.p, cov->near_idx.p, cov->blk_s.p, cov->blk_t.p,
-                         cov->leaf_off.p, cov->pts.p, n, cov->cheb.p, cov->fc.p, cov->anc_ptr.p,
-                         cov->anc_idx.p, cov->xt.p, cov->yhat.p, cov->perm.p, nrhs, Y, ldy);
+      near_multi<F32>(cov, nrhs, Y, ldy, cov->side);
     }
     FKF_CHECK_HIP(hipEventRecord(cov->ev_join, cov->side));
     {
@@ -1821,9 +2140,18 @@ void apply_multi_t(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t s
     }
     {
       FKF_TRACE("hmat_far_couple_multi", st);
-      hipLaunchKernelGGL((k_couple_mfma<D, NCB, RBW, F32>), dim3(cov->n_fc, gy), dim3(256), 0, st,
-                         cov->fc.p, cov->far_ptr.p, cov->far_col.p, cov->cheb.p, cov->kind,
-                         1.0 / cov->ell, cov->amp, cov->xhat.p, nrhs, cov->yhat.p);
+      // clusters without partners get zero coefficients
+      if (!cov->cm_all) {
+        const int64_t len = cov->n_coef * nrhs;
+        hipLaunchKernelGGL(k_zero, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st,
+                           cov->yhat.p, len);
+      }
+      if (cov->n_cm_items > 0)
+        hipLaunchKernelGGL((k_couple_mfma2<D, F32>),
+                           dim3((unsigned)cov->n_cm_items, (unsigned)((nrhs + 511) / 512)),
+                           dim3(512), 0, st, cov->cm_items.p, cov->fc.p, cov->far_ptr.p,
+                           cov->far_col.p, cov->cheb.p, cov->kind, 1.0 / cov->ell, cov->amp,
+                           cov->xhat.p, nrhs, cov->yhat.p);
     }
   }
   typedef typename std::conditional<F32, float, double>::type TT;
@@ -1836,7 +2164,7 @@ void apply_multi_t(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t s
   };
   if (cov->n_fc == 0) {
     FKF_TRACE("hmat_near_multi", st);
-    down(k_down_mfma<D, NCB, TT, 1>, st);
+    near_multi<F32>(cov, nrhs, Y, ldy, st);
     return;
   }
   FKF_TRACE("hmat_down_multi", st);
