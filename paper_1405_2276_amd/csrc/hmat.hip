@@ -64,7 +64,7 @@ struct CoupleItem {
 };
 
 // A 64-row block rb of the coefficients of far cluster s (several-column
-// couplings).
+// couplings), or of upward item u (several-column upward pass).
 struct CoupleMItem {
   int32_t s, rb;
 };
@@ -134,6 +134,8 @@ struct fkf_cov {
   fkf::DevBuf<int64_t> cp_off;
   int64_t n_up_items = 0, n_part_up = 0, n_pairs = 0, n_part_pair = 0;
   fkf::DevBuf<fkf::UpItem> up_items_m;       // several-column upward chunks
+  fkf::DevBuf<fkf::CoupleMItem> up_blocks_m; // (chunk, 64-row block), costliest first
+  int64_t n_up_blocks_m = 0;
   fkf::DevBuf<int32_t> up_ptr_m;
   int64_t n_up_items_m = 0, n_part_up_m = 0;
   // workspace
@@ -895,9 +897,6 @@ __global__ void __launch_bounds__(256) k_final1(
 // FP64 matrix cores, v_mfma_f64_16x16x4f64.  Operand layout per lane l of a
 // wavefront: A[l % 16][l / 16] (16 x 4), B[l / 16][l % 16] (4 x 16); the
 // 16 x 16 result has D[(l / 16) + 4 r][l % 16] in register r.
-// Every kernel below computes a tile of RB16 * 16 rows x NCB * 16 columns per
-// workgroup of four wavefronts; wavefront w owns row blocks w, w + 4, ... and
-// all NCB column blocks.
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ v4d mfma4(double a, double b, v4d c) {
@@ -1029,102 +1028,6 @@ __global__ void __launch_bounds__(256) k_final1_mfma2(
 }
 
 
-// Upward: partial Xhat_c = U_c^T X_c over one chunk of <= kUpChunkM points.
-// A[a][i] = prod_k L_k(x_i)[a_k] is formed from per-point Lagrange values in
-// LDS; B = X rows of the chunk (64 points at a time).
-
-template <int D, int NCB, int RBW>
-__global__ void __launch_bounds__(256) k_up_mfma(const UpItem *__restrict__ items,
-                                                 const FarCluster *__restrict__ fc,
-                                                 const double *__restrict__ pts, int64_t n,
-                                                 const double *__restrict__ cheb,
-                                                 const double *__restrict__ xt, int nrhs,
-                                                 double *__restrict__ part) {
-  constexpr int PM = PMax<D>::v;
-  constexpr int NC = NCB * 16;
-  __shared__ double Ls[D][64][PM + 1];
-  __shared__ double Bs[64][NC + 1];
-  const UpItem it = items[blockIdx.x];
-  const FarCluster c = fc[it.fc];
-  const int p = c.p, pd = c.pd;
-  const int c0 = blockIdx.y * NC;
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  const int lr = l & 15, lk = l >> 4;
-  const double *cu = cheb + p * 2 * kMaxCheb;
-  int ai[RBW][D];
-  bool aval[RBW];
-#pragma unroll
-  for (int q = 0; q < RBW; ++q) {
-    int a = (w + 4 * q) * 16 + lr;
-    aval[q] = a < pd;
-    int r = aval[q] ? a : 0;
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      ai[q][k] = r % p;
-      r /= p;
-    }
-  }
-  v4d acc[RBW][NCB];
-#pragma unroll
-  for (int q = 0; q < RBW; ++q)
-#pragma unroll
-    for (int j = 0; j < NCB; ++j) acc[q][j] = v4d{0, 0, 0, 0};
-  const int nrb = (pd + 15) / 16;
-  for (int64_t i0 = it.begin; i0 < it.end; i0 += 64) {
-    const int cnt = (int)min((int64_t)64, it.end - i0);
-    if (tid < D * 64) {
-      // one (axis, point) per thread
-      const int i = tid & 63, k = tid >> 6;
-      double L[PM];
-      if (i < cnt) {
-        double x = pts[k * n + i0 + i];
-        double z = c.hw[k] > 0 ? (x - c.ctr[k]) / c.hw[k] : 0.0;
-        lagrange_any<PM>(p, cu, cu + kMaxCheb, z, L);
-      } else {
-#pragma unroll
-        for (int a = 0; a < PM; ++a) L[a] = 0.0;
-      }
-#pragma unroll
-      for (int a = 0; a < PM; ++a) Ls[k][i][a] = L[a];
-    }
-    for (int e = tid; e < 64 * NC; e += 256) {
-      int i = e & 63, cc = e >> 6;
-      Bs[i][cc] = (i < cnt && c0 + cc < nrhs) ? xt[i0 + i + n * (c0 + cc)] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 2
-    for (int kk = 0; kk < 16; ++kk) {
-      const int i = kk * 4 + lk;
-      double b[NCB];
-#pragma unroll
-      for (int j = 0; j < NCB; ++j) b[j] = Bs[i][j * 16 + lr];
-#pragma unroll
-      for (int q = 0; q < RBW; ++q) {
-        if (w + 4 * q < nrb) {
-          double a = Ls[0][i][ai[q][0]];
-#pragma unroll
-          for (int k = 1; k < D; ++k) a *= Ls[k][i][ai[q][k]];
-          a = aval[q] ? a : 0.0;
-#pragma unroll
-          for (int j = 0; j < NCB; ++j) acc[q][j] = mfma4(a, b[j], acc[q][j]);
-        }
-      }
-    }
-    __syncthreads();
-  }
-  double *o = part + it.poff * nrhs;
-#pragma unroll
-  for (int q = 0; q < RBW; ++q)
-#pragma unroll
-    for (int j = 0; j < NCB; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int a = (w + 4 * q) * 16 + lk + 4 * r;
-        int cc = c0 + j * 16 + lr;
-        if (a < pd && cc < nrhs) o[a + (int64_t)pd * cc] = acc[q][j][r];
-      }
-}
-
 // Sum the chunk partials (pd x nrhs each) of every far cluster.
 __global__ void __launch_bounds__(256) k_up_reduce_m(const FarCluster *__restrict__ fc,
                                                      const int32_t *__restrict__ item_ptr,
@@ -1141,108 +1044,275 @@ __global__ void __launch_bounds__(256) k_up_reduce_m(const FarCluster *__restric
   }
 }
 
-// Couplings: Yhat_s = sum over admissible t of K(xi_s, xi_t) Xhat_t.  The
-// kernel entries are evaluated in registers directly as MFMA A operands; B is
-// a 64-row chunk of Xhat_t staged in LDS.
-template <int D, int NCB, int RBW, bool F32>
-__global__ void __launch_bounds__(256) k_couple_mfma(const FarCluster *__restrict__ fc,
-                                                     const int32_t *__restrict__ far_ptr,
-                                                     const int32_t *__restrict__ far_col,
-                                                     const double *__restrict__ cheb, int kind,
-                                                     double inv_ell, double theta,
-                                                     const double *__restrict__ xhat, int nrhs,
-                                                     double *__restrict__ yhat) {
-  constexpr int NC = NCB * 16;
-  __shared__ double Bs[64][NC + 1];
-  __shared__ double xit[D][64];
-  const int sidx = blockIdx.x;
-  const FarCluster cs = fc[sidx];
-  const int c0 = blockIdx.y * NC;
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+// Upward pass of the several-column product: the partial U_c^T X of one
+// chunk of cluster c's points, for one 64-row block of its coefficients and
+// 512 columns per workgroup.  Per 16 points: the per-axis Lagrange values go
+// to LDS, the workgroup forms the 64 x 16 block of basis values once
+// (double-buffered in LDS), and wavefront w multiplies it with columns
+// [64 w, 64 w + 64) of X read straight from global memory one chunk ahead.
+template <int D>
+__global__ void __launch_bounds__(512) k_up_mfma2(const CoupleMItem *__restrict__ blocks,
+                                                  const UpItem *__restrict__ items,
+                                                  const FarCluster *__restrict__ fc,
+                                                  const double *__restrict__ pts, int64_t n,
+                                                  const double *__restrict__ cheb,
+                                                  const double *__restrict__ xt, int nrhs,
+                                                  double *__restrict__ part) {
+  constexpr int PM = PMax<D>::v, LDK = 18;
+  __shared__ double Ls[D][16][PM + 1];
+  __shared__ double As[2][64 * LDK];
+  const CoupleMItem bk = blocks[blockIdx.x];
+  const UpItem it = items[bk.s];
+  const FarCluster c = fc[it.fc];
+  const int p = c.p, pd = c.pd;
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
   const int lr = l & 15, lk = l >> 4;
-  const int ps = cs.p, pds = cs.pd;
-  const double sq = kernel_c(kind);
-  const double scale = sq * inv_ell;
-  const double *us = cheb + ps * 2 * kMaxCheb;
-  double xa[RBW][D];
-  bool aval[RBW];
-#pragma unroll
-  for (int q = 0; q < RBW; ++q) {
-    int a = (w + 4 * q) * 16 + lr;
-    aval[q] = a < pds;
-    int r = aval[q] ? a : 0;
+  const int r0 = 64 * bk.rb;
+  const int rows = min(64, pd - r0);
+  const int nrb = (rows + 15) >> 4;
+  const int c0 = blockIdx.y * 512 + 64 * w;
+  const double *cu = cheb + p * 2 * kMaxCheb;
+  // basis role: row er, points ek, ek + 1 of a chunk
+  const int er = tid >> 3, ek = 2 * (tid & 7);
+  int dig[D];
+  {
+    int r = er < rows ? r0 + er : 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-      xa[q][k] = scale * (cs.ctr[k] + cs.hw[k] * us[r % ps]);
-      r /= ps;
+      dig[k] = r % p;
+      r /= p;
     }
   }
-  const int nrb = (pds + 15) / 16;
-  v4d acc[RBW][NCB];
+  auto load_b = [&](int64_t i0, double *b) {
 #pragma unroll
-  for (int q = 0; q < RBW; ++q)
+    for (int kk = 0; kk < 4; ++kk) {
+      const int64_t i = i0 + 4 * kk + lk;
+      const int64_t ic = i < it.end ? i : it.begin;
 #pragma unroll
-    for (int j = 0; j < NCB; ++j) acc[q][j] = v4d{0, 0, 0, 0};
-  for (int e = far_ptr[sidx]; e < far_ptr[sidx + 1]; ++e) {
-    const FarCluster ct = fc[far_col[e]];
-    const int pt = ct.p, pdt = ct.pd;
-    const double *ut = cheb + pt * 2 * kMaxCheb;
-    for (int b0 = 0; b0 < pdt; b0 += 64) {
-      const int cnt = min(64, pdt - b0);
-      __syncthreads();
-      for (int q = tid; q < 64 * NC; q += 256) {
-        int kb = q & 63, cc = q >> 6;
-        Bs[kb][cc] = (kb < cnt && c0 + cc < nrhs)
-                         ? xhat[ct.coef_off * nrhs + b0 + kb + (int64_t)pdt * (c0 + cc)]
-                         : 0.0;
+      for (int j = 0; j < 4; ++j) {
+        const int cc = c0 + 16 * j + lr;
+        b[4 * kk + j] = xt[ic + n * (int64_t)(cc < nrhs ? cc : 0)];
       }
-      if (tid < 64) {
-        int b = b0 + tid, r = tid < cnt ? b : 0;
+    }
+  };
+  v4d acc[4][4];
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-          xit[k][tid] = scale * (ct.ctr[k] + ct.hw[k] * ut[r % pt]);
-          r /= pt;
-        }
-      }
-      __syncthreads();
-      const int nk = (cnt + 3) / 4;
-      for (int kk = 0; kk < nk; ++kk) {
-        const int kb = kk * 4 + lk;
-        double b[NCB];
+  for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int j = 0; j < NCB; ++j) b[j] = Bs[kb][j * 16 + lr];
-        double xb[D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) xb[k] = xit[k][kb];
-#pragma unroll
-        for (int q = 0; q < RBW; ++q) {
-          if (w + 4 * q < nrb) {
-            double dx = xa[q][0] - xb[0];
-            double t2 = dx * dx;
-#pragma unroll
-            for (int k = 1; k < D; ++k) {
-              dx = xa[q][k] - xb[k];
-              t2 = fma(dx, dx, t2);
-            }
-            double kv = (aval[q] && kb < cnt) ? kernel_t2<F32>(t2, kind, theta) : 0.0;
-#pragma unroll
-            for (int j = 0; j < NCB; ++j) acc[q][j] = mfma4(kv, b[j], acc[q][j]);
+    for (int j = 0; j < 4; ++j) acc[q][j] = v4d{0, 0, 0, 0};
+  double bcur[16], bnext[16];
+  int buf = 0;
+  load_b(it.begin, bcur);
+  for (int64_t i0 = it.begin; i0 < it.end; i0 += 16) {
+    {
+      // one (axis, point, node) per thread: the barycentric Lagrange value
+      // l_a(z) = (w_a / (z - u_a)) / sum_m w_m / (z - u_m) (same operations,
+      // in the same order, as lagrange_any)
+      const int a = tid % PM, i = (tid / PM) & 15, k = tid / (PM * 16);
+      if (k < D) {
+        double v = 0.0;
+        if (a < p && i0 + i < it.end) {
+          // axis k is not a compile-time index: read the box from memory
+          // rather than from the register copy of the cluster
+          const double x = pts[k * n + i0 + i];
+          const double hw = fc[it.fc].hw[k], ctr = fc[it.fc].ctr[k];
+          const double z = hw > 0 ? (x - ctr) / hw : 0.0;
+          double s = 0.0, qa = 0.0;
+          int exact = -1;
+          for (int m = 0; m < p; ++m) {
+            const double dx = z - cu[m];
+            if (dx == 0.0) exact = m;
+            const double q = cu[kMaxCheb + m] * rcp_nr(dx == 0.0 ? 1.0 : dx);
+            s += q;
+            if (m == a) qa = q;
           }
+          v = exact >= 0 ? (a == exact ? 1.0 : 0.0) : qa * rcp_nr(s);
+        }
+        Ls[k][i][a] = v;
+      }
+    }
+    if (i0 + 16 < it.end) load_b(i0 + 16, bnext);
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      double v = Ls[0][ek + h][dig[0]];
+#pragma unroll
+      for (int k = 1; k < D; ++k) v *= Ls[k][ek + h][dig[k]];
+      As[buf][er * LDK + ek + h] = er < rows ? v : 0.0;
+    }
+    __syncthreads();
+    const double *A = As[buf];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (q < nrb) {
+          const double a = A[(16 * q + lr) * LDK + 4 * kk + lk];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[q][j] = mfma4(a, bcur[4 * kk + j], acc[q][j]);
         }
       }
     }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) bcur[i] = bnext[i];
+    buf ^= 1;
   }
-  double *o = yhat + cs.coef_off * nrhs;
+  double *o = part + it.poff * nrhs;
 #pragma unroll
-  for (int q = 0; q < RBW; ++q)
+  for (int q = 0; q < 4; ++q)
 #pragma unroll
-    for (int j = 0; j < NCB; ++j)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int a = (w + 4 * q) * 16 + lk + 4 * r;
-        int cc = c0 + j * 16 + lr;
-        if (a < pds && cc < nrhs) o[a + (int64_t)pds * cc] = acc[q][j][r];
+        const int a = 16 * q + lk + 4 * r;
+        const int cc = c0 + 16 * j + lr;
+        if (a < rows && cc < nrhs) o[r0 + a + (int64_t)pd * cc] = acc[q][j][r];
       }
+}
+
+// Downward pass of the several-column product: Y[perm, c] += U_c|_s Yhat_c
+// over the far ancestors c of leaf s, for 512 columns per workgroup.  Per
+// ancestor the per-axis Lagrange values of the leaf's points go to LDS; per
+// 16 coefficients the workgroup forms the 64 x 16 block of basis values once
+// (double-buffered in LDS), and wavefront w multiplies it with columns
+// [64 w, 64 w + 64) of Yhat_c read straight from global memory one chunk
+// ahead.
+template <int D>
+__global__ void __launch_bounds__(512) k_down_mfma2(
+    const int64_t *__restrict__ leaf_off, const double *__restrict__ pts, int64_t n,
+    const double *__restrict__ cheb, const FarCluster *__restrict__ fc,
+    const int32_t *__restrict__ anc_ptr, const int32_t *__restrict__ anc_idx,
+    const double *__restrict__ yhat, const int64_t *__restrict__ perm, int nrhs,
+    double *__restrict__ Y, int64_t ldy) {
+  constexpr int PM = PMax<D>::v, LDK = 18;
+  __shared__ double Ls[D][64][PM + 1];
+  __shared__ double As[2][64 * LDK];
+  const int s = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
+  const int lr = l & 15, lk = l >> 4;
+  const int64_t s0 = leaf_off[s], ms = leaf_off[s + 1] - s0;
+  const int nrb = (int)((ms + 15) >> 4);
+  const int c0 = blockIdx.y * 512 + 64 * w;
+  const int er = tid >> 3, ek = 2 * (tid & 7);   // basis role: point er, coefficients ek, ek+1
+  const int ea = anc_ptr[s], eb = anc_ptr[s + 1];
+  auto load_b = [&](int e, int a0, double *b) {
+    const FarCluster c = fc[anc_idx[e]];
+    const double *y = yhat + c.coef_off * nrhs;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int a = a0 + 4 * kk + lk;
+      const int ac = a < c.pd ? a : 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int cc = c0 + 16 * j + lr;
+        b[4 * kk + j] = y[ac + (int64_t)c.pd * (cc < nrhs ? cc : 0)];
+      }
+    }
+  };
+  v4d acc[4][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[q][j] = v4d{0, 0, 0, 0};
+  double bcur[16], bnext[16];
+  int buf = 0;
+  int e = ea, a0 = 0;
+  if (e < eb) load_b(e, 0, bcur);
+  while (e < eb) {
+    const int ci = anc_idx[e];
+    const int p = fc[ci].p, pd = fc[ci].pd;
+    const double *cu = cheb + p * 2 * kMaxCheb;
+    if (a0 == 0 && tid < D * 64) {
+      // Lagrange values of (axis k, point i) at the ancestor's nodes:
+      // l_a(z) = (w_a / (z - u_a)) / sum_m w_m / (z - u_m)
+      const int i = tid & 63, k = tid >> 6;
+      if (i < ms) {
+        const double x = pts[k * n + s0 + i];
+        const double hw = fc[ci].hw[k], ctr = fc[ci].ctr[k];
+        const double z = hw > 0 ? (x - ctr) / hw : 0.0;
+        double sum = 0.0;
+        int exact = -1;
+        for (int m = 0; m < p; ++m) {
+          const double dx = z - cu[m];
+          if (dx == 0.0) exact = m;
+          sum += cu[kMaxCheb + m] * rcp_nr(dx == 0.0 ? 1.0 : dx);
+        }
+        const double is = rcp_nr(sum);
+        for (int m = 0; m < PM; ++m) {
+          double v = 0.0;
+          if (m < p) {
+            const double dx = z - cu[m];
+            v = exact >= 0 ? (m == exact ? 1.0 : 0.0)
+                           : cu[kMaxCheb + m] * rcp_nr(dx == 0.0 ? 1.0 : dx) * is;
+          }
+          Ls[k][i][m] = v;
+        }
+      } else {
+        for (int m = 0; m < PM; ++m) Ls[k][i][m] = 0.0;
+      }
+    }
+    // next chunk
+    int en = e, an = a0 + 16;
+    if (an >= pd) {
+      ++en;
+      an = 0;
+    }
+    if (en < eb) load_b(en, an, bnext);
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      int a = a0 + ek + h;
+      double v = 0.0;
+      if (a < pd) {
+        v = Ls[0][er][a % p];
+        a /= p;
+#pragma unroll
+        for (int k = 1; k < D; ++k) {
+          v *= Ls[k][er][a % p];
+          a /= p;
+        }
+      }
+      As[buf][er * LDK + ek + h] = v;
+    }
+    __syncthreads();
+    const double *A = As[buf];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (q < nrb) {
+          const double av = A[(16 * q + lr) * LDK + 4 * kk + lk];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[q][j] = mfma4(av, bcur[4 * kk + j], acc[q][j]);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) bcur[i] = bnext[i];
+    buf ^= 1;
+    e = en;
+    a0 = an;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * q + lk + 4 * r;
+        const int cc = c0 + 16 * j + lr;
+        if (i < ms && cc < nrhs) {
+          double *y = Y + perm[s0 + i] + ldy * cc;
+          *y += acc[q][j][r];
+        }
+      }
+}
+
+__global__ void k_zero(double *__restrict__ p, int64_t len) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) p[i] = 0.0;
 }
 
 // Couplings of the several-column product, Yhat_s = sum over admissible t of
@@ -1253,11 +1323,6 @@ __global__ void __launch_bounds__(256) k_couple_mfma(const FarCluster *__restric
 // global memory one chunk ahead (every 32-byte sector fully used).  Rows past
 // the cluster and coefficients past the partner are zero in K; only the
 // 16-row blocks inside the cluster are multiplied.
-__global__ void k_zero(double *__restrict__ p, int64_t len) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < len) p[i] = 0.0;
-}
-
 template <int D, bool F32>
 __global__ void __launch_bounds__(512) k_couple_mfma2(
     const CoupleMItem *__restrict__ items, const FarCluster *__restrict__ fc,
@@ -1371,10 +1436,6 @@ __global__ void __launch_bounds__(512) k_couple_mfma2(
       }
 }
 
-// Near field + downward pass + scatter for one leaf and NC columns:
-// Y_s = sum_{t near s} Gamma_st X_t + sum_{far ancestors c} U_c|_s Yhat_c.
-// MODE 0: near field and downward pass, Y = result; MODE 1: near field only,
-// Y = near part; MODE 2: downward pass only, Y += far part.
 // Tiles of the ordered near pairs in MFMA operand order.  Pair e (entry e of
 // near_idx: stored tile b, used as is or transposed) becomes 4096 entries
 // frag[e][w][kk][l] = A[16 w + l % 16][4 kk + l / 16] with A = tile or
@@ -1512,151 +1573,6 @@ __global__ void __launch_bounds__(256) k_near_mfma(
       const int i = w * 16 + lk + 4 * r;
       const int cc = c0 + j * 16 + lr;
       if (i < ms && cc < nrhs) Y[perm[s0 + i] + ldy * cc] = acc[j][r];
-    }
-}
-
-template <int D, int NCB, typename TT, int MODE>
-__global__ void __launch_bounds__(256) k_down_mfma(
-    const TT *__restrict__ blk, const int32_t *__restrict__ near_ptr,
-    const int32_t *__restrict__ near_idx, const int32_t *__restrict__ bs,
-    const int32_t *__restrict__ bt, const int64_t *__restrict__ leaf_off,
-    const double *__restrict__ pts, int64_t n, const double *__restrict__ cheb,
-    const FarCluster *__restrict__ fc, const int32_t *__restrict__ anc_ptr,
-    const int32_t *__restrict__ anc_idx, const double *__restrict__ xt,
-    const double *__restrict__ yhat, const int64_t *__restrict__ perm, int nrhs,
-    double *__restrict__ Y, int64_t ldy) {
-  constexpr int PM = PMax<D>::v;
-  constexpr int NC = NCB * 16;
-  // the near tile (near-field phase) and the Lagrange values (far-field
-  // phase) share one LDS region, so that two workgroups fit on a CU
-  static_assert(D * 64 * (PM + 1) <= 64 * 65, "Lagrange table exceeds the shared region");
-  __shared__ double As_raw[64 * 65];
-  __shared__ double Bs[64][NC + 1];
-  __shared__ int32_t aidx[D == 2 ? 256 : 1024];   // packed per-axis node indices
-  double(*As)[65] = reinterpret_cast<double(*)[65]>(As_raw);
-  double(*Ls)[64][PM + 1] = reinterpret_cast<double(*)[64][PM + 1]>(As_raw);
-  const int s = blockIdx.x;
-  const int c0 = blockIdx.y * NC;
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  const int lr = l & 15, lk = l >> 4;
-  const int64_t s0 = leaf_off[s], ms = leaf_off[s + 1] - s0;
-  const int row = w * 16 + lr;   // A row of this lane (point of the leaf)
-  v4d acc[NCB];
-#pragma unroll
-  for (int j = 0; j < NCB; ++j) acc[j] = v4d{0, 0, 0, 0};
-  // near field
-  for (int e = MODE == 2 ? 0 : near_ptr[s]; e < (MODE == 2 ? 0 : near_ptr[s + 1]); ++e) {
-    const int code = near_idx[e];
-    const int64_t b = code >> 1;
-    const bool trans = code & 1;
-    const int t = trans ? bs[b] : bt[b];
-    const int64_t t0 = leaf_off[t], mt = leaf_off[t + 1] - t0;
-    __syncthreads();
-    if (sizeof(TT) == 8) {
-      const v2d *src = reinterpret_cast<const v2d *>(blk + b * 4096);
-      for (int q = tid; q < 2048; q += 256) {
-        int k = q >> 6, lane = q & 63;
-        int i = 8 * (lane & 7) + (k >> 2), j = 8 * (lane >> 3) + 2 * (k & 3);
-        v2d v = src[q];
-        if (!trans) {
-          As[i][j] = v.x;
-          As[i][j + 1] = v.y;
-        } else {
-          As[j][i] = v.x;
-          As[j + 1][i] = v.y;
-        }
-      }
-    } else {
-      const float4 *src = reinterpret_cast<const float4 *>(blk + b * 4096);
-      for (int q = tid; q < 1024; q += 256) {
-        int k = q >> 6, lane = q & 63;
-        int i = 8 * (lane & 7) + (k >> 1), j = 8 * (lane >> 3) + 4 * (k & 1);
-        float4 v = src[q];
-        const double vv[4] = {v.x, v.y, v.z, v.w};
-        for (int h = 0; h < 4; ++h) {
-          if (!trans)
-            As[i][j + h] = vv[h];
-          else
-            As[j + h][i] = vv[h];
-        }
-      }
-    }
-    for (int q = tid; q < 64 * NC; q += 256) {
-      int j = q & 63, cc = q >> 6;
-      Bs[j][cc] = (j < mt && c0 + cc < nrhs) ? xt[t0 + j + n * (c0 + cc)] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < 16; ++kk) {
-      const int k = kk * 4 + lk;
-      const double a = As[row][k];
-#pragma unroll
-      for (int j = 0; j < NCB; ++j) acc[j] = mfma4(a, Bs[k][j * 16 + lr], acc[j]);
-    }
-  }
-  // far field: U_c restricted to the leaf's points times Yhat_c
-  for (int e = MODE == 1 ? 0 : anc_ptr[s]; e < (MODE == 1 ? 0 : anc_ptr[s + 1]); ++e) {
-    const FarCluster c = fc[anc_idx[e]];
-    const int p = c.p, pd = c.pd;
-    const double *cu = cheb + p * 2 * kMaxCheb;
-    __syncthreads();
-    for (int a = tid; a < pd; a += 256) {
-      int r = a, code = 0;
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        code |= (r % p) << (8 * k);
-        r /= p;
-      }
-      aidx[a] = code;
-    }
-    if (tid < D * 64) {
-      // one (axis, point) per thread
-      const int i = tid & 63, k = tid >> 6;
-      double L[PM];
-      if (i < ms) {
-        double x = pts[k * n + s0 + i];
-        double z = c.hw[k] > 0 ? (x - c.ctr[k]) / c.hw[k] : 0.0;
-        lagrange_any<PM>(p, cu, cu + kMaxCheb, z, L);
-      } else {
-#pragma unroll
-        for (int a = 0; a < PM; ++a) L[a] = 0.0;
-      }
-#pragma unroll
-      for (int a = 0; a < PM; ++a) Ls[k][i][a] = L[a];
-    }
-    for (int a0 = 0; a0 < pd; a0 += 64) {
-      const int cnt = min(64, pd - a0);
-      __syncthreads();
-      for (int q = tid; q < 64 * NC; q += 256) {
-        int ka = q & 63, cc = q >> 6;
-        Bs[ka][cc] = (ka < cnt && c0 + cc < nrhs)
-                         ? yhat[c.coef_off * nrhs + a0 + ka + (int64_t)pd * (c0 + cc)]
-                         : 0.0;
-      }
-      __syncthreads();
-      const int nk = (cnt + 3) / 4;
-      for (int kk = 0; kk < nk; ++kk) {
-        const int ka = kk * 4 + lk;
-        const int code = aidx[a0 + ka < pd ? a0 + ka : 0];
-        double a = Ls[0][row][code & 255];
-#pragma unroll
-        for (int k = 1; k < D; ++k) a *= Ls[k][row][(code >> (8 * k)) & 255];
-        a = (ka < cnt) ? a : 0.0;
-#pragma unroll
-        for (int j = 0; j < NCB; ++j) acc[j] = mfma4(a, Bs[ka][j * 16 + lr], acc[j]);
-      }
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < NCB; ++j)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      int i = w * 16 + lk + 4 * r;
-      int cc = c0 + j * 16 + lr;
-      if (i < ms && cc < nrhs) {
-        double *y = Y + perm[s0 + i] + ldy * cc;
-        *y = MODE == 2 ? *y + acc[j][r] : acc[j][r];
-      }
     }
 }
 
@@ -1913,6 +1829,21 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
       cov->n_part_up_m = poffm;
       cov->up_items_m.upload(upm, st);
       cov->up_ptr_m.upload(uptrm, st);
+      {
+        std::vector<std::pair<int64_t, CoupleMItem>> ub;
+        for (size_t u = 0; u < upm.size(); ++u) {
+          const int pd = fcs[upm[u].fc].pd;
+          for (int rb = 0; 64 * rb < pd; ++rb)
+            ub.push_back({(int64_t)std::min(64, pd - 64 * rb) * (upm[u].end - upm[u].begin),
+                          CoupleMItem{(int32_t)u, rb}});
+        }
+        std::stable_sort(ub.begin(), ub.end(),
+                         [](const auto &a, const auto &b) { return a.first > b.first; });
+        std::vector<CoupleMItem> ubi(ub.size());
+        for (size_t i = 0; i < ub.size(); ++i) ubi[i] = ub[i].second;
+        cov->n_up_blocks_m = (int64_t)ubi.size();
+        cov->up_blocks_m.upload(ubi, st);
+      }
       std::vector<std::vector<int64_t>> cpl(cov->n_fc);
       int64_t off = 0, n_lt = 0, n_gt = 0, koff = 0;
       for (auto &pr : fpairs) {
@@ -2109,13 +2040,12 @@ void near_multi(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t s) {
                      cov->blk_t.p, cov->leaf_off.p, cov->n, cov->xt.p, cov->perm.p, nrhs, Y, ldy);
 }
 
-// Several columns on the FP64 matrix cores: upward chunks + reduction,
-// couplings per target cluster, then near field + downward + scatter per leaf.
-template <int D, int NCB, int RBW, bool F32>
+// Several columns on the FP64 matrix cores: the near field on a forked
+// stream, concurrently with the far-field chain (upward chunks + reduction,
+// couplings per cluster row block); the downward pass then adds to Y.
+template <int D, bool F32>
 void apply_multi_t(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t st) {
-  constexpr int NC = NCB * 16;
   const int64_t n = cov->n;
-  const unsigned gy = (unsigned)((nrhs + NC - 1) / NC);
   if (cov->n_fc > 0) {
     cov->xhat.reserve((size_t)cov->n_coef * nrhs);
     cov->yhat.reserve((size_t)cov->n_coef * nrhs);
@@ -2132,9 +2062,10 @@ void apply_multi_t(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t s
     FKF_CHECK_HIP(hipEventRecord(cov->ev_join, cov->side));
     {
       FKF_TRACE("hmat_far_up_multi", st);
-      hipLaunchKernelGGL((k_up_mfma<D, NCB, RBW>), dim3((unsigned)cov->n_up_items_m, gy), dim3(256),
-                         0, st, cov->up_items_m.p, cov->fc.p, cov->pts.p, n, cov->cheb.p,
-                         cov->xt.p, nrhs, cov->part_up_m.p);
+      hipLaunchKernelGGL((k_up_mfma2<D>),
+                         dim3((unsigned)cov->n_up_blocks_m, (unsigned)((nrhs + 511) / 512)),
+                         dim3(512), 0, st, cov->up_blocks_m.p, cov->up_items_m.p, cov->fc.p,
+                         cov->pts.p, n, cov->cheb.p, cov->xt.p, nrhs, cov->part_up_m.p);
       hipLaunchKernelGGL(k_up_reduce_m, dim3(cov->n_fc, 8), dim3(256), 0, st, cov->fc.p,
                          cov->up_ptr_m.p, cov->up_items_m.p, nrhs, cov->part_up_m.p, cov->xhat.p);
     }
@@ -2154,14 +2085,6 @@ void apply_multi_t(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t s
                            cov->xhat.p, nrhs, cov->yhat.p);
     }
   }
-  typedef typename std::conditional<F32, float, double>::type TT;
-  const TT *blk = F32 ? (const TT *)cov->blk32.p : (const TT *)cov->blk.p;
-  auto down = [&](auto kern, hipStream_t s) {
-    hipLaunchKernelGGL(kern, dim3(cov->n_leaves, gy), dim3(256), 0, s, blk, cov->near_ptr.p,
-                       cov->near_idx.p, cov->blk_s.p, cov->blk_t.p, cov->leaf_off.p, cov->pts.p, n,
-                       cov->cheb.p, cov->fc.p, cov->anc_ptr.p, cov->anc_idx.p, cov->xt.p,
-                       cov->yhat.p, cov->perm.p, nrhs, Y, ldy);
-  };
   if (cov->n_fc == 0) {
     FKF_TRACE("hmat_near_multi", st);
     near_multi<F32>(cov, nrhs, Y, ldy, st);
@@ -2169,20 +2092,17 @@ void apply_multi_t(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t s
   }
   FKF_TRACE("hmat_down_multi", st);
   FKF_CHECK_HIP(hipStreamWaitEvent(st, cov->ev_join, 0));
-  down(k_down_mfma<D, NCB, TT, 2>, st);
+  hipLaunchKernelGGL(k_down_mfma2<D>, dim3(cov->n_leaves, (unsigned)((nrhs + 511) / 512)),
+                     dim3(512), 0, st, cov->leaf_off.p, cov->pts.p, n, cov->cheb.p, cov->fc.p,
+                     cov->anc_ptr.p, cov->anc_idx.p, cov->yhat.p, cov->perm.p, nrhs, Y, ldy);
 }
 
 void apply_multi(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t st) {
   const bool m = cov->mixed;
   if (cov->d == 2)
-    m ? apply_multi_t<2, 4, 4, true>(cov, nrhs, Y, ldy, st)
-      : apply_multi_t<2, 4, 4, false>(cov, nrhs, Y, ldy, st);
-  else if (cov->max_pd <= 256)
-    m ? apply_multi_t<3, 4, 4, true>(cov, nrhs, Y, ldy, st)
-      : apply_multi_t<3, 4, 4, false>(cov, nrhs, Y, ldy, st);
+    m ? apply_multi_t<2, true>(cov, nrhs, Y, ldy, st) : apply_multi_t<2, false>(cov, nrhs, Y, ldy, st);
   else
-    m ? apply_multi_t<3, 1, 16, true>(cov, nrhs, Y, ldy, st)
-      : apply_multi_t<3, 1, 16, false>(cov, nrhs, Y, ldy, st);
+    m ? apply_multi_t<3, true>(cov, nrhs, Y, ldy, st) : apply_multi_t<3, false>(cov, nrhs, Y, ldy, st);
 }
 
 }  // namespace
