@@ -13,7 +13,8 @@ basis), 50 constant-H filter steps, the variance field and 4 conditional
 realizations.  The value is filter steps per second over the whole pass in
 FP64.  Beside it: steps with a new operator every step (Section 2.4) and
 steps of the extended filter for the Box-Cox observation model, both with
-the relative rank truncation 1e-5.  The same pass is then timed in the mixed-precision form (FP32 storage
+the relative rank truncation 1e-5, and the cost of the log-likelihood
+gradient (theta, length, noise) relative to the filter run alone.  The same pass is then timed in the mixed-precision form (FP32 storage
 and kernel evaluation, FP64 accumulation) and its speedup and per-result
 error (against stored oracle values at sampled cells and against the FP64
 form) are reported beside it.  The one-column H-matrix product is benchmarked
@@ -61,6 +62,8 @@ def parse():
                     help="independent filters of uneven size stepped together (0: skip)")
     ap.add_argument("--varying-steps", type=int, default=4,
                     help="steps with a new measurement operator each (0: skip)")
+    ap.add_argument("--no-gradient", action="store_true",
+                    help="skip the log-likelihood gradient component")
     ap.add_argument("--boxcox-steps", type=int, default=4,
                     help="extended-filter steps of the Box-Cox observation model (0: skip)")
     return ap.parse_args()
@@ -279,13 +282,54 @@ def extended_filter(fkf, torch, cov, wl, n_steps=4, a=4.0, rank_rtol=1e-5):
             "steady_steps_per_s": 1e3 / float(np.mean(times[1:])) if n_steps > 1 else None}
 
 
+def loglik_gradient(fkf, torch, cov, wl, ys, reps=3):
+    """The innovation log-likelihood and its derivatives in log theta, log
+    length and log sigma^2 over the workload's steps: the filter run alone
+    (GEP + steps, log-likelihood carried) against the same run with the length
+    derivative tracked (one more n_m-column product with dGamma/d length at
+    the basis build and an O(n_m^2) tangent update per step).  dGamma/d length
+    is built once beforehand (its build time is reported).  Returns the
+    times (best of reps), the ratio and the values."""
+    pts = wl.points()
+    src, rcv = wl.rays()
+    obs = fkf.Obs.from_rays(wl.shape, src, rcv, wl.noise_var)
+    t0 = time.perf_counter()
+    dcov = fkf.Cov(pts, nu=wl.nu, length=wl.length, variance=wl.variance,
+                   leaf_size=wl.leaf_size, dlength=True)
+    torch.cuda.synchronize()
+    t_dbuild = time.perf_counter() - t0
+
+    def run(track):
+        f = fkf.Filter(cov)
+        if track:
+            f.track_length(dcov)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for k in range(wl.steps):
+            f.step(obs, ys[k])
+        out = f.loglik()
+        dt = time.perf_counter() - t
+        f.close()
+        return dt, out
+
+    run(True)                                   # warm-up (workspaces)
+    tf = min(run(False)[0] for _ in range(reps))
+    tg, vals = min((run(True) for _ in range(reps)), key=lambda r: r[0])
+    dcov.close()
+    obs.close()
+    ll, d_th, d_nv, d_ln = vals
+    return {"forward_ms": tf * 1e3, "with_gradient_ms": tg * 1e3, "gradient_over_forward": tg / tf,
+            "dgamma_build_s": t_dbuild, "steps": wl.steps, "ll": ll, "dll_dlog_theta": d_th,
+            "dll_dlog_length": d_ln, "dll_dlog_noise": d_nv}
+
+
 # kernel (name prefix in the counter output) -> launch site of the trace
 TRAFFIC_KERNELS = {
     "fkf::k_jacobi_round": "eig_jacobi_round",
-    "void fkf::k_couple_mfma<2, 4, 4, false>": "hmat_far_couple_multi",
-    "void fkf::k_down_mfma<2, 4, double, 1>": "hmat_near_multi",
-    "void fkf::k_down_mfma<2, 4, double, 2>": "hmat_down_multi",
-    "void fkf::k_up_mfma<2, 4, 4>": "hmat_far_up_multi",
+    "void fkf::k_couple_mfma2<2, false>": "hmat_far_couple_multi",
+    "void fkf::k_near_mfma<double>": "hmat_near_multi",
+    "void fkf::k_down_mfma2<2>": "hmat_down_multi",
+    "void fkf::k_up_mfma2<2>": "hmat_far_up_multi",
     "void fkf::k_gemv_seg<false>": "filter_gemv",
     "fkf::k_gemm_nn": "gep_basis_gemm",
 }
@@ -512,6 +556,10 @@ def main():
     if args.varying_steps > 0:
         vary = varying_h(fkf, torch, cov, wl, ys, args.varying_steps)
         log(f"[bench] varying-H steps {vary}")
+    grad = None
+    if not args.no_gradient:
+        grad = loglik_gradient(fkf, torch, cov, wl, ys)
+        log(f"[bench] log-likelihood gradient {grad}")
     ext = None
     if args.boxcox_steps > 0:
         ext = extended_filter(fkf, torch, cov, wl, args.boxcox_steps)
@@ -612,6 +660,7 @@ def main():
             "constant_h_steps_per_s": 1e6 / step_us,
             "varying_h": vary,
             "extended_boxcox": ext,
+            "loglik_gradient": grad,
             "many_filters": many,
             "phases_ms": phases,
             "errors": acc64,
