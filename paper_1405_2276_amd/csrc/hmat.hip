@@ -1072,6 +1072,8 @@ __global__ void __launch_bounds__(512) k_up_mfma2(const CoupleMItem *__restrict_
   const int rows = min(64, pd - r0);
   const int nrb = (rows + 15) >> 4;
   const int c0 = blockIdx.y * 512 + 64 * w;
+  // 16-column blocks of this wavefront inside nrhs (wave-uniform)
+  const int ncb = min(4, max(0, (nrhs - c0 + 15) >> 4));
   const double *cu = cheb + p * 2 * kMaxCheb;
   // basis role: row er, points ek, ek + 1 of a chunk
   const int er = tid >> 3, ek = 2 * (tid & 7);
@@ -1150,7 +1152,8 @@ __global__ void __launch_bounds__(512) k_up_mfma2(const CoupleMItem *__restrict_
         if (q < nrb) {
           const double a = A[(16 * q + lr) * LDK + 4 * kk + lk];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc[q][j] = mfma4(a, bcur[4 * kk + j], acc[q][j]);
+          for (int j = 0; j < 4; ++j)
+            if (j < ncb) acc[q][j] = mfma4(a, bcur[4 * kk + j], acc[q][j]);
         }
       }
     }
@@ -1195,6 +1198,8 @@ __global__ void __launch_bounds__(512) k_down_mfma2(
   const int64_t s0 = leaf_off[s], ms = leaf_off[s + 1] - s0;
   const int nrb = (int)((ms + 15) >> 4);
   const int c0 = blockIdx.y * 512 + 64 * w;
+  // 16-column blocks of this wavefront inside nrhs (wave-uniform)
+  const int ncb = min(4, max(0, (nrhs - c0 + 15) >> 4));
   const int er = tid >> 3, ek = 2 * (tid & 7);   // basis role: point er, coefficients ek, ek+1
   const int ea = anc_ptr[s], eb = anc_ptr[s + 1];
   auto load_b = [&](int e, int a0, double *b) {
@@ -1285,7 +1290,8 @@ __global__ void __launch_bounds__(512) k_down_mfma2(
         if (q < nrb) {
           const double av = A[(16 * q + lr) * LDK + 4 * kk + lk];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc[q][j] = mfma4(av, bcur[4 * kk + j], acc[q][j]);
+          for (int j = 0; j < 4; ++j)
+            if (j < ncb) acc[q][j] = mfma4(av, bcur[4 * kk + j], acc[q][j]);
         }
       }
     }
@@ -1340,6 +1346,8 @@ __global__ void __launch_bounds__(512) k_couple_mfma2(
   const int rows = min(64, cs.pd - r0);
   const int nrb = (rows + 15) >> 4;
   const int c0 = blockIdx.y * 512 + 64 * w;
+  // 16-column blocks of this wavefront inside nrhs (wave-uniform)
+  const int ncb = min(4, max(0, (nrhs - c0 + 15) >> 4));
   const double scale = kernel_c(kind) * inv_ell;
   // K evaluation role of this thread: row er, chunk columns ek, ek + 1
   const int er = tid >> 3, ek = 2 * (tid & 7);
@@ -1413,7 +1421,8 @@ __global__ void __launch_bounds__(512) k_couple_mfma2(
         if (q < nrb) {
           const double a = K[(16 * q + lr) * LDK + 4 * kk + lk];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc[q][j] = mfma4(a, bcur[4 * kk + j], acc[q][j]);
+          for (int j = 0; j < 4; ++j)
+            if (j < ncb) acc[q][j] = mfma4(a, bcur[4 * kk + j], acc[q][j]);
         }
       }
     }
