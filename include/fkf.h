@@ -106,6 +106,11 @@ typedef struct {
   int32_t far_eval;       /* 0: store the coupling matrices K(xi_s, xi_t) at build when they
                              take at most 8 GiB (faster one-column products); 1: evaluate
                              them in every product (no coupling storage) */
+  int64_t workspace_bytes; /* bound on the workspaces of a several-column product
+                              (gathered columns, coefficient vectors, upward partials,
+                              all proportional to the number of columns); products with
+                              more columns are applied in column blocks that fit.
+                              0: 16 GiB */
 } fkf_hmat_params;
 
 typedef struct {

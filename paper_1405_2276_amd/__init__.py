@@ -50,7 +50,8 @@ class HmatParams(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("leaf_size", ctypes.c_int32),
                 ("cheb_order", ctypes.c_int32), ("cheb_order_max", ctypes.c_int32),
                 ("eta", ctypes.c_double), ("block_tol", ctypes.c_double),
-                ("precision", ctypes.c_int32), ("far_eval", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("far_eval", ctypes.c_int32),
+                ("workspace_bytes", ctypes.c_int64)]
 
 
 class FilterParams(ctypes.Structure):
@@ -251,14 +252,15 @@ PRECISION = {"fp64": 0, "mixed": 1}
 
 
 def _params(nu, length, variance, leaf_size, cheb_order, cheb_order_max, eta, block_tol,
-            precision="fp64", far_eval=False):
+            precision="fp64", far_eval=False, workspace_bytes=0):
     if nu not in MATERN:
         raise ValueError("nu must be 0.5, 1.5 or 2.5")
     if precision not in PRECISION:
         raise ValueError("precision must be 'fp64' or 'mixed'")
     kp = KernelParams(ctypes.sizeof(KernelParams), MATERN[nu], variance, length)
     hp = HmatParams(ctypes.sizeof(HmatParams), leaf_size, cheb_order, cheb_order_max,
-                    eta, block_tol, PRECISION[precision], int(bool(far_eval)))
+                    eta, block_tol, PRECISION[precision], int(bool(far_eval)),
+                    int(workspace_bytes))
     return kp, hp
 
 
@@ -305,19 +307,22 @@ class Cov:
     evaluation, FP64 accumulation; filters built on it stream their basis in
     FP32).  far_eval: evaluate the far-field coupling matrices in every product
     instead of storing them at build.  dlength: the operator dGamma/d length
-    instead of Gamma (for likelihood gradients, Filter.track_length)."""
+    instead of Gamma (for likelihood gradients, Filter.track_length).
+    workspace_bytes: bound on the several-column workspaces (0: 16 GiB);
+    wider products run in column blocks."""
 
     def __init__(self, points, nu: float = 1.5, length: float = 0.1, variance: float = 1.0,
                  leaf_size: int = 64, cheb_order: int = 6, cheb_order_max: int = 16,
                  eta: float = 1.5, block_tol: float = 1e-7, precision: str = "fp64",
-                 far_eval: bool = False, dlength: bool = False, stream=None):
+                 far_eval: bool = False, dlength: bool = False, workspace_bytes: int = 0,
+                 stream=None):
         pts = np.ascontiguousarray(points, dtype=np.float64)
         if pts.ndim != 2:
             raise ValueError("points must be (N, d)")
         self.n, self.d = pts.shape
         self.nu, self.length, self.variance = nu, length, variance
         kp, hp = _params(nu, length, variance, leaf_size, cheb_order, cheb_order_max, eta,
-                         block_tol, precision, far_eval)
+                         block_tol, precision, far_eval, workspace_bytes)
         if dlength:
             kp.kind += 3      # FKF_MATERN_*_DLENGTH
         self.precision = precision

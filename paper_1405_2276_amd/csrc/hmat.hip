@@ -1613,6 +1613,7 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
     FKF_REQUIRE(hp->precision == FKF_FP64 || hp->precision == FKF_MIXED,
                 "fkf_cov_build: unknown precision");
     FKF_REQUIRE(hp->far_eval == 0 || hp->far_eval == 1, "fkf_cov_build: far_eval must be 0 or 1");
+    FKF_REQUIRE(hp->workspace_bytes >= 0, "fkf_cov_build: workspace_bytes < 0");
     for (int64_t i = 0; i < n * d; ++i)
       FKF_REQUIRE(std::isfinite(pts_host[i]), "fkf_cov_build: non-finite coordinate");
     hipStream_t st = as_stream(stream);
@@ -2126,18 +2127,31 @@ extern "C" fkf_status fkf_cov_apply(fkf_cov *cov, const double *X, int64_t ldx, 
     FKF_REQUIRE(ldx >= cov->n && ldy >= cov->n, "fkf_cov_apply: leading dimension < n");
     hipStream_t st = as_stream(stream);
     const int64_t n = cov->n;
-    cov->xt.reserve((size_t)n * nrhs);
-    dim3 gg((unsigned)((n + 255) / 256), (unsigned)nrhs);
-    {
-      FKF_TRACE("hmat_gather", st);
-      hipLaunchKernelGGL(k_gather, gg, dim3(256), 0, st, X, ldx, nrhs, cov->perm.p, n, cov->xt.p);
+    // the several-column workspaces (gathered columns, coefficient vectors,
+    // upward partials) grow with the number of columns: apply in column
+    // blocks that keep them within the bound (at least 2 columns a block)
+    const int64_t budget = cov->hp.workspace_bytes > 0 ? cov->hp.workspace_bytes
+                                                        : (int64_t(16) << 30);
+    const int64_t per_col = 8 * (n + 2 * cov->n_coef + cov->n_part_up_m);
+    const int32_t chunk =
+        nrhs == 1 ? 1 : (int32_t)std::min<int64_t>(nrhs, std::max<int64_t>(2, budget / per_col));
+    for (int32_t c0 = 0; c0 < nrhs; c0 += chunk) {
+      const int32_t nc = std::min(chunk, nrhs - c0);
+      const double *Xc = X + ldx * (int64_t)c0;
+      double *Yc = Y + ldy * (int64_t)c0;
+      cov->xt.reserve((size_t)n * nc);
+      dim3 gg((unsigned)((n + 255) / 256), (unsigned)nc);
+      {
+        FKF_TRACE("hmat_gather", st);
+        hipLaunchKernelGGL(k_gather, gg, dim3(256), 0, st, Xc, ldx, nc, cov->perm.p, n, cov->xt.p);
+      }
+      if (nc == 1) {
+        apply_one(cov, Yc, st);
+      } else {
+        apply_multi(cov, nc, Yc, ldy, st);
+      }
+      FKF_CHECK_HIP(hipGetLastError());
     }
-    if (nrhs == 1) {
-      apply_one(cov, Y, st);
-    } else {
-      apply_multi(cov, nrhs, Y, ldy, st);
-    }
-    FKF_CHECK_HIP(hipGetLastError());
   });
 }
 

@@ -719,9 +719,18 @@ __global__ void __launch_bounds__(256) k_gemm_nn(int64_t m, int n, int k, const 
     }
 }
 
+static bool tall_shape(int64_t m, int64_t n, int64_t k);
+static void gemm_tall(int64_t m, int n, int k, double alpha, const double *A, int64_t lda,
+                      const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
+                      hipStream_t st);
+
 void gemm_nn(int64_t m, int n, int k, const double *A, int64_t lda, const double *B, int64_t ldb,
              double *C, int64_t ldc, hipStream_t st) {
   if (m <= 0 || n <= 0) return;
+  if (tall_shape(m, n, k)) {
+    gemm_tall(m, n, k, 1.0, A, lda, B, ldb, 0.0, C, ldc, st);
+    return;
+  }
   hipLaunchKernelGGL(k_gemm_nn, dim3((unsigned)((m + 63) / 64), (unsigned)((n + 63) / 64)),
                      dim3(256), 0, st, m, n, k, A, lda, B, ldb, C, ldc);
 }
@@ -835,6 +844,109 @@ __global__ void k_gemm_combine(int64_t m, int64_t n, int splits, double alpha,
   C[i + ldc * j] = v;
 }
 
+// C = alpha A B + beta C for a tall A (m x k, m large) and a short B (k x n),
+// column-major, on the FP64 matrix cores: one workgroup of eight wavefronts
+// per 64 rows x 512 columns.  Per 16-entry chunk of k the 64 x 16 block of A
+// goes through LDS (double-buffered, one barrier per chunk; loaded one chunk
+// ahead, coalesced down the columns); wavefront w multiplies it with columns
+// [64 w, 64 w + 64) of B, whose operands it reads from global memory one chunk
+// ahead (four consecutive k of a column share a 32-byte sector).  Rows past
+// m and k past the end are zero in LDS; column blocks past n are skipped.
+__global__ void __launch_bounds__(512) k_gemm_tall(int64_t m, int n, int k, double alpha,
+                                                   const double *__restrict__ A, int64_t lda,
+                                                   const double *__restrict__ B, int64_t ldb,
+                                                   double beta, double *__restrict__ C,
+                                                   int64_t ldc) {
+  constexpr int LDK = 18;
+  __shared__ double As[2][64 * LDK];
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
+  const int lr = l & 15, lk = l >> 4;
+  const int64_t m0 = (int64_t)blockIdx.x * 64;
+  const int rows = (int)min((int64_t)64, m - m0);
+  const int nrb = (rows + 15) >> 4;
+  const int c0 = blockIdx.y * 512 + 64 * w;
+  const int ncb = min(4, max(0, (n - c0 + 15) >> 4));
+  const int ar = tid & 63, ak = 2 * (tid >> 6);   // A staging: row ar, chunk columns ak, ak + 1
+  auto load_a = [&](int k0, double *a2) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int kk = k0 + ak + h;
+      a2[h] = (ar < rows && kk < k) ? A[m0 + ar + lda * (int64_t)kk] : 0.0;
+    }
+  };
+  auto load_b = [&](int k0, double *b) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int kb = k0 + 4 * kk + lk;
+      const int kc = kb < k ? kb : 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int cc = c0 + 16 * j + lr;
+        b[4 * kk + j] = B[kc + ldb * (int64_t)(cc < n ? cc : 0)];
+      }
+    }
+  };
+  v4d acc[4][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[q][j] = v4d{0, 0, 0, 0};
+  double anext[2], bcur[16], bnext[16];
+  load_a(0, anext);
+  load_b(0, bcur);
+  int buf = 0;
+  for (int k0 = 0; k0 < k; k0 += 16) {
+    As[buf][ar * LDK + ak] = anext[0];
+    As[buf][ar * LDK + ak + 1] = anext[1];
+    if (k0 + 16 < k) {
+      load_a(k0 + 16, anext);
+      load_b(k0 + 16, bnext);
+    }
+    __syncthreads();
+    const double *As_ = As[buf];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (q < nrb) {
+          const double a = As_[(16 * q + lr) * LDK + 4 * kk + lk];
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (j < ncb) acc[q][j] = mfma_f64(a, bcur[4 * kk + j], acc[q][j]);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) bcur[i] = bnext[i];
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * q + lk + 4 * r;
+        const int cc = c0 + 16 * j + lr;
+        if (i < rows && cc < n) {
+          double *c = C + m0 + i + ldc * (int64_t)cc;
+          *c = beta != 0.0 ? fma(alpha, acc[q][j][r], beta * *c) : alpha * acc[q][j][r];
+        }
+      }
+}
+
+static bool tall_shape(int64_t m, int64_t n, int64_t k) {
+  return m >= 4096 && n >= 1 && n <= INT32_MAX && k >= 1 && k <= INT32_MAX;
+}
+
+static void gemm_tall(int64_t m, int n, int k, double alpha, const double *A, int64_t lda,
+                      const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_gemm_tall, dim3((unsigned)((m + 63) / 64), (unsigned)((n + 511) / 512)),
+                     dim3(512), 0, st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
 void gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double alpha, const double *A,
           int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
           hipStream_t st, DevBuf<double> *work) {
@@ -846,6 +958,10 @@ void gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double alpha, const
     } else if (beta != 1.0) {
       throw Error{FKF_E_UNSUPPORTED, "gemm: k = 0 with beta not in {0, 1}"};
     }
+    return;
+  }
+  if (!ta && !tb && tall_shape(m, n, k)) {
+    gemm_tall(m, (int)n, (int)k, alpha, A, lda, B, ldb, beta, C, ldc, st);
     return;
   }
   const int64_t tm = (m + 63) / 64, tn = (n + 63) / 64;

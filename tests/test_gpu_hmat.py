@@ -164,3 +164,20 @@ def test_hmatvec_leading_dimensions_and_errors():
     assert torch.all(out.t()[576:] == 7.0)
     with pytest.raises(ValueError):
         cov.apply(torch.zeros(10, dtype=torch.float64, device="cuda"))
+
+
+def test_hmatvec_column_blocks_under_workspace_bound():
+    # a small workspace bound makes the 40-column product run in blocks of a
+    # few columns; every column must come out as in the one-block product
+    import paper_1405_2276_amd as fkf
+    pts = W.grid_points((40, 36))
+    kw = dict(nu=1.5, length=0.2, variance=1.0, leaf_size=48)
+    whole = fkf.Cov(pts, **kw)
+    blocks = fkf.Cov(pts, workspace_bytes=300_000, **kw)
+    X = np.random.default_rng(9).standard_normal((len(pts), 40))
+    a, b = _host(whole.apply(_dev(X))), _host(blocks.apply(_dev(X)))
+    err = np.abs(a - b).max() / np.abs(a).max()
+    _say(f"[hmat] column blocks vs one block maxdiff={err:.2e}")
+    assert err <= 1e-14
+    want = direct.cov_matvec(pts, X, 1.5, 0.2, 1.0)
+    assert np.linalg.norm(b - want) / np.linalg.norm(want) <= 1e-7
