@@ -238,20 +238,31 @@ __device__ void jacobi_solve_part(double *smem, const double *__restrict__ A, in
     int kp[2], hp[2];
     block_slot(blk[0], rprev, nb, kp[0], hp[0]);
     block_slot(blk[1], rprev, nb, kp[1], hp[1]);
-    for (int e = tid; e < 2 * kJT * kJB; e += 256) {
-      const int x = e / (kJT * kJB), a = (e >> 4) & 31, c = e & 15;
-      Jh[(x * kJT + a) * 17 + c] = Jprev[(int64_t)kp[x] * kJT * kJT + a + kJT * (hp[x] * kJB + c)];
-    }
     // wave wv: block (X, Y) = (wv >> 1, wv & 1); its previous tile (kp[X], kp[Y])
     const int X = wv >> 1, Y = wv & 1;
     double *T = Tb + wv * kTS;
     {
-      const int32_t *px = pidx + ((int64_t)rprev * npair + kp[X]) * kJT;
-      const int32_t *py = pidx + ((int64_t)rprev * npair + kp[Y]) * kJT;
-      const int gi = px[l & 31];
+      // all global loads of the formation first (J' halves and the previous
+      // tile, indices computed rather than looked up), then the LDS stores,
+      // so that the loads share one memory latency
+      double jv[2 * kJT * kJB / 256];
+#pragma unroll
+      for (int it = 0; it < 2 * kJT * kJB / 256; ++it) {
+        const int e = tid + 256 * it;
+        const int x = e / (kJT * kJB), a = (e >> 4) & 31, c = e & 15;
+        jv[it] = Jprev[(int64_t)kp[x] * kJT * kJT + a + kJT * (hp[x] * kJB + c)];
+      }
+      const int gi = pair_index(kp[X], l & 31, rprev, nb);
       double v[16];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) v[q] = A[gi + (int64_t)np * py[(l >> 5) + 2 * q]];
+      for (int q = 0; q < 16; ++q)
+        v[q] = A[gi + (int64_t)np * pair_index(kp[Y], (l >> 5) + 2 * q, rprev, nb)];
+#pragma unroll
+      for (int it = 0; it < 2 * kJT * kJB / 256; ++it) {
+        const int e = tid + 256 * it;
+        const int x = e / (kJT * kJB), a = (e >> 4) & 31, c = e & 15;
+        Jh[(x * kJT + a) * 17 + c] = jv[it];
+      }
 #pragma unroll
       for (int q = 0; q < 16; ++q) T[(l & 31) * (kJT + 1) + (l >> 5) + 2 * q] = v[q];
     }
@@ -363,18 +374,33 @@ __device__ void jacobi_update_part(double *smem, int w, const double *__restrict
     k1 = -1;
     k2 = w % npair;
   }
-  const int32_t *i1 = pidx + ((int64_t)r * npair + (isA ? k1 : 0)) * kJT;
-  const int32_t *i2 = pidx + ((int64_t)r * npair + k2) * kJT;
-  for (int e = tid; e < kJT * kJT; e += 256) {
-    int i = e & 31, j = e >> 5;
-    int gj = i2[j];
-    if (isA) {
-      Tl[i][j] = Acur[i1[i] + (int64_t)np * gj];
-      J1[i][j] = Jbuf[(int64_t)k1 * kJT * kJT + i + kJT * j];
-    } else {
-      Tl[i][j] = V[rc0 + i + (int64_t)np * gj];
+  // global indices of the pairs' local indices, computed (round-robin
+  // tournament) rather than looked up, so that the data loads do not wait on
+  // index loads
+  const int gi1 = isA ? pair_index(k1, tid & 31, r, nb) : 0;
+  {
+    double tv[kJT * kJT / 256], j1v[kJT * kJT / 256], j2v[kJT * kJT / 256];
+#pragma unroll
+    for (int it = 0; it < kJT * kJT / 256; ++it) {
+      const int e = tid + 256 * it;
+      const int i = e & 31, j = e >> 5;
+      const int gj = pair_index(k2, j, r, nb);
+      if (isA) {
+        tv[it] = Acur[gi1 + (int64_t)np * gj];
+        j1v[it] = Jbuf[(int64_t)k1 * kJT * kJT + i + kJT * j];
+      } else {
+        tv[it] = V[rc0 + i + (int64_t)np * gj];
+      }
+      j2v[it] = Jbuf[(int64_t)k2 * kJT * kJT + i + kJT * j];
     }
-    J2[i][j] = Jbuf[(int64_t)k2 * kJT * kJT + i + kJT * j];
+#pragma unroll
+    for (int it = 0; it < kJT * kJT / 256; ++it) {
+      const int e = tid + 256 * it;
+      const int i = e & 31, j = e >> 5;
+      Tl[i][j] = tv[it];
+      if (isA) J1[i][j] = j1v[it];
+      J2[i][j] = j2v[it];
+    }
   }
   __syncthreads();
   const int wv = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
@@ -384,10 +410,11 @@ __device__ void jacobi_update_part(double *smem, int w, const double *__restrict
   for (int kk = 0; kk < 8; ++kk)
     acc = mfma_f64(Tl[16 * ti + lr][4 * kk + lk], J2[4 * kk + lk][16 * tj + lr], acc);
   if (!isA) {
+    const int gj = pair_index(k2, 16 * tj + lr, r, nb);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int i = 16 * ti + lk + 4 * q, j = 16 * tj + lr;
-      V[rc0 + i + (int64_t)np * i2[j]] = acc[q];
+      const int i = 16 * ti + lk + 4 * q;
+      V[rc0 + i + (int64_t)np * gj] = acc[q];
     }
     return;
   }
@@ -398,10 +425,11 @@ __device__ void jacobi_update_part(double *smem, int w, const double *__restrict
 #pragma unroll
   for (int kk = 0; kk < 8; ++kk)
     acc = mfma_f64(J1[4 * kk + lk][16 * ti + lr], Tm[4 * kk + lk][16 * tj + lr], acc);
+  const int gj = pair_index(k2, 16 * tj + lr, r, nb);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int i = 16 * ti + lk + 4 * q, j = 16 * tj + lr;
-    Anext[i1[i] + (int64_t)np * i2[j]] = acc[q];
+    const int i = 16 * ti + lk + 4 * q;
+    Anext[pair_index(k1, i, r, nb) + (int64_t)np * gj] = acc[q];
   }
 }
 
