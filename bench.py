@@ -331,7 +331,7 @@ TRAFFIC_KERNELS = {
     "void fkf::k_down_mfma2<2>": "hmat_down_multi",
     "void fkf::k_up_mfma2<2>": "hmat_far_up_multi",
     "void fkf::k_gemv_seg<false>": "filter_gemv",
-    "fkf::k_gemm_nn": "gep_basis_gemm",
+    "fkf::k_gemm_tall": "gep_basis_gemm",
 }
 TRAFFIC_SOURCES = ["paper_1405_2276_amd/csrc/common.h", "paper_1405_2276_amd/csrc/kernels.h",
                    "paper_1405_2276_amd/csrc/hmat.hip", "paper_1405_2276_amd/csrc/linalg.hip",
@@ -607,7 +607,7 @@ def main():
         "hmat_near_multi": ("mfma", 2.0 * n_m * info["n_near_pairs"] * 4096.0, "TFLOP/s"),
         "hmat_down_multi": ("mfma", 2.0 * n_m * info["far_interp_entries"], "TFLOP/s"),
         "hmat_far_up_multi": ("mfma", 2.0 * n_m * info["far_interp_entries"], "TFLOP/s"),
-        "gep_basis_gemm": ("alu", 2.0 * n * n_m * n_m, "TFLOP/s"),
+        "gep_basis_gemm": ("mfma", 2.0 * n * n_m * n_m, "TFLOP/s"),
         # Jacobi round (one launch): the update part turns every 32 x 32 tile
         # of A into J^T A J and every tile of V into V J (3 tile products per
         # tile pair), the solve part forms its 15 pair tiles as J'^T A' J'
