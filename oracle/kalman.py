@@ -73,7 +73,8 @@ def xcov_kf(P: np.ndarray, H, R, ys, theta: float, alpha0: float = 0.0, s0=None)
     Sigma_{0|0} = alpha0 Gamma: C = Sigma H^T = alpha0 P, A = H C, v = diag Sigma.
     Per step: C^- = C + P, A^- = A + H P, v^- = v + theta; S = A^- + R;
     K = C^- S^-1; s += K (y - H s); C = C^- - K A^-; A = A^- - A^- S^-1 A^-;
-    v = v^- - rowsum(K o C^-).
+    v = v^- - rowsum(K o C^-).  Each record also carries the innovation
+    log-likelihood of the steps so far (``ll``), as ``innovation_loglik``.
     """
     Hd = H
     G = np.asarray(Hd @ P)
@@ -85,19 +86,22 @@ def xcov_kf(P: np.ndarray, H, R, ys, theta: float, alpha0: float = 0.0, s0=None)
     v = np.full(N, alpha0 * theta)
     Rd = np.diag(np.asarray(R, dtype=np.float64))
     out = []
+    ll = 0.0
     for k, y in enumerate(ys, start=1):
         Cm = C + P
         Am = A + G
         vm = v + theta
         cf = sla.cho_factor(Am + Rd)
         nu = np.asarray(y, dtype=np.float64) - np.asarray(Hd @ s).ravel()
+        ll -= 0.5 * (nu @ sla.cho_solve(cf, nu) + 2 * np.sum(np.log(np.diag(cf[0])))
+                     + len(nu) * np.log(2 * np.pi))
         s = s + Cm @ sla.cho_solve(cf, nu)
         K = sla.cho_solve(cf, Cm.T).T
         C = Cm - K @ Am
         A = Am - Am @ sla.cho_solve(cf, Am)
         A = 0.5 * (A + A.T)
         v = vm - np.sum(K * Cm, axis=1)
-        out.append({"s": s.copy(), "alpha": alpha0 + k, "var": v.copy()})
+        out.append({"s": s.copy(), "alpha": alpha0 + k, "var": v.copy(), "ll": ll})
     return out
 
 

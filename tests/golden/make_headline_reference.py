@@ -3,7 +3,10 @@
 Runs only the CPU oracle (direct P = Gamma H^T and the exact cross-covariance
 Kalman recursion of oracle.kalman.xcov_kf) on the seeded inputs of
 workloads.LARGE and stores the state estimate and variance at 4096 sampled
-cells after steps 1, 10 and 50, plus their full-vector 2-norms.
+cells after steps 1, 10 and 50, plus their full-vector 2-norms; and the
+innovation log-likelihood of the 50 steps with its central differences in
+log theta (P and theta scaled), log sigma^2 (R scaled) and log length (P
+recomputed directly at length e^(+-h)), h = 1e-4.
 
     python tests/golden/make_headline_reference.py
 
@@ -43,6 +46,20 @@ def main():
         rec[f"v{k}"] = out[k - 1]["var"][idx]
         rec[f"s{k}_norm"] = np.linalg.norm(out[k - 1]["s"])
         rec[f"v{k}_max"] = np.abs(out[k - 1]["var"]).max()
+    # log-likelihood and its derivatives (central differences, h = 1e-4)
+    h = 1e-4
+    rec["ll"] = out[-1]["ll"]
+
+    def ll_of(Pm, Rm, theta):
+        return kalman.xcov_kf(Pm, H, Rm, ys, theta)[-1]["ll"]
+    e = np.exp(h)
+    rec["dll_dlog_theta"] = (ll_of(P * e, R, wl.variance * e)
+                             - ll_of(P / e, R, wl.variance / e)) / (2 * h)
+    rec["dll_dlog_noise"] = (ll_of(P, R * e, wl.variance) - ll_of(P, R / e, wl.variance)) / (2 * h)
+    Pp = direct.cross_cov(pts, H, wl.nu, wl.length * e, wl.variance)
+    Pm = direct.cross_cov(pts, H, wl.nu, wl.length / e, wl.variance)
+    rec["dll_dlog_length"] = (ll_of(Pp, R, wl.variance) - ll_of(Pm, R, wl.variance)) / (2 * h)
+    print(f"log-likelihood and derivatives in {time.time() - t0:.1f} s", flush=True)
     np.savez_compressed(os.path.join(HERE, "headline_reference.npz"), **rec)
     print("written", flush=True)
 

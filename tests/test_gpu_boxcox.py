@@ -167,3 +167,33 @@ def test_boxcox_argument_errors_and_nonfinite_data():
     with pytest.raises(fkf.FkfError) as e:
         f.status()
     assert e.value.name == "FKF_E_NONFINITE"
+
+
+def test_boxcox_affine_case_at_headline_size():
+    # the affine case a = 1 at N = 65536 (480 rays): the extended steps (the
+    # varying-H update from the second step on) against constant-H steps on
+    # data y - H 1, a property that holds at any size
+    import torch
+    import paper_1405_2276_amd as fkf
+    wl = W.LARGE
+    _say(f"[boxcox] affine headline n={wl.n}")
+    cov = fkf.Cov(wl.points(), nu=wl.nu, length=wl.length, variance=wl.variance,
+                  leaf_size=wl.leaf_size)
+    src, rcv = wl.rays()
+    obs = fkf.Obs.from_rays(wl.shape, src, rcv, wl.noise_var)
+    ys = W.observations(wl, positive=True)
+    ones = torch.ones(wl.n, dtype=torch.float64, device="cuda")
+    shift = torch.empty(obs.n_m, dtype=torch.float64, device="cuda")
+    obs.apply(ones, out=shift)
+    fe, fl = fkf.Filter(cov), fkf.Filter(cov)
+    for k in range(3):
+        yk = torch.from_numpy(ys[k]).cuda()
+        fe.step_boxcox(obs, yk, 1.0)
+        fl.step(obs, yk - shift)
+        xe, xl = _host(fe.mean()), _host(fl.mean())
+        ve, vl = _host(fe.variance()), _host(fl.variance())
+        d = np.linalg.norm(xe - xl) / np.linalg.norm(xl)
+        dv = np.max(np.abs(ve - vl)) / np.max(vl)
+        _say(f"[boxcox] affine headline step={k + 1} state={d:.2e} var={dv:.2e}")
+        assert d <= 1e-7 and dv <= 1e-7
+    fe.status()

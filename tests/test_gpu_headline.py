@@ -42,3 +42,39 @@ def test_headline_filter_matches_oracle_at_sampled_cells():
                   f"norm err={en:.2e}", flush=True)
             assert es <= TOL and ev <= TOL and en <= TOL
     f.status()
+
+
+def test_headline_loglik_and_derivatives_match_oracle():
+    # log-likelihood of the 50 steps and its derivatives in log theta, log
+    # sigma^2 and log length against the oracle's values (cross-covariance
+    # recursion and its central differences) stored with the reference
+    import torch
+    import paper_1405_2276_amd as fkf
+    if not os.path.exists(REF):
+        pytest.skip("reference file not generated")
+    ref = np.load(REF)
+    if "ll" not in ref.files:
+        pytest.skip("reference file has no log-likelihood")
+    wl = W.LARGE
+    print(f"[headline] log-likelihood n={wl.n} steps={wl.steps}", flush=True)
+    kw = dict(nu=wl.nu, length=wl.length, variance=wl.variance, leaf_size=wl.leaf_size)
+    cov = fkf.Cov(wl.points(), **kw)
+    dcov = fkf.Cov(wl.points(), dlength=True, **kw)
+    src, rcv = wl.rays()
+    obs = fkf.Obs.from_rays(wl.shape, src, rcv, wl.noise_var)
+    ys = torch.from_numpy(W.observations(wl)).cuda()
+    f = fkf.Filter(cov)
+    f.track_length(dcov)
+    for k in range(wl.steps):
+        f.step(obs, ys[k])
+    ll, d_th, d_nv, d_ln = f.loglik()
+    errs = {}
+    for name, got, want in (("ll", ll, ref["ll"]), ("dlogtheta", d_th, ref["dll_dlog_theta"]),
+                            ("dlognoise", d_nv, ref["dll_dlog_noise"]),
+                            ("dloglength", d_ln, ref["dll_dlog_length"])):
+        errs[name] = abs(got - float(want)) / abs(float(want))
+        print(f"[headline] {name}={got:.8e} oracle={float(want):.8e} err={errs[name]:.1e}",
+              flush=True)
+    assert errs["ll"] <= TOL
+    assert errs["dlogtheta"] <= 1e-5 and errs["dlognoise"] <= 1e-5 and errs["dloglength"] <= 1e-5
+    f.status()

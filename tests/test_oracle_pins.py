@@ -183,9 +183,11 @@ def test_xcov_kf_equals_dense_kf():
     d = kalman.dense_kf(Gamma, [H] * wl.steps, [R] * wl.steps, ys, alpha0=0.5)
     P = direct.cross_cov(pts, H, wl.nu, wl.length, wl.variance)
     x = kalman.xcov_kf(P, H, R, ys, wl.variance, alpha0=0.5)
-    for a, b in zip(d, x):
+    for k, (a, b) in enumerate(zip(d, x), start=1):
         np.testing.assert_allclose(b["s"], a["s"], rtol=1e-10, atol=1e-12)
         np.testing.assert_allclose(b["var"], a["var"], rtol=1e-10, atol=1e-14)
+        ll = kalman.innovation_loglik(Gamma, [H] * k, [R] * k, ys[:k], alpha0=0.5)
+        assert b["ll"] == pytest.approx(ll, rel=1e-11)
 
 
 # --------------------------------------------------------------------- gep ---
