@@ -148,7 +148,11 @@ typedef struct fkf_filter fkf_filter;
 /* Build Gamma_sys as an H-matrix over n points of dimension d (2 or 3).
  * pts_host: n x d row-major coordinates.  Assembles the near-field blocks on
  * the device (Section 2.2.1; the paper's construction cost is O(k^2 N),
- * Section 4.1.2).  On success *out owns all device memory of the operator. */
+ * Section 4.1.2).  Besides the near tiles (near_bytes of fkf_cov_info_t) the
+ * operator keeps the tiles of all n_near_pairs ordered near pairs once more,
+ * in the operand order of the several-column product (64 x 64 entries each,
+ * FP64, or FP32 in the mixed mode).  On success *out owns all device memory
+ * of the operator. */
 fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d,
                          const fkf_kernel_params *kernel,
                          const fkf_hmat_params *hmat, void *stream,
