@@ -96,3 +96,36 @@ def test_step_many_mixed_modes_and_errors():
     assert e.value.name == "FKF_E_ARG"
     assert f1.info()["k"] == 1                  # nothing was queued
     fkf.step_many([], [], [])
+
+
+def test_step_many_carries_log_likelihood_derivatives():
+    # filters stepped together (their basis builds, including the products
+    # with dGamma/d length, spread over the stream lanes) carry the same
+    # log-likelihood and derivatives as filters stepped one by one
+    import paper_1405_2276_amd as fkf
+    wls = _batch()[:3]
+    mk = []
+    for wl in wls:
+        kw = dict(nu=wl.nu, length=wl.length, variance=wl.variance, leaf_size=wl.leaf_size)
+        cov = fkf.Cov(wl.points(), **kw)
+        dcov = fkf.Cov(wl.points(), dlength=True, **kw)
+        src, rcv = wl.rays()
+        mk.append((cov, dcov, fkf.Obs.from_rays(wl.shape, src, rcv, wl.noise_var)))
+    ys = [W.observations(wl) for wl in wls]
+    fa, fb = [], []
+    for cov, dcov, _ in mk:
+        a, b = fkf.Filter(cov), fkf.Filter(cov)
+        a.track_length(dcov)
+        b.track_length(dcov)
+        fa.append(a)
+        fb.append(b)
+    obss = [m[2] for m in mk]
+    for k in range(3):
+        fkf.step_many(fa, obss, [y[k] for y in ys])
+        for f, o, y in zip(fb, obss, ys):
+            f.step(o, y[k])
+    for i in range(3):
+        la, lb = fa[i].loglik(), fb[i].loglik()
+        _say(f"[batched] filter {i} loglik together={la} single={lb}")
+        for x, y in zip(la, lb):
+            assert abs(x - y) <= 1e-9 * max(abs(y), 1.0)
