@@ -1499,29 +1499,30 @@ __global__ void __launch_bounds__(256) k_near_repack(const TT *__restrict__ blk,
 
 // Near field of the several-column product on the FP64 matrix cores,
 // Y[perm, c] = sum over the near pairs (s, t) of A_st X_t: one workgroup per
-// (target leaf s, block of 64 columns), one wavefront per 16 rows.  The A
-// operands come from the repacked tiles straight into registers (coalesced,
-// one pair ahead); the 64 x 64 block of X_t goes through LDS, stored
-// column-major with row stride 66 (conflict-free operand reads) and
-// double-buffered, so that a pair costs one barrier.  Rows of X_t beyond the
+// (target leaf s, block of 128 columns), eight wavefronts, each owning 16 rows
+// and 64 columns.  The A operands come from the repacked tiles straight into
+// registers (coalesced, one pair ahead); the 64 x 128 block of X_t goes
+// through LDS, stored column-major with row stride 66 (conflict-free operand
+// reads) and double-buffered, so that a pair costs one barrier.  Rows of X_t beyond the
 // leaf and columns beyond nrhs are staged as zeros.
 template <typename TT>
-__global__ void __launch_bounds__(256) k_near_mfma(
+__global__ void __launch_bounds__(512) k_near_mfma(
     const TT *__restrict__ frag, const int32_t *__restrict__ near_ptr,
     const int32_t *__restrict__ near_idx, const int32_t *__restrict__ bs,
     const int32_t *__restrict__ bt, const int64_t *__restrict__ leaf_off, int64_t n,
     const double *__restrict__ xt, const int64_t *__restrict__ perm, int nrhs,
     double *__restrict__ Y, int64_t ldy) {
-  constexpr int NC = 64, LDB = 66;
+  constexpr int NC = 128, LDB = 66;
   __shared__ double Bt[2][NC * LDB];
   const int s = blockIdx.x;
   const int c0 = blockIdx.y * NC;
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int rg = w & 3, ch = w >> 2;   // 16-row group and 64-column half of this wavefront
   const int lr = l & 15, lk = l >> 4;
   const int e0 = near_ptr[s], e1 = near_ptr[s + 1];
   const int64_t s0 = leaf_off[s], ms = leaf_off[s + 1] - s0;
   double breg[16], acur[16], anext[16];
-  // X_t block of pair e into registers: thread (k = l, columns w + 4q)
+  // X_t block of pair e into registers: thread (k = l, columns w + 8q)
   auto load_b = [&](int e) {
     const int code = near_idx[e];
     const int64_t b = code >> 1;
@@ -1531,17 +1532,17 @@ __global__ void __launch_bounds__(256) k_near_mfma(
     const int64_t r = t0 + (row_ok ? l : 0);
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const int c = c0 + w + 4 * q;
+      const int c = c0 + w + 8 * q;
       const double v = xt[r + n * (int64_t)(c < nrhs ? c : 0)];
       breg[q] = (row_ok && c < nrhs) ? v : 0.0;
     }
   };
   auto store_b = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) Bt[buf][(w + 4 * q) * LDB + l] = breg[q];
+    for (int q = 0; q < 16; ++q) Bt[buf][(w + 8 * q) * LDB + l] = breg[q];
   };
   auto load_a = [&](int e, double *a) {
-    const TT *src = frag + (int64_t)e * 4096 + w * 1024 + l;
+    const TT *src = frag + (int64_t)e * 4096 + rg * 1024 + l;
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) a[kk] = (double)src[kk * 64];
   };
@@ -1561,7 +1562,7 @@ __global__ void __launch_bounds__(256) k_near_mfma(
       load_b(e + 1);
       load_a(e + 1, anext);
     }
-    const double *B = Bt[cur];
+    const double *B = Bt[cur] + (64 * ch) * LDB;
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
       const int k = 4 * kk + lk;
@@ -1579,8 +1580,8 @@ __global__ void __launch_bounds__(256) k_near_mfma(
   for (int j = 0; j < 4; ++j)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int i = w * 16 + lk + 4 * r;
-      const int cc = c0 + j * 16 + lr;
+      const int i = rg * 16 + lk + 4 * r;
+      const int cc = c0 + 64 * ch + j * 16 + lr;
       if (i < ms && cc < nrhs) Y[perm[s0 + i] + ldy * cc] = acc[j][r];
     }
 }
@@ -2045,8 +2046,8 @@ template <bool F32>
 void near_multi(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t s) {
   typedef typename std::conditional<F32, float, double>::type TT;
   const TT *frag = F32 ? (const TT *)cov->frag32.p : (const TT *)cov->frag.p;
-  hipLaunchKernelGGL(k_near_mfma<TT>, dim3(cov->n_leaves, (unsigned)((nrhs + 63) / 64)),
-                     dim3(256), 0, s, frag, cov->near_ptr.p, cov->near_idx.p, cov->blk_s.p,
+  hipLaunchKernelGGL(k_near_mfma<TT>, dim3(cov->n_leaves, (unsigned)((nrhs + 127) / 128)),
+                     dim3(512), 0, s, frag, cov->near_ptr.p, cov->near_idx.p, cov->blk_s.p,
                      cov->blk_t.p, cov->leaf_off.p, cov->n, cov->xt.p, cov->perm.p, nrhs, Y, ldy);
 }
 
