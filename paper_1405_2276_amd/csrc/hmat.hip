@@ -29,6 +29,7 @@ namespace fkf {
 struct FarCluster {
   int64_t begin, end;
   int64_t coef_off;   // offset (in units of coefficients) of this cluster
+  int64_t lag_off;    // offset of its points' Lagrange values in the table
   int32_t p, pd;      // nodes per dimension, p^d
   double ctr[kMaxDim], hw[kMaxDim];
 };
@@ -133,6 +134,8 @@ struct fkf_cov {
   fkf::DevBuf<int32_t> cp_ptr;               // pair partials of each far cluster
   fkf::DevBuf<int64_t> cp_off;
   int64_t n_up_items = 0, n_part_up = 0, n_pairs = 0, n_part_pair = 0;
+  fkf::DevBuf<double> lag;                   // Lagrange values: per far cluster, point, axis,
+                                             // PMax nodes (several-column upward pass)
   fkf::DevBuf<fkf::UpItem> up_items_m;       // several-column upward chunks
   fkf::DevBuf<fkf::CoupleMItem> up_blocks_m; // (chunk, 64-row block), costliest first
   int64_t n_up_blocks_m = 0;
@@ -1044,6 +1047,33 @@ __global__ void __launch_bounds__(256) k_up_reduce_m(const FarCluster *__restric
   }
 }
 
+// Lagrange values of every far cluster's points at its nodes, computed once
+// at build: lag[lag_off + ((i - begin) * D + k) * PMax + a] = l_a(z_k(x_i)),
+// zero for a >= p (one thread per point and axis of an upward chunk).
+template <int D>
+__global__ void __launch_bounds__(256) k_lagrange_table(const UpItem *__restrict__ items,
+                                                        const FarCluster *__restrict__ fc,
+                                                        const double *__restrict__ pts, int64_t n,
+                                                        const double *__restrict__ cheb,
+                                                        double *__restrict__ lag) {
+  constexpr int PM = PMax<D>::v;
+  const UpItem it = items[blockIdx.x];
+  const int64_t e = (int64_t)blockIdx.y * 256 + threadIdx.x;
+  const int64_t i = it.begin + e / D;
+  const int k = (int)(e % D);
+  if (i >= it.end) return;
+  const FarCluster c = fc[it.fc];
+  const double *cu = cheb + c.p * 2 * kMaxCheb;
+  const double x = pts[k * n + i];
+  const double hw = fc[it.fc].hw[k], ctr = fc[it.fc].ctr[k];
+  const double z = hw > 0 ? (x - ctr) / hw : 0.0;
+  double L[PM];
+  lagrange_any<PM>(c.p, cu, cu + kMaxCheb, z, L);
+  double *o = lag + c.lag_off + ((i - c.begin) * D + k) * PM;
+#pragma unroll
+  for (int a = 0; a < PM; ++a) o[a] = L[a];
+}
+
 // Upward pass of the several-column product: the partial U_c^T X of one
 // chunk of cluster c's points, for one 64-row block of its coefficients and
 // 512 columns per workgroup.  Per 16 points: the per-axis Lagrange values go
@@ -1054,8 +1084,7 @@ template <int D>
 __global__ void __launch_bounds__(512) k_up_mfma2(const CoupleMItem *__restrict__ blocks,
                                                   const UpItem *__restrict__ items,
                                                   const FarCluster *__restrict__ fc,
-                                                  const double *__restrict__ pts, int64_t n,
-                                                  const double *__restrict__ cheb,
+                                                  const double *__restrict__ lag, int64_t n,
                                                   const double *__restrict__ xt, int nrhs,
                                                   double *__restrict__ part) {
   constexpr int PM = PMax<D>::v, LDK = 18;
@@ -1074,7 +1103,6 @@ __global__ void __launch_bounds__(512) k_up_mfma2(const CoupleMItem *__restrict_
   const int c0 = blockIdx.y * 512 + 64 * w;
   // 16-column blocks of this wavefront inside nrhs (wave-uniform)
   const int ncb = min(4, max(0, (nrhs - c0 + 15) >> 4));
-  const double *cu = cheb + p * 2 * kMaxCheb;
   // basis role: row er, points ek, ek + 1 of a chunk
   const int er = tid >> 3, ek = 2 * (tid & 7);
   int dig[D];
@@ -1108,31 +1136,12 @@ __global__ void __launch_bounds__(512) k_up_mfma2(const CoupleMItem *__restrict_
   load_b(it.begin, bcur);
   for (int64_t i0 = it.begin; i0 < it.end; i0 += 16) {
     {
-      // one (axis, point, node) per thread: the barycentric Lagrange value
-      // l_a(z) = (w_a / (z - u_a)) / sum_m w_m / (z - u_m) (same operations,
-      // in the same order, as lagrange_any)
+      // one (axis, point, node) per thread, from the table built with the
+      // operator
       const int a = tid % PM, i = (tid / PM) & 15, k = tid / (PM * 16);
-      if (k < D) {
-        double v = 0.0;
-        if (a < p && i0 + i < it.end) {
-          // axis k is not a compile-time index: read the box from memory
-          // rather than from the register copy of the cluster
-          const double x = pts[k * n + i0 + i];
-          const double hw = fc[it.fc].hw[k], ctr = fc[it.fc].ctr[k];
-          const double z = hw > 0 ? (x - ctr) / hw : 0.0;
-          double s = 0.0, qa = 0.0;
-          int exact = -1;
-          for (int m = 0; m < p; ++m) {
-            const double dx = z - cu[m];
-            if (dx == 0.0) exact = m;
-            const double q = cu[kMaxCheb + m] * rcp_nr(dx == 0.0 ? 1.0 : dx);
-            s += q;
-            if (m == a) qa = q;
-          }
-          v = exact >= 0 ? (a == exact ? 1.0 : 0.0) : qa * rcp_nr(s);
-        }
-        Ls[k][i][a] = v;
-      }
+      if (k < D)
+        Ls[k][i][a] = i0 + i < it.end ? lag[c.lag_off + ((i0 + i - c.begin) * D + k) * PM + a]
+                                      : 0.0;
     }
     if (i0 + 16 < it.end) load_b(i0 + 16, bnext);
     __syncthreads();
@@ -1754,10 +1763,14 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
     for (auto &pr : far) fpairs.emplace_back(far_id(pr.first), far_id(pr.second));
     cov->n_fc = (int)fcs.size();
     int64_t off = 0;
+    int64_t lag_total = 0;
+    const int pmax_d = d == 2 ? PMax<2>::v : PMax<3>::v;
     for (auto &c : fcs) {
       c.coef_off = off;
       off += c.pd;
       cov->max_pd = std::max(cov->max_pd, c.pd);
+      c.lag_off = lag_total;
+      lag_total += (c.end - c.begin) * d * pmax_d;
     }
     cov->n_coef = off;
     cov->n_interp = 0;
@@ -1840,6 +1853,7 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
       cov->n_part_up_m = poffm;
       cov->up_items_m.upload(upm, st);
       cov->up_ptr_m.upload(uptrm, st);
+      cov->lag.alloc((size_t)std::max<int64_t>(lag_total, 1));
       {
         std::vector<std::pair<int64_t, CoupleMItem>> ub;
         for (size_t u = 0; u < upm.size(); ++u) {
@@ -1899,6 +1913,19 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
     std::vector<double> ch((kMaxCheb + 1) * 2 * kMaxCheb, 0.0);
     for (int p = 1; p <= kMaxCheb; ++p) cheb_nodes(p, &ch[p * 2 * kMaxCheb], &ch[p * 2 * kMaxCheb + kMaxCheb]);
     cov->cheb.upload(ch, st);
+    // Lagrange table of the several-column upward pass (needs the node table)
+    if (cov->n_up_items_m > 0) {
+      const unsigned gy = (unsigned)((kUpChunkM * d + 255) / 256);
+      if (d == 2)
+        hipLaunchKernelGGL(k_lagrange_table<2>, dim3((unsigned)cov->n_up_items_m, gy), dim3(256), 0,
+                           st, cov->up_items_m.p, cov->fc.p, cov->pts.p, n, cov->cheb.p,
+                           cov->lag.p);
+      else
+        hipLaunchKernelGGL(k_lagrange_table<3>, dim3((unsigned)cov->n_up_items_m, gy), dim3(256), 0,
+                           st, cov->up_items_m.p, cov->fc.p, cov->pts.p, n, cov->cheb.p,
+                           cov->lag.p);
+      FKF_CHECK_HIP(hipGetLastError());
+    }
     const int64_t kbytes = cov->n_kst * (int64_t)(cov->mixed ? sizeof(float) : sizeof(double));
     if (cov->n_pairs > 0 && kbytes <= kMaxCouplingBytes && hp->far_eval == 0) {
       void *dst;
@@ -2076,7 +2103,7 @@ void apply_multi_t(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t s
       hipLaunchKernelGGL((k_up_mfma2<D>),
                          dim3((unsigned)cov->n_up_blocks_m, (unsigned)((nrhs + 511) / 512)),
                          dim3(512), 0, st, cov->up_blocks_m.p, cov->up_items_m.p, cov->fc.p,
-                         cov->pts.p, n, cov->cheb.p, cov->xt.p, nrhs, cov->part_up_m.p);
+                         cov->lag.p, n, cov->xt.p, nrhs, cov->part_up_m.p);
       hipLaunchKernelGGL(k_up_reduce_m, dim3(cov->n_fc, 8), dim3(256), 0, st, cov->fc.p,
                          cov->up_ptr_m.p, cov->up_items_m.p, nrhs, cov->part_up_m.p, cov->xhat.p);
     }
