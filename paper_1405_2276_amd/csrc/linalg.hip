@@ -38,11 +38,13 @@ __device__ __forceinline__ int pair_index(int k, int i, int round, int nb) {
 // zeta = aqq - app and eta = 2 apq, t = sign(zeta) eta / (|zeta| + sqrt(zeta^2
 // + eta^2)) is the smaller root of t^2 + 2 tau t - 1 = 0 (tau = zeta / eta).
 // The angle is evaluated in FP32 on (zeta, eta) scaled to [-1, 1] (a short
-// dependency chain of single-precision operations); c = 1 / sqrt(1 + t^2)
-// (FP32 seed and two FP64 Newton steps) and s = t c make the applied rotation
-// orthogonal to FP64 rounding, so the entry apq is reduced by the angle's
-// relative error (~1e-7) rather than zeroed, and the next sweep removes the
-// remainder.  Branch-free; skipped (identity) when
+// dependency chain of single-precision operations; the sum of squares lies in
+// [1, 2], so the hardware square root needs no range scaling); c = 1 /
+// sqrt(1 + t^2) (FP32 seed y0 with relative error e/2, e = 1 - q y0^2, then
+// one third-order step y0 (1 + e/2 + 3 e^2/8), leaving ~e^3) and s = t c make
+// the applied rotation orthogonal to FP64 rounding, so the entry apq is
+// reduced by the angle's relative error (~1e-7) rather than zeroed, and the
+// next sweep removes the remainder.  Branch-free; skipped (identity) when
 // |apq| <= max(tol_rel sqrt|app aqq|, tol_abs) (compared in squares).
 __device__ __forceinline__ bool jacobi_rotation(double app, double aqq, double apq, double tol_rel,
                                                 double tol_abs, double &c, double &s) {
@@ -52,14 +54,13 @@ __device__ __forceinline__ bool jacobi_rotation(double app, double aqq, double a
   const float m = fmaxf(fabsf(z), fabsf(e));
   const float sc = __builtin_amdgcn_rcpf(rot ? m : 1.0f);
   const float zs = z * sc, es = e * sc;
-  const float r = __fsqrt_rn(fmaf(zs, zs, es * es));
+  const float r = __builtin_amdgcn_sqrtf(fmaf(zs, zs, es * es));
   const float tf = copysignf(1.0f, zs) * es * __builtin_amdgcn_rcpf(rot ? fabsf(zs) + r : 1.0f);
   const double t = (double)tf;
   const double q = fma(t, t, 1.0);
-  double y = (double)__builtin_amdgcn_rsqf((float)q);
-  const double h = 0.5 * q;
-  y = y * fma(-h * y, y, 1.5);
-  y = y * fma(-h * y, y, 1.5);
+  const double y0 = (double)__builtin_amdgcn_rsqf((float)q);
+  const double ey = fma(-q * y0, y0, 1.0);
+  const double y = fma(y0 * ey, fma(0.375, ey, 0.5), y0);
   c = rot ? y : 1.0;
   s = rot ? t * y : 0.0;
   return rot;
@@ -182,16 +183,12 @@ __device__ __forceinline__ void block_slot(int B, int r, int nb, int &k, int &h)
 // pairs (i in P, j in Q) in 16 sub-rounds of 16 disjoint rotations (i with
 // 16 + (i + u) mod 16), and the first round of a sweep also visits the pairs
 // within each block beforehand (15 sub-rounds, round-robin within P and Q).
-__device__ __forceinline__ void sub_round_pair(int u, bool first, int k, int &p, int &q) {
-  if (first && u < kJB - 1) {
-    const int base = k < kJB / 2 ? 0 : kJB, kk = k & (kJB / 2 - 1);
-    p = base + rr_player(kk, u, kJB);
-    q = base + rr_player(kJB - 1 - kk, u, kJB);
-  } else {
-    const int sr = first ? u - (kJB - 1) : u;
-    p = k;
-    q = kJB + ((k + sr) & (kJB - 1));
-  }
+// intra_pair: the pair of index k of a within-block sub-round u (k < 8: the
+// 8 pairs of block P, k >= 8: those of block Q).
+__device__ __forceinline__ void intra_pair(int u, int k, int &p, int &q) {
+  const int base = k < kJB / 2 ? 0 : kJB, kk = k & (kJB / 2 - 1);
+  p = base + rr_player(kk, u, kJB);
+  q = base + rr_player(kJB - 1 - kk, u, kJB);
 }
 
 constexpr int kTS = kJT * (kJT + 1);   // doubles in one padded 32 x 32 LDS tile
@@ -299,44 +296,51 @@ __device__ void jacobi_solve_part(double *smem, const double *__restrict__ A, in
   const double tol_abs = 1e-15 * fro[0], tol_rel = 1e-15;
   const int P1 = tid >> 4, P2 = tid & 15;
   const int jr = tid >> 4;   // J rows jr and jr + 16, column pair P2
-  const bool first = r == 0;
-  const int nsub = first ? 2 * kJB - 1 : kJB;
   double(*Sc)[kJT + 1] = S0;
   double(*Sn)[kJT + 1] = S1;
-  __syncthreads();
-  for (int u = 0; u < nsub; ++u) {
-    int p1, q1, p2, q2;
-    sub_round_pair(u, first, P1, p1, q1);
-    sub_round_pair(u, first, P2, p2, q2);
+  // One sub-round: this thread's 2 x 2 block (rows p1, q1; columns p2, q2)
+  // of the next tile and its entries of J (rows jr, jr + 16; columns p2, q2).
+  // The J entries are read with the tile entries, before the rotations, so
+  // that both reads share one LDS latency.
+  auto sub_round = [&](int p1, int q1, int p2, int q2) {
     const double a11 = Sc[p1][p1], a12 = Sc[q1][q1], a13 = Sc[p1][q1];
     const double a21 = Sc[p2][p2], a22 = Sc[q2][q2], a23 = Sc[p2][q2];
     const double b11 = Sc[p1][p2], b12 = Sc[p1][q2];
     const double b21 = Sc[q1][p2], b22 = Sc[q1][q2];
+    const double jp0 = Jm[jr][p2], jq0 = Jm[jr][q2];
+    const double jp1 = Jm[jr + 16][p2], jq1 = Jm[jr + 16][q2];
     double c1, s1, c2, s2;
-    const bool r1 = jacobi_rotation(a11, a12, a13, tol_rel, tol_abs, c1, s1);
+    (void)jacobi_rotation(a11, a12, a13, tol_rel, tol_abs, c1, s1);
     const bool r2 = jacobi_rotation(a21, a22, a23, tol_rel, tol_abs, c2, s2);
     if (r2 && P1 == 0) rot_any = 1;
     const double t11 = c2 * b11 - s2 * b12, t12 = s2 * b11 + c2 * b12;
     const double t21 = c2 * b21 - s2 * b22, t22 = s2 * b21 + c2 * b22;
-    const double n11 = c1 * t11 - s1 * t21, n12 = c1 * t12 - s1 * t22;
-    const double n21 = s1 * t11 + c1 * t21, n22 = s1 * t12 + c1 * t22;
-    (void)r1;
-    Sn[p1][p2] = n11;
-    Sn[p1][q2] = n12;
-    Sn[q1][p2] = n21;
-    Sn[q1][q2] = n22;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int row = jr + 16 * h;
-      const double jp = Jm[row][p2], jq = Jm[row][q2];
-      Jm[row][p2] = c2 * jp - s2 * jq;
-      Jm[row][q2] = s2 * jp + c2 * jq;
-    }
+    Sn[p1][p2] = c1 * t11 - s1 * t21;
+    Sn[p1][q2] = c1 * t12 - s1 * t22;
+    Sn[q1][p2] = s1 * t11 + c1 * t21;
+    Sn[q1][q2] = s1 * t12 + c1 * t22;
+    Jm[jr][p2] = c2 * jp0 - s2 * jq0;
+    Jm[jr][q2] = s2 * jp0 + c2 * jq0;
+    Jm[jr + 16][p2] = c2 * jp1 - s2 * jq1;
+    Jm[jr + 16][q2] = s2 * jp1 + c2 * jq1;
     double(*t)[kJT + 1] = Sc;
     Sc = Sn;
     Sn = t;
     __syncthreads();
+  };
+  __syncthreads();
+  if (r == 0) {
+    // first round of a sweep: the pairs within each block (round-robin)
+    for (int u = 0; u < kJB - 1; ++u) {
+      int p1, q1, p2, q2;
+      intra_pair(u, P1, p1, q1);
+      intra_pair(u, P2, p2, q2);
+      sub_round(p1, q1, p2, q2);
+    }
   }
+#pragma unroll
+  for (int u = 0; u < kJB; ++u)
+    sub_round(P1, kJB + ((P1 + u) & (kJB - 1)), P2, kJB + ((P2 + u) & (kJB - 1)));
   double *Jo = Jout + (int64_t)k * kJT * kJT;
   for (int e = tid; e < kJT * kJT; e += 256) {
     int i = e & 31, j = e >> 5;
