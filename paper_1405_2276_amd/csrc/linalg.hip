@@ -37,28 +37,27 @@ __device__ __forceinline__ int pair_index(int k, int i, int round, int nb) {
 // Rotation (c, s) for the 2 x 2 symmetric block [app apq; apq aqq]: with
 // zeta = aqq - app and eta = 2 apq, t = sign(zeta) eta / (|zeta| + sqrt(zeta^2
 // + eta^2)) is the smaller root of t^2 + 2 tau t - 1 = 0 (tau = zeta / eta).
-// The angle is evaluated in FP32 on (zeta, eta) scaled to [-1, 1] (a short
-// dependency chain of single-precision operations; the sum of squares lies in
-// [1, 2], so the hardware square root needs no range scaling); c = 1 /
-// sqrt(1 + t^2) (FP32 seed y0 with relative error e/2, e = 1 - q y0^2, then
-// one third-order step y0 (1 + e/2 + 3 e^2/8), leaving ~e^3) and s = t c make
-// the applied rotation orthogonal to FP64 rounding, so the entry apq is
-// reduced by the angle's relative error (~1e-7) rather than zeroed, and the
-// next sweep removes the remainder.  Branch-free; skipped (identity) when
-// |apq| <= max(tol_rel sqrt|app aqq|, tol_abs) (compared in squares).
+// The angle is evaluated on (zeta, eta) scaled to [-1, 1] with the hardware
+// FP64 reciprocal and reciprocal square root (no refinement: a short
+// dependency chain, accurate to far more than the next sweep needs); c = 1 /
+// sqrt(1 + t^2) (hardware seed y0, e = 1 - q y0^2, then one third-order step
+// y0 (1 + e/2 + 3 e^2/8)) and s = t c make the applied rotation orthogonal to
+// FP64 rounding, so the entry apq is reduced by the angle's relative error
+// rather than zeroed, and the next sweep removes the remainder.  Branch-free;
+// skipped (identity) when |apq| <= max(tol_rel sqrt|app aqq|, tol_abs)
+// (compared in squares).
 __device__ __forceinline__ bool jacobi_rotation(double app, double aqq, double apq, double tol_rel,
                                                 double tol_abs, double &c, double &s) {
   const double a2 = apq * apq;
   const bool rot = a2 > tol_rel * tol_rel * fabs(app * aqq) && a2 > tol_abs * tol_abs;
-  const float z = (float)(aqq - app), e = (float)(2.0 * apq);
-  const float m = fmaxf(fabsf(z), fabsf(e));
-  const float sc = __builtin_amdgcn_rcpf(rot ? m : 1.0f);
-  const float zs = z * sc, es = e * sc;
-  const float r = __builtin_amdgcn_sqrtf(fmaf(zs, zs, es * es));
-  const float tf = copysignf(1.0f, zs) * es * __builtin_amdgcn_rcpf(rot ? fabsf(zs) + r : 1.0f);
-  const double t = (double)tf;
+  const double z = aqq - app, e = 2.0 * apq;
+  const double sc = __builtin_amdgcn_rcp(rot ? fmax(fabs(z), fabs(e)) : 1.0);
+  const double zs = z * sc, es = e * sc;
+  const double h2 = fma(zs, zs, es * es);   // in [1, 2] when rot
+  const double den = fabs(zs) + h2 * __builtin_amdgcn_rsq(rot ? h2 : 1.0);
+  const double t = (zs < 0.0 ? -es : es) * __builtin_amdgcn_rcp(den);
   const double q = fma(t, t, 1.0);
-  const double y0 = (double)__builtin_amdgcn_rsqf((float)q);
+  const double y0 = __builtin_amdgcn_rsq(q);
   const double ey = fma(-q * y0, y0, 1.0);
   const double y = fma(y0 * ey, fma(0.375, ey, 0.5), y0);
   c = rot ? y : 1.0;
@@ -301,18 +300,19 @@ __device__ void jacobi_solve_part(double *smem, const double *__restrict__ A, in
   // One sub-round: this thread's 2 x 2 block (rows p1, q1; columns p2, q2)
   // of the next tile and its entries of J (rows jr, jr + 16; columns p2, q2).
   // The J entries are read with the tile entries, before the rotations, so
-  // that both reads share one LDS latency.
+  // that both reads share one LDS latency.  Each thread computes the rotation
+  // of its column pair P2 only: its row pair P1 (< 16) is the column pair of
+  // lane P1 of the same wavefront, whose rotation is read across lanes.
   auto sub_round = [&](int p1, int q1, int p2, int q2) {
-    const double a11 = Sc[p1][p1], a12 = Sc[q1][q1], a13 = Sc[p1][q1];
     const double a21 = Sc[p2][p2], a22 = Sc[q2][q2], a23 = Sc[p2][q2];
     const double b11 = Sc[p1][p2], b12 = Sc[p1][q2];
     const double b21 = Sc[q1][p2], b22 = Sc[q1][q2];
     const double jp0 = Jm[jr][p2], jq0 = Jm[jr][q2];
     const double jp1 = Jm[jr + 16][p2], jq1 = Jm[jr + 16][q2];
-    double c1, s1, c2, s2;
-    (void)jacobi_rotation(a11, a12, a13, tol_rel, tol_abs, c1, s1);
+    double c2, s2;
     const bool r2 = jacobi_rotation(a21, a22, a23, tol_rel, tol_abs, c2, s2);
     if (r2 && P1 == 0) rot_any = 1;
+    const double c1 = __shfl(c2, P1), s1 = __shfl(s2, P1);
     const double t11 = c2 * b11 - s2 * b12, t12 = s2 * b11 + c2 * b12;
     const double t21 = c2 * b21 - s2 * b22, t22 = s2 * b21 + c2 * b22;
     Sn[p1][p2] = c1 * t11 - s1 * t21;
