@@ -184,7 +184,9 @@ void fkf_cov_destroy(fkf_cov *cov);
 
 /* Measurement operator H (n_m x n) from host CSR arrays (rowptr has n_m+1
  * entries, col in [0, n)), plus the diagonal of the noise covariance R
- * (noise_var_host, n_m entries, each > 0). */
+ * (noise_var_host, n_m entries, each > 0).  The stored rows are sorted by
+ * column with repeated columns summed (fkf_obs_shape and fkf_obs_get_csr
+ * report that form; both constructors store it). */
 fkf_status fkf_obs_create_csr(int32_t n_m, int64_t n, const int64_t *rowptr_host,
                               const int32_t *col_host, const double *val_host,
                               const double *noise_var_host, void *stream,
@@ -221,6 +223,20 @@ fkf_status fkf_obs_get_csr(const fkf_obs *obs, int64_t *rowptr_host,
 /* y_dev (n_m) = H x_dev (n). */
 fkf_status fkf_obs_apply(const fkf_obs *obs, const double *x_dev, double *y_dev,
                          void *stream);
+
+/* P_dev (n x n_m, leading dimension ldp >= n) = Gamma H^T, the cross
+ * covariance whose range carries the Rayleigh-Ritz step of the generalized
+ * eigenproblem (Section 2.2.2; in the offline stage of Section 4.1.2 H is
+ * sparse and the products with Gamma dominate).  The moments of the far
+ * clusters are summed over the nonzeros of H; an operator without far field,
+ * or an H with a row of more than 2048 entries, takes fkf_cov_apply of the
+ * dense H^T instead.  Either way the result equals fkf_cov_apply of the dense
+ * H^T up to rounding order.  cov and obs must have the same n (FKF_E_ARG
+ * otherwise); P must not overlap the operator's memory.  Allocates a dense
+ * H^T (8 n n_m bytes) for the call and synchronises the stream before
+ * returning. */
+fkf_status fkf_obs_cross_cov(fkf_cov *cov, const fkf_obs *obs, double *P_dev, int64_t ldp,
+                             void *stream);
 
 void fkf_obs_destroy(fkf_obs *obs);
 

@@ -95,6 +95,7 @@ _sig("fkf_obs_create_rays", _i, [ctypes.c_int32, _c_i32_p, ctypes.c_int32, _c_db
 _sig("fkf_obs_shape", _i, [_vp, _c_i32_p, _c_i64_p, _c_i64_p])
 _sig("fkf_obs_get_csr", _i, [_vp, _c_i64_p, _c_i32_p, _c_dbl_p])
 _sig("fkf_obs_apply", _i, [_vp, _vp, _vp, _vp])
+_sig("fkf_obs_cross_cov", _i, [_vp, _vp, _vp, ctypes.c_int64, _vp])
 _sig("fkf_obs_destroy", None, [_vp])
 _sig("fkf_filter_create", _i, [_vp, _vp, ctypes.c_double, ctypes.POINTER(FilterParams), _vp,
                                ctypes.POINTER(_vp)])
@@ -437,6 +438,17 @@ class Obs:
         if out is None:
             out = torch.empty(self.n_m, dtype=torch.float64, device=x.device)
         _check(_lib.fkf_obs_apply(self._h, x.data_ptr(), out.data_ptr(), _stream(stream)))
+        return out
+
+    def cross_cov(self, cov, out=None, stream=None):
+        """P = Gamma H^T as a column-major (N, n_m) CUDA float64 tensor
+        (fkf_obs_cross_cov: far-cluster moments summed over the nonzeros of H)."""
+        if out is None:
+            out = fortran_empty(self.n, self.n_m)
+        optr, ldp, k = _colmajor(out)
+        if out.shape[0] != self.n or k != self.n_m:
+            raise ValueError("out must be (N, n_m)")
+        _check(_lib.fkf_obs_cross_cov(cov._h, self._h, optr, ldp, _stream(stream)))
         return out
 
     def close(self):

@@ -38,6 +38,7 @@
 struct fkf_obs {
   int n_m = 0;
   int64_t n = 0, nnz = 0;
+  int64_t max_row = 0;     // entries in the longest row
   uint64_t gen = 0;
   std::vector<int64_t> rowptr_h;
   std::vector<int32_t> col_h;
@@ -104,6 +105,11 @@ int64_t cov_n(const fkf_cov *cov);
 bool cov_mixed(const fkf_cov *cov);
 int cov_kind(const fkf_cov *cov);
 double cov_length(const fkf_cov *cov);
+// Gamma H^T from the rows of the sparse H (CSR, device; Xd the dense H^T for
+// the near field): false, with nothing queued, where that form does not apply
+bool cov_apply_sparse_rows(fkf_cov *cov, int n_m, const int64_t *rowptr, const int32_t *col,
+                           const double *val, int64_t nnz, int64_t max_row, const double *Xd,
+                           double *Y, int64_t ldy, hipStream_t st);
 
 static std::atomic<uint64_t> g_obs_gen{1};
 
@@ -512,6 +518,19 @@ static void gemv_seg(const fkf_filter *f, const double *z, bool square, hipStrea
   gemv_seg_m(f->U0.p, f->ldu, f->n_m, f->n, z, square, f->part.p, st);
 }
 
+// P = Gamma H^T (ld n): the several-column product with the far-cluster
+// moments summed over the nonzeros of H where that form applies, else the
+// product with the dense H^T.
+static void cross_cov(fkf_cov *cov, const fkf_obs *o, const double *Ht, double *P,
+                      hipStream_t st) {
+  const int64_t n = o->n;
+  if (cov_apply_sparse_rows(cov, o->n_m, o->rowptr.p, o->col.p, o->val.p, o->nnz, o->max_row, Ht,
+                            P, n, st))
+    return;
+  fkf_status rc = fkf_cov_apply(cov, Ht, n, o->n_m, P, n, (void *)st);
+  if (rc != FKF_OK) throw Error{rc, std::string("covariance product failed: ") + fkf_last_error()};
+}
+
 // Rayleigh-Ritz for the generalized eigenproblem H^T R^-1 H x = lambda Gamma^-1 x
 // on range(Gamma H^T): P = Gamma H^T (H-matrix product), G = H P, and the
 // eigenpairs (lam descending, We) of A = R^-1/2 sym(G) R^-1/2.  Ht holds the
@@ -531,8 +550,7 @@ static void compute_gep(fkf_filter *f, const fkf_obs *o, DevBuf<double> &Ht, Dev
   dense_ht(o->rowptr.p, o->col.p, o->val.p, nm, n, Ht.p, st);
   {
     FKF_TRACE("gep_cross_cov", st);
-    fkf_status rc = fkf_cov_apply(f->cov, Ht.p, n, nm, P.p, n, (void *)st);
-    if (rc != FKF_OK) throw Error{rc, std::string("covariance product failed: ") + fkf_last_error()};
+    cross_cov(f->cov, o, Ht.p, P.p, st);
   }
   innovation_gram(o->rowptr.p, o->col.p, o->val.p, nm, n, P.p, o->noise.p, G.p, A.p, st);
   {
@@ -631,8 +649,7 @@ static void build_bases(fkf_filter *const *fs, const fkf_obs *const *os, int cou
     dense_ht(o->rowptr.p, o->col.p, o->val.p, nm, n, Ht.p, si);
     {
       FKF_TRACE("gep_cross_cov", si);
-      fkf_status rc = fkf_cov_apply(f->cov, Ht.p, n, nm, bw[i].P.p, n, (void *)si);
-      if (rc != FKF_OK) throw Error{rc, std::string("covariance product failed: ") + fkf_last_error()};
+      cross_cov(f->cov, o, Ht.p, bw[i].P.p, si);
     }
     innovation_gram(o->rowptr.p, o->col.p, o->val.p, nm, n, bw[i].P.p, o->noise.p, bw[i].G.p,
                     bw[i].A.p, si);
@@ -929,7 +946,42 @@ static double obs_ll_const(const std::vector<double> &noise) {
   return -0.5 * (s + (double)noise.size() * std::log(2.0 * M_PI));
 }
 
+// Rows sorted by column with repeated columns summed (one stored entry per
+// nonzero of H), so that every consumer of the operator (products with H and
+// H^T, the dense H^T, the sparse moments) sees the same matrix.
+static void obs_canonical(fkf_obs *o) {
+  std::vector<int64_t> rp(1, 0);
+  std::vector<int32_t> cl;
+  std::vector<double> vl;
+  cl.reserve(o->col_h.size());
+  vl.reserve(o->val_h.size());
+  std::vector<std::pair<int32_t, double>> row;
+  int64_t mx = 0;
+  for (int m = 0; m < o->n_m; ++m) {
+    row.clear();
+    for (int64_t e = o->rowptr_h[m]; e < o->rowptr_h[m + 1]; ++e)
+      row.emplace_back(o->col_h[e], o->val_h[e]);
+    std::stable_sort(row.begin(), row.end(),
+                     [](const auto &a, const auto &b) { return a.first < b.first; });
+    for (auto &cv : row) {
+      if ((int64_t)cl.size() > rp.back() && cl.back() == cv.first) vl.back() += cv.second;
+      else {
+        cl.push_back(cv.first);
+        vl.push_back(cv.second);
+      }
+    }
+    rp.push_back((int64_t)cl.size());
+    mx = std::max<int64_t>(mx, rp[m + 1] - rp[m]);
+  }
+  o->rowptr_h = std::move(rp);
+  o->col_h = std::move(cl);
+  o->val_h = std::move(vl);
+  o->nnz = (int64_t)o->col_h.size();
+  o->max_row = mx;
+}
+
 static void obs_finish(fkf_obs *o, hipStream_t st) {
+  obs_canonical(o);
   o->rowptr.upload(o->rowptr_h, st);
   o->col.upload(o->col_h, st);
   o->val.upload(o->val_h, st);
@@ -1030,6 +1082,25 @@ extern "C" fkf_status fkf_obs_apply(const fkf_obs *o, const double *x, double *y
     FKF_REQUIRE(o && x && y, "fkf_obs_apply: NULL argument");
     spmv(o->rowptr.p, o->col.p, o->val.p, o->n_m, x, y, as_stream(stream));
     FKF_CHECK_HIP(hipGetLastError());
+  });
+}
+
+extern "C" fkf_status fkf_obs_cross_cov(fkf_cov *cov, const fkf_obs *o, double *P, int64_t ldp,
+                                        void *stream) {
+  return guarded([&] {
+    FKF_REQUIRE(cov && o && P, "fkf_obs_cross_cov: NULL argument");
+    FKF_REQUIRE(cov_n(cov) == o->n, "fkf_obs_cross_cov: size mismatch between cov and obs");
+    FKF_REQUIRE(ldp >= o->n, "fkf_obs_cross_cov: leading dimension < n");
+    hipStream_t st = as_stream(stream);
+    DevBuf<double> Ht;
+    Ht.alloc((size_t)o->n * o->n_m);
+    dense_ht(o->rowptr.p, o->col.p, o->val.p, o->n_m, o->n, Ht.p, st);
+    if (!cov_apply_sparse_rows(cov, o->n_m, o->rowptr.p, o->col.p, o->val.p, o->nnz, o->max_row,
+                               Ht.p, P, ldp, st)) {
+      fkf_status rc = fkf_cov_apply(cov, Ht.p, o->n, o->n_m, P, ldp, (void *)st);
+      if (rc != FKF_OK) throw Error{rc, std::string("covariance product failed: ") + fkf_last_error()};
+    }
+    FKF_CHECK_HIP(hipStreamSynchronize(st));   // Ht is released on return
   });
 }
 
@@ -1143,6 +1214,7 @@ static const fkf_obs *boxcox_linearize(fkf_filter *f, const fkf_obs *o, double a
     L->n_m = o->n_m;
     L->n = o->n;
     L->nnz = o->nnz;
+    L->max_row = o->max_row;
     L->noise_h = o->noise_h;
     L->ll_const = o->ll_const;
     L->rowptr.copy_from(o->rowptr.p, (size_t)o->n_m + 1, st);

@@ -141,8 +141,15 @@ struct fkf_cov {
   int64_t n_up_blocks_m = 0;
   fkf::DevBuf<int32_t> up_ptr_m;
   int64_t n_up_items_m = 0, n_part_up_m = 0;
+  // sparse right-hand sides (rows of a sparse matrix as the columns): tree
+  // position of every point and the leaf range [first, end) of every far
+  // cluster; sp_ok when every far cluster is a whole range of leaves
+  fkf::DevBuf<int32_t> iperm, fc_leaf;
+  bool sp_ok = false;
   // workspace
   fkf::DevBuf<double> xt, yt, part, xhat, yhat, part_up, part_pair, part_up_m;
+  fkf::DevBuf<int32_t> sp_tix, sp_cnt;   // sparse rows in tree order, per-leaf counts
+  fkf::DevBuf<double> sp_val;
   // fork/join of the near field onto a second stream
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -1786,6 +1793,27 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
     std::vector<int32_t> ap, ai;
     to_csr(alist, ap, ai);
     cov->fc.upload(fcs, st);
+    {
+      // leaf range of every far cluster and the tree position of every point
+      // (the sparse right-hand sides of the several-column product)
+      std::vector<int32_t> fl(2 * fcs.size());
+      bool ok = n <= (int64_t)INT32_MAX;
+      for (size_t c = 0; c < fcs.size() && ok; ++c) {
+        auto b = std::lower_bound(loff.begin(), loff.end(), fcs[c].begin);
+        auto e = std::lower_bound(loff.begin(), loff.end(), fcs[c].end);
+        ok = b != loff.end() && e != loff.end() && *b == fcs[c].begin && *e == fcs[c].end;
+        fl[2 * c] = (int32_t)(b - loff.begin());
+        fl[2 * c + 1] = (int32_t)(e - loff.begin());
+      }
+      if (ok && !fcs.empty()) {
+        std::vector<int32_t> ip(n);
+        for (int64_t i = 0; i < n; ++i) ip[t.perm[i]] = (int32_t)i;
+        cov->fc_leaf.upload(fl, st);
+        cov->iperm.upload(ip, st);
+        FKF_CHECK_HIP(hipStreamSynchronize(st));   // fl, ip are host temporaries
+        cov->sp_ok = true;
+      }
+    }
     cov->far_ptr.upload(fp, st);
     cov->far_col.upload(fcol, st);
     {
@@ -2078,16 +2106,133 @@ void near_multi(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t s) {
                      cov->blk_t.p, cov->leaf_off.p, cov->n, cov->xt.p, cov->perm.p, nrhs, Y, ldy);
 }
 
+// ------------------------------------------- sparse right-hand sides ---
+// The columns of the several-column product may be the rows of a sparse
+// matrix (the transposed measurement operator: a ray crosses O(sqrt n)
+// cells).  The moments U_c^T X_c of a far cluster c then reduce to sums over
+// the nonzeros inside c, which replaces the upward pass's dense products
+// (the paper applies the covariance to the dense columns; the sums are the
+// same up to rounding order).
+
+// Rows longer than this are not taken by the sparse moments (LDS sort size).
+constexpr int kSpRowMax = 2048;
+
+// One workgroup per row j of the sparse matrix: its entries moved to tree
+// order (position iperm[col]) and sorted ascending (bitonic sort in LDS of
+// the key (position, entry), so equal positions keep their order), written
+// to tix / val at the row's offset; and for every leaf boundary s = 0 ..
+// n_leaves the number of the row's entries in leaves before s,
+// cnt[j (n_leaves + 1) + s].  The host guarantees len <= kSpRowMax.
+__global__ void __launch_bounds__(256) k_sparse_rows(
+    const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+    const double *__restrict__ val, const int32_t *__restrict__ iperm,
+    const int64_t *__restrict__ leaf_off, int n_leaves, int32_t *__restrict__ tix,
+    double *__restrict__ tval, int32_t *__restrict__ cnt) {
+  __shared__ int64_t key[kSpRowMax];
+  const int j = blockIdx.x, tid = threadIdx.x;
+  const int64_t e0 = rowptr[j];
+  const int len = (int)(rowptr[j + 1] - e0);
+  int m = 1;
+  while (m < len) m <<= 1;
+  for (int e = tid; e < m; e += 256)
+    key[e] = e < len ? ((int64_t)iperm[col[e0 + e]] << 32) | e : INT64_MAX;
+  __syncthreads();
+  for (int k = 2; k <= m; k <<= 1)
+    for (int h = k >> 1; h > 0; h >>= 1) {
+      for (int i = tid; i < m; i += 256) {
+        const int x = i ^ h;
+        if (x > i) {
+          const int64_t a = key[i], b = key[x];
+          if ((a > b) == ((i & k) == 0)) {
+            key[i] = b;
+            key[x] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  const int64_t o = e0 - rowptr[0];
+  for (int e = tid; e < len; e += 256) {
+    const int64_t kv = key[e];
+    tix[o + e] = (int32_t)(kv >> 32);
+    tval[o + e] = val[e0 + (kv & 0xffffffff)];
+  }
+  for (int q = tid; q <= n_leaves; q += 256) {
+    const int64_t b = leaf_off[q];
+    int lo = 0, hi = len;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if ((key[mid] >> 32) < b) lo = mid + 1;
+      else hi = mid;
+    }
+    cnt[(int64_t)j * (n_leaves + 1) + q] = lo;
+  }
+}
+
+// Moments of far cluster c = blockIdx.x for four sparse rows per workgroup
+// (rows j0 + 4 blockIdx.y + w, one wavefront each, lanes over the
+// coefficients a): xhat[c.coef_off nrhs + a + pd (j - j0)] = sum over the
+// row's entries (i, v) inside c of v * prod_k l_{a_k}(z_k(x_i)), in the
+// sorted order; the entries inside c are those between the counts at the
+// cluster's first and end leaf.  Rows without entries in c give zeros.
+template <int D>
+__global__ void __launch_bounds__(256) k_up_sparse(
+    const FarCluster *__restrict__ fc, const int32_t *__restrict__ fc_leaf,
+    const double *__restrict__ lag, const int64_t *__restrict__ rowptr, int j0, int nrhs,
+    const int32_t *__restrict__ tix, const double *__restrict__ tval,
+    const int32_t *__restrict__ cnt, int n_leaves, double *__restrict__ xhat) {
+  constexpr int PM = PMax<D>::v;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int jj = blockIdx.y * 4 + w;
+  if (jj >= nrhs) return;
+  const int j = j0 + jj;
+  const FarCluster c = fc[blockIdx.x];
+  const int32_t *cj = cnt + (int64_t)j * (n_leaves + 1);
+  const int64_t base = rowptr[j] - rowptr[0];
+  const int64_t lo = base + cj[fc_leaf[2 * blockIdx.x]];
+  const int64_t hi = base + cj[fc_leaf[2 * blockIdx.x + 1]];
+  double *o = xhat + c.coef_off * nrhs + (int64_t)c.pd * jj;
+  for (int a0 = 0; a0 < c.pd; a0 += 64) {
+    const int a = a0 + l;
+    int dig[D];
+    {
+      int r = a < c.pd ? a : 0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        dig[k] = r % c.p;
+        r /= c.p;
+      }
+    }
+    double acc = 0.0;
+    for (int64_t e = lo; e < hi; ++e) {
+      const double *L = lag + c.lag_off + (int64_t)(tix[e] - c.begin) * D * PM;
+      double b = L[dig[0]];
+#pragma unroll
+      for (int k = 1; k < D; ++k) b *= L[k * PM + dig[k]];
+      acc = fma(tval[e], b, acc);
+    }
+    if (a < c.pd) o[a] = acc;
+  }
+}
+
+// Columns of a several-column product given as sparse rows: row pointers
+// (device) and the first row j0 of the current column block.
+struct SparseRhs {
+  const int64_t *rowptr;
+  int j0;
+};
+
 // Several columns on the FP64 matrix cores: the near field on a forked
 // stream, concurrently with the far-field chain (upward chunks + reduction,
 // couplings per cluster row block); the downward pass then adds to Y.
 template <int D, bool F32>
-void apply_multi_t(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t st) {
+void apply_multi_t(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t st,
+                   const SparseRhs *sp) {
   const int64_t n = cov->n;
   if (cov->n_fc > 0) {
     cov->xhat.reserve((size_t)cov->n_coef * nrhs);
     cov->yhat.reserve((size_t)cov->n_coef * nrhs);
-    cov->part_up_m.reserve((size_t)cov->n_part_up_m * nrhs);
+    if (!sp) cov->part_up_m.reserve((size_t)cov->n_part_up_m * nrhs);
     // near field on the side stream, concurrent with the far-field chain;
     // the downward pass then adds to its result
     ensure_side_stream(cov);
@@ -2098,7 +2243,13 @@ void apply_multi_t(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t s
       near_multi<F32>(cov, nrhs, Y, ldy, cov->side);
     }
     FKF_CHECK_HIP(hipEventRecord(cov->ev_join, cov->side));
-    {
+    if (sp) {
+      FKF_TRACE("hmat_far_up_sparse", st);
+      hipLaunchKernelGGL((k_up_sparse<D>), dim3((unsigned)cov->n_fc, (unsigned)((nrhs + 3) / 4)),
+                         dim3(256), 0, st, cov->fc.p, cov->fc_leaf.p, cov->lag.p, sp->rowptr,
+                         sp->j0, nrhs, cov->sp_tix.p, cov->sp_val.p, cov->sp_cnt.p,
+                         cov->n_leaves, cov->xhat.p);
+    } else {
       FKF_TRACE("hmat_far_up_multi", st);
       hipLaunchKernelGGL((k_up_mfma2<D>),
                          dim3((unsigned)cov->n_up_blocks_m, (unsigned)((nrhs + 511) / 512)),
@@ -2135,12 +2286,15 @@ void apply_multi_t(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t s
                      cov->anc_ptr.p, cov->anc_idx.p, cov->yhat.p, cov->perm.p, nrhs, Y, ldy);
 }
 
-void apply_multi(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t st) {
+void apply_multi(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t st,
+                 const SparseRhs *sp = nullptr) {
   const bool m = cov->mixed;
   if (cov->d == 2)
-    m ? apply_multi_t<2, true>(cov, nrhs, Y, ldy, st) : apply_multi_t<2, false>(cov, nrhs, Y, ldy, st);
+    m ? apply_multi_t<2, true>(cov, nrhs, Y, ldy, st, sp)
+      : apply_multi_t<2, false>(cov, nrhs, Y, ldy, st, sp);
   else
-    m ? apply_multi_t<3, true>(cov, nrhs, Y, ldy, st) : apply_multi_t<3, false>(cov, nrhs, Y, ldy, st);
+    m ? apply_multi_t<3, true>(cov, nrhs, Y, ldy, st, sp)
+      : apply_multi_t<3, false>(cov, nrhs, Y, ldy, st, sp);
 }
 
 }  // namespace
@@ -2182,6 +2336,45 @@ extern "C" fkf_status fkf_cov_apply(fkf_cov *cov, const double *X, int64_t ldx, 
     }
   });
 }
+
+namespace fkf {
+
+bool cov_apply_sparse_rows(fkf_cov *cov, int n_m, const int64_t *rowptr, const int32_t *col,
+                           const double *val, int64_t nnz, int64_t max_row, const double *Xd,
+                           double *Y, int64_t ldy, hipStream_t st) {
+  if (!cov->sp_ok || cov->n_fc == 0 || n_m < 2 || max_row > kSpRowMax) return false;
+  const int64_t n = cov->n;
+  cov->sp_tix.reserve((size_t)std::max<int64_t>(nnz, 1));
+  cov->sp_val.reserve((size_t)std::max<int64_t>(nnz, 1));
+  cov->sp_cnt.reserve((size_t)n_m * (cov->n_leaves + 1));
+  hipLaunchKernelGGL(k_sparse_rows, dim3((unsigned)n_m), dim3(256), 0, st, rowptr, col, val,
+                     cov->iperm.p, cov->leaf_off.p, cov->n_leaves, cov->sp_tix.p, cov->sp_val.p,
+                     cov->sp_cnt.p);
+  FKF_CHECK_HIP(hipGetLastError());
+  // column blocks within the workspace bound, as in the dense product (no
+  // upward partials here; at most 4 * 65535 columns for the moments' grid)
+  const int64_t budget = cov->hp.workspace_bytes > 0 ? cov->hp.workspace_bytes
+                                                      : (int64_t(16) << 30);
+  const int64_t per_col = 8 * (n + 2 * cov->n_coef);
+  const int32_t chunk = (int32_t)std::min<int64_t>(
+      {(int64_t)n_m, std::max<int64_t>(2, budget / per_col), int64_t(4) * 65535});
+  for (int32_t c0 = 0; c0 < n_m; c0 += chunk) {
+    const int32_t nc = std::min(chunk, n_m - c0);
+    cov->xt.reserve((size_t)n * nc);
+    dim3 gg((unsigned)((n + 255) / 256), (unsigned)nc);
+    {
+      FKF_TRACE("hmat_gather", st);
+      hipLaunchKernelGGL(k_gather, gg, dim3(256), 0, st, Xd + n * (int64_t)c0, n, nc, cov->perm.p,
+                         n, cov->xt.p);
+    }
+    const SparseRhs sp{rowptr, c0};
+    apply_multi(cov, nc, Y + ldy * (int64_t)c0, ldy, st, &sp);
+    FKF_CHECK_HIP(hipGetLastError());
+  }
+  return true;
+}
+
+}  // namespace fkf
 
 extern "C" fkf_status fkf_cov_info(const fkf_cov *cov, fkf_cov_info_t *info) {
   return guarded([&] {
