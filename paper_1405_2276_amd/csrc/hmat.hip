@@ -2203,8 +2203,23 @@ __global__ void __launch_bounds__(256) k_up_sparse(
         r /= c.p;
       }
     }
+    // four entries' loads in flight at a time; the sum keeps the sorted order
     double acc = 0.0;
-    for (int64_t e = lo; e < hi; ++e) {
+    int64_t e = lo;
+    for (; e + 4 <= hi; e += 4) {
+      double v[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double *L = lag + c.lag_off + (int64_t)(tix[e + u] - c.begin) * D * PM;
+        v[u] = tval[e + u];
+        b[u] = L[dig[0]];
+#pragma unroll
+        for (int k = 1; k < D; ++k) b[u] *= L[k * PM + dig[k]];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = fma(v[u], b[u], acc);
+    }
+    for (; e < hi; ++e) {
       const double *L = lag + c.lag_off + (int64_t)(tix[e] - c.begin) * D * PM;
       double b = L[dig[0]];
 #pragma unroll
