@@ -105,11 +105,11 @@ int64_t cov_n(const fkf_cov *cov);
 bool cov_mixed(const fkf_cov *cov);
 int cov_kind(const fkf_cov *cov);
 double cov_length(const fkf_cov *cov);
-// Gamma H^T from the rows of the sparse H (CSR, device; Xd the dense H^T for
-// the near field): false, with nothing queued, where that form does not apply
+// Gamma H^T from the rows of the sparse H (CSR, device): false, with nothing
+// queued, where that form does not apply
 bool cov_apply_sparse_rows(fkf_cov *cov, int n_m, const int64_t *rowptr, const int32_t *col,
-                           const double *val, int64_t nnz, int64_t max_row, const double *Xd,
-                           double *Y, int64_t ldy, hipStream_t st);
+                           const double *val, int64_t nnz, int64_t max_row, double *Y,
+                           int64_t ldy, hipStream_t st);
 
 static std::atomic<uint64_t> g_obs_gen{1};
 
@@ -518,16 +518,20 @@ static void gemv_seg(const fkf_filter *f, const double *z, bool square, hipStrea
   gemv_seg_m(f->U0.p, f->ldu, f->n_m, f->n, z, square, f->part.p, st);
 }
 
-// P = Gamma H^T (ld n): the several-column product with the far-cluster
-// moments summed over the nonzeros of H where that form applies, else the
-// product with the dense H^T.
-static void cross_cov(fkf_cov *cov, const fkf_obs *o, const double *Ht, double *P,
-                      hipStream_t st) {
+// P = Gamma H^T (n x n_m, leading dimension ldp): the several-column product
+// taking its columns as the sparse rows of H where that form applies, else
+// the product with the dense H^T (in Ht: formed here unless ht_ready).
+static void cross_cov(fkf_cov *cov, const fkf_obs *o, DevBuf<double> &Ht, double *P,
+                      int64_t ldp, hipStream_t st, bool ht_ready = false) {
   const int64_t n = o->n;
-  if (cov_apply_sparse_rows(cov, o->n_m, o->rowptr.p, o->col.p, o->val.p, o->nnz, o->max_row, Ht,
-                            P, n, st))
+  if (cov_apply_sparse_rows(cov, o->n_m, o->rowptr.p, o->col.p, o->val.p, o->nnz, o->max_row, P,
+                            ldp, st))
     return;
-  fkf_status rc = fkf_cov_apply(cov, Ht, n, o->n_m, P, n, (void *)st);
+  if (!ht_ready) {
+    Ht.reserve((size_t)n * o->n_m);
+    dense_ht(o->rowptr.p, o->col.p, o->val.p, o->n_m, n, Ht.p, st);
+  }
+  fkf_status rc = fkf_cov_apply(cov, Ht.p, n, o->n_m, P, ldp, (void *)st);
   if (rc != FKF_OK) throw Error{rc, std::string("covariance product failed: ") + fkf_last_error()};
 }
 
@@ -541,16 +545,16 @@ static void compute_gep(fkf_filter *f, const fkf_obs *o, DevBuf<double> &Ht, Dev
                         DevBuf<double> &We, hipStream_t st) {
   const int64_t n = f->n;
   const int nm = o->n_m;
-  Ht.reserve((size_t)n * nm);
   P.reserve((size_t)n * nm);
   G.reserve((size_t)nm * nm);
   A.reserve((size_t)nm * nm);
   lam.reserve(nm);
   We.reserve((size_t)nm * nm);
+  Ht.reserve((size_t)n * nm);   // the dense H^T, also used after the eigensolve
   dense_ht(o->rowptr.p, o->col.p, o->val.p, nm, n, Ht.p, st);
   {
     FKF_TRACE("gep_cross_cov", st);
-    cross_cov(f->cov, o, Ht.p, P.p, st);
+    cross_cov(f->cov, o, Ht, P.p, n, st, true);
   }
   innovation_gram(o->rowptr.p, o->col.p, o->val.p, nm, n, P.p, o->noise.p, G.p, A.p, st);
   {
@@ -639,17 +643,14 @@ static void build_bases(fkf_filter *const *fs, const fkf_obs *const *os, int cou
     const int64_t n = f->n;
     const int nm = o->n_m;
     hipStream_t si = sti(i);
-    DevBuf<double> &Ht = bw[i].Ht;
-    Ht.reserve((size_t)n * nm);
     bw[i].P.reserve((size_t)n * nm);
     bw[i].G.reserve((size_t)nm * nm);
     bw[i].A.reserve((size_t)nm * nm);
     f->lam.alloc(nm);
     f->Ve.alloc((size_t)nm * nm);
-    dense_ht(o->rowptr.p, o->col.p, o->val.p, nm, n, Ht.p, si);
     {
       FKF_TRACE("gep_cross_cov", si);
-      cross_cov(f->cov, o, Ht.p, bw[i].P.p, si);
+      cross_cov(f->cov, o, bw[i].Ht, bw[i].P.p, n, si);
     }
     innovation_gram(o->rowptr.p, o->col.p, o->val.p, nm, n, bw[i].P.p, o->noise.p, bw[i].G.p,
                     bw[i].A.p, si);
@@ -683,6 +684,8 @@ static void build_bases(fkf_filter *const *fs, const fkf_obs *const *os, int cou
       // Ad = X^T (dGamma/d ell) X with X = H^T Ve; Cd starts at alpha Ad
       FKF_TRACE("loglik_length_setup", si);
       bw[i].X.reserve((size_t)n * nm);
+      bw[i].Ht.reserve((size_t)n * nm);
+      dense_ht(o->rowptr.p, o->col.p, o->val.p, nm, n, bw[i].Ht.p, si);
       gemm_nn(n, nm, nm, bw[i].Ht.p, n, f->Ve.p, nm, bw[i].X.p, n, si);
       fkf_status rc = fkf_cov_apply(f->dcov, bw[i].X.p, n, nm, bw[i].P.p, n, (void *)si);
       if (rc != FKF_OK) throw Error{rc, std::string("derivative product failed: ") + fkf_last_error()};
@@ -1092,14 +1095,8 @@ extern "C" fkf_status fkf_obs_cross_cov(fkf_cov *cov, const fkf_obs *o, double *
     FKF_REQUIRE(cov_n(cov) == o->n, "fkf_obs_cross_cov: size mismatch between cov and obs");
     FKF_REQUIRE(ldp >= o->n, "fkf_obs_cross_cov: leading dimension < n");
     hipStream_t st = as_stream(stream);
-    DevBuf<double> Ht;
-    Ht.alloc((size_t)o->n * o->n_m);
-    dense_ht(o->rowptr.p, o->col.p, o->val.p, o->n_m, o->n, Ht.p, st);
-    if (!cov_apply_sparse_rows(cov, o->n_m, o->rowptr.p, o->col.p, o->val.p, o->nnz, o->max_row,
-                               Ht.p, P, ldp, st)) {
-      fkf_status rc = fkf_cov_apply(cov, Ht.p, o->n, o->n_m, P, ldp, (void *)st);
-      if (rc != FKF_OK) throw Error{rc, std::string("covariance product failed: ") + fkf_last_error()};
-    }
+    DevBuf<double> Ht;   // dense H^T, only where the sparse form does not apply
+    cross_cov(cov, o, Ht, P, ldp, st);
     FKF_CHECK_HIP(hipStreamSynchronize(st));   // Ht is released on return
   });
 }

@@ -109,6 +109,7 @@ struct fkf_cov {
   bool mixed = false;
   fkf::DevBuf<int32_t> part_ptr, part_idx;   // per leaf: entries blk*2 + side
   fkf::DevBuf<int32_t> near_ptr, near_idx;   // per leaf: entries blk*2 + transposed
+  fkf::DevBuf<int32_t> near_src;             // source leaf of each near_idx entry
   // tiles of the ordered near pairs (near_idx order) in FP64 MFMA A-operand
   // order, for the several-column product (FP32 in the mixed mode)
   fkf::DevBuf<double> frag;
@@ -1716,6 +1717,16 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
     cov->part_idx.upload(pi, st);
     cov->near_ptr.upload(np_, st);
     cov->near_idx.upload(ni, st);
+    {
+      // source leaf of every ordered near pair (near_idx order)
+      std::vector<int32_t> nsrc(ni.size());
+      for (size_t e = 0; e < ni.size(); ++e) {
+        const int64_t b = ni[e] >> 1;
+        nsrc[e] = (ni[e] & 1) ? bs2[b] : bt2[b];
+      }
+      cov->near_src.upload(nsrc, st);
+      FKF_CHECK_HIP(hipStreamSynchronize(st));   // nsrc is a host temporary
+    }
     cov->mixed = hp->precision == FKF_MIXED;
     if (cov->mixed) {
       cov->blk32.alloc((size_t)cov->n_blk * 4096);
@@ -2230,6 +2241,46 @@ __global__ void __launch_bounds__(256) k_up_sparse(
   }
 }
 
+// Near field of the several-column product for sparse columns:
+// Y[perm[s0 + i], j - j0] = sum over the near pairs e = (s, t) of target leaf
+// s, in list order, of sum over row j's entries (p, v) inside leaf t, in
+// sorted order, of A_st[i, p - t0] v, with the entries of A_st read from the
+// repacked tiles (the values the dense near field multiplies; entry (i, k) of
+// tile e at e 4096 + (i / 16) 1024 + (k / 4) 64 + (k % 4) 16 + i % 16).  One
+// workgroup per (target leaf s = blockIdx.x, 4 rows), one wavefront per row
+// j, lanes over the leaf's points.  Rows without entries near s give zeros.
+template <typename TT>
+__global__ void __launch_bounds__(256) k_near_sparse(
+    const TT *__restrict__ frag, const int32_t *__restrict__ near_ptr,
+    const int32_t *__restrict__ near_src, const int64_t *__restrict__ leaf_off,
+    const int64_t *__restrict__ rowptr, int j0, int nrhs, const int32_t *__restrict__ tix,
+    const double *__restrict__ tval, const int32_t *__restrict__ cnt, int n_leaves,
+    const int64_t *__restrict__ perm, double *__restrict__ Y, int64_t ldy) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int jj = blockIdx.y * 4 + w;
+  if (jj >= nrhs) return;
+  const int s = blockIdx.x, j = j0 + jj;
+  const int e0 = near_ptr[s], e1 = near_ptr[s + 1];
+  const int64_t s0 = leaf_off[s], ms = leaf_off[s + 1] - s0;
+  const int32_t *cj = cnt + (int64_t)j * (n_leaves + 1);
+  const int64_t base = rowptr[j] - rowptr[0];
+  const int ir = l < ms ? l : 0;
+  const int64_t rowoff = (ir >> 4) * 1024 + (ir & 15);
+  double acc = 0.0;
+  for (int e = e0; e < e1; ++e) {
+    const int t = near_src[e];
+    const int64_t lo = base + cj[t], hi = base + cj[t + 1];
+    if (lo == hi) continue;
+    const int64_t t0 = leaf_off[t];
+    const TT *A = frag + (int64_t)e * 4096 + rowoff;
+    for (int64_t h = lo; h < hi; ++h) {
+      const int k = (int)(tix[h] - t0);
+      acc = fma((double)A[(k >> 2) * 64 + (k & 3) * 16], tval[h], acc);
+    }
+  }
+  if (l < ms) Y[perm[s0 + l] + ldy * (int64_t)jj] = acc;
+}
+
 // Columns of a several-column product given as sparse rows: row pointers
 // (device) and the first row j0 of the current column block.
 struct SparseRhs {
@@ -2253,7 +2304,15 @@ void apply_multi_t(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t s
     ensure_side_stream(cov);
     FKF_CHECK_HIP(hipEventRecord(cov->ev_fork, st));
     FKF_CHECK_HIP(hipStreamWaitEvent(cov->side, cov->ev_fork, 0));
-    {
+    if (sp) {
+      FKF_TRACE("hmat_near_sparse", cov->side);
+      typedef typename std::conditional<F32, float, double>::type TT;
+      const TT *frag = F32 ? (const TT *)cov->frag32.p : (const TT *)cov->frag.p;
+      hipLaunchKernelGGL(k_near_sparse<TT>, dim3(cov->n_leaves, (unsigned)((nrhs + 3) / 4)),
+                         dim3(256), 0, cov->side, frag, cov->near_ptr.p, cov->near_src.p,
+                         cov->leaf_off.p, sp->rowptr, sp->j0, nrhs, cov->sp_tix.p,
+                         cov->sp_val.p, cov->sp_cnt.p, cov->n_leaves, cov->perm.p, Y, ldy);
+    } else {
       FKF_TRACE("hmat_near_multi", cov->side);
       near_multi<F32>(cov, nrhs, Y, ldy, cov->side);
     }
@@ -2355,10 +2414,9 @@ extern "C" fkf_status fkf_cov_apply(fkf_cov *cov, const double *X, int64_t ldx, 
 namespace fkf {
 
 bool cov_apply_sparse_rows(fkf_cov *cov, int n_m, const int64_t *rowptr, const int32_t *col,
-                           const double *val, int64_t nnz, int64_t max_row, const double *Xd,
-                           double *Y, int64_t ldy, hipStream_t st) {
+                           const double *val, int64_t nnz, int64_t max_row, double *Y,
+                           int64_t ldy, hipStream_t st) {
   if (!cov->sp_ok || cov->n_fc == 0 || n_m < 2 || max_row > kSpRowMax) return false;
-  const int64_t n = cov->n;
   cov->sp_tix.reserve((size_t)std::max<int64_t>(nnz, 1));
   cov->sp_val.reserve((size_t)std::max<int64_t>(nnz, 1));
   cov->sp_cnt.reserve((size_t)n_m * (cov->n_leaves + 1));
@@ -2366,22 +2424,15 @@ bool cov_apply_sparse_rows(fkf_cov *cov, int n_m, const int64_t *rowptr, const i
                      cov->iperm.p, cov->leaf_off.p, cov->n_leaves, cov->sp_tix.p, cov->sp_val.p,
                      cov->sp_cnt.p);
   FKF_CHECK_HIP(hipGetLastError());
-  // column blocks within the workspace bound, as in the dense product (no
-  // upward partials here; at most 4 * 65535 columns for the moments' grid)
+  // column blocks within the workspace bound, as in the dense product (only
+  // the coefficient vectors here; at most 4 * 65535 columns for the grids)
   const int64_t budget = cov->hp.workspace_bytes > 0 ? cov->hp.workspace_bytes
                                                       : (int64_t(16) << 30);
-  const int64_t per_col = 8 * (n + 2 * cov->n_coef);
+  const int64_t per_col = 8 * 2 * cov->n_coef;
   const int32_t chunk = (int32_t)std::min<int64_t>(
       {(int64_t)n_m, std::max<int64_t>(2, budget / per_col), int64_t(4) * 65535});
   for (int32_t c0 = 0; c0 < n_m; c0 += chunk) {
     const int32_t nc = std::min(chunk, n_m - c0);
-    cov->xt.reserve((size_t)n * nc);
-    dim3 gg((unsigned)((n + 255) / 256), (unsigned)nc);
-    {
-      FKF_TRACE("hmat_gather", st);
-      hipLaunchKernelGGL(k_gather, gg, dim3(256), 0, st, Xd + n * (int64_t)c0, n, nc, cov->perm.p,
-                         n, cov->xt.p);
-    }
     const SparseRhs sp{rowptr, c0};
     apply_multi(cov, nc, Y + ldy * (int64_t)c0, ldy, st, &sp);
     FKF_CHECK_HIP(hipGetLastError());

@@ -1,5 +1,6 @@
-"""GPU parity of the cross covariance Gamma H^T (fkf_obs_cross_cov), whose
-far-cluster moments are summed over the nonzeros of the sparse H, against
+"""GPU parity of the cross covariance Gamma H^T (fkf_obs_cross_cov), which
+takes the columns H^T as the sparse rows of H (near field and far-cluster
+moments summed over the nonzeros of H), against
 the several-column product of the same operator with the dense H^T
 (fkf_cov_apply) and against the direct oracle.
 
@@ -118,16 +119,15 @@ def test_cross_cov_mixed_precision():
 
 
 def test_cross_cov_column_blocks_under_workspace_bound():
-    # a workspace bound that allows a few columns per block: several blocks,
-    # the last one ragged
+    # a workspace bound that allows 7 columns per block (the sparse form keeps
+    # two coefficient vectors per column): several blocks, the last one ragged
     import paper_1405_2276_amd as fkf
     c = CASES["rays-64x64"]
     pts = c["pts"]()
-    n = len(pts)
     cov0 = fkf.Cov(pts, nu=c["nu"], length=c["ell"], variance=c["theta"], leaf_size=c["leaf"])
     ncoef = cov0.info()["far_coef_per_rhs"]
     cov = fkf.Cov(pts, nu=c["nu"], length=c["ell"], variance=c["theta"], leaf_size=c["leaf"],
-                  workspace_bytes=8 * (n + 2 * ncoef) * 7)
+                  workspace_bytes=8 * 2 * ncoef * 7)
     obs = c["obs"](fkf)
     H, Htd = _dense_ht(fkf, obs)
     assert H.shape[0] % 7 != 0
