@@ -150,6 +150,7 @@ struct fkf_cov {
   // workspace
   fkf::DevBuf<double> xt, yt, part, xhat, yhat, part_up, part_pair, part_up_m;
   fkf::DevBuf<int32_t> sp_tix, sp_cnt;   // sparse rows in tree order, per-leaf counts
+  fkf::DevBuf<int32_t> sp_nzb;           // nonzero 16-column blocks of the moments
   fkf::DevBuf<double> sp_val;
   // fork/join of the near field onto a second stream
   hipStream_t side = nullptr;
@@ -1351,7 +1352,8 @@ __global__ void __launch_bounds__(512) k_couple_mfma2(
     const CoupleMItem *__restrict__ items, const FarCluster *__restrict__ fc,
     const int32_t *__restrict__ far_ptr, const int32_t *__restrict__ far_col,
     const double *__restrict__ cheb, int kind, double inv_ell, double amp,
-    const double *__restrict__ xhat, int nrhs, double *__restrict__ yhat) {
+    const double *__restrict__ xhat, int nrhs, double *__restrict__ yhat,
+    const int32_t *__restrict__ nzb) {
   constexpr int KC = 16, LDK = 18;
   __shared__ double Ks[2][64 * LDK];
   const CoupleMItem it = items[blockIdx.x];
@@ -1398,6 +1400,20 @@ __global__ void __launch_bounds__(512) k_couple_mfma2(
       Ks[buf][er * LDK + ek + h] = (er < rows && kb < ct.pd) ? kv : 0.0;
     }
   };
+  // with nzb (moments of sparse columns: nzb[t ncb16 + b] = 0 when the
+  // 16-column block b of partner t's coefficients is exactly zero): bit j of
+  // the wave-uniform mask is set when block j of this wavefront is nonzero;
+  // zero blocks are not multiplied (their products would add zeros)
+  const int ncb16 = (nrhs + 15) >> 4;
+  auto nz_mask = [&](int e) -> int {
+    if (!nzb) return 0xf;
+    const int32_t *f = nzb + (int64_t)far_col[e] * ncb16 + (c0 >> 4);
+    int m = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (j < ncb && f[j]) m |= 1 << j;
+    return __builtin_amdgcn_readfirstlane(m);
+  };
   auto load_b = [&](int e, int k0, double *b) {
     const FarCluster ct = fc[far_col[e]];
     const double *x = xhat + ct.coef_off * nrhs;
@@ -1419,6 +1435,7 @@ __global__ void __launch_bounds__(512) k_couple_mfma2(
     for (int j = 0; j < 4; ++j) acc[q][j] = v4d{0, 0, 0, 0};
   double bcur[16], bnext[16];
   int e = e0, k0 = 0, buf = 0;
+  int mcur = e < e1 ? nz_mask(e) : 0, mnext = mcur;
   if (e < e1) load_b(e, k0, bcur);
   while (e < e1) {
     eval_chunk(e, k0, buf);
@@ -1427,6 +1444,7 @@ __global__ void __launch_bounds__(512) k_couple_mfma2(
     if (kn >= fc[far_col[e]].pd) {
       ++en;
       kn = 0;
+      if (en < e1) mnext = nz_mask(en);
     }
     if (en < e1) load_b(en, kn, bnext);
     __syncthreads();
@@ -1439,7 +1457,7 @@ __global__ void __launch_bounds__(512) k_couple_mfma2(
           const double a = K[(16 * q + lr) * LDK + 4 * kk + lk];
 #pragma unroll
           for (int j = 0; j < 4; ++j)
-            if (j < ncb) acc[q][j] = mfma4(a, bcur[4 * kk + j], acc[q][j]);
+            if (j < ncb && (mcur >> j & 1)) acc[q][j] = mfma4(a, bcur[4 * kk + j], acc[q][j]);
         }
       }
     }
@@ -1447,6 +1465,7 @@ __global__ void __launch_bounds__(512) k_couple_mfma2(
     for (int i = 0; i < 16; ++i) bcur[i] = bnext[i];
     e = en;
     k0 = kn;
+    mcur = mnext;
     buf ^= 1;
   }
   double *o = yhat + cs.coef_off * nrhs;
@@ -2180,6 +2199,29 @@ __global__ void __launch_bounds__(256) k_sparse_rows(
   }
 }
 
+// Nonzero flags of the sparse moments, one thread per (far cluster c, block
+// b of 16 rows of the current column block): nzb[c ncb16 + b] = 1 when one of
+// the rows j0 + 16 b .. j0 + 16 b + 15 (< j0 + nrhs) has an entry inside c.
+__global__ void __launch_bounds__(256) k_sparse_nzb(const int32_t *__restrict__ fc_leaf,
+                                                    int n_fc, const int32_t *__restrict__ cnt,
+                                                    int n_leaves, int j0, int nrhs,
+                                                    int32_t *__restrict__ nzb) {
+  const int ncb16 = (nrhs + 15) >> 4;
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= (int64_t)n_fc * ncb16) return;
+  const int c = (int)(g / ncb16), b = (int)(g % ncb16);
+  const int L0 = fc_leaf[2 * c], L1 = fc_leaf[2 * c + 1];
+  int any = 0;
+  for (int q = 0; q < 16; ++q) {
+    const int jj = 16 * b + q;
+    if (jj < nrhs) {
+      const int32_t *cj = cnt + (int64_t)(j0 + jj) * (n_leaves + 1);
+      any |= cj[L1] > cj[L0];
+    }
+  }
+  nzb[g] = any;
+}
+
 // Moments of far cluster c = blockIdx.x for four sparse rows per workgroup
 // (rows j0 + 4 blockIdx.y + w, one wavefront each, lanes over the
 // coefficients a): xhat[c.coef_off nrhs + a + pd (j - j0)] = sum over the
@@ -2340,12 +2382,21 @@ void apply_multi_t(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t s
         hipLaunchKernelGGL(k_zero, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st,
                            cov->yhat.p, len);
       }
+      const int32_t *nzb = nullptr;
+      if (sp && cov->n_cm_items > 0) {
+        const int64_t nf = (int64_t)cov->n_fc * ((nrhs + 15) / 16);
+        cov->sp_nzb.reserve((size_t)nf);
+        hipLaunchKernelGGL(k_sparse_nzb, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, st,
+                           cov->fc_leaf.p, cov->n_fc, cov->sp_cnt.p, cov->n_leaves, sp->j0, nrhs,
+                           cov->sp_nzb.p);
+        nzb = cov->sp_nzb.p;
+      }
       if (cov->n_cm_items > 0)
         hipLaunchKernelGGL((k_couple_mfma2<D, F32>),
                            dim3((unsigned)cov->n_cm_items, (unsigned)((nrhs + 511) / 512)),
                            dim3(512), 0, st, cov->cm_items.p, cov->fc.p, cov->far_ptr.p,
                            cov->far_col.p, cov->cheb.p, cov->kind, 1.0 / cov->ell, cov->amp,
-                           cov->xhat.p, nrhs, cov->yhat.p);
+                           cov->xhat.p, nrhs, cov->yhat.p, nzb);
     }
   }
   if (cov->n_fc == 0) {
