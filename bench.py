@@ -327,9 +327,9 @@ def loglik_gradient(fkf, torch, cov, wl, ys, reps=3):
 TRAFFIC_KERNELS = {
     "fkf::k_jacobi_round": "eig_jacobi_round",
     "void fkf::k_couple_mfma2<2, false>": "hmat_far_couple_multi",
-    "void fkf::k_near_mfma<double>": "hmat_near_multi",
+    "void (anonymous namespace)::k_near_sparse<double>": "hmat_near_sparse",
     "void fkf::k_down_mfma2<2>": "hmat_down_multi",
-    "void fkf::k_up_mfma2<2>": "hmat_far_up_multi",
+    "void (anonymous namespace)::k_up_sparse<2>": "hmat_far_up_sparse",
     "void fkf::k_gemv_seg<false>": "filter_gemv",
     "fkf::k_gemm_tall": "gep_basis_gemm",
 }
