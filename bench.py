@@ -593,7 +593,7 @@ def main():
     # ---- roofline of the dominant kernel of the FP64 pass
     per = {k: (c, ms) for k, (c, ms) in trace.items()}
     # entries of the coupling matrices over all ordered admissible pairs
-    k_entries = 2.0 * info["far_bytes"] / 8.0
+    k_entries = 2.0 * info["far_pair_entries"]
     npad = -(-n_m // 32) * 32          # eigensolver: padded order
     ntile = npad // 32                 # block pairs per round = 32-row tiles per column
     models = {

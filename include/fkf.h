@@ -134,9 +134,13 @@ typedef struct {
   int64_t covered_entries;   /* sum of |s|*|t| over all blocks (= n*n for a partition) */
   int64_t far_interp_entries; /* sum over far clusters c of |c| * p_c^dim: interpolation-basis
                                   entries one upward (or downward) pass touches per column */
-  int64_t far_bytes;         /* bytes of the stored coupling matrices K(xi_s, xi_t), one per
-                                unordered admissible pair; 0 when they are evaluated on the
-                                fly (kept only up to 8 GiB) */
+  int64_t far_bytes;         /* bytes of the stored coupling matrices K(xi_t, xi_s), one per
+                                distinct geometry of an ordered admissible pair (s, t)
+                                (pairs whose node counts, half-widths and centre offset
+                                agree to 2^-40 of the extent share one); 0 when they are
+                                evaluated on the fly (kept only up to 8 GiB) */
+  int64_t far_pair_entries;  /* entries of the coupling matrices of all unordered admissible
+                                pairs (the work of one coupling pass per column) */
 } fkf_cov_info_t;
 
 typedef struct fkf_cov fkf_cov;

@@ -65,7 +65,8 @@ class CovInfo(ctypes.Structure):
                 ("n_near_pairs", ctypes.c_int64), ("n_far_pairs", ctypes.c_int64),
                 ("near_bytes", ctypes.c_int64), ("far_coef_per_rhs", ctypes.c_int64),
                 ("cheb_p", ctypes.c_int32 * 32), ("covered_entries", ctypes.c_int64),
-                ("far_interp_entries", ctypes.c_int64), ("far_bytes", ctypes.c_int64)]
+                ("far_interp_entries", ctypes.c_int64), ("far_bytes", ctypes.c_int64),
+                ("far_pair_entries", ctypes.c_int64)]
 
 
 def _sig(name, res, args):

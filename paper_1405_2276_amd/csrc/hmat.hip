@@ -15,6 +15,7 @@
 //     coefficient vectors.
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <cstring>
 #include <memory>
 #include <numeric>
@@ -70,16 +71,6 @@ struct CoupleMItem {
   int32_t s, rb;
 };
 
-// A sub-block of stored couplings with every offset resolved at build, so a
-// wavefront needs one (scalar) descriptor load before streaming K.
-struct CoupleItemSt {
-  int64_t koff;            // K[r0][c0] in the stored couplings
-  int64_t xs_off, xt_off;  // xhat_s[r0], xhat_t[c0]
-  int64_t ys_off, yt_off;  // row-sum and column-sum outputs in the pair partials
-  int32_t rows, cols, ldk; // sub-block extent, row stride of K (= pd_t)
-  int32_t pad;
-};
-
 // Couplings are stored (evaluated once at build) when they take at most this
 // many bytes; otherwise every product evaluates them again.
 constexpr int64_t kMaxCouplingBytes = int64_t(8) << 30;
@@ -125,12 +116,15 @@ struct fkf_cov {
   fkf::DevBuf<fkf::UpItem> up_items;
   fkf::DevBuf<int32_t> up_ptr;               // items of each far cluster
   fkf::DevBuf<fkf::PairItem> pairs;          // unordered admissible pairs (large first)
-  int64_t n_kst = 0;                         // entries of all coupling matrices
+  fkf::DevBuf<fkf::PairItem> upairs;         // one pair per distinct stored coupling matrix
+  int64_t n_upairs = 0;
+  int64_t n_kst = 0;                         // entries of the distinct stored coupling matrices
+  int64_t n_kpair = 0;                       // entries of the coupling matrices of all pairs
   fkf::DevBuf<double> kst;                   // stored couplings (FP64 mode)
   fkf::DevBuf<float> kst32;                  // stored couplings (mixed mode)
   bool stored = false;
   fkf::DevBuf<fkf::CoupleItem> citems;       // 64 x 64 coupling sub-blocks
-  fkf::DevBuf<fkf::CoupleItemSt> citems_st;  // the same sub-blocks, stored couplings
+  fkf::DevBuf<int64_t> far_koff;             // stored matrix of each far list entry
   int64_t n_citems = 0;
   fkf::DevBuf<int32_t> cp_ptr;               // pair partials of each far cluster
   fkf::DevBuf<int64_t> cp_off;
@@ -706,41 +700,47 @@ __global__ void __launch_bounds__(256) k_couple_blk(const CoupleItem *__restrict
   if (col_ok) part_pair[pr.off + (int64_t)ncb * pds + (int64_t)it.rb * pdt + c0 + l] = cacc;
 }
 
-// Stored-coupling variant of k_couple_blk: the same sub-block product with
-// all offsets taken from one descriptor; the 32 row loads of K are issued
-// together from clamped (in-block) addresses and out-of-block entries are
-// zeroed afterwards.
+// One column with stored couplings, target-major: yhat[c.coef_off + a] = sum
+// over the partners t of far cluster c of sum_b K(xi_t, xi_c)[b][a]
+// xhat[t.coef_off + b], the matrix stored (for the geometry of the ordered
+// pair) row-major with the partner's nodes as rows, so that lanes over a read
+// it coalesced.  One workgroup per (far cluster, block of 64 coefficients):
+// wavefront w takes the partners e = w, w + 4, ... of the far list (eight
+// rows of K in flight), and the four partial sums are added in wavefront
+// order through LDS (fixed order, deterministic).
 template <typename KT>
-__global__ void __launch_bounds__(256) k_couple_st(const CoupleItemSt *__restrict__ items,
-                                                   int64_t n_items, const KT *__restrict__ kst,
-                                                   const double *__restrict__ xhat,
-                                                   double *__restrict__ part_pair) {
-  __shared__ double xsv[4][kRowBlk];
+__global__ void __launch_bounds__(256) k_couple_rows1(const FarCluster *__restrict__ fc,
+                                                      const int32_t *__restrict__ far_ptr,
+                                                      const int32_t *__restrict__ far_col,
+                                                      const int64_t *__restrict__ far_koff,
+                                                      const KT *__restrict__ kst,
+                                                      const double *__restrict__ xhat,
+                                                      double *__restrict__ yhat) {
+  __shared__ double ps[4][64];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
-  const int64_t q = (int64_t)blockIdx.x * 4 + w;
-  if (q >= n_items) return;   // whole wavefront leaves together
-  const CoupleItemSt it = items[q];
-  const int rows = it.rows, cols = it.cols, ldk = it.ldk;
-  const bool col_ok = l < cols;
-  const KT *src = kst + it.koff + (col_ok ? l : 0);
-  KT kv[kRowBlk];
+  const int c = blockIdx.x;
+  const FarCluster cs = fc[c];
+  const int a = 64 * blockIdx.y + l;
+  if (64 * (int)blockIdx.y >= cs.pd) return;   // whole workgroup leaves together
+  const int ar = a < cs.pd ? a : 0;
+  double acc = 0.0;
+  for (int e = far_ptr[c] + w; e < far_ptr[c + 1]; e += 4) {
+    const FarCluster ct = fc[far_col[e]];
+    const KT *K = kst + far_koff[e] + ar;
+    const double *x = xhat + ct.coef_off;
+    int b = 0;
+    for (; b + 8 <= ct.pd; b += 8) {
+      double k[8];
 #pragma unroll
-  for (int a = 0; a < kRowBlk; ++a) kv[a] = src[min(a, rows - 1) * ldk];
-  if (l < kRowBlk) xsv[w][l] = l < rows ? xhat[it.xs_off + l] : 0.0;
-  const double xtb = col_ok ? xhat[it.xt_off + l] : 0.0;
-  __builtin_amdgcn_s_waitcnt(0);
-  __builtin_amdgcn_wave_barrier();
-  double v[kRowBlk];
-  double cacc = 0.0;
+      for (int u = 0; u < 8; ++u) k[u] = (double)K[(int64_t)(b + u) * cs.pd];
 #pragma unroll
-  for (int a = 0; a < kRowBlk; ++a) {
-    const double k = (a < rows && col_ok) ? (double)kv[a] : 0.0;
-    v[a] = k * xtb;
-    cacc = fma(k, xsv[w][a], cacc);
+      for (int u = 0; u < 8; ++u) acc = fma(k[u], x[b + u], acc);
+    }
+    for (; b < ct.pd; ++b) acc = fma((double)K[(int64_t)b * cs.pd], x[b], acc);
   }
-  FKF_ROW_SUMS_32(v, l);
-  if (l < rows) part_pair[it.ys_off + l] = v[0];
-  if (col_ok) part_pair[it.yt_off + l] = cacc;
+  ps[w][l] = acc;
+  __syncthreads();
+  if (w == 0 && a < cs.pd) yhat[cs.coef_off + a] = ((ps[0][l] + ps[1][l]) + ps[2][l]) + ps[3][l];
 }
 
 // Build-time evaluation of the coupling matrices K(xi_s, xi_t) of every
@@ -1627,6 +1627,41 @@ __global__ void __launch_bounds__(512) k_near_mfma(
 // ------------------------------------------------------------------ host ---
 using namespace fkf;
 
+namespace {
+
+// Stored coupling matrices are shared by pairs of the same geometry:
+// K(xi_s, xi_t) depends on a pair of boxes only through the node counts, the
+// half-widths and the offset of the two box centres.  coupling_quantum gives
+// the scale that maps lengths to integers of 2^-40 of the extent of the
+// boxes; coupling_key the key of the pair (a, b) with p_a, p_b nodes per
+// dimension.  Pairs with equal keys point at one stored matrix.
+double coupling_quantum(int d, const std::vector<const double *> &ctr,
+                        const std::vector<const double *> &hw) {
+  double ext = 0.0;
+  for (int k = 0; k < d; ++k) {
+    double lo = INFINITY, hi = -INFINITY;
+    for (size_t c = 0; c < ctr.size(); ++c) {
+      lo = std::min(lo, ctr[c][k] - hw[c][k]);
+      hi = std::max(hi, ctr[c][k] + hw[c][k]);
+    }
+    ext = std::max(ext, hi - lo);
+  }
+  return ext > 0 ? std::ldexp(1.0, 40) / ext : 0.0;
+}
+
+std::vector<int64_t> coupling_key(int d, int pa, int pb, const double *ca, const double *ha,
+                                  const double *cb, const double *hb, double q) {
+  std::vector<int64_t> key{pa, pb};
+  for (int k = 0; k < d; ++k) {
+    key.push_back(std::llround((ca[k] - cb[k]) * q));
+    key.push_back(std::llround(ha[k] * q));
+    key.push_back(std::llround(hb[k] * q));
+  }
+  return key;
+}
+
+}  // namespace
+
 extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d,
                                     const fkf_kernel_params *kp, const fkf_hmat_params *hp,
                                     void *stream, fkf_cov **out) {
@@ -1796,8 +1831,14 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
       fcs.push_back(c);
       return fidx[node];
     };
+    // far clusters numbered in order of first appearance in the pair list
+    // (first member before second); the plan numbers them the same way
     std::vector<std::pair<int, int>> fpairs;
-    for (auto &pr : far) fpairs.emplace_back(far_id(pr.first), far_id(pr.second));
+    for (auto &pr : far) {
+      const int a = far_id(pr.first);
+      const int b = far_id(pr.second);
+      fpairs.emplace_back(a, b);
+    }
     cov->n_fc = (int)fcs.size();
     int64_t off = 0;
     int64_t lag_total = 0;
@@ -1929,6 +1970,41 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
       }
       std::vector<std::vector<int64_t>> cpl(cov->n_fc);
       int64_t off = 0, n_lt = 0, n_gt = 0, koff = 0;
+      // stored coupling matrices, one per geometry of an ordered pair (target
+      // c, partner t): K(xi_t, xi_c) row-major with the partner's nodes as
+      // rows; far list entries of the same geometry share it
+      double qscale;
+      {
+        std::vector<const double *> cs, hs;
+        for (const FarCluster &c : fcs) {
+          cs.push_back(c.ctr);
+          hs.push_back(c.hw);
+        }
+        qscale = coupling_quantum(d, cs, hs);
+      }
+      std::map<std::vector<int64_t>, int64_t> kshape;
+      std::vector<PairItem> uprs;
+      std::vector<int64_t> fko(fcol.size());
+      for (int c = 0; c < cov->n_fc; ++c)
+        for (int e = fp[c]; e < fp[c + 1]; ++e) {
+          const FarCluster &tg = fcs[c], &pt = fcs[fcol[e]];
+          std::vector<int64_t> key = coupling_key(d, pt.p, tg.p, pt.ctr, pt.hw, tg.ctr, tg.hw,
+                                                  qscale);
+          auto it = kshape.find(key);
+          if (it != kshape.end()) {
+            fko[e] = it->second;
+          } else {
+            PairItem q{};
+            q.s = fcol[e];
+            q.t = c;
+            q.koff = koff;
+            uprs.push_back(q);
+            kshape.emplace(std::move(key), koff);
+            fko[e] = koff;
+            koff += (int64_t)pt.pd * tg.pd;
+          }
+        }
+      int64_t n_kpair = 0;
       for (auto &pr : fpairs) {
         if (pr.first < pr.second) {
           ++n_lt;
@@ -1938,7 +2014,6 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
           q.s = pr.first;
           q.t = pr.second;
           q.off = off;
-          q.koff = koff;
           for (int cb = 0; cb < ncb; ++cb) cpl[pr.first].push_back(off + (int64_t)cb * pds);
           for (int rb = 0; rb < nrb; ++rb)
             cpl[pr.second].push_back(off + (int64_t)ncb * pds + (int64_t)rb * pdt);
@@ -1946,7 +2021,7 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
             for (int cb = 0; cb < ncb; ++cb)
               cis.push_back(CoupleItem{(int32_t)prs.size(), (int16_t)rb, (int16_t)cb});
           off += (int64_t)ncb * pds + (int64_t)nrb * pdt;
-          koff += (int64_t)pds * pdt;
+          n_kpair += (int64_t)pds * pdt;
           prs.push_back(q);
         } else {
           ++n_gt;
@@ -1954,11 +2029,16 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
       }
       if (n_lt != n_gt) throw Error{FKF_E_ARG, "fkf_cov_build: admissible pairs are not symmetric"};
       cov->n_kst = koff;
+      cov->n_kpair = n_kpair;
       cov->n_pairs = (int64_t)prs.size();
       cov->n_part_pair = off;
       cov->n_citems = (int64_t)cis.size();
       cov->citems.upload(cis, st);
       cov->pairs.upload(prs, st);
+      cov->n_upairs = (int64_t)uprs.size();
+      cov->upairs.upload(uprs, st);
+      cov->far_koff.upload(fko, st);
+      FKF_CHECK_HIP(hipStreamSynchronize(st));   // prs, uprs, fko are host temporaries
       std::vector<int32_t> cptr(1, 0);
       std::vector<int64_t> coff;
       for (auto &v : cpl) {
@@ -1995,7 +2075,7 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
         dst = cov->kst.p;
       }
       auto store = [&](auto kern) {
-        hipLaunchKernelGGL(kern, dim3((unsigned)cov->n_pairs), dim3(256), 0, st, cov->pairs.p,
+        hipLaunchKernelGGL(kern, dim3((unsigned)cov->n_upairs), dim3(256), 0, st, cov->upairs.p,
                            cov->fc.p, cov->cheb.p, cov->kind, 1.0 / cov->ell, cov->amp, dst);
       };
       if (d == 3)
@@ -2003,25 +2083,6 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
       else
         cov->mixed ? store(k_couple_store<2, true>) : store(k_couple_store<2, false>);
       cov->stored = true;
-      std::vector<CoupleItemSt> cst;
-      cst.reserve(cis.size());
-      for (const CoupleItem &ci : cis) {
-        const PairItem &q = prs[ci.pair];
-        const int pds = fcs[q.s].pd, pdt = fcs[q.t].pd;
-        const int ncb = (pdt + 63) / 64;
-        const int r0 = kRowBlk * ci.rb, c0 = 64 * ci.cb;
-        CoupleItemSt e{};
-        e.koff = q.koff + (int64_t)r0 * pdt + c0;
-        e.xs_off = fcs[q.s].coef_off + r0;
-        e.xt_off = fcs[q.t].coef_off + c0;
-        e.ys_off = q.off + (int64_t)ci.cb * pds + r0;
-        e.yt_off = q.off + (int64_t)ncb * pds + (int64_t)ci.rb * pdt + c0;
-        e.rows = std::min(kRowBlk, pds - r0);
-        e.cols = std::min(64, pdt - c0);
-        e.ldk = pdt;
-        cst.push_back(e);
-      }
-      cov->citems_st.upload(cst, st);
     }
     FKF_CHECK_HIP(hipStreamSynchronize(st));
     *out = cov.release();
@@ -2089,14 +2150,16 @@ void apply_one(fkf_cov *cov, double *Y, hipStream_t st) {
                            cov->kind, 1.0 / cov->ell, cov->amp, cov->xhat.p,
                            cov->part_pair.p);
       };
-      const unsigned gc = (unsigned)((cov->n_citems + 3) / 4);
-      if (cov->stored && cov->n_citems > 0) {
+      if (cov->stored) {
+        const dim3 g((unsigned)cov->n_fc, (unsigned)((cov->max_pd + 63) / 64));
         if (cov->mixed)
-          hipLaunchKernelGGL(k_couple_st<float>, dim3(gc), dim3(256), 0, st, cov->citems_st.p,
-                             cov->n_citems, cov->kst32.p, cov->xhat.p, cov->part_pair.p);
+          hipLaunchKernelGGL(k_couple_rows1<float>, g, dim3(256), 0, st, cov->fc.p,
+                             cov->far_ptr.p, cov->far_col.p, cov->far_koff.p, cov->kst32.p,
+                             cov->xhat.p, cov->yhat.p);
         else
-          hipLaunchKernelGGL(k_couple_st<double>, dim3(gc), dim3(256), 0, st, cov->citems_st.p,
-                             cov->n_citems, cov->kst.p, cov->xhat.p, cov->part_pair.p);
+          hipLaunchKernelGGL(k_couple_rows1<double>, g, dim3(256), 0, st, cov->fc.p,
+                             cov->far_ptr.p, cov->far_col.p, cov->far_koff.p, cov->kst.p,
+                             cov->xhat.p, cov->yhat.p);
       } else {
         const int sel = (d3 ? 2 : 0) + (cov->mixed ? 1 : 0);
         switch (sel) {
@@ -2105,9 +2168,10 @@ void apply_one(fkf_cov *cov, double *Y, hipStream_t st) {
           case 2: launch(k_couple_blk<3, false>); break;
           default: launch(k_couple_blk<3, true>); break;
         }
+        hipLaunchKernelGGL(k_couple_reduce, dim3((cov->n_fc + 3) / 4), dim3(256), 0, st,
+                           cov->fc.p, cov->n_fc, cov->cp_ptr.p, cov->cp_off.p, cov->part_pair.p,
+                           cov->yhat.p);
       }
-      hipLaunchKernelGGL(k_couple_reduce, dim3((cov->n_fc + 3) / 4), dim3(256), 0, st, cov->fc.p,
-                         cov->n_fc, cov->cp_ptr.p, cov->cp_off.p, cov->part_pair.p, cov->yhat.p);
     }
   }
   FKF_CHECK_HIP(hipStreamWaitEvent(st, cov->ev_join, 0));
@@ -2509,6 +2573,7 @@ extern "C" fkf_status fkf_cov_info(const fkf_cov *cov, fkf_cov_info_t *info) {
         cov->stored ? cov->n_kst * (int64_t)(cov->mixed ? sizeof(float) : sizeof(double)) : 0;
     info->far_coef_per_rhs = cov->n_coef;
     info->far_interp_entries = cov->n_interp;
+    info->far_pair_entries = cov->n_kpair;
     for (int l = 0; l < 32 && l < (int)cov->level_p.size(); ++l) info->cheb_p[l] = cov->level_p[l];
     info->covered_entries = cov->covered;
   });
@@ -2556,18 +2621,42 @@ extern "C" fkf_status fkf_cov_plan(const double *pts_host, int64_t n, int32_t d,
       if (t.nodes[pr.first].leaf <= t.nodes[pr.second].leaf) ++nb;
       cov += t.nodes[pr.first].size() * t.nodes[pr.second].size();
     }
-    int64_t nk = 0;
-    for (auto &pr : far) {
-      cov += t.nodes[pr.first].size() * t.nodes[pr.second].size();
-      if (pr.first < pr.second) {
+    int64_t nk = 0, nk_all = 0;
+    {
+      // as at build: one stored matrix per distinct pair geometry
+      std::vector<char> isf(t.nodes.size(), 0);
+      for (auto &pr : far) isf[pr.first] = isf[pr.second] = 1;
+      std::vector<double> ctr(t.nodes.size() * kMaxDim, 0.0), hw(t.nodes.size() * kMaxDim, 0.0);
+      std::vector<const double *> cs, hs;
+      for (size_t nd = 0; nd < t.nodes.size(); ++nd) {
+        for (int k = 0; k < d; ++k) {
+          ctr[nd * kMaxDim + k] = 0.5 * (t.nodes[nd].lo[k] + t.nodes[nd].hi[k]);
+          hw[nd * kMaxDim + k] = 0.5 * (t.nodes[nd].hi[k] - t.nodes[nd].lo[k]);
+        }
+        if (isf[nd]) {
+          cs.push_back(&ctr[nd * kMaxDim]);
+          hs.push_back(&hw[nd * kMaxDim]);
+        }
+      }
+      const double q = coupling_quantum(d, cs, hs);
+      // one stored matrix per geometry of an ordered pair (target, partner),
+      // keyed as at build with the partner's nodes as rows
+      std::map<std::vector<int64_t>, int> shapes;
+      for (auto &pr : far) {
+        cov += t.nodes[pr.first].size() * t.nodes[pr.second].size();
+        const int pt = lp[t.nodes[pr.first].level], pp = lp[t.nodes[pr.second].level];
         int64_t a = 1, b = 1;
         for (int k = 0; k < d; ++k) {
-          a *= lp[t.nodes[pr.first].level];
-          b *= lp[t.nodes[pr.second].level];
+          a *= pt;
+          b *= pp;
         }
-        nk += a * b;
+        if (pr.first < pr.second) nk_all += a * b;
+        const size_t i = (size_t)pr.second * kMaxDim, j = (size_t)pr.first * kMaxDim;
+        if (shapes.emplace(coupling_key(d, pp, pt, &ctr[i], &hw[i], &ctr[j], &hw[j], q), 0).second)
+          nk += a * b;
       }
     }
+    info->far_pair_entries = nk_all;
     {
       std::vector<char> is_far(t.nodes.size(), 0);
       for (auto &pr : far) is_far[pr.first] = is_far[pr.second] = 1;

@@ -63,12 +63,24 @@ def test_headline_grid_partition_is_the_3x3_leaf_neighbourhood():
                      precision="mixed")
     assert mixed["near_bytes"] * 2 == info["near_bytes"]
     assert mixed["cheb_p"] == info["cheb_p"]
-    # stored couplings: one pd_s x pd_t matrix per unordered admissible pair,
-    # at least the smallest order's p^4 entries per pair
+    # coupling matrices: at least the smallest order's p^4 entries for every
+    # unordered admissible pair; stored once per distinct geometry of an
+    # ordered pair, which on this regular grid is a small fraction of them
     assert info["far_bytes"] == 2 * mixed["far_bytes"] > 0
-    assert info["far_bytes"] >= 8 * (info["n_far_pairs"] // 2) * min(info["cheb_p"]) ** 4
+    assert info["far_pair_entries"] >= (info["n_far_pairs"] // 2) * min(info["cheb_p"]) ** 4
+    assert info["far_bytes"] < 8 * info["far_pair_entries"] // 10
     ev = fkf.plan(wl.points(), nu=wl.nu, length=wl.length, variance=wl.variance, far_eval=True)
     assert ev["far_bytes"] == 0 and ev["near_bytes"] == info["near_bytes"]
+
+
+def test_plan_stores_every_coupling_of_irregular_points():
+    # boxes of random points never repeat a geometry: one stored matrix per
+    # ordered admissible pair (both orientations of every unordered one)
+    import paper_1405_2276_amd as fkf
+    pts = np.random.default_rng(3).uniform(0, 1, (6000, 2))
+    info = fkf.plan(pts, nu=1.5, length=0.15, variance=1.0)
+    assert info["n_far_pairs"] > 0
+    assert info["far_bytes"] == 2 * 8 * info["far_pair_entries"]
 
 
 @pytest.mark.parametrize("shape,nsrc,nrcv", [((32, 32), 8, 8), ((128, 128), 16, 15),

@@ -64,16 +64,27 @@ def test_hmatvec_matches_direct(name, nrhs):
     assert err <= TOL
 
 
+@pytest.mark.parametrize("points", ["grid-96x72", "irregular-5000"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_stored_and_evaluated_couplings_agree(precision):
-    # the far field with couplings stored at build and evaluated in every
-    # product: the same entries, so the products agree to rounding
+def test_stored_and_evaluated_couplings_agree(precision, points):
+    # the far field with couplings stored at build (one matrix per distinct
+    # geometry of an ordered pair: shared across most pairs on the grid, none
+    # shared for random points) and evaluated in every product: the same
+    # entries up to rounding, so the products agree to rounding
     import paper_1405_2276_amd as fkf
-    pts = W.grid_points((96, 72))
+    pts = (W.grid_points((96, 72)) if points.startswith("grid")
+           else np.random.default_rng(5).uniform(0, 1, (5000, 2)))
     kw = dict(nu=1.5, length=0.12, variance=1.0, precision=precision)
     c_st = fkf.Cov(pts, **kw)
     c_ev = fkf.Cov(pts, far_eval=True, **kw)
-    assert c_st.info()["far_bytes"] > 0 and c_ev.info()["far_bytes"] == 0
+    inf = c_st.info()
+    assert inf["far_bytes"] > 0 and c_ev.info()["far_bytes"] == 0
+    assert inf["far_bytes"] == fkf.plan(pts, **kw)["far_bytes"]
+    per = 4 if precision == "mixed" else 8
+    shared = inf["far_bytes"] < 2 * per * inf["far_pair_entries"]
+    _say(f"[hmat] {points}: {inf['far_bytes']} stored coupling bytes for "
+         f"{inf['far_pair_entries']} pair entries")
+    assert shared == points.startswith("grid")
     X = np.random.default_rng(21).standard_normal((len(pts), 5))
     for cols in (X[:, 0], X):
         a = _host(c_st.apply(_dev(cols)))
