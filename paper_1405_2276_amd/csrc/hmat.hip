@@ -1192,6 +1192,15 @@ __global__ void __launch_bounds__(512) k_up_mfma2(const CoupleMItem *__restrict_
       }
 }
 
+// Workgroups are dealt to the eight XCDs in turn (linear workgroup id mod
+// 8).  xcd_contiguous maps workgroup b of n so that each XCD's workgroups
+// cover one contiguous range of indices, e.g. of leaves, whose shared
+// ancestors' data then stays in that XCD's L2.  A bijection of [0, n).
+__device__ __forceinline__ int xcd_contiguous(int b, int n) {
+  const int x = b & 7, k = b >> 3, q = n >> 3, r = n & 7;
+  return x * q + min(x, r) + k;
+}
+
 // Downward pass of the several-column product: Y[perm, c] += U_c|_s Yhat_c
 // over the far ancestors c of leaf s, for 512 columns per workgroup.  Per
 // ancestor the per-axis Lagrange values of the leaf's points go to LDS; per
@@ -1209,7 +1218,7 @@ __global__ void __launch_bounds__(512) k_down_mfma2(
   constexpr int PM = PMax<D>::v, LDK = 18;
   __shared__ double Ls[D][64][PM + 1];
   __shared__ double As[2][64 * LDK];
-  const int s = blockIdx.x;
+  const int s = xcd_contiguous(blockIdx.x, gridDim.x);   // leaves of a subtree on one XCD
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
   const int lr = l & 15, lk = l >> 4;
@@ -2544,8 +2553,9 @@ bool cov_apply_sparse_rows(fkf_cov *cov, int n_m, const int64_t *rowptr, const i
   const int64_t budget = cov->hp.workspace_bytes > 0 ? cov->hp.workspace_bytes
                                                       : (int64_t(16) << 30);
   const int64_t per_col = 8 * 2 * cov->n_coef;
-  const int32_t chunk = (int32_t)std::min<int64_t>(
+  int32_t chunk = (int32_t)std::min<int64_t>(
       {(int64_t)n_m, std::max<int64_t>(2, budget / per_col), int64_t(4) * 65535});
+  while (chunk > 2 && n_m % chunk == 1) --chunk;   // no block of a single column
   for (int32_t c0 = 0; c0 < n_m; c0 += chunk) {
     const int32_t nc = std::min(chunk, n_m - c0);
     const SparseRhs sp{rowptr, c0};

@@ -136,6 +136,14 @@ def test_cross_cov_column_blocks_under_workspace_bound():
     e = _rel(got, dense)
     _say(f"[xcov] blocks of 7 columns (n_m={H.shape[0]}) vs one block {e:.2e}")
     assert e <= 1e-12
+    # a bound of n_m - 1 columns would leave a block of one column: the
+    # blocks are shrunk so that none is
+    n_m = H.shape[0]
+    cov1 = fkf.Cov(pts, nu=c["nu"], length=c["ell"], variance=c["theta"], leaf_size=c["leaf"],
+                   workspace_bytes=8 * 2 * ncoef * (n_m - 1))
+    e1 = _rel(_host(obs.cross_cov(cov1)), dense)
+    _say(f"[xcov] bound of {n_m - 1} columns vs one block {e1:.2e}")
+    assert e1 <= 1e-12
 
 
 def test_cross_cov_repeated_columns_are_summed():
