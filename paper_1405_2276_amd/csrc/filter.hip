@@ -518,6 +518,11 @@ static void gemv_seg(const fkf_filter *f, const double *z, bool square, hipStrea
   gemv_seg_m(f->U0.p, f->ldu, f->n_m, f->n, z, square, f->part.p, st);
 }
 
+// Stopping tolerance of the projected generalized eigenproblem (relative
+// off-diagonal norm): 1e-12 in FP64; 1e-10 for a mixed-precision filter,
+// whose FP32 storage already perturbs the results by ~1e-7 relative.
+static double gep_tol(const fkf_filter *f) { return f->mixed ? 1e-10 : 1e-12; }
+
 // P = Gamma H^T (n x n_m, leading dimension ldp): the several-column product
 // taking its columns as the sparse rows of H where that form applies, else
 // the product with the dense H^T (in Ht: formed here unless ht_ready).
@@ -559,7 +564,7 @@ static void compute_gep(fkf_filter *f, const fkf_obs *o, DevBuf<double> &Ht, Dev
   innovation_gram(o->rowptr.p, o->col.p, o->val.p, nm, n, P.p, o->noise.p, G.p, A.p, st);
   {
     FKF_TRACE("gep_eig", st);
-    sym_eig(A.p, nm, nm, lam.p, We.p, nm, st, f->eig);
+    sym_eig(A.p, nm, nm, lam.p, We.p, nm, st, f->eig, gep_tol(f));
   }
   hipLaunchKernelGGL(k_clamp_nonneg, dim3(blocks(nm)), dim3(256), 0, st, lam.p, nm);
 }
@@ -659,7 +664,9 @@ static void build_bases(fkf_filter *const *fs, const fkf_obs *const *os, int cou
   if (multi) lanes_join(*lp, st);
   {
     FKF_TRACE("gep_eig", st);
-    sym_eig_batched(probs.data(), count, st, fs[0]->eig);
+    double tol = 1.0;
+    for (int i = 0; i < count; ++i) tol = std::min(tol, gep_tol(fs[i]));
+    sym_eig_batched(probs.data(), count, st, fs[0]->eig, tol);
   }
   if (multi) lanes_fork(*lp, st);
   for (int i = 0; i < count; ++i) {

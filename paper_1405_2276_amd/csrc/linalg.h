@@ -30,15 +30,17 @@ struct EigWork {
 
 // Eigen-decomposition of a symmetric n x n FP64 matrix A (column-major, lda)
 // by two-sided block Jacobi: w (n, descending) and W (n x n, column j the
-// eigenvector of w[j], ldw).  Returns the number of sweeps used.  Synchronises
-// the stream once per sweep to test convergence.
+// eigenvector of w[j], ldw), stopped when the off-diagonal Frobenius norm is
+// below tol ||A||_F.  Returns the number of sweeps used.  Synchronises the
+// stream once per sweep to test convergence.
 int sym_eig(const double *A, int64_t lda, int n, double *w, double *W, int64_t ldw,
-            hipStream_t st, EigWork &ws);
+            hipStream_t st, EigWork &ws, double tol = 1e-12);
 
 // The same for count independent problems in one sequence of launches (all
 // padded to the largest order, one convergence flag each).  Returns the
 // number of sweeps of the slowest problem.
-int sym_eig_batched(const EigProblem *probs, int count, hipStream_t st, EigWork &ws);
+int sym_eig_batched(const EigProblem *probs, int count, hipStream_t st, EigWork &ws,
+                    double tol = 1e-12);
 
 // y (n_m) = H x for CSR H.
 void spmv(const int64_t *rowptr, const int32_t *col, const double *val, int n_m,

@@ -19,7 +19,8 @@ namespace fkf {
 // giving an orthogonal J_k, and then every 32 x 32 tile of A is updated as
 // J_k1^T A J_k2 and V as V J_k.  A sweep (nb - 1 rounds) rotates every index
 // pair once; the iteration stops when the off-diagonal Frobenius norm falls
-// below 1e-12 ||A||_F (or a sweep rotates nothing).  Padding indices carry
+// below tol ||A||_F (1e-12 unless the caller asks otherwise; or a sweep
+// rotates nothing).  Padding indices carry
 // zero rows/columns and are never rotated.
 
 constexpr int kJB = 16;   // block size
@@ -506,7 +507,7 @@ EigWork::~EigWork() {
   if (ev) (void)hipEventDestroy(ev);
 }
 
-int sym_eig_batched(const EigProblem *probs, int count, hipStream_t st, EigWork &ws) {
+int sym_eig_batched(const EigProblem *probs, int count, hipStream_t st, EigWork &ws, double tol) {
   int nmax = 0;
   for (int b = 0; b < count; ++b) nmax = std::max(nmax, probs[b].n);
   if (count <= 0 || nmax <= 0) return 0;
@@ -554,8 +555,8 @@ int sym_eig_batched(const EigProblem *probs, int count, hipStream_t st, EigWork 
   // Rounds are launched as k_jacobi_round: the solve of round r runs next to
   // the update of round r - 1 (A double-buffered, J double-buffered); the last
   // update of a sweep runs alone before the convergence test.  A problem has
-  // converged when its relative off-diagonal norm is below 1e-12 (a
-  // perturbation of at most 1e-12 ||A||_F on the eigenvalues) or a sweep
+  // converged when its relative off-diagonal norm is below tol (a
+  // perturbation of at most tol ||A||_F on the eigenvalues) or a sweep
   // rotates nothing; the batch stops when all have.  The test of sweep s is
   // read on the host while sweep s + 1 is already queued (no idle GPU during
   // the host round trip); launches of a converged problem are empty.
@@ -596,7 +597,7 @@ int sym_eig_batched(const EigProblem *probs, int count, hipStream_t st, EigWork 
     ++sweeps;
     *done_host = 0;
     hipLaunchKernelGGL(k_eig_converged, dim3(1), dim3(256), 0, st, ws.fro.p, ws.cnt.p, np, count,
-                       1e-12, ca, (int *)done_host);
+                       tol, ca, (int *)done_host);
     FKF_CHECK_HIP(hipEventRecord(ws.ev, st));
     ca_prev = ca;
     if (sw == 39) FKF_CHECK_HIP(hipEventSynchronize(ws.ev));
@@ -610,10 +611,10 @@ int sym_eig_batched(const EigProblem *probs, int count, hipStream_t st, EigWork 
 }
 
 int sym_eig(const double *A, int64_t lda, int n, double *w, double *W, int64_t ldw,
-            hipStream_t st, EigWork &ws) {
+            hipStream_t st, EigWork &ws, double tol) {
   if (n <= 0) return 0;
   EigProblem p{A, lda, n, 0, w, W, ldw};
-  return sym_eig_batched(&p, 1, st, ws);
+  return sym_eig_batched(&p, 1, st, ws, tol);
 }
 
 // ========================================================= sparse products ===
