@@ -23,7 +23,10 @@
  *     buffers are float64.
  *   - Multi-column arrays are column-major with an explicit leading dimension.
  *   - Handles own all device memory they allocate; *_destroy frees it (after
- *     synchronising the device).  A handle is used by one thread at a time.
+ *     synchronising the device).  A handle is used by one thread at a time,
+ *     and the device work of calls on one handle (which share its workspace)
+ *     must not overlap: queue them on one stream, or synchronise between
+ *     streams.
  *   - Argument errors are reported synchronously.  Numeric failures detected
  *     on the device (non-finite data, a non-positive-definite Gram matrix) are
  *     latched in the filter and reported by fkf_filter_status() and by the next
