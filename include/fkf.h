@@ -52,7 +52,7 @@ typedef enum {
   FKF_E_RANK = -5,         /* the low-rank term would exceed max_rank */
   FKF_E_NONFINITE = -6,    /* NaN/Inf met in data or state */
   FKF_E_ORDER = -7,        /* call out of order (e.g. step after a failure) */
-  FKF_E_UNSUPPORTED = -8   /* valid request that this build does not support */
+  FKF_E_UNSUPPORTED = -8   /* valid request that this library does not support */
 } fkf_status;
 
 /* Matern smoothness nu = 1/2, 3/2, 5/2: the half-integer cases whose Bessel
