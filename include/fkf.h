@@ -367,9 +367,11 @@ void fkf_filter_destroy(fkf_filter *f);
 const char *fkf_last_error(void);
 
 /* Tracing: when enabled (on != 0), the library records a HIP event pair on the
- * launch stream around each instrumented launch site; fkf_trace_query returns
- * the number of recorded launches of a site and their summed duration in
- * milliseconds (synchronising on the recorded events).  Enabling or disabling
+ * launch stream around each instrumented launch site (the round launches of
+ * one eigensolver sweep share one pair, so no events separate those
+ * back-to-back kernels); fkf_trace_query returns the number of recorded
+ * launches of a site and their summed duration in milliseconds (synchronising
+ * on the recorded events).  Enabling or disabling
  * synchronises the device and clears all records.  Site names are listed,
  * comma-separated, by fkf_trace_names (FKF_E_ARG when cap is too small). */
 fkf_status fkf_trace_enable(int32_t on);

@@ -569,19 +569,21 @@ int sym_eig_batched(const EigProblem *probs, int count, hipStream_t st, EigWork 
     hipLaunchKernelGGL(k_set_int_strided, dim3((count + 255) / 256), dim3(256), 0, st, ws.cnt.p,
                        cstride, count, 0);
     int rprev = -1;
-    for (int r = 0; r <= nb - 1; ++r) {
-      const bool solve = r < nb - 1;
-      const unsigned grid = (solve ? npair : 0) + (rprev >= 0 ? grid_upd : 0);
-      {
-        FKF_TRACE("eig_jacobi_round", st);
+    {
+      // the sweep's nb launches are timed as one interval (no events between
+      // the back-to-back round kernels)
+      FKF_TRACE_N("eig_jacobi_round", st, nb);
+      for (int r = 0; r <= nb - 1; ++r) {
+        const bool solve = r < nb - 1;
+        const unsigned grid = (solve ? npair : 0) + (rprev >= 0 ? grid_upd : 0);
         hipLaunchKernelGGL(k_jacobi_round, dim3(grid, count), dim3(256), 0, st, Ab[ca],
                            Ab[ca ^ 1], ws.V.p, np, nb, ws.pidx.p, r, solve ? 1 : 0, rprev,
                            Jb[cj ^ 1], Jb[cj], ws.fro.p, ws.cnt.p);
-      }
-      if (rprev >= 0) ca ^= 1;   // the update wrote the other A buffer
-      if (solve) {
-        cj ^= 1;                 // this solve's rotations are pending now
-        rprev = r;
+        if (rprev >= 0) ca ^= 1;   // the update wrote the other A buffer
+        if (solve) {
+          cj ^= 1;                 // this solve's rotations are pending now
+          rprev = r;
+        }
       }
     }
     hipLaunchKernelGGL(k_offnorm_cols, dim3(np, count), dim3(256), 0, st, Ab[ca], np, ws.fro.p, 0);

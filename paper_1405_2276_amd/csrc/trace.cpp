@@ -1,6 +1,7 @@
 // Optional per-launch timing with HIP events (tracing subsystem).  When
 // enabled, instrumented launch sites record a start/stop event pair on their
-// stream; fkf_trace_query sums the durations per site name.
+// stream (one pair may cover several launches of the site); fkf_trace_query
+// sums the durations and the launches per site name.
 #include <map>
 #include <mutex>
 #include <string>
@@ -12,13 +13,17 @@ namespace fkf {
 namespace {
 std::mutex g_mu;
 bool g_on = false;
-std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> g_ev;
+struct Rec {
+  hipEvent_t a, b;
+  int launches;
+};
+std::map<std::string, std::vector<Rec>> g_ev;
 
 void clear_locked() {
   for (auto &kv : g_ev)
-    for (auto &pr : kv.second) {
-      (void)hipEventDestroy(pr.first);
-      (void)hipEventDestroy(pr.second);
+    for (auto &r : kv.second) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
     }
   g_ev.clear();
 }
@@ -26,7 +31,8 @@ void clear_locked() {
 
 bool trace_on() { return g_on; }
 
-TraceScope::TraceScope(const char *name, hipStream_t st) : name_(name), st_(st) {
+TraceScope::TraceScope(const char *name, hipStream_t st, int launches)
+    : name_(name), st_(st), launches_(launches) {
   if (!g_on) return;
   if (hipEventCreate(&a_) != hipSuccess || hipEventCreate(&b_) != hipSuccess) return;
   (void)hipEventRecord(a_, st_);
@@ -37,7 +43,7 @@ TraceScope::~TraceScope() {
   if (!active_) return;
   (void)hipEventRecord(b_, st_);
   std::lock_guard<std::mutex> lk(g_mu);
-  g_ev[name_].emplace_back(a_, b_);
+  g_ev[name_].push_back(Rec{a_, b_, launches_});
 }
 
 }  // namespace fkf
@@ -61,12 +67,12 @@ extern "C" fkf_status fkf_trace_query(const char *name, int64_t *count, double *
     *total_ms = 0;
     auto it = g_ev.find(name);
     if (it == g_ev.end()) return;
-    for (auto &pr : it->second) {
-      FKF_CHECK_HIP(hipEventSynchronize(pr.second));
+    for (auto &r : it->second) {
+      FKF_CHECK_HIP(hipEventSynchronize(r.b));
       float ms = 0;
-      FKF_CHECK_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+      FKF_CHECK_HIP(hipEventElapsedTime(&ms, r.a, r.b));
       *total_ms += ms;
-      *count += 1;
+      *count += r.launches;
     }
   });
 }

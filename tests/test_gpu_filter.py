@@ -153,3 +153,29 @@ def test_error_paths():
     assert e.value.name == "FKF_E_ARG"
     with pytest.raises(fkf.FkfError):
         fkf.Filter(cov, alpha0=-1.0)
+
+
+def test_trace_counts_launches():
+    # the tracing subsystem: one basis GEMV per constant-H step; the
+    # eigensolver's round launches are recorded a sweep at a time (nb
+    # launches per sweep, nb = padded n_m / 16)
+    wl = W.tiny(shape=(24, 20), n_src=5, n_rcv=6, steps=3, leaf_size=16, cfg_id=120)
+    fkf, pts, cov, obs, H, R = _setup(wl)
+    ys = W.observations(wl)
+    fkf.trace_enable(True)
+    try:
+        f = fkf.Filter(cov)
+        for k in range(wl.steps):
+            f.step(obs, ys[k])
+        f.status()
+        rep = fkf.trace_report()
+    finally:
+        fkf.trace_enable(False)
+    nb = -(-H.shape[0] // 32) * 32 // 16
+    c_gemv, ms_gemv = rep["filter_gemv"]
+    c_jac, ms_jac = rep["eig_jacobi_round"]
+    print(f"[filter] trace gemv {c_gemv} launches {ms_gemv:.3f} ms; "
+          f"jacobi {c_jac} launches ({c_jac // nb} sweeps) {ms_jac:.3f} ms", flush=True)
+    assert c_gemv == wl.steps and ms_gemv > 0
+    assert c_jac > 0 and c_jac % nb == 0 and ms_jac > 0
+    assert fkf.trace_report() == {}
