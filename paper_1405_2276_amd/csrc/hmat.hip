@@ -2220,19 +2220,20 @@ void near_multi(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t s) {
 // Rows longer than this are not taken by the sparse moments (LDS sort size).
 constexpr int kSpRowMax = 2048;
 
-// One workgroup per row j of the sparse matrix: its entries moved to tree
-// order (position iperm[col]) and sorted ascending (bitonic sort in LDS of
-// the key (position, entry), so equal positions keep their order), written
-// to tix / val at the row's offset; and for every leaf boundary s = 0 ..
-// n_leaves the number of the row's entries in leaves before s,
-// cnt[j (n_leaves + 1) + s].  The host guarantees len <= kSpRowMax.
+// One workgroup per row j = j0 + blockIdx.x of the sparse matrix: its
+// entries moved to tree order (position iperm[col]) and sorted ascending
+// (bitonic sort in LDS of the key (position, entry), so equal positions keep
+// their order), written to tix / val at the row's offset; and for every leaf
+// boundary s = 0 .. n_leaves the number of the row's entries in leaves
+// before s, cnt[blockIdx.x (n_leaves + 1) + s] (rows of the current column
+// block).  The host guarantees len <= kSpRowMax.
 __global__ void __launch_bounds__(256) k_sparse_rows(
     const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
     const double *__restrict__ val, const int32_t *__restrict__ iperm,
-    const int64_t *__restrict__ leaf_off, int n_leaves, int32_t *__restrict__ tix,
+    const int64_t *__restrict__ leaf_off, int n_leaves, int j0, int32_t *__restrict__ tix,
     double *__restrict__ tval, int32_t *__restrict__ cnt) {
   __shared__ int64_t key[kSpRowMax];
-  const int j = blockIdx.x, tid = threadIdx.x;
+  const int j = j0 + blockIdx.x, tid = threadIdx.x;
   const int64_t e0 = rowptr[j];
   const int len = (int)(rowptr[j + 1] - e0);
   int m = 1;
@@ -2268,16 +2269,17 @@ __global__ void __launch_bounds__(256) k_sparse_rows(
       if ((key[mid] >> 32) < b) lo = mid + 1;
       else hi = mid;
     }
-    cnt[(int64_t)j * (n_leaves + 1) + q] = lo;
+    cnt[(int64_t)blockIdx.x * (n_leaves + 1) + q] = lo;
   }
 }
 
 // Nonzero flags of the sparse moments, one thread per (far cluster c, block
 // b of 16 rows of the current column block): nzb[c ncb16 + b] = 1 when one of
-// the rows j0 + 16 b .. j0 + 16 b + 15 (< j0 + nrhs) has an entry inside c.
+// the block's rows 16 b .. 16 b + 15 (< nrhs; counts by row of the column
+// block) has an entry inside c.
 __global__ void __launch_bounds__(256) k_sparse_nzb(const int32_t *__restrict__ fc_leaf,
                                                     int n_fc, const int32_t *__restrict__ cnt,
-                                                    int n_leaves, int j0, int nrhs,
+                                                    int n_leaves, int nrhs,
                                                     int32_t *__restrict__ nzb) {
   const int ncb16 = (nrhs + 15) >> 4;
   const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -2288,7 +2290,7 @@ __global__ void __launch_bounds__(256) k_sparse_nzb(const int32_t *__restrict__ 
   for (int q = 0; q < 16; ++q) {
     const int jj = 16 * b + q;
     if (jj < nrhs) {
-      const int32_t *cj = cnt + (int64_t)(j0 + jj) * (n_leaves + 1);
+      const int32_t *cj = cnt + (int64_t)jj * (n_leaves + 1);
       any |= cj[L1] > cj[L0];
     }
   }
@@ -2313,7 +2315,7 @@ __global__ void __launch_bounds__(256) k_up_sparse(
   if (jj >= nrhs) return;
   const int j = j0 + jj;
   const FarCluster c = fc[blockIdx.x];
-  const int32_t *cj = cnt + (int64_t)j * (n_leaves + 1);
+  const int32_t *cj = cnt + (int64_t)jj * (n_leaves + 1);
   const int64_t base = rowptr[j] - rowptr[0];
   const int64_t lo = base + cj[fc_leaf[2 * blockIdx.x]];
   const int64_t hi = base + cj[fc_leaf[2 * blockIdx.x + 1]];
@@ -2377,7 +2379,7 @@ __global__ void __launch_bounds__(256) k_near_sparse(
   const int s = blockIdx.x, j = j0 + jj;
   const int e0 = near_ptr[s], e1 = near_ptr[s + 1];
   const int64_t s0 = leaf_off[s], ms = leaf_off[s + 1] - s0;
-  const int32_t *cj = cnt + (int64_t)j * (n_leaves + 1);
+  const int32_t *cj = cnt + (int64_t)jj * (n_leaves + 1);
   const int64_t base = rowptr[j] - rowptr[0];
   const int ir = l < ms ? l : 0;
   const int64_t rowoff = (ir >> 4) * 1024 + (ir & 15);
@@ -2460,7 +2462,7 @@ void apply_multi_t(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t s
         const int64_t nf = (int64_t)cov->n_fc * ((nrhs + 15) / 16);
         cov->sp_nzb.reserve((size_t)nf);
         hipLaunchKernelGGL(k_sparse_nzb, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, st,
-                           cov->fc_leaf.p, cov->n_fc, cov->sp_cnt.p, cov->n_leaves, sp->j0, nrhs,
+                           cov->fc_leaf.p, cov->n_fc, cov->sp_cnt.p, cov->n_leaves, nrhs,
                            cov->sp_nzb.p);
         nzb = cov->sp_nzb.p;
       }
@@ -2543,21 +2545,21 @@ bool cov_apply_sparse_rows(fkf_cov *cov, int n_m, const int64_t *rowptr, const i
   if (!cov->sp_ok || cov->n_fc == 0 || n_m < 2 || max_row > kSpRowMax) return false;
   cov->sp_tix.reserve((size_t)std::max<int64_t>(nnz, 1));
   cov->sp_val.reserve((size_t)std::max<int64_t>(nnz, 1));
-  cov->sp_cnt.reserve((size_t)n_m * (cov->n_leaves + 1));
-  hipLaunchKernelGGL(k_sparse_rows, dim3((unsigned)n_m), dim3(256), 0, st, rowptr, col, val,
-                     cov->iperm.p, cov->leaf_off.p, cov->n_leaves, cov->sp_tix.p, cov->sp_val.p,
-                     cov->sp_cnt.p);
-  FKF_CHECK_HIP(hipGetLastError());
-  // column blocks within the workspace bound, as in the dense product (only
-  // the coefficient vectors here; at most 4 * 65535 columns for the grids)
+  // column blocks within the workspace bound, as in the dense product (here
+  // the two coefficient vectors and the per-leaf counts of each column; at
+  // most 4 * 65535 columns for the grids)
   const int64_t budget = cov->hp.workspace_bytes > 0 ? cov->hp.workspace_bytes
                                                       : (int64_t(16) << 30);
-  const int64_t per_col = 8 * 2 * cov->n_coef;
+  const int64_t per_col = 8 * 2 * cov->n_coef + 4 * (cov->n_leaves + 1);
   int32_t chunk = (int32_t)std::min<int64_t>(
       {(int64_t)n_m, std::max<int64_t>(2, budget / per_col), int64_t(4) * 65535});
   while (chunk > 2 && n_m % chunk == 1) --chunk;   // no block of a single column
+  cov->sp_cnt.reserve((size_t)std::min(chunk, n_m) * (cov->n_leaves + 1));
   for (int32_t c0 = 0; c0 < n_m; c0 += chunk) {
     const int32_t nc = std::min(chunk, n_m - c0);
+    hipLaunchKernelGGL(k_sparse_rows, dim3((unsigned)nc), dim3(256), 0, st, rowptr, col, val,
+                       cov->iperm.p, cov->leaf_off.p, cov->n_leaves, c0, cov->sp_tix.p,
+                       cov->sp_val.p, cov->sp_cnt.p);
     const SparseRhs sp{rowptr, c0};
     apply_multi(cov, nc, Y + ldy * (int64_t)c0, ldy, st, &sp);
     FKF_CHECK_HIP(hipGetLastError());
