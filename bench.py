@@ -347,7 +347,7 @@ def _sources_sha256(files):
     return h.hexdigest()
 
 
-def write_traffic(fetch_csv, write_csv):
+def write_traffic(fetch_csv, write_csv, out=None):
     """profiles/traffic.json from two counter runs of `bench.py --profile`
     (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, --output-format csv): the
     mean KiB per dispatch of each traced kernel, and the factors that map the
@@ -376,19 +376,19 @@ def write_traffic(fetch_csv, write_csv):
                                "true_each_way": true_kib},
            "sites": sites, "sources": TRAFFIC_SOURCES,
            "sources_sha256": _sources_sha256(TRAFFIC_SOURCES)}
-    out = os.path.join(ROOT, "profiles", "traffic.json")
+    out = out or os.path.join(ROOT, "profiles", "traffic.json")
     with open(out, "w") as fh:
         json.dump(rec, fh, indent=1, sort_keys=True)
         fh.write("\n")
     print(out)
 
 
-def traffic_for(site):
+def traffic_for(site, path=None):
     """HBM bytes per launch of a kernel site from the committed counter runs
     (profiles/traffic.json: FETCH_SIZE and WRITE_SIZE per dispatch, scaled by
     what the counters read for a copy kernel of known size), or None when
     absent or taken on different kernel sources."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = path or os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
