@@ -126,6 +126,18 @@ CUBE = Workload("crosswell-64^3", 5, (64, 64, 64), 0.5, 0.15, 1e-4, (4, 8), (8, 
 WORKLOADS = {w.name: w for w in (SMALL, MEDIUM, LARGE, CUBE)}
 
 
+def crosswell_vertical(n_src: int, n_rcv: int):
+    """Sources on the bottom edge y=0, receivers on the top edge y=1 (the
+    crosswell geometry turned by a right angle): source i at ((i+1/2)/n_src, 0),
+    receiver j at ((j+1/2)/n_rcv, 1), ray m pairs source m // n_rcv with
+    receiver m % n_rcv."""
+    xs = (np.arange(n_src) + 0.5) / n_src
+    xr = (np.arange(n_rcv) + 0.5) / n_rcv
+    src = np.array([[a, 0.0] for a in xs for _ in xr])
+    rcv = np.array([[b, 1.0] for _ in xs for b in xr])
+    return src, rcv
+
+
 def batch(count: int = 64, steps: int = 10):
     """Independent filters of uneven size for the many-filter form: square
     grids with side uniform on {64, 72, ..., 256} (N = 4096 ... 65536),
@@ -198,8 +210,11 @@ class Truth:
     def cells(self, k: int) -> np.ndarray:
         return self.value(k, self.wl.points())
 
-    def travel_times(self, k: int) -> np.ndarray:
-        src, rcv = self.wl.rays()
+    def travel_times(self, k: int, src=None, rcv=None) -> np.ndarray:
+        """Line integrals of s_k along the workload's rays, or along the
+        straight rays src[m] -> rcv[m] when given."""
+        if src is None:
+            src, rcv = self.wl.rays()
         t, wq = np.polynomial.legendre.leggauss(self.n_quad)
         t = 0.5 * (t + 1.0)
         wq = 0.5 * wq
