@@ -173,6 +173,21 @@ fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d,
 fkf_status fkf_cov_apply(fkf_cov *cov, const double *X_dev, int64_t ldx,
                          int32_t nrhs, double *Y_dev, int64_t ldy, void *stream);
 
+/* The product of fkf_cov_apply (same arguments, same kernels, same result)
+ * for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  It calls
+ * no hipMalloc/hipFree: the workspace lives in a fixed 64 MiB array of device
+ * memory per GPU that the library holds from its load until the process
+ * ends, and the columns are applied in blocks whose workspace fits it
+ * (one column at a time when two do not fit).  FKF_E_ARG when even the
+ * one-column workspace of the operator (8 bytes per point plus the near-field
+ * partials and far-field vectors, about 6 MiB at N = 65536) exceeds it.  All
+ * calls on one GPU share that array: calls whose device work overlaps (on
+ * different streams, or from different threads) race and give wrong
+ * results, so serialise them. */
+fkf_status fkf_cov_apply_noalloc(fkf_cov *cov, const double *X_dev, int64_t ldx,
+                                 int32_t nrhs, double *Y_dev, int64_t ldy, void *stream);
+
 fkf_status fkf_cov_info(const fkf_cov *cov, fkf_cov_info_t *info);
 
 /* Host-only planning: builds the cluster tree, the block partition and the

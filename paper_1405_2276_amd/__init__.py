@@ -82,6 +82,8 @@ _lib.fkf_version.restype = ctypes.c_char_p
 _sig("fkf_cov_build", _i, [_c_dbl_p, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(KernelParams),
                            ctypes.POINTER(HmatParams), _vp, ctypes.POINTER(_vp)])
 _sig("fkf_cov_apply", _i, [_vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp, ctypes.c_int64, _vp])
+_sig("fkf_cov_apply_noalloc", _i, [_vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp, ctypes.c_int64,
+                                   _vp])
 _sig("fkf_cov_info", _i, [_vp, ctypes.POINTER(CovInfo)])
 _sig("fkf_cov_perm", _i, [_vp, _c_i64_p])
 _sig("fkf_cov_plan", _i, [_c_dbl_p, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(KernelParams),
@@ -348,6 +350,19 @@ class Cov:
                    else fortran_empty(self.n, k, X.device))
         optr, ldy, _ = _colmajor(out)
         _check(_lib.fkf_cov_apply(self._h, ptr, ldx, k, optr, ldy, _stream(stream)))
+        return out
+
+    def apply_noalloc(self, X, out, stream=None):
+        """Y = Gamma X into the caller's ``out`` through fkf_cov_apply_noalloc
+        (no device allocation in the library: its workspace is a fixed
+        per-device array)."""
+        ptr, ldx, k = _colmajor(X)
+        if X.shape[0] != self.n or out.shape[0] != self.n:
+            raise ValueError("X and out must have N rows")
+        optr, ldy, ko = _colmajor(out)
+        if ko != k:
+            raise ValueError("out must have as many columns as X")
+        _check(_lib.fkf_cov_apply_noalloc(self._h, ptr, ldx, k, optr, ldy, _stream(stream)))
         return out
 
     def info(self) -> dict:

@@ -18,6 +18,7 @@
 #include <map>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <type_traits>
 
@@ -74,6 +75,17 @@ struct CoupleMItem {
 // Couplings are stored (evaluated once at build) when they take at most this
 // many bytes; otherwise every product evaluates them again.
 constexpr int64_t kMaxCouplingBytes = int64_t(8) << 30;
+
+// Device workspaces of one product block (carved from one allocation).
+struct ApplyWs {
+  double *xt = nullptr;         // gathered columns, tree order
+  double *part = nullptr;       // one column: near-field partials, 128 per stored block
+  double *xhat = nullptr;       // far-cluster moments U_c^T x_c
+  double *yhat = nullptr;       // far-cluster coupled coefficients
+  double *part_up = nullptr;    // one column: upward chunk partials
+  double *part_pair = nullptr;  // one column: coupling partials (couplings evaluated)
+  double *part_up_m = nullptr;  // several columns: upward chunk partials
+};
 
 }  // namespace fkf
 
@@ -142,7 +154,7 @@ struct fkf_cov {
   fkf::DevBuf<int32_t> iperm, fc_leaf;
   bool sp_ok = false;
   // workspace
-  fkf::DevBuf<double> xt, yt, part, xhat, yhat, part_up, part_pair, part_up_m;
+  fkf::DevBuf<double> ws;                // product workspace (grown on demand)
   fkf::DevBuf<int32_t> sp_tix, sp_cnt;   // sparse rows in tree order, per-leaf counts
   fkf::DevBuf<int32_t> sp_nzb;           // nonzero 16-column blocks of the moments
   fkf::DevBuf<double> sp_val;
@@ -2093,6 +2105,11 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
         cov->mixed ? store(k_couple_store<2, true>) : store(k_couple_store<2, false>);
       cov->stored = true;
     }
+    // second stream and fork/join events of the products (the near field
+    // runs beside the far-field chain)
+    FKF_CHECK_HIP(hipStreamCreateWithFlags(&cov->side, hipStreamNonBlocking));
+    FKF_CHECK_HIP(hipEventCreateWithFlags(&cov->ev_fork, hipEventDisableTiming));
+    FKF_CHECK_HIP(hipEventCreateWithFlags(&cov->ev_join, hipEventDisableTiming));
     FKF_CHECK_HIP(hipStreamSynchronize(st));
     *out = cov.release();
   });
@@ -2103,19 +2120,14 @@ namespace {
 // One column: near field (HBM-bound) on a forked stream, far field (ALU-bound)
 // on the caller's stream, joined before the final pass.
 // Second stream (default priority) and fork/join events of a covariance
-// operator, created on first use.
+// operator, created by fkf_cov_build.
 static void ensure_side_stream(fkf_cov *cov) {
-  if (!cov->side) {
-    FKF_CHECK_HIP(hipStreamCreateWithFlags(&cov->side, hipStreamNonBlocking));
-    FKF_CHECK_HIP(hipEventCreateWithFlags(&cov->ev_fork, hipEventDisableTiming));
-    FKF_CHECK_HIP(hipEventCreateWithFlags(&cov->ev_join, hipEventDisableTiming));
-  }
+  if (!cov->side) throw Error{FKF_E_ORDER, "covariance operator has no side stream"};
 }
 
-void apply_one(fkf_cov *cov, double *Y, hipStream_t st) {
+void apply_one(fkf_cov *cov, const ApplyWs &ws, double *Y, hipStream_t st) {
   const int64_t n = cov->n;
   ensure_side_stream(cov);
-  cov->part.reserve((size_t)std::max<int64_t>(cov->n_blk, 1) * 128);
   FKF_CHECK_HIP(hipEventRecord(cov->ev_fork, st));
   FKF_CHECK_HIP(hipStreamWaitEvent(cov->side, cov->ev_fork, 0));
   {
@@ -2123,32 +2135,28 @@ void apply_one(fkf_cov *cov, double *Y, hipStream_t st) {
     if (cov->n_blk && cov->mixed)
       hipLaunchKernelGGL(k_near_sym1_32, dim3((unsigned)((cov->n_blk + 3) / 4)), dim3(256), 0,
                          cov->side, cov->blk32.p, cov->blk_s.p, cov->blk_t.p, cov->leaf_off.p,
-                         cov->xt.p, cov->n_blk, cov->part.p);
+                         ws.xt, cov->n_blk, ws.part);
     else if (cov->n_blk)
       hipLaunchKernelGGL(k_near_sym1, dim3((unsigned)((cov->n_blk + 3) / 4)), dim3(256), 0,
                          cov->side, cov->blk.p, cov->blk_s.p, cov->blk_t.p, cov->leaf_off.p,
-                         cov->xt.p, cov->n_blk, cov->part.p);
+                         ws.xt, cov->n_blk, ws.part);
   }
   FKF_CHECK_HIP(hipEventRecord(cov->ev_join, cov->side));
   const bool d3 = cov->d == 3;
   if (cov->n_fc > 0) {
-    cov->xhat.reserve((size_t)cov->n_coef);
-    cov->yhat.reserve((size_t)cov->n_coef);
-    cov->part_up.reserve((size_t)std::max<int64_t>(cov->n_part_up, 1));
-    cov->part_pair.reserve((size_t)std::max<int64_t>(cov->n_part_pair, 1));
     {
       FKF_TRACE("hmat_far_up_1rhs", st);
       if (d3)
         hipLaunchKernelGGL(k_up1<3>, dim3((unsigned)cov->n_up_items), dim3(64), 0, st,
-                           cov->up_items.p, cov->fc.p, cov->pts.p, n, cov->cheb.p, cov->xt.p,
-                           cov->part_up.p);
+                           cov->up_items.p, cov->fc.p, cov->pts.p, n, cov->cheb.p, ws.xt,
+                           ws.part_up);
       else
         hipLaunchKernelGGL(k_up1_mfma2, dim3((unsigned)cov->n_up_items), dim3(64), 0, st,
-                           cov->up_items.p, cov->fc.p, cov->pts.p, n, cov->cheb.p, cov->xt.p,
-                           cov->part_up.p);
+                           cov->up_items.p, cov->fc.p, cov->pts.p, n, cov->cheb.p, ws.xt,
+                           ws.part_up);
       hipLaunchKernelGGL(k_up_reduce, dim3((cov->n_fc + 3) / 4), dim3(256), 0, st, cov->fc.p,
                          cov->n_fc, cov->up_ptr.p,
-                         cov->up_items.p, cov->part_up.p, cov->xhat.p);
+                         cov->up_items.p, ws.part_up, ws.xhat);
     }
     {
       FKF_TRACE("hmat_far_couple_1rhs", st);
@@ -2156,19 +2164,19 @@ void apply_one(fkf_cov *cov, double *Y, hipStream_t st) {
         if (cov->n_citems > 0)
           hipLaunchKernelGGL(kern, dim3((unsigned)((cov->n_citems + 3) / 4)), dim3(256), 0, st,
                            cov->citems.p, cov->n_citems, cov->pairs.p, cov->fc.p, cov->cheb.p,
-                           cov->kind, 1.0 / cov->ell, cov->amp, cov->xhat.p,
-                           cov->part_pair.p);
+                           cov->kind, 1.0 / cov->ell, cov->amp, ws.xhat,
+                           ws.part_pair);
       };
       if (cov->stored) {
         const dim3 g((unsigned)cov->n_fc, (unsigned)((cov->max_pd + 63) / 64));
         if (cov->mixed)
           hipLaunchKernelGGL(k_couple_rows1<float>, g, dim3(256), 0, st, cov->fc.p,
                              cov->far_ptr.p, cov->far_col.p, cov->far_koff.p, cov->kst32.p,
-                             cov->xhat.p, cov->yhat.p);
+                             ws.xhat, ws.yhat);
         else
           hipLaunchKernelGGL(k_couple_rows1<double>, g, dim3(256), 0, st, cov->fc.p,
                              cov->far_ptr.p, cov->far_col.p, cov->far_koff.p, cov->kst.p,
-                             cov->xhat.p, cov->yhat.p);
+                             ws.xhat, ws.yhat);
       } else {
         const int sel = (d3 ? 2 : 0) + (cov->mixed ? 1 : 0);
         switch (sel) {
@@ -2178,8 +2186,8 @@ void apply_one(fkf_cov *cov, double *Y, hipStream_t st) {
           default: launch(k_couple_blk<3, true>); break;
         }
         hipLaunchKernelGGL(k_couple_reduce, dim3((cov->n_fc + 3) / 4), dim3(256), 0, st,
-                           cov->fc.p, cov->n_fc, cov->cp_ptr.p, cov->cp_off.p, cov->part_pair.p,
-                           cov->yhat.p);
+                           cov->fc.p, cov->n_fc, cov->cp_ptr.p, cov->cp_off.p, ws.part_pair,
+                           ws.yhat);
       }
     }
   }
@@ -2189,24 +2197,24 @@ void apply_one(fkf_cov *cov, double *Y, hipStream_t st) {
     if (d3)
       hipLaunchKernelGGL(k_final1<3>, dim3(cov->n_leaves), dim3(256), 0, st, cov->leaf_off.p,
                          cov->pts.p, n, cov->cheb.p, cov->fc.p, cov->anc_ptr.p, cov->anc_idx.p,
-                         cov->yhat.p, cov->part.p, cov->part_ptr.p, cov->part_idx.p, cov->perm.p,
+                         ws.yhat, ws.part, cov->part_ptr.p, cov->part_idx.p, cov->perm.p,
                          Y);
     else
       hipLaunchKernelGGL(k_final1_mfma2, dim3(cov->n_leaves), dim3(256), 0, st, cov->leaf_off.p,
                          cov->pts.p, n, cov->cheb.p, cov->fc.p, cov->anc_ptr.p, cov->anc_idx.p,
-                         cov->yhat.p, cov->part.p, cov->part_ptr.p, cov->part_idx.p, cov->perm.p,
+                         ws.yhat, ws.part, cov->part_ptr.p, cov->part_idx.p, cov->perm.p,
                          Y);
   }
 }
 
 // Near field of the several-column product (written to Y in caller order).
 template <bool F32>
-void near_multi(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t s) {
+void near_multi(fkf_cov *cov, const ApplyWs &ws, int nrhs, double *Y, int64_t ldy, hipStream_t s) {
   typedef typename std::conditional<F32, float, double>::type TT;
   const TT *frag = F32 ? (const TT *)cov->frag32.p : (const TT *)cov->frag.p;
   hipLaunchKernelGGL(k_near_mfma<TT>, dim3(cov->n_leaves, (unsigned)((nrhs + 127) / 128)),
                      dim3(512), 0, s, frag, cov->near_ptr.p, cov->near_idx.p, cov->blk_s.p,
-                     cov->blk_t.p, cov->leaf_off.p, cov->n, cov->xt.p, cov->perm.p, nrhs, Y, ldy);
+                     cov->blk_t.p, cov->leaf_off.p, cov->n, ws.xt, cov->perm.p, nrhs, Y, ldy);
 }
 
 // ------------------------------------------- sparse right-hand sides ---
@@ -2409,13 +2417,10 @@ struct SparseRhs {
 // stream, concurrently with the far-field chain (upward chunks + reduction,
 // couplings per cluster row block); the downward pass then adds to Y.
 template <int D, bool F32>
-void apply_multi_t(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t st,
-                   const SparseRhs *sp) {
+void apply_multi_t(fkf_cov *cov, const ApplyWs &ws, int nrhs, double *Y, int64_t ldy,
+                   hipStream_t st, const SparseRhs *sp) {
   const int64_t n = cov->n;
   if (cov->n_fc > 0) {
-    cov->xhat.reserve((size_t)cov->n_coef * nrhs);
-    cov->yhat.reserve((size_t)cov->n_coef * nrhs);
-    if (!sp) cov->part_up_m.reserve((size_t)cov->n_part_up_m * nrhs);
     // near field on the side stream, concurrent with the far-field chain;
     // the downward pass then adds to its result
     ensure_side_stream(cov);
@@ -2431,7 +2436,7 @@ void apply_multi_t(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t s
                          cov->sp_val.p, cov->sp_cnt.p, cov->n_leaves, cov->perm.p, Y, ldy);
     } else {
       FKF_TRACE("hmat_near_multi", cov->side);
-      near_multi<F32>(cov, nrhs, Y, ldy, cov->side);
+      near_multi<F32>(cov, ws, nrhs, Y, ldy, cov->side);
     }
     FKF_CHECK_HIP(hipEventRecord(cov->ev_join, cov->side));
     if (sp) {
@@ -2439,15 +2444,15 @@ void apply_multi_t(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t s
       hipLaunchKernelGGL((k_up_sparse<D>), dim3((unsigned)cov->n_fc, (unsigned)((nrhs + 3) / 4)),
                          dim3(256), 0, st, cov->fc.p, cov->fc_leaf.p, cov->lag.p, sp->rowptr,
                          sp->j0, nrhs, cov->sp_tix.p, cov->sp_val.p, cov->sp_cnt.p,
-                         cov->n_leaves, cov->xhat.p);
+                         cov->n_leaves, ws.xhat);
     } else {
       FKF_TRACE("hmat_far_up_multi", st);
       hipLaunchKernelGGL((k_up_mfma2<D>),
                          dim3((unsigned)cov->n_up_blocks_m, (unsigned)((nrhs + 511) / 512)),
                          dim3(512), 0, st, cov->up_blocks_m.p, cov->up_items_m.p, cov->fc.p,
-                         cov->lag.p, n, cov->xt.p, nrhs, cov->part_up_m.p);
+                         cov->lag.p, n, ws.xt, nrhs, ws.part_up_m);
       hipLaunchKernelGGL(k_up_reduce_m, dim3(cov->n_fc, 8), dim3(256), 0, st, cov->fc.p,
-                         cov->up_ptr_m.p, cov->up_items_m.p, nrhs, cov->part_up_m.p, cov->xhat.p);
+                         cov->up_ptr_m.p, cov->up_items_m.p, nrhs, ws.part_up_m, ws.xhat);
     }
     {
       FKF_TRACE("hmat_far_couple_multi", st);
@@ -2455,7 +2460,7 @@ void apply_multi_t(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t s
       if (!cov->cm_all) {
         const int64_t len = cov->n_coef * nrhs;
         hipLaunchKernelGGL(k_zero, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st,
-                           cov->yhat.p, len);
+                           ws.yhat, len);
       }
       const int32_t *nzb = nullptr;
       if (sp && cov->n_cm_items > 0) {
@@ -2471,30 +2476,129 @@ void apply_multi_t(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t s
                            dim3((unsigned)cov->n_cm_items, (unsigned)((nrhs + 511) / 512)),
                            dim3(512), 0, st, cov->cm_items.p, cov->fc.p, cov->far_ptr.p,
                            cov->far_col.p, cov->cheb.p, cov->kind, 1.0 / cov->ell, cov->amp,
-                           cov->xhat.p, nrhs, cov->yhat.p, nzb);
+                           ws.xhat, nrhs, ws.yhat, nzb);
     }
   }
   if (cov->n_fc == 0) {
     FKF_TRACE("hmat_near_multi", st);
-    near_multi<F32>(cov, nrhs, Y, ldy, st);
+    near_multi<F32>(cov, ws, nrhs, Y, ldy, st);
     return;
   }
   FKF_TRACE("hmat_down_multi", st);
   FKF_CHECK_HIP(hipStreamWaitEvent(st, cov->ev_join, 0));
   hipLaunchKernelGGL(k_down_mfma2<D>, dim3(cov->n_leaves, (unsigned)((nrhs + 511) / 512)),
                      dim3(512), 0, st, cov->leaf_off.p, cov->pts.p, n, cov->cheb.p, cov->fc.p,
-                     cov->anc_ptr.p, cov->anc_idx.p, cov->yhat.p, cov->perm.p, nrhs, Y, ldy);
+                     cov->anc_ptr.p, cov->anc_idx.p, ws.yhat, cov->perm.p, nrhs, Y, ldy);
 }
 
-void apply_multi(fkf_cov *cov, int nrhs, double *Y, int64_t ldy, hipStream_t st,
-                 const SparseRhs *sp = nullptr) {
+void apply_multi(fkf_cov *cov, const ApplyWs &ws, int nrhs, double *Y, int64_t ldy,
+                 hipStream_t st, const SparseRhs *sp = nullptr) {
   const bool m = cov->mixed;
   if (cov->d == 2)
-    m ? apply_multi_t<2, true>(cov, nrhs, Y, ldy, st, sp)
-      : apply_multi_t<2, false>(cov, nrhs, Y, ldy, st, sp);
+    m ? apply_multi_t<2, true>(cov, ws, nrhs, Y, ldy, st, sp)
+      : apply_multi_t<2, false>(cov, ws, nrhs, Y, ldy, st, sp);
   else
-    m ? apply_multi_t<3, true>(cov, nrhs, Y, ldy, st, sp)
-      : apply_multi_t<3, false>(cov, nrhs, Y, ldy, st, sp);
+    m ? apply_multi_t<3, true>(cov, ws, nrhs, Y, ldy, st, sp)
+      : apply_multi_t<3, false>(cov, ws, nrhs, Y, ldy, st, sp);
+}
+
+}  // namespace
+
+namespace {
+
+// Doubles of each workspace region of an nc-column product block: the
+// gathered columns xt, and either the one-column near partials and far-field
+// vectors or the several-column coefficient vectors and upward partials.
+// Regions start on 256-byte boundaries.
+inline int64_t ws_round(int64_t x) { return (x + 31) / 32 * 32; }
+
+int64_t ws_doubles(const fkf_cov *cov, int nc) {
+  int64_t t = ws_round(cov->n * nc);
+  if (nc == 1) {
+    t += ws_round(std::max<int64_t>(cov->n_blk, 1) * 128);
+    if (cov->n_fc > 0)
+      t += 2 * ws_round(cov->n_coef) + ws_round(std::max<int64_t>(cov->n_part_up, 1)) +
+           ws_round(std::max<int64_t>(cov->n_part_pair, 1));
+  } else if (cov->n_fc > 0) {
+    t += 2 * ws_round(cov->n_coef * nc) + ws_round(cov->n_part_up_m * nc);
+  }
+  return t;
+}
+
+// The workspace of an nc-column block laid out from base (ws_doubles(cov, nc)
+// doubles of device memory).
+ApplyWs ws_carve(const fkf_cov *cov, int nc, double *base) {
+  ApplyWs ws{};
+  double *q = base;
+  auto take = [&](int64_t len) {
+    double *r = q;
+    q += ws_round(len);
+    return r;
+  };
+  ws.xt = take(cov->n * nc);
+  if (nc == 1) {
+    ws.part = take(std::max<int64_t>(cov->n_blk, 1) * 128);
+    if (cov->n_fc > 0) {
+      ws.xhat = take(cov->n_coef);
+      ws.yhat = take(cov->n_coef);
+      ws.part_up = take(std::max<int64_t>(cov->n_part_up, 1));
+      ws.part_pair = take(std::max<int64_t>(cov->n_part_pair, 1));
+    }
+  } else if (cov->n_fc > 0) {
+    ws.xhat = take(cov->n_coef * nc);
+    ws.yhat = take(cov->n_coef * nc);
+    ws.part_up_m = take(cov->n_part_up_m * nc);
+  }
+  return ws;
+}
+
+// Y = Gamma X in column blocks of at most `chunk` columns; the workspace of
+// each block is laid out from `base`, or (base == nullptr) from the handle's
+// workspace buffer, grown on demand.
+void apply_blocks(fkf_cov *cov, const double *X, int64_t ldx, int32_t nrhs, double *Y,
+                  int64_t ldy, int32_t chunk, double *base, hipStream_t st) {
+  const int64_t n = cov->n;
+  for (int32_t c0 = 0; c0 < nrhs; c0 += chunk) {
+    const int32_t nc = std::min(chunk, nrhs - c0);
+    const double *Xc = X + ldx * (int64_t)c0;
+    double *Yc = Y + ldy * (int64_t)c0;
+    if (!base) cov->ws.reserve((size_t)ws_doubles(cov, nc));
+    const ApplyWs ws = ws_carve(cov, nc, base ? base : cov->ws.p);
+    dim3 gg((unsigned)((n + 255) / 256), (unsigned)nc);
+    {
+      FKF_TRACE("hmat_gather", st);
+      hipLaunchKernelGGL(k_gather, gg, dim3(256), 0, st, Xc, ldx, nc, cov->perm.p, n, ws.xt);
+    }
+    if (nc == 1) {
+      apply_one(cov, ws, Yc, st);
+    } else {
+      apply_multi(cov, ws, nc, Yc, ldy, st);
+    }
+    FKF_CHECK_HIP(hipGetLastError());
+  }
+}
+
+// ---------------------------------------------- allocation-free product ---
+// Workspace of fkf_cov_apply_noalloc: one array per device, set up by the
+// code object's load and held until the process ends.  Host code must never
+// pass `scratch` itself to a kernel (on the host it only names the symbol):
+// the device address of each device's copy comes from hipGetSymbolAddress.
+constexpr int64_t kScratchBytes = int64_t(64) << 20;
+__device__ __align__(256) double scratch[kScratchBytes / 8];
+
+double *scratch_ptr() {
+  static std::mutex mu;
+  static std::map<int, double *> ptrs;   // per device
+  int dev = 0;
+  FKF_CHECK_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = ptrs.find(dev);
+  if (it != ptrs.end()) return it->second;
+  void *p = nullptr;
+  FKF_CHECK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) throw Error{FKF_E_HIP, "hipGetSymbolAddress returned a null scratch address"};
+  ptrs.emplace(dev, static_cast<double *>(p));
+  return static_cast<double *>(p);
 }
 
 }  // namespace
@@ -2507,33 +2611,47 @@ extern "C" fkf_status fkf_cov_apply(fkf_cov *cov, const double *X, int64_t ldx, 
     if (nrhs == 0) return;
     FKF_REQUIRE(X != nullptr && Y != nullptr, "fkf_cov_apply: NULL array");
     FKF_REQUIRE(ldx >= cov->n && ldy >= cov->n, "fkf_cov_apply: leading dimension < n");
-    hipStream_t st = as_stream(stream);
-    const int64_t n = cov->n;
     // the several-column workspaces (gathered columns, coefficient vectors,
     // upward partials) grow with the number of columns: apply in column
     // blocks that keep them within the bound (at least 2 columns a block)
     const int64_t budget = cov->hp.workspace_bytes > 0 ? cov->hp.workspace_bytes
                                                         : (int64_t(16) << 30);
-    const int64_t per_col = 8 * (n + 2 * cov->n_coef + cov->n_part_up_m);
+    const int64_t per_col = 8 * (cov->n + 2 * cov->n_coef + cov->n_part_up_m);
     const int32_t chunk =
         nrhs == 1 ? 1 : (int32_t)std::min<int64_t>(nrhs, std::max<int64_t>(2, budget / per_col));
-    for (int32_t c0 = 0; c0 < nrhs; c0 += chunk) {
-      const int32_t nc = std::min(chunk, nrhs - c0);
-      const double *Xc = X + ldx * (int64_t)c0;
-      double *Yc = Y + ldy * (int64_t)c0;
-      cov->xt.reserve((size_t)n * nc);
-      dim3 gg((unsigned)((n + 255) / 256), (unsigned)nc);
-      {
-        FKF_TRACE("hmat_gather", st);
-        hipLaunchKernelGGL(k_gather, gg, dim3(256), 0, st, Xc, ldx, nc, cov->perm.p, n, cov->xt.p);
+    apply_blocks(cov, X, ldx, nrhs, Y, ldy, chunk, nullptr, as_stream(stream));
+  });
+}
+
+extern "C" fkf_status fkf_cov_apply_noalloc(fkf_cov *cov, const double *X, int64_t ldx,
+                                            int32_t nrhs, double *Y, int64_t ldy,
+                                            void *stream) {
+  return guarded([&] {
+    FKF_REQUIRE(cov != nullptr, "fkf_cov_apply_noalloc: NULL handle");
+    FKF_REQUIRE(nrhs >= 0, "fkf_cov_apply_noalloc: nrhs < 0");
+    if (nrhs == 0) return;
+    FKF_REQUIRE(X != nullptr && Y != nullptr, "fkf_cov_apply_noalloc: NULL array");
+    FKF_REQUIRE(ldx >= cov->n && ldy >= cov->n, "fkf_cov_apply_noalloc: leading dimension < n");
+    const int64_t cap = kScratchBytes / 8;
+    const int64_t one = ws_doubles(cov, 1);
+    if (one > cap)
+      throw Error{FKF_E_ARG, "fkf_cov_apply_noalloc: the one-column workspace of this operator (" +
+                                 std::to_string((one * 8) >> 20) +
+                                 " MiB) exceeds the fixed scratch of " +
+                                 std::to_string(kScratchBytes >> 20) + " MiB"};
+    // widest column block whose workspace fits the scratch (one column at a
+    // time when not even two fit)
+    int32_t chunk = 1;
+    if (nrhs > 1 && ws_doubles(cov, 2) <= cap) {
+      int32_t lo = 2, hi = nrhs;
+      while (lo < hi) {
+        const int32_t mid = lo + (hi - lo + 1) / 2;
+        if (ws_doubles(cov, mid) <= cap) lo = mid;
+        else hi = mid - 1;
       }
-      if (nc == 1) {
-        apply_one(cov, Yc, st);
-      } else {
-        apply_multi(cov, nc, Yc, ldy, st);
-      }
-      FKF_CHECK_HIP(hipGetLastError());
+      chunk = lo;
     }
+    apply_blocks(cov, X, ldx, nrhs, Y, ldy, chunk, scratch_ptr(), as_stream(stream));
   });
 }
 
@@ -2555,13 +2673,19 @@ bool cov_apply_sparse_rows(fkf_cov *cov, int n_m, const int64_t *rowptr, const i
       {(int64_t)n_m, std::max<int64_t>(2, budget / per_col), int64_t(4) * 65535});
   while (chunk > 2 && n_m % chunk == 1) --chunk;   // no block of a single column
   cov->sp_cnt.reserve((size_t)std::min(chunk, n_m) * (cov->n_leaves + 1));
+  // the coefficient vectors of a block (no gathered columns, no upward partials)
+  const int64_t coef = ws_round(cov->n_coef * std::min(chunk, n_m));
+  cov->ws.reserve((size_t)(2 * coef));
+  ApplyWs ws{};
+  ws.xhat = cov->ws.p;
+  ws.yhat = cov->ws.p + coef;
   for (int32_t c0 = 0; c0 < n_m; c0 += chunk) {
     const int32_t nc = std::min(chunk, n_m - c0);
     hipLaunchKernelGGL(k_sparse_rows, dim3((unsigned)nc), dim3(256), 0, st, rowptr, col, val,
                        cov->iperm.p, cov->leaf_off.p, cov->n_leaves, c0, cov->sp_tix.p,
                        cov->sp_val.p, cov->sp_cnt.p);
     const SparseRhs sp{rowptr, c0};
-    apply_multi(cov, nc, Y + ldy * (int64_t)c0, ldy, st, &sp);
+    apply_multi(cov, ws, nc, Y + ldy * (int64_t)c0, ldy, st, &sp);
     FKF_CHECK_HIP(hipGetLastError());
   }
   return true;
