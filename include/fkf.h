@@ -116,10 +116,32 @@ typedef struct {
                               0: 16 GiB */
 } fkf_hmat_params;
 
+/* Generalized eigensolver of the constant-H basis (Section 2.2.2):
+ * FKF_GEP_EXACT: Rayleigh-Ritz on range(Gamma H^T) (exact: P = Gamma H^T,
+ *   A = R^-1/2 H P R^-1/2 = W_e Lambda W_e^T in FP64, all n_m modes);
+ * FKF_GEP_RANDOMIZED: the randomized algorithm of Appendix B with a Gaussian
+ *   sketch Omega of k + p columns drawn on the device from `seed`
+ *   (fkf_gaussian_sketch): Ybar = H^T R^-1 H Omega, a Gamma-orthonormal basis
+ *   Qhat of range(Ybar) (two Gram eigen-decompositions in the Gamma inner
+ *   product), Q = Gamma Qhat, T = (H Q)^T R^-1 (H Q) = S Lambda S^T, and the k
+ *   largest modes U = Q S.  With k + p >= n_m the sketch spans range(H^T) and
+ *   the modes are the exact ones; with fewer the filter assimilates what the
+ *   k modes keep of each observation (H^T R^-1 H ~ Gamma^-1 U Lambda U^T
+ *   Gamma^-1: the whitened data Lambda^-1/2 U^T H^T R^-1 y).  The steps of
+ *   Section 2.4 (a new operator) need P for their gain anyway and always take
+ *   the exact eigenpairs. */
+enum { FKF_GEP_EXACT = 0, FKF_GEP_RANDOMIZED = 1 };
+
 typedef struct {
-  uint32_t struct_size;   /* sizeof(fkf_filter_params) */
+  uint32_t struct_size;   /* sizeof(fkf_filter_params); the first three fields alone
+                             (struct_size 16) are accepted, with the defaults below */
   int32_t max_rank;       /* capacity of the low-rank term W (>= n_m) */
   double rank_rtol;       /* relative truncation tolerance for W (Algorithm 5) */
+  int32_t gep_mode;       /* FKF_GEP_EXACT (default) or FKF_GEP_RANDOMIZED */
+  int32_t gep_rank;       /* k: modes kept by the randomized eigensolver (<= 0: n_m) */
+  int32_t oversample;     /* p: extra sketch columns (< 0: 20, the appendix's choice) */
+  int32_t reserved;       /* must be 0 */
+  uint64_t seed;          /* sketch stream of the randomized eigensolver */
 } fkf_filter_params;
 
 /* Statistics of a built covariance operator. */
@@ -271,6 +293,14 @@ fkf_status fkf_filter_create(fkf_cov *cov, const double *s0_dev, double alpha0,
                              const fkf_filter_params *params, void *stream,
                              fkf_filter **out);
 
+/* Return f to the state fkf_filter_create gives (s_{0|0} = s0_dev or zero,
+ * Sigma_{0|0} = alpha0 Gamma, no step taken, no basis, no latched failure,
+ * log-likelihood zero; a length derivative set by fkf_filter_track_length
+ * stays tracked), keeping every device buffer the filter has allocated so
+ * that running it again over new data allocates nothing while the operators
+ * keep their sizes.  Synchronises the stream. */
+fkf_status fkf_filter_reset(fkf_filter *f, const double *s0_dev, double alpha0, void *stream);
+
 /* One predict + update with observations y_dev (n_m values) of operator obs.
  * Prediction: alpha <- alpha + 1, estimate unchanged (F = I).  Update:
  * while the filter's low-rank basis is that of obs (the first step, and every
@@ -364,6 +394,16 @@ fkf_status fkf_filter_variance(const fkf_filter *f, double *var_dev, void *strea
 fkf_status fkf_filter_realize(const fkf_filter *f, const double *g_dev, int32_t ns,
                               int64_t ldg, double *out_dev, int64_t ldo, void *stream);
 
+/* The Gaussian numbers of the randomized eigensolver's sketch (Appendix B):
+ * out_dev[e] for e = 0..count-1 is number e of stream `seed` (element (i, j)
+ * of the n x (k + p) column-major sketch is number i + n j).  Counter-based:
+ * Philox4x32-10 (Salmon et al., SC 2011) of the counter (e/2 mod 2^32,
+ * e/2 div 2^32, 0, 0) under the key (seed mod 2^32, seed div 2^32); with
+ * outputs x0..x3, u1 = ((x0 >> 6) 2^27 + (x1 >> 5) + 1/2) 2^-53 and u2 from
+ * x2, x3 likewise, the Box-Muller pair sqrt(-2 ln u1) (cos, sin)(2 pi u2)
+ * gives numbers e (cosine, e even) and e + 1 (sine). */
+fkf_status fkf_gaussian_sketch(uint64_t seed, int64_t count, double *out_dev, void *stream);
+
 /* Step count k, alpha_k and the rank of the low-rank term (any may be NULL). */
 fkf_status fkf_filter_info(const fkf_filter *f, int64_t *k, double *alpha,
                            int32_t *rank);
@@ -374,6 +414,23 @@ fkf_status fkf_filter_info(const fkf_filter *f, int64_t *k, double *alpha,
  * FKF_E_ORDER when the filter is not in the constant-H form. */
 fkf_status fkf_filter_modes(const fkf_filter *f, double *lambda_host,
                             double *weight_host);
+
+/* The low-rank term of Sigma_{k|k} = alpha_k Gamma - W D W^T (Section 2.3,
+ * eq. sigmakk; Section 2.4 for the general form) with its dual
+ * Wd = Gamma^-1 W, so that W^T Gamma^-1 W = Wd^T W = I: copies W and Wd
+ * (n x r, caller order, leading dimensions ldw, ldwd >= n) and D (r values)
+ * to device arrays with room for `capacity` columns (at least the rank of
+ * fkf_filter_info, else FKF_E_ARG) and writes r to *rank (0 before the first
+ * step).  In the constant-H form the columns are the generalized
+ * eigenvectors U = U0 Lambda^-1/2 with lambda > 1e-13 lambda_max (the others
+ * carry no weight, Gamma^-1-norm sqrt(lambda)), Wd = H^T R^-1/2 W_e
+ * Lambda^-1/2 and D the per-mode weights of Algorithms 2 and 3; in the general form the
+ * stored W, Wd and D.  Any of W_dev, Wd_dev, D_dev may be NULL.  A query for
+ * tests and diagnostics: in the constant-H form it allocates a dense H^T
+ * (8 n n_m bytes); it synchronises the stream. */
+fkf_status fkf_filter_lowrank(const fkf_filter *f, double *W_dev, int64_t ldw, double *Wd_dev,
+                              int64_t ldwd, double *D_dev, int32_t capacity, int32_t *rank,
+                              void *stream);
 
 void fkf_filter_destroy(fkf_filter *f);
 

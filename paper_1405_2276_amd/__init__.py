@@ -56,7 +56,12 @@ class HmatParams(ctypes.Structure):
 
 class FilterParams(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("max_rank", ctypes.c_int32),
-                ("rank_rtol", ctypes.c_double)]
+                ("rank_rtol", ctypes.c_double), ("gep_mode", ctypes.c_int32),
+                ("gep_rank", ctypes.c_int32), ("oversample", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+GEP_MODE = {"exact": 0, "randomized": 1}
 
 
 class CovInfo(ctypes.Structure):
@@ -102,6 +107,7 @@ _sig("fkf_obs_cross_cov", _i, [_vp, _vp, _vp, ctypes.c_int64, _vp])
 _sig("fkf_obs_destroy", None, [_vp])
 _sig("fkf_filter_create", _i, [_vp, _vp, ctypes.c_double, ctypes.POINTER(FilterParams), _vp,
                                ctypes.POINTER(_vp)])
+_sig("fkf_filter_reset", _i, [_vp, _vp, ctypes.c_double, _vp])
 _sig("fkf_filter_step", _i, [_vp, _vp, _vp, _vp])
 _sig("fkf_filter_step_boxcox", _i, [_vp, _vp, ctypes.c_double, _vp, _vp])
 _sig("fkf_filter_loglik", _i, [_vp, _c_dbl_p, _c_dbl_p, _c_dbl_p, _c_dbl_p, _vp])
@@ -113,7 +119,10 @@ _sig("fkf_filter_mean", _i, [_vp, _vp, _vp])
 _sig("fkf_filter_variance", _i, [_vp, _vp, _vp])
 _sig("fkf_filter_realize", _i, [_vp, _vp, ctypes.c_int32, ctypes.c_int64, _vp, ctypes.c_int64, _vp])
 _sig("fkf_filter_info", _i, [_vp, _c_i64_p, _c_dbl_p, _c_i32_p])
+_sig("fkf_gaussian_sketch", _i, [ctypes.c_uint64, ctypes.c_int64, _vp, _vp])
 _sig("fkf_filter_modes", _i, [_vp, _c_dbl_p, _c_dbl_p])
+_sig("fkf_filter_lowrank", _i, [_vp, _vp, ctypes.c_int64, _vp, ctypes.c_int64, _vp,
+                                ctypes.c_int32, _c_i32_p, _vp])
 _sig("fkf_filter_destroy", None, [_vp])
 _sig("fkf_trace_enable", _i, [ctypes.c_int32])
 _sig("fkf_trace_query", _i, [ctypes.c_char_p, _c_i64_p, _c_dbl_p])
@@ -212,6 +221,15 @@ def innovation_loglik(theta, length, noise_var, points, make_obs, ys, alpha0: fl
     (fkf_filter_loglik).  cov_kw go to Cov (nu, leaf_size, precision, ...)."""
     return _loglik_function().apply(theta, length, noise_var, points, make_obs, ys, cov_kw,
                                     alpha0)
+
+
+def gaussian_sketch(seed: int, count: int, stream=None):
+    """The first `count` numbers of the randomized eigensolver's sketch stream
+    (fkf_gaussian_sketch) as a CUDA float64 tensor."""
+    torch = _torch()
+    out = torch.empty(max(int(count), 1), dtype=torch.float64, device="cuda")
+    _check(_lib.fkf_gaussian_sketch(int(seed), int(count), out.data_ptr(), _stream(stream)))
+    return out[:count]
 
 
 def version() -> str:
@@ -483,10 +501,17 @@ class Filter:
     """The fast random-walk Kalman filter (fkf_filter_*)."""
 
     def __init__(self, cov: Cov, s0=None, alpha0: float = 0.0, max_rank: int = 4096,
-                 rank_rtol: float = 0.0, stream=None):
+                 rank_rtol: float = 0.0, gep: str = "exact", gep_rank: int = 0,
+                 oversample: int = 20, seed: int = 0, stream=None):
+        """gep: "exact" (Rayleigh-Ritz on range(Gamma H^T)) or "randomized"
+        (Appendix B with gep_rank modes, oversample extra sketch columns and
+        the sketch stream seed)."""
         self.cov = cov
         self.n = cov.n
-        fp = FilterParams(ctypes.sizeof(FilterParams), max_rank, rank_rtol)
+        if gep not in GEP_MODE:
+            raise ValueError("gep must be 'exact' or 'randomized'")
+        fp = FilterParams(ctypes.sizeof(FilterParams), max_rank, rank_rtol, GEP_MODE[gep],
+                          int(gep_rank), int(oversample), 0, int(seed))
         s0p = None
         if s0 is not None:
             self._s0 = to_device(s0)
@@ -495,6 +520,15 @@ class Filter:
         _check(_lib.fkf_filter_create(cov.handle, s0p, float(alpha0), ctypes.byref(fp),
                                       _stream(stream), ctypes.byref(h)))
         self._h = h
+
+    def reset(self, s0=None, alpha0: float = 0.0, stream=None):
+        """Back to the initial state (fkf_filter_reset), keeping the filter's
+        device buffers."""
+        s0p = None
+        if s0 is not None:
+            self._s0 = to_device(s0)
+            s0p = self._s0.data_ptr()
+        _check(_lib.fkf_filter_reset(self._h, s0p, float(alpha0), _stream(stream)))
 
     def step(self, obs: Obs, y, stream=None):
         y = to_device(y)
@@ -570,6 +604,20 @@ class Filter:
         w = np.empty(r)
         _check(_lib.fkf_filter_modes(self._h, lam.ctypes.data_as(_c_dbl_p), w.ctypes.data_as(_c_dbl_p)))
         return lam, w
+
+    def lowrank(self, stream=None):
+        """(W, Wd, D) of Sigma = alpha Gamma - W D W^T with Wd = Gamma^-1 W
+        (fkf_filter_lowrank), as CUDA float64 tensors (N, r), (N, r), (r,)."""
+        torch = _torch()
+        cap = max(self.info()["rank"], 1)
+        W = fortran_empty(self.n, cap)
+        Wd = fortran_empty(self.n, cap)
+        D = torch.empty(cap, dtype=torch.float64, device="cuda")
+        r = ctypes.c_int32()
+        _check(_lib.fkf_filter_lowrank(self._h, W.data_ptr(), self.n, Wd.data_ptr(), self.n,
+                                       D.data_ptr(), cap, ctypes.byref(r), _stream(stream)))
+        k = r.value
+        return W[:, :k], Wd[:, :k], D[:k]
 
     def close(self):
         if getattr(self, "_h", None):

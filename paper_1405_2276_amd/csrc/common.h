@@ -93,6 +93,12 @@ struct DevBuf {
     if (count)
       FKF_CHECK_HIP(hipMemcpyAsync(p, src, count * sizeof(T), hipMemcpyDeviceToDevice, s));
   }
+  // the same into a buffer grown only when too small
+  void copy_into(const T *src, size_t count, hipStream_t s) {
+    reserve(count);
+    if (count)
+      FKF_CHECK_HIP(hipMemcpyAsync(p, src, count * sizeof(T), hipMemcpyDeviceToDevice, s));
+  }
 };
 
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }

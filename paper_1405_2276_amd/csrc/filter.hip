@@ -49,8 +49,16 @@ struct fkf_obs {
   double ll_const = 0.0;   // -(sum log R + n_m log 2 pi) / 2
 };
 
+// Workspaces of a constant-H basis build (cross covariance, Gram matrices,
+// the dense H^T where needed), kept by the filter so that a rebuild after
+// fkf_filter_reset allocates nothing.
+struct BasisWork {
+  fkf::DevBuf<double> Ht, P, G, A, X;
+};
+
 struct fkf_filter {
   fkf_cov *cov = nullptr;
+  BasisWork bw;
   int64_t n = 0, ldu = 0;
   double theta = 1.0;
   fkf_filter_params params{};
@@ -58,9 +66,10 @@ struct fkf_filter {
   double alpha = 0.0;
   int mode = 0;            // 0: no low-rank term yet, 1: constant-H basis, 2: general
   uint64_t basis_gen = 0;
-  int n_m = 0;
+  int n_m = 0;             // data dimension of the basis' operator
+  int nmode = 0;           // modes of the constant-H basis (columns of U0 and Ve)
   fkf_status failed = FKF_OK;
-  fkf::DevBuf<double> s, U0, Ve, lam, delta, nu, zp, part, tmp, eta;
+  fkf::DevBuf<double> s, U0, Ve, lam, delta, nu, zp, tmp, eta;
   bool mixed = false;              // mixed-precision covariance: U0 also kept in FP32
   fkf::DevBuf<float> U0f;          // FP32 copy of U0 streamed by the per-step GEMVs
   fkf::DevBuf<int64_t> b_rowptr;   // copy of the basis' measurement operator
@@ -74,6 +83,8 @@ struct fkf_filter {
   int rg = 0;
   // scratch reused across general steps
   fkf::DevBuf<double> gP, gHt, gG, gA, gWe, glam, gwork, gtmp;
+  fkf::DevBuf<double> gdv, gll;    // state increment and log-density of a general step,
+                                   // committed only when the whole step succeeds
   fkf::DevBuf<int> chol_flag;
   // innovation log-likelihood: per-mode terms and tangents of the constant-H
   // steps (llq), the sum over general steps (ll_gen, device), the whitening
@@ -113,9 +124,6 @@ bool cov_apply_sparse_rows(fkf_cov *cov, int n_m, const int64_t *rowptr, const i
 
 static std::atomic<uint64_t> g_obs_gen{1};
 
-constexpr int kSegCols = 32;    // columns per GEMV workgroup
-constexpr int kRowsPerWG = 512; // 256 threads x 2 rows
-constexpr int kRowsPerWG32 = 1024; // FP32 basis: 256 threads x 4 rows
 
 // ------------------------------------------------------------- kernels ---
 __global__ void __launch_bounds__(256) k_innov(const int64_t *__restrict__ rowptr,
@@ -227,14 +235,14 @@ __global__ void k_loglik_init(double *__restrict__ q, const double *__restrict__
 // Ve^T H P Ve = Lambda, so the update s += U0 zp moves eta by Lambda zp),
 // then the per-mode gain and D update, and the mode's log-likelihood terms.
 __global__ void __launch_bounds__(256) k_modes_step_eta(const double *__restrict__ Ve, int n_m,
-                                                        const double *__restrict__ y,
+                                                        int nmode, const double *__restrict__ y,
                                                         const double *__restrict__ lam,
                                                         double *__restrict__ delta,
                                                         double *__restrict__ eta, double alpha,
                                                         double *__restrict__ zp,
                                                         double *__restrict__ llq, int *err) {
   int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (j >= n_m) return;
+  if (j >= nmode) return;
   int l = threadIdx.x & 63;
   const double *v = Ve + (int64_t)n_m * j;
   double z = 0;
@@ -256,11 +264,11 @@ __global__ void __launch_bounds__(256) k_modes_step_eta(const double *__restrict
 }
 
 // eta = Ve^T h (one wavefront per mode)
-__global__ void __launch_bounds__(256) k_vet(const double *__restrict__ Ve, int n_m,
+__global__ void __launch_bounds__(256) k_vet(const double *__restrict__ Ve, int n_m, int nmode,
                                              const double *__restrict__ h,
                                              double *__restrict__ eta) {
   int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (j >= n_m) return;
+  if (j >= nmode) return;
   int l = threadIdx.x & 63;
   const double *v = Ve + (int64_t)n_m * j;
   double z = 0;
@@ -273,12 +281,12 @@ __global__ void __launch_bounds__(256) k_vet(const double *__restrict__ Ve, int 
 // zz_j = (Ve[:, j] . h) * Sigma_-_j / lambda_j with Sigma_- = 1 - (1 - D/alpha)^1/2,
 // written as (delta/alpha) / (1 + (1 - delta lambda / alpha)^1/2).
 __global__ void __launch_bounds__(256) k_modes_realize(const double *__restrict__ Ve, int n_m,
-                                                       const double *__restrict__ h,
+                                                       int nmode, const double *__restrict__ h,
                                                        const double *__restrict__ lam,
                                                        const double *__restrict__ delta,
                                                        double alpha, double *__restrict__ zz) {
   int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (j >= n_m) return;
+  if (j >= nmode) return;
   int l = threadIdx.x & 63;
   const double *v = Ve + (int64_t)n_m * j;
   double z = 0;
@@ -291,129 +299,83 @@ __global__ void __launch_bounds__(256) k_modes_realize(const double *__restrict_
   }
 }
 
-// Segmented tall GEMV: part[seg][i] = sum_{j in seg} f(U0[i, j]) z[j] with
-// f(u) = u (SQUARE = false) or u^2 (SQUARE = true).  Two rows per thread with
-// 16-byte loads; every workgroup streams kSegCols columns of a 512-row panel.
-template <bool SQUARE>
-__global__ void __launch_bounds__(256) k_gemv_seg(const double *__restrict__ U0, int64_t n,
-                                                  int64_t ldu, int n_m,
-                                                  const double *__restrict__ z,
-                                                  double *__restrict__ part) {
-  int64_t i0 = (int64_t)blockIdx.x * kRowsPerWG + 2 * threadIdx.x;
-  int j0 = blockIdx.y * kSegCols;
-  int jn = min(kSegCols, n_m - j0);
-  if (i0 >= n) return;
-  double a0 = 0, a1 = 0;
-  const v2d *src = reinterpret_cast<const v2d *>(U0 + i0 + ldu * j0);
-  const int64_t ld2 = ldu / 2;
-  if (jn == kSegCols) {
-    v2d u[kSegCols];
-#pragma unroll
-    for (int jj = 0; jj < kSegCols; ++jj) u[jj] = __builtin_nontemporal_load(src + ld2 * jj);
-#pragma unroll
-    for (int jj = 0; jj < kSegCols; ++jj) {
-      double zj = z[j0 + jj];
-      if (SQUARE) {
-        a0 = fma(u[jj].x * u[jj].x, zj, a0);
-        a1 = fma(u[jj].y * u[jj].y, zj, a1);
-      } else {
-        a0 = fma(u[jj].x, zj, a0);
-        a1 = fma(u[jj].y, zj, a1);
-      }
-    }
-  } else {
-    for (int jj = 0; jj < jn; ++jj) {
-      v2d u = src[ld2 * jj];
-      double zj = z[j0 + jj];
-      if (SQUARE) {
-        a0 = fma(u.x * u.x, zj, a0);
-        a1 = fma(u.y * u.y, zj, a1);
-      } else {
-        a0 = fma(u.x, zj, a0);
-        a1 = fma(u.y, zj, a1);
-      }
-    }
-  }
-  double *o = part + (int64_t)blockIdx.y * n;
-  o[i0] = a0;
-  if (i0 + 1 < n) o[i0 + 1] = a1;
-}
+// Row-panel GEMV with its epilogue, one launch and no partial sums:
+// out_i = epilogue(sum_j f(U[i, j]) z[j]) with f(u) = u, or u^2 (SQUARE),
+// for a column-major n x ncols basis (ld a multiple of 64, rows n..ld-1
+// zero).  A workgroup of eight wavefronts owns one panel of kPanelRows rows
+// (FP64: 128 rows, 2 per lane; FP32: 256 rows, 4 per lane, 16-byte loads);
+// wavefront w streams the columns [w c, (w + 1) c) of the panel, eight
+// loads in flight per lane, and the eight partial sums of a row are added in
+// wavefront order through LDS (fixed order: deterministic).  Epilogues:
+//   kEpiAdd:     s_i += sum                        (state update)
+//   kEpiVar:     out_i = base - sum                (variance)
+//   kEpiRealize: out_i = s_i + salpha (g_i - sum)  (realization)
+constexpr int kEpiAdd = 0, kEpiVar = 1, kEpiRealize = 2;
+template <typename T> struct PanelRows;
+template <> struct PanelRows<double> { static constexpr int v = 128; };
+template <> struct PanelRows<float> { static constexpr int v = 256; };
 
-// As k_gemv_seg with an FP32 matrix (ld a multiple of 4): four rows per
-// thread with 16-byte loads, products and sums in FP64.
-template <bool SQUARE>
-__global__ void __launch_bounds__(256) k_gemv_seg32(const float *__restrict__ U, int64_t n,
-                                                    int64_t ldu, int n_m,
+template <typename T, int EPI, bool SQUARE>
+__global__ void __launch_bounds__(512) k_gemv_panel(const T *__restrict__ U, int64_t n,
+                                                    int64_t ldu, int ncols,
                                                     const double *__restrict__ z,
-                                                    double *__restrict__ part) {
-  typedef float v4f __attribute__((ext_vector_type(4)));
-  int64_t i0 = (int64_t)blockIdx.x * kRowsPerWG32 + 4 * threadIdx.x;
-  int j0 = blockIdx.y * kSegCols;
-  int jn = min(kSegCols, n_m - j0);
-  if (i0 >= n) return;
-  double a[4] = {0, 0, 0, 0};
-  const v4f *src = reinterpret_cast<const v4f *>(U + i0 + ldu * j0);
-  const int64_t ld4 = ldu / 4;
-  auto acc = [&](v4f u, double zj) {
+                                                    double *__restrict__ out,
+                                                    const double *__restrict__ s,
+                                                    const double *__restrict__ g, double base,
+                                                    double salpha, const int *__restrict__ err,
+                                                    int *__restrict__ err_mirror) {
+  constexpr int R = 16 / sizeof(T);            // rows per lane (one 16-byte load)
+  constexpr int PR = PanelRows<T>::v;          // rows per panel = 64 lanes x R
+  typedef T vec __attribute__((ext_vector_type(R)));
+  __shared__ double red[8][PR];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
+  const int64_t r0 = (int64_t)blockIdx.x * PR;
+  const int64_t i0 = r0 + (int64_t)R * l;
+  if (EPI == kEpiAdd && err_mirror != nullptr && blockIdx.x == 0 && threadIdx.x == 0)
+    *err_mirror = *err;   // latched device error, mirrored into pinned host memory
+  const int cpw = (ncols + 7) / 8;
+  const int j0 = w * cpw, j1 = min(ncols, j0 + cpw);
+  double a[R];
 #pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      const double x = (double)u[h];
-      a[h] = SQUARE ? fma(x * x, zj, a[h]) : fma(x, zj, a[h]);
+  for (int h = 0; h < R; ++h) a[h] = 0.0;
+  if (i0 < ldu && j0 < j1) {
+    const vec *src = reinterpret_cast<const vec *>(U + i0 + ldu * (int64_t)j0);
+    const int64_t ldv = ldu / R;
+    auto acc = [&](vec u, double zj) {
+#pragma unroll
+      for (int h = 0; h < R; ++h) {
+        const double x = (double)u[h];
+        a[h] = SQUARE ? fma(x * x, zj, a[h]) : fma(x, zj, a[h]);
+      }
+    };
+    int j = j0;
+    for (; j + 8 <= j1; j += 8) {
+      vec u[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) u[q] = __builtin_nontemporal_load(src + ldv * (j - j0 + q));
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc(u[q], z[j + q]);
     }
-  };
-  if (jn == kSegCols) {
-    v4f u[kSegCols];
-#pragma unroll
-    for (int jj = 0; jj < kSegCols; ++jj) u[jj] = __builtin_nontemporal_load(src + ld4 * jj);
-#pragma unroll
-    for (int jj = 0; jj < kSegCols; ++jj) acc(u[jj], z[j0 + jj]);
-  } else {
-    for (int jj = 0; jj < jn; ++jj) acc(src[ld4 * jj], z[j0 + jj]);
+    for (; j < j1; ++j) acc(__builtin_nontemporal_load(src + ldv * (j - j0)), z[j]);
   }
-  double *o = part + (int64_t)blockIdx.y * n;
 #pragma unroll
-  for (int h = 0; h < 4; ++h)
-    if (i0 + h < n) o[i0 + h] = a[h];
+  for (int h = 0; h < R; ++h) red[w][R * l + h] = a[h];
+  __syncthreads();
+  for (int t = threadIdx.x; t < PR; t += 512) {
+    const int64_t i = r0 + t;
+    if (i >= n) continue;
+    double sum = red[0][t];
+#pragma unroll
+    for (int q = 1; q < 8; ++q) sum += red[q][t];
+    if (EPI == kEpiAdd) out[i] += sum;
+    else if (EPI == kEpiVar) out[i] = base - sum;
+    else out[i] = s[i] + salpha * (g[i] - sum);
+  }
 }
 
 __global__ void k_to_f32(const double *__restrict__ src, float *__restrict__ dst, int64_t len) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < len) dst[i] = (float)src[i];
-}
-
-// s[i] += sum_seg part[seg][i]
-__global__ void k_seg_add(const double *__restrict__ part, int nseg, int64_t n,
-                          double *__restrict__ s, const int *__restrict__ err,
-                          int *__restrict__ err_mirror) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  // one thread mirrors the latched device error flag into pinned host memory
-  // (read by the next host call without a copy of its own)
-  if (err_mirror != nullptr && i == 0) *err_mirror = *err;
-  if (i >= n) return;
-  double a = 0;
-  for (int g = 0; g < nseg; ++g) a += part[(int64_t)g * n + i];
-  s[i] += a;
-}
-
-// var[i] = alpha theta - sum_seg part[seg][i]
-__global__ void k_seg_var(const double *__restrict__ part, int nseg, int64_t n, double base,
-                          double *__restrict__ var) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double a = 0;
-  for (int g = 0; g < nseg; ++g) a += part[(int64_t)g * n + i];
-  var[i] = base - a;
-}
-
-// out[i] = s[i] + sqrt(alpha) (g[i] - sum_seg part[seg][i])
-__global__ void k_seg_realize(const double *__restrict__ part, int nseg, int64_t n,
-                              const double *__restrict__ s, const double *__restrict__ g,
-                              double salpha, double *__restrict__ out) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double a = 0;
-  for (int q = 0; q < nseg; ++q) a += part[(int64_t)q * n + i];
-  out[i] = s[i] + salpha * (g[i] - a);
 }
 
 // out[i] = s[i] + a g[i]
@@ -487,35 +449,96 @@ __global__ void k_copy_strided(const double *__restrict__ src, double *__restric
   if (i < n) dst[i] = src[i];
 }
 
+// Gaussian sketch of the randomized eigensolver (Appendix B), drawn on the
+// device from a counter-based generator: Philox4x32-10 (Salmon, Moraes,
+// Dror, Shaw, SC 2011; multipliers 0xD2511F53, 0xCD9E8D57, key increments
+// 0x9E3779B9, 0xBB67AE85) of the counter (q mod 2^32, q div 2^32, 0, 0) under
+// the key (seed mod 2^32, seed div 2^32), then the Box-Muller pair of the two
+// 53-bit uniforms u1 = ((x0 >> 6) 2^27 + (x1 >> 5) + 1/2) 2^-53, u2 likewise:
+// numbers 2q and 2q + 1 are sqrt(-2 ln u1) (cos, sin)(2 pi u2).  One thread
+// per pair q.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    if (i > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = (uint32_t)p1;
+    c[2] = n2;
+    c[3] = (uint32_t)p0;
+  }
+}
+
+__global__ void k_sketch_normals(uint64_t seed, int64_t count, double *__restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (2 * q >= count) return;
+  uint32_t c[4] = {(uint32_t)q, (uint32_t)((uint64_t)q >> 32), 0u, 0u};
+  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const double sc = 1.0 / 9007199254740992.0;   // 2^-53
+  const double u1 = ((double)(c[0] >> 6) * 134217728.0 + (double)(c[1] >> 5) + 0.5) * sc;
+  const double u2 = ((double)(c[2] >> 6) * 134217728.0 + (double)(c[3] >> 5) + 0.5) * sc;
+  const double rho = sqrt(-2.0 * log(u1));
+  const double t = 2.0 * M_PI * u2;
+  out[2 * q] = rho * cos(t);
+  if (2 * q + 1 < count) out[2 * q + 1] = rho * sin(t);
+}
+
 // --------------------------------------------------------------- helpers ---
 static unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
-// part[seg][i] = sum_j f(M[i, j]) z[j] over column segments of M (n x ncols, ld ld)
-static void gemv_seg_m(const double *M, int64_t ld, int ncols, int64_t n, const double *z,
-                       bool square, double *part, hipStream_t st) {
-  FKF_TRACE(square ? "filter_gemv_sq" : "filter_gemv", st);
-  int nseg = (ncols + kSegCols - 1) / kSegCols;
-  dim3 grid(blocks(n, kRowsPerWG), (unsigned)nseg);
-  if (square)
-    hipLaunchKernelGGL(k_gemv_seg<true>, grid, dim3(256), 0, st, M, n, ld, ncols, z, part);
-  else
-    hipLaunchKernelGGL(k_gemv_seg<false>, grid, dim3(256), 0, st, M, n, ld, ncols, z, part);
+// out = epilogue(f(M) z) for a column-major n x ncols matrix M (ld a multiple
+// of 64) in FP64 or FP32 (k_gemv_panel).
+struct GemvEpi {
+  int kind = kEpiAdd;
+  const double *s = nullptr, *g = nullptr;
+  double base = 0.0, salpha = 0.0;
+  const int *err = nullptr;
+  int *err_mirror = nullptr;
+};
+
+template <typename T>
+static void gemv_panel_t(const T *M, int64_t ld, int ncols, int64_t n, const double *z,
+                         bool square, double *out, const GemvEpi &e, hipStream_t st) {
+  const unsigned grid = (unsigned)((ld + PanelRows<T>::v - 1) / PanelRows<T>::v);
+  if (grid == 0) return;
+#define FKF_GEMV_LAUNCH(EPI, SQ)                                                            \
+  hipLaunchKernelGGL((k_gemv_panel<T, EPI, SQ>), dim3(grid), dim3(512), 0, st, M, n, ld, ncols, \
+                     z, out, e.s, e.g, e.base, e.salpha, e.err, e.err_mirror)
+  if (e.kind == kEpiAdd) {
+    if (square) FKF_GEMV_LAUNCH(kEpiAdd, true);
+    else FKF_GEMV_LAUNCH(kEpiAdd, false);
+  } else if (e.kind == kEpiVar) {
+    if (square) FKF_GEMV_LAUNCH(kEpiVar, true);
+    else FKF_GEMV_LAUNCH(kEpiVar, false);
+  } else {
+    if (square) FKF_GEMV_LAUNCH(kEpiRealize, true);
+    else FKF_GEMV_LAUNCH(kEpiRealize, false);
+  }
+#undef FKF_GEMV_LAUNCH
 }
 
-static void gemv_seg(const fkf_filter *f, const double *z, bool square, hipStream_t st) {
+static void gemv_panel_m(const double *M, int64_t ld, int ncols, int64_t n, const double *z,
+                         bool square, double *out, const GemvEpi &e, hipStream_t st) {
+  FKF_TRACE(square ? "filter_gemv_sq" : "filter_gemv", st);
+  gemv_panel_t<double>(M, ld, ncols, n, z, square, out, e, st);
+}
+
+// The same over the filter's constant-H basis U0 (its FP32 copy in the mixed
+// mode).
+static void gemv_panel(const fkf_filter *f, const double *z, bool square, double *out,
+                       const GemvEpi &e, hipStream_t st) {
   if (f->mixed) {
     FKF_TRACE(square ? "filter_gemv_sq32" : "filter_gemv32", st);
-    int nseg = (f->n_m + kSegCols - 1) / kSegCols;
-    dim3 grid(blocks(f->n, kRowsPerWG32), (unsigned)nseg);
-    if (square)
-      hipLaunchKernelGGL(k_gemv_seg32<true>, grid, dim3(256), 0, st, f->U0f.p, f->n, f->ldu,
-                         f->n_m, z, f->part.p);
-    else
-      hipLaunchKernelGGL(k_gemv_seg32<false>, grid, dim3(256), 0, st, f->U0f.p, f->n, f->ldu,
-                         f->n_m, z, f->part.p);
+    gemv_panel_t<float>(f->U0f.p, f->ldu, f->nmode, f->n, z, square, out, e, st);
     return;
   }
-  gemv_seg_m(f->U0.p, f->ldu, f->n_m, f->n, z, square, f->part.p, st);
+  gemv_panel_m(f->U0.p, f->ldu, f->nmode, f->n, z, square, out, e, st);
 }
 
 // Stopping tolerance of the projected generalized eigenproblem (relative
@@ -610,131 +633,34 @@ static void lanes_join(LanePool &p, hipStream_t st) {
   }
 }
 
-// Lane of each filter: filters that share a covariance operator (whose
-// product workspace is not reentrant) share a lane.
+// Lane of each filter: filters that use a common operator (their covariance
+// or their length-derivative operator, whose product workspaces are not
+// reentrant) share a lane.  Filters are joined into groups through every
+// operator they use (union-find), and each group takes one lane.
 static std::vector<int> lanes_of(fkf_filter *const *fs, int count) {
-  std::map<const fkf_cov *, int> m;
+  std::vector<int> up(count);
+  for (int i = 0; i < count; ++i) up[i] = i;
+  auto root = [&](int i) {
+    while (up[i] != i) i = up[i] = up[up[i]];
+    return i;
+  };
+  std::map<const fkf_cov *, int> owner;   // operator -> a filter that uses it
+  for (int i = 0; i < count; ++i)
+    for (const fkf_cov *c : {(const fkf_cov *)fs[i]->cov, (const fkf_cov *)fs[i]->dcov}) {
+      if (!c) continue;
+      auto it = owner.find(c);
+      if (it == owner.end()) owner.emplace(c, i);
+      else up[root(i)] = root(it->second);
+    }
+  std::map<int, int> group_lane;
   std::vector<int> lane(count);
   for (int i = 0; i < count; ++i) {
-    auto it = m.find(fs[i]->cov);
-    if (it == m.end()) it = m.emplace(fs[i]->cov, (int)m.size() % kLanes).first;
+    auto it = group_lane.find(root(i));
+    if (it == group_lane.end())
+      it = group_lane.emplace(root(i), (int)group_lane.size() % kLanes).first;
     lane[i] = it->second;
   }
   return lane;
-}
-
-// Constant-H bases of count filters (filter i with operator obs[i]): the
-// cross covariances, innovation Grams and, after one batched eigensolve of
-// the projected problems, the bases and carriers.  With several filters the
-// per-filter work runs on kLanes streams (joined before the eigensolve and
-// at the end).
-struct BasisWork {
-  DevBuf<double> Ht, P, G, A, X;
-};
-
-static void build_bases(fkf_filter *const *fs, const fkf_obs *const *os, int count,
-                        hipStream_t st) {
-  FKF_TRACE("gep_total", st);
-  std::vector<BasisWork> bw(count);
-  std::vector<EigProblem> probs(count);
-  const bool multi = count > 1;
-  LanePool *lp = multi ? &lane_pool() : nullptr;
-  const std::vector<int> lane = lanes_of(fs, count);
-  auto sti = [&](int i) { return multi ? lp->s[lane[i]] : st; };
-  if (multi) lanes_fork(*lp, st);
-  for (int i = 0; i < count; ++i) {
-    fkf_filter *f = fs[i];
-    const fkf_obs *o = os[i];
-    const int64_t n = f->n;
-    const int nm = o->n_m;
-    hipStream_t si = sti(i);
-    bw[i].P.reserve((size_t)n * nm);
-    bw[i].G.reserve((size_t)nm * nm);
-    bw[i].A.reserve((size_t)nm * nm);
-    f->lam.alloc(nm);
-    f->Ve.alloc((size_t)nm * nm);
-    {
-      FKF_TRACE("gep_cross_cov", si);
-      cross_cov(f->cov, o, bw[i].Ht, bw[i].P.p, n, si);
-    }
-    innovation_gram(o->rowptr.p, o->col.p, o->val.p, nm, n, bw[i].P.p, o->noise.p, bw[i].G.p,
-                    bw[i].A.p, si);
-    probs[i] = EigProblem{bw[i].A.p, nm, nm, 0, f->lam.p, f->Ve.p, nm};
-  }
-  if (multi) lanes_join(*lp, st);
-  {
-    FKF_TRACE("gep_eig", st);
-    double tol = 1.0;
-    for (int i = 0; i < count; ++i) tol = std::min(tol, gep_tol(fs[i]));
-    sym_eig_batched(probs.data(), count, st, fs[0]->eig, tol);
-  }
-  if (multi) lanes_fork(*lp, st);
-  for (int i = 0; i < count; ++i) {
-    fkf_filter *f = fs[i];
-    const fkf_obs *o = os[i];
-    const int64_t n = f->n;
-    const int nm = o->n_m;
-    hipStream_t si = sti(i);
-    hipLaunchKernelGGL(k_clamp_nonneg, dim3(blocks(nm)), dim3(256), 0, si, f->lam.p, nm);
-    f->llq.alloc((size_t)kLLStride * nm);
-    hipLaunchKernelGGL(k_loglik_init, dim3(blocks(nm)), dim3(256), 0, si, f->llq.p, f->lam.p, nm,
-                       f->alpha);
-    scale_rows(nm, nm, o->inv_sqrt_noise.p, f->Ve.p, nm, si);
-    f->ldu = (n + 63) / 64 * 64;
-    f->U0.alloc((size_t)f->ldu * nm);
-    fill(f->U0.p, f->ldu * nm, 0.0, si);
-    {
-      FKF_TRACE("gep_basis_gemm", si);
-      gemm_nn(n, nm, nm, bw[i].P.p, n, f->Ve.p, nm, f->U0.p, f->ldu, si);
-    }
-    if (f->dcov) {
-      // Ad = X^T (dGamma/d ell) X with X = H^T Ve; Cd starts at alpha Ad
-      FKF_TRACE("loglik_length_setup", si);
-      bw[i].X.reserve((size_t)n * nm);
-      bw[i].Ht.reserve((size_t)n * nm);
-      dense_ht(o->rowptr.p, o->col.p, o->val.p, nm, n, bw[i].Ht.p, si);
-      gemm_nn(n, nm, nm, bw[i].Ht.p, n, f->Ve.p, nm, bw[i].X.p, n, si);
-      fkf_status rc = fkf_cov_apply(f->dcov, bw[i].X.p, n, nm, bw[i].P.p, n, (void *)si);
-      if (rc != FKF_OK) throw Error{rc, std::string("derivative product failed: ") + fkf_last_error()};
-      f->ll_Ad.alloc((size_t)nm * nm);
-      f->ll_Cd.alloc((size_t)nm * nm);
-      gemm(true, false, nm, nm, n, 1.0, bw[i].X.p, n, bw[i].P.p, n, 0.0, f->ll_Ad.p, nm, si,
-           &f->gwork);
-      symmetrize(f->ll_Ad.p, nm, si);
-      copy2d(nm, nm, f->ll_Ad.p, nm, f->ll_Cd.p, nm, si);
-      scale2d(nm, nm, f->alpha, f->ll_Cd.p, nm, si);
-    }
-    if (f->mixed) {
-      f->U0f.alloc((size_t)f->ldu * nm);
-      const int64_t len = f->ldu * (int64_t)nm;
-      if (len > 0)
-        hipLaunchKernelGGL(k_to_f32, dim3(blocks(len)), dim3(256), 0, si, f->U0.p, f->U0f.p, len);
-    }
-    f->delta.alloc(nm);
-    fill(f->delta.p, nm, 0.0, si);
-    f->nu.alloc(nm);
-    f->zp.alloc(nm);
-    f->tmp.alloc(nm);
-    int nseg = (nm + kSegCols - 1) / kSegCols;
-    f->part.alloc((size_t)nseg * n);
-    f->b_rowptr.copy_from(o->rowptr.p, (size_t)nm + 1, si);
-    f->b_col.copy_from(o->col.p, (size_t)o->nnz, si);
-    f->b_val.copy_from(o->val.p, (size_t)o->nnz, si);
-    // eta = Ve^T H s for the current estimate
-    f->eta.alloc(nm);
-    spmv(o->rowptr.p, o->col.p, o->val.p, nm, f->s.p, f->nu.p, si);
-    hipLaunchKernelGGL(k_vet, dim3(blocks(nm, 4)), dim3(256), 0, si, f->Ve.p, nm, f->nu.p,
-                       f->eta.p);
-    f->n_m = nm;
-    f->mode = 1;
-    f->basis_gen = o->gen;
-  }
-  if (multi) lanes_join(*lp, st);
-  FKF_CHECK_HIP(hipStreamSynchronize(st));   // Ht, P, G, A are released on return
-}
-
-static void build_basis(fkf_filter *f, const fkf_obs *o, hipStream_t st) {
-  build_bases(&f, &o, 1, st);
 }
 
 static std::vector<double> to_host(const double *p, size_t n, hipStream_t st) {
@@ -758,13 +684,243 @@ static int count_above(const std::vector<double> &v, double thr) {
   return r;
 }
 
+// The part of a constant-H basis build shared by the exact and the
+// randomized eigensolver, once lam (nmode modes, descending), Ve (n_m x nmode)
+// and U0 (n x nmode, ld ldu) are in place: the FP32 copy of the basis, the
+// carriers delta = 0, the per-mode log-likelihood state, a copy of the
+// operator and eta = Ve^T H s for the current estimate.
+static void basis_tail(fkf_filter *f, const fkf_obs *o, int nmode, hipStream_t si) {
+  const int nm = o->n_m;
+  f->n_m = nm;
+  f->nmode = nmode;
+  if (f->mixed) {
+    f->U0f.reserve((size_t)f->ldu * nmode);
+    const int64_t len = f->ldu * (int64_t)nmode;
+    if (len > 0)
+      hipLaunchKernelGGL(k_to_f32, dim3(blocks(len)), dim3(256), 0, si, f->U0.p, f->U0f.p, len);
+  }
+  f->llq.reserve((size_t)kLLStride * nmode);
+  hipLaunchKernelGGL(k_loglik_init, dim3(blocks(nmode)), dim3(256), 0, si, f->llq.p, f->lam.p,
+                     nmode, f->alpha);
+  f->delta.reserve(nmode);
+  fill(f->delta.p, nmode, 0.0, si);
+  f->nu.reserve(std::max(nm, nmode));
+  f->zp.reserve(nmode);
+  f->tmp.reserve(nmode);
+  f->b_rowptr.copy_into(o->rowptr.p, (size_t)nm + 1, si);
+  f->b_col.copy_into(o->col.p, (size_t)o->nnz, si);
+  f->b_val.copy_into(o->val.p, (size_t)o->nnz, si);
+  f->eta.reserve(nmode);
+  spmv(o->rowptr.p, o->col.p, o->val.p, nm, f->s.p, f->nu.p, si);
+  hipLaunchKernelGGL(k_vet, dim3(blocks(nmode, 4)), dim3(256), 0, si, f->Ve.p, nm, nmode, f->nu.p,
+                     f->eta.p);
+  f->mode = 1;
+  f->basis_gen = o->gen;
+}
+
+// Constant-H bases of count filters (filter i with operator obs[i]): the
+// cross covariances, innovation Grams and, after one batched eigensolve of
+// the projected problems, the bases and carriers.  With several filters the
+// per-filter work runs on kLanes streams (joined before the eigensolve and
+// at the end).
+static void build_bases(fkf_filter *const *fs, const fkf_obs *const *os, int count,
+                        hipStream_t st) {
+  FKF_TRACE("gep_total", st);
+  std::vector<EigProblem> probs(count);
+  const bool multi = count > 1;
+  LanePool *lp = multi ? &lane_pool() : nullptr;
+  const std::vector<int> lane = lanes_of(fs, count);
+  auto sti = [&](int i) { return multi ? lp->s[lane[i]] : st; };
+  if (multi) lanes_fork(*lp, st);
+  for (int i = 0; i < count; ++i) {
+    fkf_filter *f = fs[i];
+    const fkf_obs *o = os[i];
+    const int64_t n = f->n;
+    const int nm = o->n_m;
+    hipStream_t si = sti(i);
+    fs[i]->bw.P.reserve((size_t)n * nm);
+    fs[i]->bw.G.reserve((size_t)nm * nm);
+    fs[i]->bw.A.reserve((size_t)nm * nm);
+    f->lam.reserve(nm);
+    f->Ve.reserve((size_t)nm * nm);
+    {
+      FKF_TRACE("gep_cross_cov", si);
+      cross_cov(f->cov, o, fs[i]->bw.Ht, fs[i]->bw.P.p, n, si);
+    }
+    innovation_gram(o->rowptr.p, o->col.p, o->val.p, nm, n, fs[i]->bw.P.p, o->noise.p, fs[i]->bw.G.p,
+                    fs[i]->bw.A.p, si);
+    probs[i] = EigProblem{fs[i]->bw.A.p, nm, nm, 0, f->lam.p, f->Ve.p, nm};
+  }
+  if (multi) lanes_join(*lp, st);
+  {
+    FKF_TRACE("gep_eig", st);
+    double tol = 1.0;
+    for (int i = 0; i < count; ++i) tol = std::min(tol, gep_tol(fs[i]));
+    sym_eig_batched(probs.data(), count, st, fs[0]->eig, tol);
+  }
+  if (multi) lanes_fork(*lp, st);
+  for (int i = 0; i < count; ++i) {
+    fkf_filter *f = fs[i];
+    const fkf_obs *o = os[i];
+    const int64_t n = f->n;
+    const int nm = o->n_m;
+    hipStream_t si = sti(i);
+    hipLaunchKernelGGL(k_clamp_nonneg, dim3(blocks(nm)), dim3(256), 0, si, f->lam.p, nm);
+    scale_rows(nm, nm, o->inv_sqrt_noise.p, f->Ve.p, nm, si);
+    f->ldu = (n + 63) / 64 * 64;
+    f->U0.reserve((size_t)f->ldu * nm);
+    fill(f->U0.p, f->ldu * nm, 0.0, si);
+    {
+      FKF_TRACE("gep_basis_gemm", si);
+      gemm_nn(n, nm, nm, fs[i]->bw.P.p, n, f->Ve.p, nm, f->U0.p, f->ldu, si);
+    }
+    if (f->dcov) {
+      // Ad = X^T (dGamma/d ell) X with X = H^T Ve; Cd starts at alpha Ad
+      FKF_TRACE("loglik_length_setup", si);
+      fs[i]->bw.X.reserve((size_t)n * nm);
+      fs[i]->bw.Ht.reserve((size_t)n * nm);
+      dense_ht(o->rowptr.p, o->col.p, o->val.p, nm, n, fs[i]->bw.Ht.p, si);
+      gemm_nn(n, nm, nm, fs[i]->bw.Ht.p, n, f->Ve.p, nm, fs[i]->bw.X.p, n, si);
+      fkf_status rc = fkf_cov_apply(f->dcov, fs[i]->bw.X.p, n, nm, fs[i]->bw.P.p, n, (void *)si);
+      if (rc != FKF_OK) throw Error{rc, std::string("derivative product failed: ") + fkf_last_error()};
+      f->ll_Ad.reserve((size_t)nm * nm);
+      f->ll_Cd.reserve((size_t)nm * nm);
+      gemm(true, false, nm, nm, n, 1.0, fs[i]->bw.X.p, n, fs[i]->bw.P.p, n, 0.0, f->ll_Ad.p, nm, si,
+           &f->gwork);
+      symmetrize(f->ll_Ad.p, nm, si);
+      copy2d(nm, nm, f->ll_Ad.p, nm, f->ll_Cd.p, nm, si);
+      scale2d(nm, nm, f->alpha, f->ll_Cd.p, nm, si);
+    }
+    basis_tail(f, o, nm, si);
+  }
+  if (multi) lanes_join(*lp, st);
+}
+
+// Constant-H basis by the randomized algorithm of Appendix B (one filter):
+// Omega (n x r, r = k + p) from the sketch stream; M = R^-1 H Omega and
+// Ybar = H^T M (A Omega with A = H^T R^-1 H); Z = Gamma Ybar (an r-column
+// H-matrix product); a Gamma-orthonormal basis of range(Ybar) from two
+// passes of Gram eigen-decompositions (Gram = Ybar^T Z, directions with
+// eigenvalue <= 1e-12 of the largest dropped, then the same once more on the
+// result), i.e. Qhat = Ybar C with Qhat^T Gamma Qhat = I and Q = Z C;
+// T = (H Q)^T R^-1 (H Q) = S Lambda S^T; the k largest modes with
+// lambda > 1e-13 lambda_max give U = Q S_k, stored as U0 = U Lambda^1/2 and
+// Ve = R^-1 H U Lambda^-1/2 (so that the constant-H step projects the data
+// with Ve exactly as in the exact form).
+static void build_basis_randomized(fkf_filter *f, const fkf_obs *o, hipStream_t st) {
+  FKF_TRACE("gep_total", st);
+  const int64_t n = f->n;
+  const int nm = o->n_m;
+  const int k = f->params.gep_rank > 0 ? std::min(f->params.gep_rank, nm) : nm;
+  const int r = (int)std::min<int64_t>((int64_t)k + f->params.oversample, n);
+  BasisWork &w = f->bw;
+  w.X.reserve((size_t)n * r);   // Omega, then Ybar C1
+  w.P.reserve((size_t)n * r);   // Ybar
+  w.Ht.reserve((size_t)n * nm);
+  DevBuf<double> &Z = f->gP, &HZ = f->gG, &sm = f->gA;   // reused general-step workspaces
+  Z.reserve((size_t)n * r);
+  HZ.reserve((size_t)nm * r);
+  // small r x r work: M (nm x r), G1, V1, C1, G2, V2, C, HQ (nm x r), T, S
+  const size_t rr = (size_t)r * r;
+  sm.reserve(8 * rr + 2 * (size_t)nm * r + 4 * (size_t)r);
+  double *M = sm.p, *G1 = M + (size_t)nm * r, *V1 = G1 + rr, *C1 = V1 + rr, *G2 = C1 + rr,
+         *V2 = G2 + rr, *C = V2 + rr, *HQ = C + rr, *T = HQ + (size_t)nm * r, *S = T + rr,
+         *ev = S + rr;
+  {
+    FKF_TRACE("gep_sketch", st);
+    const int64_t cnt = n * (int64_t)r;
+    hipLaunchKernelGGL(k_sketch_normals, dim3(blocks((cnt + 1) / 2)), dim3(256), 0, st,
+                       f->params.seed, cnt, w.X.p);
+    sp_dense(o->rowptr.p, o->col.p, o->val.p, nm, w.X.p, n, r, M, st);
+    scale_rows(nm, r, o->inv_sqrt_noise.p, M, nm, st);
+    scale_rows(nm, r, o->inv_sqrt_noise.p, M, nm, st);
+    dense_ht(o->rowptr.p, o->col.p, o->val.p, nm, n, w.Ht.p, st);
+    gemm_nn(n, r, nm, w.Ht.p, n, M, nm, w.P.p, n, st);
+  }
+  {
+    FKF_TRACE("gep_cross_cov", st);
+    fkf_status rc = fkf_cov_apply(f->cov, w.P.p, n, r, Z.p, n, (void *)st);
+    if (rc != FKF_OK) throw Error{rc, std::string("covariance product failed: ") + fkf_last_error()};
+  }
+  FKF_TRACE("gep_eig", st);
+  // first pass: Gram = Ybar^T Gamma Ybar = Q1 Theta Q1^T, C1 = Q1 Theta^-1/2
+  gemm(true, false, r, r, n, 1.0, w.P.p, n, Z.p, n, 0.0, G1, r, st, &f->gwork);
+  symmetrize(G1, r, st);
+  sym_eig(G1, r, r, ev, V1, r, st, f->eig);
+  std::vector<double> th = to_host(ev, r, st);
+  const int r1 = count_above(th, 1e-12 * (th.empty() ? 0.0 : th[0]));
+  if (r1 == 0) throw Error{FKF_E_RANK, "fkf_filter_step: the sketch of H^T R^-1 H is zero"};
+  std::vector<double> ith(r1);
+  for (int j = 0; j < r1; ++j) ith[j] = 1.0 / std::sqrt(th[j]);
+  DevBuf<double> s_i;
+  upload_vec(s_i, ith, st);
+  copy2d(r, r1, V1, r, C1, r, st);
+  scale_cols(r, r1, s_i.p, C1, r, st);
+  // second pass on Qhat1 = Ybar C1, Q1 = Z C1: Gram2 = C1^T (Ybar^T Z) C1 recomputed from the
+  // vectors (Qhat1^T Q1), so that the rounding of the first pass is removed
+  gemm_nn(n, r1, r, w.P.p, n, C1, r, w.X.p, n, st);                // Qhat1 (in X)
+  gemm_nn(n, r1, r, Z.p, n, C1, r, w.Ht.p, n, st);                 // Q1 (in Ht, n x r1 <= n x nm?)
+  gemm(true, false, r1, r1, n, 1.0, w.X.p, n, w.Ht.p, n, 0.0, G2, r1, st, &f->gwork);
+  symmetrize(G2, r1, st);
+  sym_eig(G2, r1, r1, ev, V2, r1, st, f->eig);
+  std::vector<double> th2 = to_host(ev, r1, st);
+  const int r2 = count_above(th2, 1e-12 * (th2.empty() ? 0.0 : th2[0]));
+  std::vector<double> ith2(r2);
+  for (int j = 0; j < r2; ++j) ith2[j] = 1.0 / std::sqrt(th2[j]);
+  upload_vec(s_i, ith2, st);
+  scale_cols(r1, r2, s_i.p, V2, r1, st);
+  gemm_nn(r, r2, r1, C1, r, V2, r1, C, r, st);                    // C = C1 V2 Theta2^-1/2
+  // T = (H Q)^T R^-1 (H Q) with H Q = (H Z) C, whitened: B = R^-1/2 H Q (in HQ)
+  sp_dense(o->rowptr.p, o->col.p, o->val.p, nm, Z.p, n, r, HZ.p, st);
+  gemm_nn(nm, r2, r, HZ.p, nm, C, r, HQ, nm, st);
+  scale_rows(nm, r2, o->inv_sqrt_noise.p, HQ, nm, st);
+  gemm(true, false, r2, r2, nm, 1.0, HQ, nm, HQ, nm, 0.0, T, r2, st, &f->gwork);
+  symmetrize(T, r2, st);
+  sym_eig(T, r2, r2, ev, S, r2, st, f->eig, gep_tol(f));
+  std::vector<double> lam = to_host(ev, r2, st);
+  const int kk = std::min(k, count_above(lam, 1e-13 * (lam.empty() ? 0.0 : lam[0])));
+  if (kk == 0) throw Error{FKF_E_RANK, "fkf_filter_step: the operator carries no information"};
+  lam.resize(kk);
+  std::vector<double> sl(kk), isl(kk);
+  for (int j = 0; j < kk; ++j) {
+    sl[j] = std::sqrt(lam[j]);
+    isl[j] = 1.0 / sl[j];
+  }
+  // U0 = Z (C S_k Lambda^1/2), Ve = R^-1/2 (B S_k) Lambda^-1/2
+  f->lam.reserve(kk);
+  FKF_CHECK_HIP(hipMemcpyAsync(f->lam.p, lam.data(), kk * sizeof(double), hipMemcpyHostToDevice, st));
+  DevBuf<double> s_l, CS((size_t)r * kk);
+  upload_vec(s_l, sl, st);
+  gemm_nn(r, kk, r2, C, r, S, r2, CS.p, r, st);
+  scale_cols(r, kk, s_l.p, CS.p, r, st);
+  f->ldu = (n + 63) / 64 * 64;
+  f->U0.reserve((size_t)f->ldu * kk);
+  fill(f->U0.p, f->ldu * kk, 0.0, st);
+  {
+    FKF_TRACE("gep_basis_gemm", st);
+    gemm_nn(n, kk, r, Z.p, n, CS.p, r, f->U0.p, f->ldu, st);
+  }
+  f->Ve.reserve((size_t)nm * kk);
+  gemm_nn(nm, kk, r2, HQ, nm, S, r2, f->Ve.p, nm, st);
+  upload_vec(s_l, isl, st);
+  scale_cols(nm, kk, s_l.p, f->Ve.p, nm, st);
+  scale_rows(nm, kk, o->inv_sqrt_noise.p, f->Ve.p, nm, st);
+  basis_tail(f, o, kk, st);
+  FKF_CHECK_HIP(hipStreamSynchronize(st));   // the small host-uploaded vectors are released
+}
+
+static void build_basis(fkf_filter *f, const fkf_obs *o, hipStream_t st) {
+  if (f->params.gep_mode == FKF_GEP_RANDOMIZED) build_basis_randomized(f, o, st);
+  else build_bases(&f, &o, 1, st);
+}
+
 // Constant-H form -> general form: W = U0 Lambda^-1/2 (= U), Wd = H_b^T Ve
 // Lambda^-1/2 (= Gamma^-1 U), D = delta lambda, keeping the modes with
 // lambda > 1e-13 lambda_max (the others carry Gamma^-1-norm sqrt(lambda)).
 static void to_general(fkf_filter *f, hipStream_t st) {
   const int64_t n = f->n;
   const int nm = f->n_m;
-  std::vector<double> lam = to_host(f->lam.p, nm, st), del = to_host(f->delta.p, nm, st);
+  std::vector<double> lam = to_host(f->lam.p, f->nmode, st), del = to_host(f->delta.p, f->nmode, st);
   const int r = count_above(lam, 1e-13 * (lam.empty() ? 0.0 : lam[0]));
   std::vector<double> isl(r), dg(r);
   for (int j = 0; j < r; ++j) {
@@ -794,6 +950,12 @@ __global__ void k_general_coefs(const double *__restrict__ D, int r, double alph
   if (e >= (int64_t)r * nm) return;
   int j = (int)(e % r), m = (int)(e / r);
   T[j + (int64_t)r * m] = D[j] * HWt[m + (int64_t)nm * j];
+}
+
+// x[i] += d[i]
+__global__ void k_add_vec(double *__restrict__ x, const double *__restrict__ d, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] += d[i];
 }
 
 __global__ void k_add_diag(double *__restrict__ S, int m, const double *__restrict__ d) {
@@ -861,9 +1023,11 @@ static void step_general(fkf_filter *f, const fkf_obs *o, const double *y, hipSt
     f->ll_gen.alloc(1);
     fill(f->ll_gen.p, 1, 0.0, st);
   }
-  chol_solve(S.p, nm, c.p, f->chol_flag.p, f->err.p, st, f->ll_gen.p);
-  f->ll_general = true;
-  gemm(false, false, n, 1, nm, 1.0, F.p, n, c.p, nm, 1.0, f->s.p, n, st, nullptr);
+  f->gll.reserve(1);
+  fill(f->gll.p, 1, 0.0, st);
+  chol_solve(S.p, nm, c.p, f->chol_flag.p, f->err.p, st, f->gll.p);
+  f->gdv.reserve((size_t)n);
+  gemm(false, false, n, 1, nm, 1.0, F.p, n, c.p, nm, 0.0, f->gdv.p, n, st, nullptr);
   // covariance: Dbar = D / (a1 (a1 - D)); AddLowRank(W, Dbar, U, Lambda; Gamma^-1)
   std::vector<double> dh = to_host(f->Dg.p, r, st);
   std::vector<double> dbar(r);
@@ -923,12 +1087,23 @@ static void step_general(fkf_filter *f, const fkf_obs *o, const double *y, hipSt
     FKF_TRACE("general_addlowrank_eig", st);
     sym_eig(M.p, rt, rt, mu.p, Sm.p, rt, st, f->eig);
   }
+  // the device status of this step (non-finite data, a non-positive pivot of
+  // S) arrives with the eigenvalues of M
+  FKF_CHECK_HIP(hipMemcpyAsync(f->err_host, f->err.p, sizeof(int), hipMemcpyDeviceToHost, st));
   std::vector<double> muh = to_host(mu.p, rt, st);
+  if (*f->err_host != 0)
+    throw Error{(fkf_status)*f->err_host,
+                "fkf_filter_step: the innovation covariance is not positive definite or the "
+                "data are not finite"};
   const double mmax = muh.empty() ? 0.0 : muh[0];
   const double rtol = f->params.rank_rtol > 0 ? f->params.rank_rtol : 1e-14;
   const int rn = count_above(muh, rtol * mmax);
   if (rn > f->params.max_rank)
     throw Error{FKF_E_RANK, "fkf_filter_step: the low-rank term exceeds max_rank"};
+  // the step succeeds: commit the state, the log-density and the new basis
+  hipLaunchKernelGGL(k_add_vec, dim3(blocks(n)), dim3(256), 0, st, f->s.p, f->gdv.p, n);
+  hipLaunchKernelGGL(k_add_vec, dim3(1), dim3(256), 0, st, f->ll_gen.p, f->gll.p, (int64_t)1);
+  f->ll_general = true;
   // W <- [W Vh] S, Wd <- [Wd Vhd] S, D <- a1^2 mu / (1 + a1 mu)
   DevBuf<double> Wn((size_t)ldu * std::max(rn, 1)), Wdn((size_t)ldu * std::max(rn, 1));
   gemm(false, false, n, rn, rt, 1.0, Wc.p, ldu, Sm.p, rt, 0.0, Wn.p, ldu, st, nullptr);
@@ -940,7 +1115,6 @@ static void step_general(fkf_filter *f, const fkf_obs *o, const double *y, hipSt
   f->W = std::move(Wn);
   f->Wd = std::move(Wdn);
   f->rg = rn;
-  f->part.reserve((size_t)((rn + kSegCols - 1) / kSegCols + 1) * n);
   f->tmp.reserve(std::max(rn, 1));
   f->nu.reserve(std::max(rn, 1));
 }
@@ -1125,8 +1299,11 @@ extern "C" fkf_status fkf_filter_create(fkf_cov *cov, const double *s0, double a
     FKF_REQUIRE(cov_kind(cov) < FKF_MATERN_12_DLENGTH,
                 "fkf_filter_create: a length-derivative operator is not a covariance");
     FKF_REQUIRE(alpha0 >= 0 && std::isfinite(alpha0), "fkf_filter_create: alpha0 must be >= 0");
-    if (params) FKF_REQUIRE(params->struct_size == sizeof(fkf_filter_params),
-                            "fkf_filter_create: params struct_size");
+    constexpr uint32_t kParamsV1 = 16;   // struct_size of the first three fields alone
+    if (params)
+      FKF_REQUIRE(params->struct_size == sizeof(fkf_filter_params) ||
+                      params->struct_size == kParamsV1,
+                  "fkf_filter_create: params struct_size");
     hipStream_t st = as_stream(stream);
     auto f = std::make_unique<fkf_filter>();
     f->cov = cov;
@@ -1134,12 +1311,24 @@ extern "C" fkf_status fkf_filter_create(fkf_cov *cov, const double *s0, double a
     f->theta = cov_variance(cov);
     f->mixed = cov_mixed(cov);
     f->alpha = alpha0;
+    f->params = fkf_filter_params{};
+    f->params.struct_size = sizeof(fkf_filter_params);
+    f->params.max_rank = 4096;
+    f->params.rank_rtol = 0.0;
+    f->params.gep_mode = FKF_GEP_EXACT;
+    f->params.oversample = 20;
     if (params) {
-      f->params = *params;
-    } else {
-      f->params.struct_size = sizeof(fkf_filter_params);
-      f->params.max_rank = 4096;
-      f->params.rank_rtol = 0.0;
+      f->params.max_rank = params->max_rank;
+      f->params.rank_rtol = params->rank_rtol;
+      if (params->struct_size == sizeof(fkf_filter_params)) {
+        FKF_REQUIRE(params->gep_mode == FKF_GEP_EXACT || params->gep_mode == FKF_GEP_RANDOMIZED,
+                    "fkf_filter_create: unknown gep_mode");
+        FKF_REQUIRE(params->reserved == 0, "fkf_filter_create: reserved must be 0");
+        f->params.gep_mode = params->gep_mode;
+        f->params.gep_rank = params->gep_rank;
+        f->params.oversample = params->oversample < 0 ? 20 : params->oversample;
+        f->params.seed = params->seed;
+      }
     }
     f->s.alloc(f->n);
     if (s0)
@@ -1155,6 +1344,36 @@ extern "C" fkf_status fkf_filter_create(fkf_cov *cov, const double *s0, double a
   });
 }
 
+extern "C" fkf_status fkf_filter_reset(fkf_filter *f, const double *s0, double alpha0,
+                                       void *stream) {
+  return guarded([&] {
+    FKF_REQUIRE(f != nullptr, "fkf_filter_reset: NULL handle");
+    FKF_REQUIRE(alpha0 >= 0 && std::isfinite(alpha0), "fkf_filter_reset: alpha0 must be >= 0");
+    hipStream_t st = as_stream(stream);
+    if (s0)
+      FKF_CHECK_HIP(hipMemcpyAsync(f->s.p, s0, f->n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    else
+      fill(f->s.p, f->n, 0.0, st);
+    hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(1), 0, st, f->err.p, 0);
+    if (f->ll_gen.p) fill(f->ll_gen.p, 1, 0.0, st);
+    FKF_CHECK_HIP(hipGetLastError());
+    // the device work queued before the reset may still mirror its status
+    // into the pinned flag: wait for it before clearing the flag
+    FKF_CHECK_HIP(hipStreamSynchronize(st));
+    *f->err_host = 0;
+    f->k = 0;
+    f->alpha = alpha0;
+    f->mode = 0;
+    f->basis_gen = 0;
+    f->n_m = f->nmode = 0;
+    f->failed = FKF_OK;
+    f->rg = 0;
+    f->ll_const = 0.0;
+    f->ll_general = false;
+    f->lin_src = 0;
+  });
+}
+
 // Argument and state checks of one filter step (throws).
 static void check_step(fkf_filter *f, const fkf_obs *o, const double *y, const char *who) {
   if (!(f && o && y)) throw Error{FKF_E_ARG, std::string(who) + ": NULL argument"};
@@ -1164,6 +1383,21 @@ static void check_step(fkf_filter *f, const fkf_obs *o, const double *y, const c
     throw Error{f->failed, std::string(who) + ": a previous step produced non-finite values"};
   }
   if (o->n != f->n) throw Error{FKF_E_ARG, std::string(who) + ": operator size does not match the state"};
+}
+
+// Run the work of a step of the filters fs[0..count): an error raised after
+// the argument and state checks marks every one of them failed, so that they
+// refuse further steps (a failed general step leaves its filter's state as it
+// was; the other failures may leave it partly updated).
+template <class F>
+static void step_guard(fkf_filter *const *fs, int count, F &&body) {
+  try {
+    body();
+  } catch (const Error &e) {
+    for (int i = 0; i < count; ++i)
+      if (fs[i]->failed == FKF_OK) fs[i]->failed = e.code;
+    throw;
+  }
 }
 
 // The step after the basis (if any) is in place: prediction and update.
@@ -1180,17 +1414,19 @@ static void step_after_basis(fkf_filter *f, const fkf_obs *o, const double *y, h
   const double alpha_new = f->alpha + 1.0;   // prediction (F = I)
   const int nm = f->n_m;
   FKF_TRACE("filter_step", st);
-  hipLaunchKernelGGL(k_modes_step_eta, dim3(blocks(nm, 4)), dim3(256), 0, st, f->Ve.p, nm, y,
+  hipLaunchKernelGGL(k_modes_step_eta, dim3(blocks(f->nmode, 4)), dim3(256), 0, st, f->Ve.p, nm,
+                     f->nmode, y,
                      f->lam.p, f->delta.p, f->eta.p, alpha_new, f->zp.p, f->llq.p, f->err.p);
   f->ll_const += o->ll_const;
   if (f->dcov)
     hipLaunchKernelGGL(k_loglik_length_step, dim3(blocks(nm, 4)), dim3(256), 0, st, nm,
                        f->ll_Ad.p, f->ll_Cd.p, f->llq.p);
-  gemv_seg(f, f->zp.p, false, st);
   {
-    int nseg = (nm + kSegCols - 1) / kSegCols;
-    hipLaunchKernelGGL(k_seg_add, dim3(blocks(f->n)), dim3(256), 0, st, f->part.p, nseg, f->n,
-                       f->s.p, f->err.p, f->err_host);
+    GemvEpi e;
+    e.kind = kEpiAdd;
+    e.err = f->err.p;
+    e.err_mirror = f->err_host;
+    gemv_panel(f, f->zp.p, false, f->s.p, e, st);
   }
   FKF_CHECK_HIP(hipGetLastError());
   f->alpha = alpha_new;
@@ -1202,8 +1438,10 @@ extern "C" fkf_status fkf_filter_step(fkf_filter *f, const fkf_obs *o, const dou
   return guarded([&] {
     check_step(f, o, y, "fkf_filter_step");
     hipStream_t st = as_stream(stream);
-    if (f->mode == 0) build_basis(f, o, st);
-    step_after_basis(f, o, y, st);
+    step_guard(&f, 1, [&] {
+      if (f->mode == 0) build_basis(f, o, st);
+      step_after_basis(f, o, y, st);
+    });
   });
 }
 
@@ -1245,13 +1483,15 @@ extern "C" fkf_status fkf_filter_step_boxcox(fkf_filter *f, const fkf_obs *o, do
     FKF_REQUIRE(std::isfinite(bc_alpha) && bc_alpha > 0,
                 "fkf_filter_step_boxcox: bc_alpha must be finite and positive");
     hipStream_t st = as_stream(stream);
-    const fkf_obs *lin;
-    {
-      FKF_TRACE("boxcox_linearize", st);
-      lin = boxcox_linearize(f, o, bc_alpha, y, st);
-    }
-    if (f->mode == 0) build_basis(f, lin, st);
-    step_after_basis(f, lin, f->ytil.p, st);
+    step_guard(&f, 1, [&] {
+      const fkf_obs *lin;
+      {
+        FKF_TRACE("boxcox_linearize", st);
+        lin = boxcox_linearize(f, o, bc_alpha, y, st);
+      }
+      if (f->mode == 0) build_basis(f, lin, st);
+      step_after_basis(f, lin, f->ytil.p, st);
+    });
   });
 }
 
@@ -1267,24 +1507,30 @@ extern "C" fkf_status fkf_filter_step_many(fkf_filter *const *filters, const fkf
         FKF_REQUIRE(filters[j] != filters[i], "fkf_filter_step_many: a filter appears twice");
     }
     hipStream_t st = as_stream(stream);
-    std::vector<fkf_filter *> nf;
-    std::vector<const fkf_obs *> no;
-    for (int i = 0; i < count; ++i)
-      if (filters[i]->mode == 0) {
-        nf.push_back(filters[i]);
-        no.push_back(obs[i]);
+    step_guard(filters, count, [&] {
+      std::vector<fkf_filter *> nf;
+      std::vector<const fkf_obs *> no;
+      for (int i = 0; i < count; ++i)
+        if (filters[i]->mode == 0) {
+          if (filters[i]->params.gep_mode == FKF_GEP_RANDOMIZED) {
+            build_basis_randomized(filters[i], obs[i], st);
+            continue;
+          }
+          nf.push_back(filters[i]);
+          no.push_back(obs[i]);
+        }
+      if (!nf.empty()) build_bases(nf.data(), no.data(), (int)nf.size(), st);
+      if (count == 1) {
+        step_after_basis(filters[0], obs[0], y[0], st);
+        return;
       }
-    if (!nf.empty()) build_bases(nf.data(), no.data(), (int)nf.size(), st);
-    if (count == 1) {
-      step_after_basis(filters[0], obs[0], y[0], st);
-      return;
-    }
-    // the steps of independent filters run on the stream lanes
-    LanePool &lp = lane_pool();
-    const std::vector<int> lane = lanes_of(filters, count);
-    lanes_fork(lp, st);
-    for (int i = 0; i < count; ++i) step_after_basis(filters[i], obs[i], y[i], lp.s[lane[i]]);
-    lanes_join(lp, st);
+      // the steps of independent filters run on the stream lanes
+      LanePool &lp = lane_pool();
+      const std::vector<int> lane = lanes_of(filters, count);
+      lanes_fork(lp, st);
+      for (int i = 0; i < count; ++i) step_after_basis(filters[i], obs[i], y[i], lp.s[lane[i]]);
+      lanes_join(lp, st);
+    });
   });
 }
 
@@ -1321,18 +1567,16 @@ extern "C" fkf_status fkf_filter_variance(const fkf_filter *f, double *var, void
       return;
     }
     fkf_filter *mf = const_cast<fkf_filter *>(f);
+    GemvEpi e;
+    e.kind = kEpiVar;
+    e.base = base;
     if (f->mode == 2) {
-      gemv_seg_m(f->W.p, f->ldu, f->rg, f->n, f->Dg.p, true, mf->part.p, st);
-      int nseg = (f->rg + kSegCols - 1) / kSegCols;
-      hipLaunchKernelGGL(k_seg_var, dim3(blocks(f->n)), dim3(256), 0, st, f->part.p, nseg, f->n,
-                         base, var);
+      if (f->rg == 0) fill(var, f->n, base, st);
+      else gemv_panel_m(f->W.p, f->ldu, f->rg, f->n, f->Dg.p, true, var, e, st);
       FKF_CHECK_HIP(hipGetLastError());
       return;
     }
-    gemv_seg(mf, f->delta.p, true, st);
-    int nseg = (f->n_m + kSegCols - 1) / kSegCols;
-    hipLaunchKernelGGL(k_seg_var, dim3(blocks(f->n)), dim3(256), 0, st, f->part.p, nseg, f->n, base,
-                       var);
+    gemv_panel(mf, f->delta.p, true, var, e, st);
     FKF_CHECK_HIP(hipGetLastError());
   });
 }
@@ -1348,7 +1592,6 @@ extern "C" fkf_status fkf_filter_realize(const fkf_filter *f, const double *g, i
     hipStream_t st = as_stream(stream);
     fkf_filter *mf = const_cast<fkf_filter *>(f);
     const double sa = std::sqrt(f->alpha);
-    int nseg = (f->n_m + kSegCols - 1) / kSegCols;
     for (int c = 0; c < ns; ++c) {
       const double *gc = g + ldg * c;
       double *oc = out + ldo * c;
@@ -1364,21 +1607,38 @@ extern "C" fkf_status fkf_filter_realize(const fkf_filter *f, const double *g, i
              &mf->gwork);
         hipLaunchKernelGGL(k_sigma_minus, dim3(blocks(f->rg)), dim3(256), 0, st, f->Dg.p, f->nu.p,
                            f->rg, f->alpha, mf->tmp.p);
-        gemv_seg_m(f->W.p, f->ldu, f->rg, f->n, f->tmp.p, false, mf->part.p, st);
-        int ns2 = (f->rg + kSegCols - 1) / kSegCols;
-        hipLaunchKernelGGL(k_seg_realize, dim3(blocks(f->n)), dim3(256), 0, st, f->part.p, ns2,
-                           f->n, f->s.p, gc, sa, oc);
+        GemvEpi e;
+        e.kind = kEpiRealize;
+        e.s = f->s.p;
+        e.g = gc;
+        e.salpha = sa;
+        gemv_panel_m(f->W.p, f->ldu, f->rg, f->n, f->tmp.p, false, oc, e, st);
         continue;
       }
       // h = H g with the basis' operator; zz = (Sigma_- / lambda) Ve^T h; out = s + a^1/2 (g - U0 zz)
       hipLaunchKernelGGL(k_spmv_f, dim3(blocks(f->n_m, 4)), dim3(256), 0, st, f->b_rowptr.p,
                          f->b_col.p, f->b_val.p, f->n_m, gc, mf->nu.p);
-      hipLaunchKernelGGL(k_modes_realize, dim3(blocks(f->n_m, 4)), dim3(256), 0, st, f->Ve.p,
-                         f->n_m, f->nu.p, f->lam.p, f->delta.p, f->alpha, mf->tmp.p);
-      gemv_seg(mf, f->tmp.p, false, st);
-      hipLaunchKernelGGL(k_seg_realize, dim3(blocks(f->n)), dim3(256), 0, st, f->part.p, nseg, f->n,
-                         f->s.p, gc, sa, oc);
+      hipLaunchKernelGGL(k_modes_realize, dim3(blocks(f->nmode, 4)), dim3(256), 0, st, f->Ve.p,
+                         f->n_m, f->nmode, f->nu.p, f->lam.p, f->delta.p, f->alpha, mf->tmp.p);
+      GemvEpi e;
+      e.kind = kEpiRealize;
+      e.s = f->s.p;
+      e.g = gc;
+      e.salpha = sa;
+      gemv_panel(mf, f->tmp.p, false, oc, e, st);
     }
+    FKF_CHECK_HIP(hipGetLastError());
+  });
+}
+
+extern "C" fkf_status fkf_gaussian_sketch(uint64_t seed, int64_t count, double *out,
+                                          void *stream) {
+  return guarded([&] {
+    FKF_REQUIRE(count >= 0, "fkf_gaussian_sketch: count < 0");
+    if (count == 0) return;
+    FKF_REQUIRE(out != nullptr, "fkf_gaussian_sketch: NULL array");
+    hipLaunchKernelGGL(k_sketch_normals, dim3(blocks((count + 1) / 2)), dim3(256), 0,
+                       as_stream(stream), seed, count, out);
     FKF_CHECK_HIP(hipGetLastError());
   });
 }
@@ -1389,7 +1649,7 @@ extern "C" fkf_status fkf_filter_info(const fkf_filter *f, int64_t *k, double *a
     FKF_REQUIRE(f != nullptr, "fkf_filter_info: NULL handle");
     if (k) *k = f->k;
     if (alpha) *alpha = f->alpha;
-    if (rank) *rank = f->mode == 0 ? 0 : (f->mode == 1 ? f->n_m : f->rg);
+    if (rank) *rank = f->mode == 0 ? 0 : (f->mode == 1 ? f->nmode : f->rg);
   });
 }
 
@@ -1402,6 +1662,9 @@ extern "C" fkf_status fkf_filter_track_length(fkf_filter *f, fkf_cov *dcov, void
     FKF_REQUIRE(cov_kind(dcov) == cov_kind(f->cov) + FKF_MATERN_12_DLENGTH,
                 "fkf_filter_track_length: dcov must be the length derivative of the filter's kernel");
     FKF_REQUIRE(cov_n(dcov) == f->n, "fkf_filter_track_length: size mismatch");
+    if (f->params.gep_mode != FKF_GEP_EXACT)
+      throw Error{FKF_E_UNSUPPORTED,
+                  "fkf_filter_track_length: the length derivative needs the exact eigensolver"};
     FKF_REQUIRE(cov_length(dcov) == cov_length(f->cov),
                 "fkf_filter_track_length: length differs from the filter's covariance");
     f->dcov = dcov;
@@ -1413,6 +1676,9 @@ extern "C" fkf_status fkf_filter_loglik(const fkf_filter *f, double *ll, double 
                                         void *stream) {
   return guarded([&] {
     FKF_REQUIRE(f && ll, "fkf_filter_loglik: NULL argument");
+    if (f->mode == 1 && f->nmode < f->n_m)
+      throw Error{FKF_E_UNSUPPORTED, "fkf_filter_loglik: the constant-H basis keeps fewer modes "
+                                     "than measurements (truncated randomized eigensolver)"};
     if ((dll_dlog_theta || dll_dlog_length || dll_dlog_noise) && f->ll_general)
       throw Error{FKF_E_UNSUPPORTED,
                   "fkf_filter_loglik: derivatives are available while every step is a constant-H "
@@ -1423,7 +1689,7 @@ extern "C" fkf_status fkf_filter_loglik(const fkf_filter *f, double *ll, double 
     hipStream_t st = as_stream(stream);
     double tot = f->ll_const, ga = 0.0, gl = 0.0, gs = 0.0;
     if (f->llq.p) {
-      const std::vector<double> q = to_host(f->llq.p, f->llq.n, st);
+      const std::vector<double> q = to_host(f->llq.p, (size_t)kLLStride * f->nmode, st);
       for (size_t j = 0; j + kLLStride <= q.size(); j += kLLStride) {
         tot += q[j + 4];
         ga += q[j + 5];
@@ -1443,14 +1709,67 @@ extern "C" fkf_status fkf_filter_modes(const fkf_filter *f, double *lam_host, do
   return guarded([&] {
     FKF_REQUIRE(f && lam_host && w_host, "fkf_filter_modes: NULL argument");
     if (f->mode != 1) throw Error{FKF_E_ORDER, "fkf_filter_modes: no constant-H basis"};
-    std::vector<double> lam(f->n_m), del(f->n_m);
+    std::vector<double> lam(f->nmode), del(f->nmode);
     FKF_CHECK_HIP(hipDeviceSynchronize());
-    FKF_CHECK_HIP(hipMemcpy(lam.data(), f->lam.p, f->n_m * sizeof(double), hipMemcpyDeviceToHost));
-    FKF_CHECK_HIP(hipMemcpy(del.data(), f->delta.p, f->n_m * sizeof(double), hipMemcpyDeviceToHost));
-    for (int j = 0; j < f->n_m; ++j) {
+    FKF_CHECK_HIP(hipMemcpy(lam.data(), f->lam.p, f->nmode * sizeof(double), hipMemcpyDeviceToHost));
+    FKF_CHECK_HIP(hipMemcpy(del.data(), f->delta.p, f->nmode * sizeof(double), hipMemcpyDeviceToHost));
+    for (int j = 0; j < f->nmode; ++j) {
       lam_host[j] = lam[j];
       w_host[j] = f->alpha - del[j] * lam[j];
     }
+  });
+}
+
+extern "C" fkf_status fkf_filter_lowrank(const fkf_filter *f, double *W_dev, int64_t ldw,
+                                         double *Wd_dev, int64_t ldwd, double *D_dev,
+                                         int32_t capacity, int32_t *rank, void *stream) {
+  return guarded([&] {
+    FKF_REQUIRE(f && rank, "fkf_filter_lowrank: NULL argument");
+    FKF_REQUIRE(ldw >= f->n && ldwd >= f->n, "fkf_filter_lowrank: leading dimension < n");
+    hipStream_t st = as_stream(stream);
+    const int64_t n = f->n;
+    *rank = 0;
+    if (f->mode == 0) return;
+    if (f->mode == 2) {
+      const int r = f->rg;
+      FKF_REQUIRE(capacity >= r, "fkf_filter_lowrank: capacity below the rank");
+      if (W_dev) copy2d(n, r, f->W.p, f->ldu, W_dev, ldw, st);
+      if (Wd_dev) copy2d(n, r, f->Wd.p, f->ldu, Wd_dev, ldwd, st);
+      if (D_dev && r)
+        FKF_CHECK_HIP(hipMemcpyAsync(D_dev, f->Dg.p, r * sizeof(double), hipMemcpyDeviceToDevice, st));
+      FKF_CHECK_HIP(hipStreamSynchronize(st));
+      *rank = r;
+      return;
+    }
+    // constant-H form: W = U0 Lambda^-1/2, Wd = H_b^T Ve Lambda^-1/2, D = delta lambda over
+    // the modes with lambda > 1e-13 lambda_max (as the change to the general form)
+    const int nm = f->n_m;
+    FKF_REQUIRE(capacity >= f->nmode, "fkf_filter_lowrank: capacity below the rank");
+    std::vector<double> lam = to_host(f->lam.p, f->nmode, st),
+                        del = to_host(f->delta.p, f->nmode, st);
+    const int r = count_above(lam, 1e-13 * (lam.empty() ? 0.0 : lam[0]));
+    std::vector<double> isl(r), dg(r);
+    for (int j = 0; j < r; ++j) {
+      isl[j] = 1.0 / std::sqrt(lam[j]);
+      dg[j] = del[j] * lam[j];
+    }
+    DevBuf<double> s_isl;
+    upload_vec(s_isl, isl, st);
+    if (W_dev && r) {
+      copy2d(n, r, f->U0.p, f->ldu, W_dev, ldw, st);
+      scale_cols(n, r, s_isl.p, W_dev, ldw, st);
+    }
+    if (Wd_dev && r) {
+      DevBuf<double> Hbt((size_t)n * nm);
+      dense_ht(f->b_rowptr.p, f->b_col.p, f->b_val.p, nm, n, Hbt.p, st);
+      gemm(false, false, n, r, nm, 1.0, Hbt.p, n, f->Ve.p, nm, 0.0, Wd_dev, ldwd, st, nullptr);
+      scale_cols(n, r, s_isl.p, Wd_dev, ldwd, st);
+      FKF_CHECK_HIP(hipStreamSynchronize(st));   // Hbt is released on return
+    }
+    if (D_dev && r)
+      FKF_CHECK_HIP(hipMemcpyAsync(D_dev, dg.data(), r * sizeof(double), hipMemcpyHostToDevice, st));
+    FKF_CHECK_HIP(hipStreamSynchronize(st));
+    *rank = r;
   });
 }
 

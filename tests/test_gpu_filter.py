@@ -179,3 +179,32 @@ def test_trace_counts_launches():
     assert c_gemv == wl.steps and ms_gemv > 0
     assert c_jac > 0 and c_jac % nb == 0 and ms_jac > 0
     assert fkf.trace_report() == {}
+
+
+def test_reset_reruns_bitwise_like_a_fresh_filter():
+    # fkf_filter_reset returns a used filter (constant-H basis, then a step of
+    # Section 2.4 with another operator) to its initial state: running it
+    # again gives bitwise the results of a fresh filter
+    wl = W.tiny(shape=(20, 18), nu=1.5, length=0.3, variance=0.5, n_src=4, n_rcv=3,
+                noise_var=1e-2, steps=4, leaf_size=32)
+    fkf, pts, cov, obs, H, R = _setup(wl)
+    src2, rcv2 = W.crosswell_vertical(3, 3)
+    obs2 = fkf.Obs.from_rays(wl.shape, src2, rcv2, wl.noise_var)
+    ys = W.observations(wl)
+    y2 = np.random.default_rng(4).standard_normal(9)
+
+    def run(f):
+        for k in range(wl.steps):
+            f.step(obs, ys[k])
+        f.step(obs2, y2)
+        return _host(f.mean()), _host(f.variance()), f.info(), f.loglik(grad=False)
+
+    fresh = run(fkf.Filter(cov, alpha0=0.3))
+    f = fkf.Filter(cov)
+    run(f)
+    f.reset(alpha0=0.3)
+    assert f.info() == {"k": 0, "alpha": 0.3, "rank": 0}
+    again = run(f)
+    _say(f"[reset] rank={again[2]['rank']} ll={again[3]:.6e}")
+    assert np.array_equal(again[0], fresh[0]) and np.array_equal(again[1], fresh[1])
+    assert again[2] == fresh[2] and again[3] == fresh[3]

@@ -1,7 +1,14 @@
 """GPU parity at the full 256 x 256 size (N = 65536, 480 rays, 50 steps)
 against stored oracle values (tests/golden/headline_reference.npz, written
-by tests/golden/make_headline_reference.py from the oracle only) at 4096
-sampled cells, in the launch configuration bench.py times."""
+by tests/golden/make_headline_reference.py from the oracle only) on every
+cell of the field after steps 1, 10 and 50, in the launch configuration
+bench.py times.
+
+Bars (FP64 mode, the method's 1e-6): the state as the largest cell error over
+the largest |state| and as the relative 2-norm; the variance as the largest
+cell error over the largest variance.  The largest per-cell relative
+variance error is reported and bounded by 1e-5 (a cell's posterior variance
+can be far below the largest one)."""
 import os
 import sys
 
@@ -15,7 +22,35 @@ REF = os.path.join(os.path.dirname(__file__), "golden", "headline_reference.npz"
 TOL = 1e-6
 
 
-def test_headline_filter_matches_oracle_at_sampled_cells():
+def field_errors(s, v, ref, k):
+    """Errors of a state / variance field against the stored oracle field."""
+    rs, rv = ref[f"s{k}"], ref[f"v{k}"]
+    return {
+        "state_maxabs": float(np.abs(s - rs).max() / np.abs(rs).max()),
+        "state_2norm": float(np.linalg.norm(s - rs) / np.linalg.norm(rs)),
+        "var_maxabs": float(np.abs(v - rv).max() / np.abs(rv).max()),
+        "var_cellrel": float((np.abs(v - rv) / np.abs(rv)).max()),
+        "worst_state_cell": int(np.argmax(np.abs(s - rs))),
+    }
+
+
+def check_field(tag, s, v, ref, k, tol=TOL, cell_tol=TOL):
+    """State: relative 2-norm <= tol (the method's measure of the state bar)
+    and largest cell error / largest |state| <= cell_tol; variance: largest
+    cell error / largest variance <= tol and largest per-cell relative error
+    <= 10 tol."""
+    if ref[f"s{k}"].shape != s.shape:
+        pytest.skip("reference file holds no whole fields; regenerate it")
+    e = field_errors(s, v, ref, k)
+    print(f"[{tag}] step={k} state maxabs={e['state_maxabs']:.2e} 2norm={e['state_2norm']:.2e} "
+          f"var maxabs={e['var_maxabs']:.2e} var cellrel={e['var_cellrel']:.2e} "
+          f"(worst state cell {e['worst_state_cell']})", flush=True)
+    assert e["state_2norm"] <= tol and e["state_maxabs"] <= cell_tol
+    assert e["var_maxabs"] <= tol and e["var_cellrel"] <= 10 * tol
+    return e
+
+
+def test_headline_filter_matches_oracle_on_every_cell():
     import torch
     import paper_1405_2276_amd as fkf
     if not os.path.exists(REF):
@@ -29,18 +64,12 @@ def test_headline_filter_matches_oracle_at_sampled_cells():
     obs = fkf.Obs.from_rays(wl.shape, src, rcv, wl.noise_var)
     ys = torch.from_numpy(W.observations(wl)).cuda()
     f = fkf.Filter(cov)
-    idx = ref["idx"]
     for k in range(1, wl.steps + 1):
         f.step(obs, ys[k - 1])
         if k in set(ref["steps"].tolist()):
             s = f.mean().cpu().numpy()
             v = f.variance().cpu().numpy()
-            es = np.linalg.norm(s[idx] - ref[f"s{k}"]) / np.linalg.norm(ref[f"s{k}"])
-            ev = np.abs(v[idx] - ref[f"v{k}"]).max() / ref[f"v{k}_max"]
-            en = abs(np.linalg.norm(s) - ref[f"s{k}_norm"]) / ref[f"s{k}_norm"]
-            print(f"[headline] step={k} sampled state err={es:.2e} var err={ev:.2e} "
-                  f"norm err={en:.2e}", flush=True)
-            assert es <= TOL and ev <= TOL and en <= TOL
+            check_field("headline", s, v, ref, k)
     f.status()
 
 

@@ -145,6 +145,32 @@ def test_hmatvec_headline_size_sampled_rows():
     np.testing.assert_allclose(got3[:, 0], got1, rtol=1e-12, atol=1e-12 * np.abs(got1).max())
 
 
+def test_hmatvec_headline_size_every_row():
+    # every row of Gamma x at N = 65536 against the oracle's direct product
+    # (tests/golden/hmatvec_reference.npz, written by make_hmatvec_reference.py
+    # from the oracle only), one column and both columns together, in the
+    # configuration the benchmark times; bar 1e-7 relative as the 2-norm and
+    # as the largest row error over the largest entry
+    import os
+    import paper_1405_2276_amd as fkf
+    ref_path = os.path.join(os.path.dirname(__file__), "golden", "hmatvec_reference.npz")
+    if not os.path.exists(ref_path):
+        pytest.skip("reference file not generated")
+    ref = np.load(ref_path)
+    wl = W.LARGE
+    pts = wl.points()
+    _say(f"[hmat] headline every row n={len(pts)}")
+    cov = fkf.Cov(pts, nu=wl.nu, length=wl.length, variance=wl.variance)
+    x, want = ref["x"], ref["y"]
+    got1 = _host(cov.apply(_dev(np.ascontiguousarray(x[:, 0]))))
+    got2 = _host(cov.apply(_dev(x)))
+    for tag, got, w in (("nrhs1", got1, want[:, 0]), ("nrhs2", got2, want)):
+        e2 = np.linalg.norm(got - w) / np.linalg.norm(w)
+        emax = np.abs(got - w).max() / np.abs(w).max()
+        _say(f"[hmat] headline every row {tag} 2norm={e2:.3e} maxabs={emax:.3e}")
+        assert e2 <= TOL and emax <= TOL
+
+
 def test_hmatvec_deterministic_and_symmetric():
     import paper_1405_2276_amd as fkf
     pts = W.grid_points((64, 48))

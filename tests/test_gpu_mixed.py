@@ -112,9 +112,10 @@ def test_mixed_medium_filter_matches_cross_covariance_kf():
     assert worst_s <= TOL and worst_v <= TOL
 
 
-def test_mixed_headline_matches_oracle_at_sampled_cells():
+def test_mixed_headline_matches_oracle_on_every_cell():
     import torch
     import paper_1405_2276_amd as fkf
+    from test_gpu_headline import check_field
     if not os.path.exists(REF):
         pytest.skip("reference file not generated")
     ref = np.load(REF)
@@ -126,16 +127,14 @@ def test_mixed_headline_matches_oracle_at_sampled_cells():
     obs = fkf.Obs.from_rays(wl.shape, src, rcv, wl.noise_var)
     ys = torch.from_numpy(W.observations(wl)).cuda()
     f = fkf.Filter(cov)
-    idx = ref["idx"]
     check = set(ref["steps"].tolist())
     for k in range(1, wl.steps + 1):
         f.step(obs, ys[k - 1])
         if k in check:
             s, v = _host(f.mean()), _host(f.variance())
-            es = np.linalg.norm(s[idx] - ref[f"s{k}"]) / np.linalg.norm(ref[f"s{k}"])
-            ev = np.abs(v[idx] - ref[f"v{k}"]).max() / ref[f"v{k}_max"]
-            en = abs(np.linalg.norm(s) - ref[f"s{k}_norm"]) / ref[f"s{k}_norm"]
-            _say(f"[mixed] headline step={k} state err={es:.2e} var err={ev:.2e} "
-                 f"norm err={en:.2e}")
-            assert es <= TOL and ev <= TOL and en <= TOL
+            # FP32 storage of the operator: the state meets the 1e-6 bar as a
+            # relative 2-norm (6.2e-7 at step 50) while its largest cell error
+            # reaches 1.03e-6 of the largest |state|; the per-cell gate here
+            # is 2e-6, which still catches an error confined to one leaf
+            check_field("mixed headline", s, v, ref, k, cell_tol=2e-6)
     f.status()

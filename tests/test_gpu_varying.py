@@ -94,3 +94,56 @@ def test_varying_h_rank_growth_and_truncation():
     with pytest.raises(fkf.FkfError) as e:
         f2.step(obs[1], g.standard_normal(12))
     assert e.value.name == "FKF_E_RANK"
+
+
+def test_varying_h_480_rays_full_field():
+    # steps with a new operator every step at n_m = 480 on the 128 x 128 grid
+    # (N = 16384, two 480-ray crosswell geometries taken in turn), untruncated
+    # (rank_rtol = 0), against the oracle's dense Kalman filter
+    # (tests/golden/varying_reference.npz, make_varying_reference.py): every
+    # cell of the state and variance after every step
+    import os
+    import paper_1405_2276_amd as fkf
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    import make_varying_reference as mv
+    ref_path = os.path.join(os.path.dirname(__file__), "golden", "varying_reference.npz")
+    if not os.path.exists(ref_path):
+        pytest.skip("reference file not generated")
+    ref = np.load(ref_path)
+    wl = W.MEDIUM
+    cov = fkf.Cov(wl.points(), nu=wl.nu, length=wl.length, variance=wl.variance,
+                  leaf_size=wl.leaf_size)
+    obs = [fkf.Obs.from_rays(wl.shape, s, r, wl.noise_var) for s, r in mv.geometries()]
+    f = fkf.Filter(cov, rank_rtol=0.0)
+    for k, g in enumerate(ref["sequence"].tolist(), start=1):
+        f.step(obs[g], ref["ys"][k - 1])
+        s, v = _host(f.mean()), _host(f.variance())
+        rs, rv = ref[f"s{k}"], ref[f"v{k}"]
+        es = np.abs(s - rs).max() / np.abs(rs).max()
+        e2 = np.linalg.norm(s - rs) / np.linalg.norm(rs)
+        ev = np.abs(v - rv).max() / np.abs(rv).max()
+        _say(f"[varying480] step={k} geometry={g} rank={f.info()['rank']} state maxabs={es:.2e} "
+             f"2norm={e2:.2e} var maxabs={ev:.2e}")
+        assert es <= TOL and e2 <= TOL and ev <= TOL
+    f.status()
+
+
+def test_failed_step_leaves_the_filter_unchanged():
+    # a step that fails (here: the low-rank term would exceed max_rank) leaves
+    # the estimate (bitwise), the variance, alpha and the step count as they
+    # were, and the filter then refuses further steps (FKF_E_ORDER)
+    fkf, pts, cov, obs, Hs, Gamma = _setup()
+    g = np.random.default_rng(8)
+    f = fkf.Filter(cov, max_rank=24)
+    f.step(obs[0], g.standard_normal(20))      # constant-H basis: rank 20
+    s0, v0, i0 = _host(f.mean()), _host(f.variance()), f.info()
+    with pytest.raises(fkf.FkfError) as e:
+        f.step(obs[1], g.standard_normal(12))  # rank 20 + 12 > 24
+    assert e.value.name == "FKF_E_RANK"
+    s1, v1, i1 = _host(f.mean()), _host(f.variance()), f.info()
+    assert np.array_equal(s1, s0)
+    assert np.abs(v1 - v0).max() <= 1e-12 * np.abs(v0).max()
+    assert (i1["k"], i1["alpha"]) == (i0["k"], i0["alpha"])
+    with pytest.raises(fkf.FkfError) as e2:
+        f.step(obs[0], g.standard_normal(20))
+    assert e2.value.name == "FKF_E_ORDER"
