@@ -363,7 +363,7 @@ TRAFFIC_KERNELS = {
     "void (anonymous namespace)::k_near_sparse<double>": "hmat_near_sparse",
     "void fkf::k_down_mfma2<2>": "hmat_down_multi",
     "void (anonymous namespace)::k_up_sparse<2>": "hmat_far_up_sparse",
-    "void fkf::k_gemv_seg<false>": "filter_gemv",
+    "void fkf::k_gemv_panel<double, 0, false>": "filter_gemv",
     "fkf::k_gemm_tall": "gep_basis_gemm",
 }
 TRAFFIC_SOURCES = ["paper_1405_2276_amd/csrc/common.h", "paper_1405_2276_amd/csrc/kernels.h",

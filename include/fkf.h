@@ -166,6 +166,10 @@ typedef struct {
                                 evaluated on the fly (kept only up to 8 GiB) */
   int64_t far_pair_entries;  /* entries of the coupling matrices of all unordered admissible
                                 pairs (the work of one coupling pass per column) */
+  int64_t coupling_groups;   /* one-column product with stored couplings: groups of far
+                                clusters that couple through the same sequence of stored
+                                matrices (0 when the per-cluster kernel is used) */
+  int64_t coupling_items;    /* work items of the grouped one-column couplings */
 } fkf_cov_info_t;
 
 typedef struct fkf_cov fkf_cov;

@@ -71,7 +71,8 @@ class CovInfo(ctypes.Structure):
                 ("near_bytes", ctypes.c_int64), ("far_coef_per_rhs", ctypes.c_int64),
                 ("cheb_p", ctypes.c_int32 * 32), ("covered_entries", ctypes.c_int64),
                 ("far_interp_entries", ctypes.c_int64), ("far_bytes", ctypes.c_int64),
-                ("far_pair_entries", ctypes.c_int64)]
+                ("far_pair_entries", ctypes.c_int64), ("coupling_groups", ctypes.c_int64),
+                ("coupling_items", ctypes.c_int64)]
 
 
 def _sig(name, res, args):

@@ -305,7 +305,7 @@ __global__ void __launch_bounds__(256) k_modes_realize(const double *__restrict_
 // zero).  A workgroup of eight wavefronts owns one panel of kPanelRows rows
 // (FP64: 128 rows, 2 per lane; FP32: 256 rows, 4 per lane, 16-byte loads);
 // wavefront w streams the columns [w c, (w + 1) c) of the panel, eight
-// loads in flight per lane, and the eight partial sums of a row are added in
+// loads in flight per lane (sixteen measured slower), and the eight partial sums of a row are added in
 // wavefront order through LDS (fixed order: deterministic).  Epilogues:
 //   kEpiAdd:     s_i += sum                        (state update)
 //   kEpiVar:     out_i = base - sum                (variance)

@@ -66,6 +66,23 @@ struct CoupleItem {
   int16_t rb, cb;
 };
 
+// One-column couplings grouped by coupling sequence: far clusters whose far
+// lists, sorted by stored matrix, use the same sequence of matrices (the
+// interior clusters of a level of a regular grid) form a group, and one work
+// item multiplies a 64-row block of every matrix of the sequence with the
+// moments of the matching partners of up to kGrpSlots targets of the group.
+struct GroupItem {
+  int32_t seq;     // first entry of the group's sequence in grp_koff / grp_pdt
+  int32_t len;     // matrices in the sequence
+  int32_t pd;      // coefficients of each target (columns of every stored matrix)
+  int32_t rb;      // 64-row block of the targets' coefficients
+  int32_t slot0;   // first target slot of the item (grp_tcoef)
+  int32_t nslot;   // targets of the item (<= kGrpSlots)
+  int32_t xbase;   // grp_xoff row of slot0 (rows of len entries per slot)
+  int32_t pad;
+};
+constexpr int kGrpSlots = 8;
+
 // A 64-row block rb of the coefficients of far cluster s (several-column
 // couplings), or of upward item u (several-column upward pass).
 struct CoupleMItem {
@@ -137,6 +154,14 @@ struct fkf_cov {
   bool stored = false;
   fkf::DevBuf<fkf::CoupleItem> citems;       // 64 x 64 coupling sub-blocks
   fkf::DevBuf<int64_t> far_koff;             // stored matrix of each far list entry
+  // grouped one-column couplings (stored couplings shared by many targets)
+  fkf::DevBuf<fkf::GroupItem> grp_items;
+  fkf::DevBuf<int64_t> grp_koff;             // sequences of stored matrices
+  fkf::DevBuf<int32_t> grp_pdt;              // partner coefficients of each sequence entry
+  fkf::DevBuf<int32_t> grp_tcoef;            // coef_off of the target of each slot
+  fkf::DevBuf<int32_t> grp_xoff;             // coef_off of the partner, per slot and entry
+  int64_t n_grp_items = 0, n_grp_groups = 0;
+  bool grouped = false;
   int64_t n_citems = 0;
   fkf::DevBuf<int32_t> cp_ptr;               // pair partials of each far cluster
   fkf::DevBuf<int64_t> cp_off;
@@ -481,6 +506,34 @@ __device__ __forceinline__ void lagrange_reg(int p, const double *__restrict__ u
     double is = 1.0 / s;
 #pragma unroll
     for (int a = 0; a < PM; ++a) L[a] *= is;
+  }
+}
+
+// Lagrange values at the p <= PM Chebyshev nodes u (first kind) in product
+// form, without divisions: L_a(x) = w'_a prod_{b != a} (x - u_b) with
+// w'_a = 1 / prod_{b != a} (u_a - u_b) = (2^(p-1) / p) (-1)^a sin(theta_a),
+// i.e. the stored normalised weights w_a times 2^(p-1) / p, and the products
+// taken as prefix times suffix (3p multiplications; each L_a to ~2p rounding
+// errors; at a node x = u_a the others vanish exactly).  L[a] = 0 for
+// a >= p.  For x in [-1, 1].
+template <int PM>
+__device__ __forceinline__ void lagrange_prod(int p, const double *__restrict__ u,
+                                              const double *__restrict__ w, double x,
+                                              double (&L)[PM]) {
+  double d[PM], pre[PM];
+  double acc = 1.0;
+#pragma unroll
+  for (int a = 0; a < PM; ++a) {
+    d[a] = a < p ? x - u[a] : 1.0;
+    pre[a] = acc;                 // prod_{b < a} (x - u_b)
+    acc *= d[a];
+  }
+  const double sc = __builtin_ldexp(1.0, p - 1) / p;
+  double suf = 1.0;               // prod_{b > a} (x - u_b)
+#pragma unroll
+  for (int a = PM - 1; a >= 0; --a) {
+    L[a] = a < p ? sc * w[a] * pre[a] * suf : 0.0;
+    suf *= d[a];
   }
 }
 
@@ -927,6 +980,76 @@ __device__ __forceinline__ v4d mfma4(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// One column with stored couplings, grouped: item it covers rows
+// [64 rb, 64 rb + 64) of the coupled coefficients of up to kGrpSlots
+// targets that share one sequence of stored matrices K_e (K_e(b, a) at
+// koff_e + b pd + a, the partner's nodes b as rows):
+// y_c[a] = sum_e sum_b K_e(b, a) x_{t_e(c)}[b].  Lanes run over the rows a
+// (coalesced reads of K), each entry K_e(b, a) read once serves every target
+// of the item, and the partners' moments x_{t_e(c)}[b..b+7] are wave-uniform
+// (scalar loads).  Wavefront w takes the sequence entries e = w, w + 8, ...;
+// the eight partial sums are added in wavefront order through LDS (fixed
+// order, deterministic).
+template <typename KT>
+__global__ void __launch_bounds__(512) k_couple_grp1(const GroupItem *__restrict__ items,
+                                                     const int64_t *__restrict__ grp_koff,
+                                                     const int32_t *__restrict__ grp_pdt,
+                                                     const int32_t *__restrict__ grp_tcoef,
+                                                     const int32_t *__restrict__ grp_xoff,
+                                                     const KT *__restrict__ kst,
+                                                     const double *__restrict__ xhat,
+                                                     double *__restrict__ yhat) {
+  constexpr int T = kGrpSlots;
+  __shared__ double red[8][T][64];
+  const GroupItem it = items[blockIdx.x];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
+  const int a = 64 * it.rb + l;
+  const bool aok = a < it.pd;
+  const int ar = aok ? a : 0;
+  double acc[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) acc[t] = 0.0;
+  for (int e = w; e < it.len; e += 8) {
+    const int pdt = grp_pdt[it.seq + e];
+    const KT *K = kst + grp_koff[it.seq + e] + ar;
+    const double *x[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+      x[t] = xhat + grp_xoff[it.xbase + (t < it.nslot ? t : 0) * it.len + e];
+    int b = 0;
+    for (; b + 8 <= pdt; b += 8) {
+      double k[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) k[u] = (double)K[(int64_t)(b + u) * it.pd];
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+        if (t < it.nslot) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc[t] = fma(k[u], x[t][b + u], acc[t]);
+        }
+    }
+    for (; b < pdt; ++b) {
+      const double k = (double)K[(int64_t)b * it.pd];
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+        if (t < it.nslot) acc[t] = fma(k, x[t][b], acc[t]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < T; ++t) red[w][t][l] = acc[t];
+  __syncthreads();
+  for (int e2 = threadIdx.x; e2 < T * 64; e2 += 512) {
+    const int t = e2 >> 6, row = e2 & 63;
+    const int ao = 64 * it.rb + row;
+    if (t < it.nslot && ao < it.pd) {
+      double v = red[0][t][row];
+#pragma unroll
+      for (int q = 1; q < 8; ++q) v += red[q][t][row];
+      yhat[grp_tcoef[it.slot0 + t] + ao] = v;
+    }
+  }
+}
+
 // Upward pass, one column, two dimensions, on the FP64 matrix cores: for one
 // chunk of <= kUpChunk points of a far cluster, Xhat[a0][a1] =
 // sum_i L0_i[a0] (x_i L1_i[a1]) is a 16 x 16 product accumulated over the
@@ -951,8 +1074,8 @@ __global__ void __launch_bounds__(64) k_up1_mfma2(const UpItem *__restrict__ ite
     double L0[16], L1[16];
     if (i < it.end) {
       const double x0 = pts[i], x1 = pts[n + i], xv = xt[i];
-      lagrange_any<16>(p, cu, cu + kMaxCheb, c.hw[0] > 0 ? (x0 - c.ctr[0]) / c.hw[0] : 0.0, L0);
-      lagrange_any<16>(p, cu, cu + kMaxCheb, c.hw[1] > 0 ? (x1 - c.ctr[1]) / c.hw[1] : 0.0, L1);
+      lagrange_prod<16>(p, cu, cu + kMaxCheb, c.hw[0] > 0 ? (x0 - c.ctr[0]) / c.hw[0] : 0.0, L0);
+      lagrange_prod<16>(p, cu, cu + kMaxCheb, c.hw[1] > 0 ? (x1 - c.ctr[1]) / c.hw[1] : 0.0, L1);
 #pragma unroll
       for (int a = 0; a < 16; ++a) L1[a] *= xv;
     } else {
@@ -1008,8 +1131,8 @@ __global__ void __launch_bounds__(256) k_final1_mfma2(
     const double *yh = yhat + c.coef_off;
     double L0[16], L1[16];
     if (l < m) {
-      lagrange_any<16>(p, cu, cu + kMaxCheb, c.hw[0] > 0 ? (x0 - c.ctr[0]) / c.hw[0] : 0.0, L0);
-      lagrange_any<16>(p, cu, cu + kMaxCheb, c.hw[1] > 0 ? (x1 - c.ctr[1]) / c.hw[1] : 0.0, L1);
+      lagrange_prod<16>(p, cu, cu + kMaxCheb, c.hw[0] > 0 ? (x0 - c.ctr[0]) / c.hw[0] : 0.0, L0);
+      lagrange_prod<16>(p, cu, cu + kMaxCheb, c.hw[1] > 0 ? (x1 - c.ctr[1]) / c.hw[1] : 0.0, L1);
     } else {
 #pragma unroll
       for (int a = 0; a < 16; ++a) L0[a] = L1[a] = 0.0;
@@ -1910,7 +2033,9 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
     cov->far_col.upload(fcol, st);
     {
       // several-column coupling blocks: (cluster, 64-row block), ordered by
-      // decreasing work (rows x sum of the partners' coefficients)
+      // decreasing work (rows x sum of the partners' coefficients).  (Dealing
+      // them to the eight XCDs level by level in spatial runs, so that an
+      // XCD's items share partners, measured 10 % slower than this order.)
       std::vector<std::pair<int64_t, CoupleMItem>> cm;
       for (int s = 0; s < cov->n_fc; ++s) {
         int64_t kext = 0;
@@ -2059,6 +2184,83 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
       cov->n_upairs = (int64_t)uprs.size();
       cov->upairs.upload(uprs, st);
       cov->far_koff.upload(fko, st);
+      {
+        // groups of targets with the same sequence of stored matrices (far
+        // list sorted by matrix, ties by partner): key = pd, then the
+        // (matrix, partner pd) pairs
+        std::map<std::vector<int64_t>, int> gid;
+        std::vector<std::vector<int>> members;
+        std::vector<std::vector<std::pair<int64_t, int>>> gseq;
+        std::vector<std::vector<int32_t>> tx(cov->n_fc);   // sorted partner coef offsets
+        bool fits = cov->n_coef < (int64_t)INT32_MAX;
+        for (int c = 0; c < cov->n_fc && fits; ++c) {
+          std::vector<std::pair<int64_t, int>> ent;   // (matrix, partner)
+          for (int e = fp[c]; e < fp[c + 1]; ++e) ent.emplace_back(fko[e], fcol[e]);
+          std::sort(ent.begin(), ent.end());
+          std::vector<int64_t> key{fcs[c].pd};
+          for (auto &q : ent) {
+            key.push_back(q.first);
+            key.push_back(fcs[q.second].pd);
+            tx[c].push_back((int32_t)fcs[q.second].coef_off);
+          }
+          auto it = gid.find(key);
+          if (it == gid.end()) {
+            it = gid.emplace(std::move(key), (int)members.size()).first;
+            members.emplace_back();
+            std::vector<std::pair<int64_t, int>> sq;
+            for (auto &q : ent) sq.emplace_back(q.first, fcs[q.second].pd);
+            gseq.push_back(std::move(sq));
+          }
+          members[it->second].push_back(c);
+        }
+        // worth it when the groups are large (a regular grid) and the
+        // couplings are FP64 (measured on the 256 x 256 grid: 50 us against
+        // 70 us per target in FP64, but 51 us against 36 us in FP32, whose
+        // per-target reads of the stored matrices are half as many bytes);
+        // irregular points keep the per-target kernel
+        if (!cov->mixed && fits && !members.empty() &&
+            cov->n_fc >= 4 * (int64_t)members.size()) {
+          std::vector<int64_t> gk;
+          std::vector<int32_t> gpd, tcoef, xoff;
+          std::vector<std::pair<int64_t, GroupItem>> items;
+          for (size_t g = 0; g < members.size(); ++g) {
+            const int seq = (int)gk.size(), len = (int)gseq[g].size();
+            int64_t work = 0;
+            for (auto &q : gseq[g]) {
+              gk.push_back(q.first);
+              gpd.push_back(q.second);
+              work += q.second;
+            }
+            const int pd = fcs[members[g][0]].pd;
+            for (size_t i0 = 0; i0 < members[g].size(); i0 += kGrpSlots) {
+              const int slot0 = (int)tcoef.size(), xbase = (int)xoff.size();
+              const int ns = (int)std::min<size_t>(kGrpSlots, members[g].size() - i0);
+              for (int i = 0; i < ns; ++i) {
+                const int c = members[g][i0 + i];
+                tcoef.push_back((int32_t)fcs[c].coef_off);
+                xoff.insert(xoff.end(), tx[c].begin(), tx[c].end());
+              }
+              for (int rb = 0; rb * 64 < pd; ++rb) {
+                GroupItem gi{seq, len, pd, rb, slot0, ns, xbase, 0};
+                items.emplace_back(-work * std::min(64, pd - 64 * rb), gi);
+              }
+            }
+          }
+          std::stable_sort(items.begin(), items.end(),
+                           [](const auto &a, const auto &b) { return a.first < b.first; });
+          std::vector<GroupItem> gi;
+          for (auto &q : items) gi.push_back(q.second);
+          cov->n_grp_items = (int64_t)gi.size();
+          cov->n_grp_groups = (int64_t)members.size();
+          cov->grp_items.upload(gi, st);
+          cov->grp_koff.upload(gk, st);
+          cov->grp_pdt.upload(gpd, st);
+          cov->grp_tcoef.upload(tcoef, st);
+          cov->grp_xoff.upload(xoff.empty() ? std::vector<int32_t>(1, 0) : xoff, st);
+          cov->grouped = true;
+          FKF_CHECK_HIP(hipStreamSynchronize(st));   // host temporaries
+        }
+      }
       FKF_CHECK_HIP(hipStreamSynchronize(st));   // prs, uprs, fko are host temporaries
       std::vector<int32_t> cptr(1, 0);
       std::vector<int64_t> coff;
@@ -2167,7 +2369,11 @@ void apply_one(fkf_cov *cov, const ApplyWs &ws, double *Y, hipStream_t st) {
                            cov->kind, 1.0 / cov->ell, cov->amp, ws.xhat,
                            ws.part_pair);
       };
-      if (cov->stored) {
+      if (cov->stored && cov->grouped) {   // FP64 couplings only
+        hipLaunchKernelGGL(k_couple_grp1<double>, dim3((unsigned)cov->n_grp_items), dim3(512), 0,
+                           st, cov->grp_items.p, cov->grp_koff.p, cov->grp_pdt.p, cov->grp_tcoef.p,
+                           cov->grp_xoff.p, cov->kst.p, ws.xhat, ws.yhat);
+      } else if (cov->stored) {
         const dim3 g((unsigned)cov->n_fc, (unsigned)((cov->max_pd + 63) / 64));
         if (cov->mixed)
           hipLaunchKernelGGL(k_couple_rows1<float>, g, dim3(256), 0, st, cov->fc.p,
@@ -2710,6 +2916,8 @@ extern "C" fkf_status fkf_cov_info(const fkf_cov *cov, fkf_cov_info_t *info) {
     info->far_coef_per_rhs = cov->n_coef;
     info->far_interp_entries = cov->n_interp;
     info->far_pair_entries = cov->n_kpair;
+    info->coupling_groups = cov->grouped ? cov->n_grp_groups : 0;
+    info->coupling_items = cov->grouped ? cov->n_grp_items : 0;
     for (int l = 0; l < 32 && l < (int)cov->level_p.size(); ++l) info->cheb_p[l] = cov->level_p[l];
     info->covered_entries = cov->covered;
   });
