@@ -358,7 +358,7 @@ def loglik_gradient(fkf, torch, cov, wl, ys, reps=3):
 
 # kernel (name prefix in the counter output) -> launch site of the trace
 TRAFFIC_KERNELS = {
-    "fkf::k_jacobi_round": "eig_jacobi_round",
+    "void fkf::(anonymous namespace)::k_tridiag<8, 2>": "eig_tridiag",
     "void fkf::k_couple_mfma2<2, false>": "hmat_far_couple_multi",
     "void (anonymous namespace)::k_near_sparse<double>": "hmat_near_sparse",
     "void fkf::k_down_mfma2<2>": "hmat_down_multi",
@@ -368,7 +368,7 @@ TRAFFIC_KERNELS = {
 }
 TRAFFIC_SOURCES = ["paper_1405_2276_amd/csrc/common.h", "paper_1405_2276_amd/csrc/kernels.h",
                    "paper_1405_2276_amd/csrc/hmat.hip", "paper_1405_2276_amd/csrc/linalg.hip",
-                   "paper_1405_2276_amd/csrc/filter.hip"]
+                   "paper_1405_2276_amd/csrc/eig_dc.hip", "paper_1405_2276_amd/csrc/filter.hip"]
 
 
 def _sources_sha256(files):
@@ -625,7 +625,6 @@ def main():
     per = {k: (c, ms) for k, (c, ms) in trace.items()}
     # entries of the coupling matrices over all ordered admissible pairs
     k_entries = 2.0 * info["far_pair_entries"]
-    npad = -(-n_m // 32) * 32          # eigensolver: padded order
     models = {
         # site: (bound, algorithmic units per launch, unit)
         "filter_gemv": ("hbm", 8.0 * n * n_m + 16.0 * n_m, "GB/s"),
@@ -638,14 +637,10 @@ def main():
         "hmat_down_multi": ("mfma", 2.0 * n_m * info["far_interp_entries"], "TFLOP/s"),
         "hmat_far_up_multi": ("mfma", 2.0 * n_m * info["far_interp_entries"], "TFLOP/s"),
         "gep_basis_gemm": ("mfma", 2.0 * n * n_m * n_m, "TFLOP/s"),
-        # Jacobi round (one launch): the method's work is the plane rotations
-        # it applies.  A sweep rotates each of the n_m (n_m - 1) / 2 index
-        # pairs once, and one rotation of A (two rows, two columns) and of V
-        # (two columns) costs 18 n_m flops; a sweep is nb = np / 16 launches.
-        # (How the kernel applies them, as blocked tile products on the
-        # matrix cores, is not counted.)
-        "eig_jacobi_round": ("mfma", 18.0 * n_m * (n_m * (n_m - 1) / 2.0) / (npad // 16),
-                             "TFLOP/s"),
+        # Householder reduction to tridiagonal form (one launch): 4 n^3 / 3
+        # flops (a symmetric rank-2 update and a matrix-vector product per
+        # reflector), on the FP64 vector units
+        "eig_tridiag": ("alu", 4.0 * n_m ** 3 / 3.0, "TFLOP/s"),
     }
     # single-kernel sites (composite sites excluded)
     leaf_sites = [k for k in per if k not in ("gep_total", "gep_cross_cov", "gep_eig",

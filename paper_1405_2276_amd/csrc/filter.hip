@@ -587,7 +587,7 @@ static void compute_gep(fkf_filter *f, const fkf_obs *o, DevBuf<double> &Ht, Dev
   innovation_gram(o->rowptr.p, o->col.p, o->val.p, nm, n, P.p, o->noise.p, G.p, A.p, st);
   {
     FKF_TRACE("gep_eig", st);
-    sym_eig(A.p, nm, nm, lam.p, We.p, nm, st, f->eig, gep_tol(f));
+    sym_eig(A.p, nm, nm, lam.p, We.p, nm, st, f->eig, gep_tol(f), f->err.p);
   }
   hipLaunchKernelGGL(k_clamp_nonneg, dim3(blocks(nm)), dim3(256), 0, st, lam.p, nm);
 }
@@ -756,7 +756,7 @@ static void build_bases(fkf_filter *const *fs, const fkf_obs *const *os, int cou
     FKF_TRACE("gep_eig", st);
     double tol = 1.0;
     for (int i = 0; i < count; ++i) tol = std::min(tol, gep_tol(fs[i]));
-    sym_eig_batched(probs.data(), count, st, fs[0]->eig, tol);
+    sym_eig_batched(probs.data(), count, st, fs[0]->eig, tol, fs[0]->err.p);
   }
   if (multi) lanes_fork(*lp, st);
   for (int i = 0; i < count; ++i) {
@@ -846,7 +846,7 @@ static void build_basis_randomized(fkf_filter *f, const fkf_obs *o, hipStream_t 
   // first pass: Gram = Ybar^T Gamma Ybar = Q1 Theta Q1^T, C1 = Q1 Theta^-1/2
   gemm(true, false, r, r, n, 1.0, w.P.p, n, Z.p, n, 0.0, G1, r, st, &f->gwork);
   symmetrize(G1, r, st);
-  sym_eig(G1, r, r, ev, V1, r, st, f->eig);
+  sym_eig(G1, r, r, ev, V1, r, st, f->eig, 1e-12, f->err.p);
   std::vector<double> th = to_host(ev, r, st);
   const int r1 = count_above(th, 1e-12 * (th.empty() ? 0.0 : th[0]));
   if (r1 == 0) throw Error{FKF_E_RANK, "fkf_filter_step: the sketch of H^T R^-1 H is zero"};
@@ -862,7 +862,7 @@ static void build_basis_randomized(fkf_filter *f, const fkf_obs *o, hipStream_t 
   gemm_nn(n, r1, r, Z.p, n, C1, r, w.Ht.p, n, st);                 // Q1 (in Ht, n x r1 <= n x nm?)
   gemm(true, false, r1, r1, n, 1.0, w.X.p, n, w.Ht.p, n, 0.0, G2, r1, st, &f->gwork);
   symmetrize(G2, r1, st);
-  sym_eig(G2, r1, r1, ev, V2, r1, st, f->eig);
+  sym_eig(G2, r1, r1, ev, V2, r1, st, f->eig, 1e-12, f->err.p);
   std::vector<double> th2 = to_host(ev, r1, st);
   const int r2 = count_above(th2, 1e-12 * (th2.empty() ? 0.0 : th2[0]));
   std::vector<double> ith2(r2);
@@ -876,7 +876,7 @@ static void build_basis_randomized(fkf_filter *f, const fkf_obs *o, hipStream_t 
   scale_rows(nm, r2, o->inv_sqrt_noise.p, HQ, nm, st);
   gemm(true, false, r2, r2, nm, 1.0, HQ, nm, HQ, nm, 0.0, T, r2, st, &f->gwork);
   symmetrize(T, r2, st);
-  sym_eig(T, r2, r2, ev, S, r2, st, f->eig, gep_tol(f));
+  sym_eig(T, r2, r2, ev, S, r2, st, f->eig, gep_tol(f), f->err.p);
   std::vector<double> lam = to_host(ev, r2, st);
   const int kk = std::min(k, count_above(lam, 1e-13 * (lam.empty() ? 0.0 : lam[0])));
   if (kk == 0) throw Error{FKF_E_RANK, "fkf_filter_step: the operator carries no information"};
@@ -1049,7 +1049,7 @@ static void step_general(fkf_filter *f, const fkf_obs *o, const double *y, hipSt
   symmetrize(Gm.p, rk, st);
   {
     FKF_TRACE("general_gram_eig", st);
-    sym_eig(Gm.p, rk, rk, th.p, Q.p, rk, st, f->eig);
+    sym_eig(Gm.p, rk, rk, th.p, Q.p, rk, st, f->eig, 1e-12, f->err.p);
   }
   std::vector<double> thh = to_host(th.p, rk, st);
   const int rp = count_above(thh, 1e-12);
@@ -1085,7 +1085,7 @@ static void step_general(fkf_filter *f, const fkf_obs *o, const double *y, hipSt
   DevBuf<double> mu(std::max(rt, 1)), Sm((size_t)std::max(rt, 1) * std::max(rt, 1));
   {
     FKF_TRACE("general_addlowrank_eig", st);
-    sym_eig(M.p, rt, rt, mu.p, Sm.p, rt, st, f->eig);
+    sym_eig(M.p, rt, rt, mu.p, Sm.p, rt, st, f->eig, 1e-12, f->err.p);
   }
   // the device status of this step (non-finite data, a non-positive pivot of
   // S) arrives with the eigenvalues of M

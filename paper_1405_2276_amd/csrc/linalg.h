@@ -25,22 +25,43 @@ struct EigWork {
   int pidx_np = -1;
   int *cnt_host = nullptr;   // pinned host scratch (4 ints; [2]: convergence flag)
   hipEvent_t ev = nullptr;   // marks the convergence test of the last sweep
+  // reduction + divide-and-conquer solver: merge tree of order dc_n (node,
+  // wave and tile tables, launch ranges per tree height) and its arrays
+  struct DcLevel {
+    int node0, nodes, wave0, waves, tile0, tiles;
+  };
+  std::vector<DcLevel> dc_levels;
+  int dc_n = -1;
+  DevBuf<int32_t> dc_nodes, dc_wmap, dc_tiles;
+  DevBuf<double> hv, Qc, Qp, U, dels, vec;
+  DevBuf<int> ivec;
   ~EigWork();
 };
 
-// Eigen-decomposition of a symmetric n x n FP64 matrix A (column-major, lda)
-// by two-sided block Jacobi: w (n, descending) and W (n x n, column j the
-// eigenvector of w[j], ldw), stopped when the off-diagonal Frobenius norm is
-// below tol ||A||_F.  Returns the number of sweeps used.  Synchronises the
-// stream once per sweep to test convergence.
+// Eigen-decomposition of a symmetric n x n FP64 matrix A (column-major, lda):
+// w (n, descending) and W (n x n, column j the eigenvector of w[j], ldw).
+// Orders 3..1024 take sym_eig_dc (tol unused; returns 0); other orders take
+// two-sided block Jacobi, stopped when the off-diagonal Frobenius norm is
+// below tol ||A||_F, returning the number of sweeps (the stream is
+// synchronised once per sweep to test convergence).
 int sym_eig(const double *A, int64_t lda, int n, double *w, double *W, int64_t ldw,
-            hipStream_t st, EigWork &ws, double tol = 1e-12);
+            hipStream_t st, EigWork &ws, double tol = 1e-12, int *err = nullptr);
 
-// The same for count independent problems in one sequence of launches (all
-// padded to the largest order, one convergence flag each).  Returns the
-// number of sweeps of the slowest problem.
+// Householder tridiagonalization + divide and conquer + back-transformation
+// for 3 <= n <= 1024 (eig_dc.hip), same outputs as sym_eig.  A failure of the
+// reduction's exchanges (its workgroups never all ran together) is latched
+// into the device int *err as FKF_E_HIP (an existing error is kept); without
+// err the stream is synchronised once and the failure thrown.
+bool sym_eig_dc_supported(int n);
+void sym_eig_dc(const double *A, int64_t lda, int n, double *w, double *W, int64_t ldw,
+                hipStream_t st, EigWork &ws, int *err = nullptr);
+
+// The same for count independent problems: one problem of a supported order
+// takes sym_eig_dc (err as there; returns 0); otherwise block Jacobi in one
+// sequence of launches (all padded to the largest order, one convergence flag
+// each), returning the number of sweeps of the slowest problem.
 int sym_eig_batched(const EigProblem *probs, int count, hipStream_t st, EigWork &ws,
-                    double tol = 1e-12);
+                    double tol = 1e-12, int *err = nullptr);
 
 // y (n_m) = H x for CSR H.
 void spmv(const int64_t *rowptr, const int32_t *col, const double *val, int n_m,

@@ -507,7 +507,13 @@ EigWork::~EigWork() {
   if (ev) (void)hipEventDestroy(ev);
 }
 
-int sym_eig_batched(const EigProblem *probs, int count, hipStream_t st, EigWork &ws, double tol) {
+int sym_eig_batched(const EigProblem *probs, int count, hipStream_t st, EigWork &ws, double tol,
+                    int *err) {
+  if (count == 1 && sym_eig_dc_supported(probs[0].n)) {
+    const EigProblem &p = probs[0];
+    sym_eig_dc(p.A, p.lda, p.n, p.w, p.W, p.ldw, st, ws, err);
+    return 0;
+  }
   int nmax = 0;
   for (int b = 0; b < count; ++b) nmax = std::max(nmax, probs[b].n);
   if (count <= 0 || nmax <= 0) return 0;
@@ -613,8 +619,12 @@ int sym_eig_batched(const EigProblem *probs, int count, hipStream_t st, EigWork 
 }
 
 int sym_eig(const double *A, int64_t lda, int n, double *w, double *W, int64_t ldw,
-            hipStream_t st, EigWork &ws, double tol) {
+            hipStream_t st, EigWork &ws, double tol, int *err) {
   if (n <= 0) return 0;
+  if (sym_eig_dc_supported(n)) {
+    sym_eig_dc(A, lda, n, w, W, ldw, st, ws, err);
+    return 0;
+  }
   EigProblem p{A, lda, n, 0, w, W, ldw};
   return sym_eig_batched(&p, 1, st, ws, tol);
 }

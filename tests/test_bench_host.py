@@ -18,7 +18,8 @@ import bench
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY = ("void at::native::vectorized_elementwise_kernel<4, at::native::AUnaryFunctor<double, "
         "double, double, at::native::MulFunctor<double> > >(int, ...)")
-JACOBI = "fkf::k_jacobi_round(double const*, double*, double*, int, int, int const*, int, int)"
+TRIDIAG = ("void fkf::(anonymous namespace)::k_tridiag<8, 2>(double const*, long, int, int, "
+           "double*, double*, double*, double*, unsigned long long*, int*)")
 
 
 def _csv(path, ctr, rows):
@@ -38,20 +39,20 @@ def test_traffic_scaling_and_source_hash(tmp_path):
     # them on WRITE_SIZE (factor 1); a copy of another size is not the
     # calibration; two dispatches of the round kernel average
     _csv(fetch, "FETCH_SIZE", [(COPY, 1 << 23, true_kib / 2), (COPY, 1 << 20, 1.0),
-                               (JACOBI, 119040, 100.0), (JACOBI, 119040, 300.0),
+                               (TRIDIAG, 119040, 100.0), (TRIDIAG, 119040, 300.0),
                                ("fkf::k_unlisted(int)", 256, 5.0)])
-    _csv(write, "WRITE_SIZE", [(COPY, 1 << 23, true_kib), (JACOBI, 119040, 50.0)])
+    _csv(write, "WRITE_SIZE", [(COPY, 1 << 23, true_kib), (TRIDIAG, 119040, 50.0)])
     out = tmp_path / "traffic.json"
     bench.write_traffic(str(fetch), str(write), out=str(out))
     rec = json.load(open(out))
     assert rec["fetch_factor"] == 2.0 and rec["write_factor"] == 1.0
-    assert rec["sites"] == {"eig_jacobi_round": {"fetch_kib": 200.0, "write_kib": 50.0}}
-    assert bench.traffic_for("eig_jacobi_round", path=str(out)) == (200.0 * 2 + 50.0) * 1024.0
+    assert rec["sites"] == {"eig_tridiag": {"fetch_kib": 200.0, "write_kib": 50.0}}
+    assert bench.traffic_for("eig_tridiag", path=str(out)) == (200.0 * 2 + 50.0) * 1024.0
     assert bench.traffic_for("filter_gemv", path=str(out)) is None
-    assert bench.traffic_for("eig_jacobi_round", path=str(tmp_path / "absent.json")) is None
+    assert bench.traffic_for("eig_tridiag", path=str(tmp_path / "absent.json")) is None
     rec["sources_sha256"] = "0" * 64     # counters taken on other kernel sources
     json.dump(rec, open(out, "w"))
-    assert bench.traffic_for("eig_jacobi_round", path=str(out)) is None
+    assert bench.traffic_for("eig_tridiag", path=str(out)) is None
 
 
 def test_bench_refuses_more_than_one_gpu():

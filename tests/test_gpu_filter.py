@@ -157,8 +157,8 @@ def test_error_paths():
 
 def test_trace_counts_launches():
     # the tracing subsystem: one basis GEMV per constant-H step; the
-    # eigensolver's round launches are recorded a sweep at a time (nb
-    # launches per sweep, nb = padded n_m / 16)
+    # projected eigenproblem (one per basis) records its three stages:
+    # tridiagonal reduction, divide and conquer, back-transformation
     wl = W.tiny(shape=(24, 20), n_src=5, n_rcv=6, steps=3, leaf_size=16, cfg_id=120)
     fkf, pts, cov, obs, H, R = _setup(wl)
     ys = W.observations(wl)
@@ -171,13 +171,12 @@ def test_trace_counts_launches():
         rep = fkf.trace_report()
     finally:
         fkf.trace_enable(False)
-    nb = -(-H.shape[0] // 32) * 32 // 16
     c_gemv, ms_gemv = rep["filter_gemv"]
-    c_jac, ms_jac = rep["eig_jacobi_round"]
-    print(f"[filter] trace gemv {c_gemv} launches {ms_gemv:.3f} ms; "
-          f"jacobi {c_jac} launches ({c_jac // nb} sweeps) {ms_jac:.3f} ms", flush=True)
+    eig = {k: rep[k] for k in ("eig_tridiag", "eig_dc", "eig_back")}
+    print(f"[filter] trace gemv {c_gemv} launches {ms_gemv:.3f} ms; eigensolver {eig}", flush=True)
     assert c_gemv == wl.steps and ms_gemv > 0
-    assert c_jac > 0 and c_jac % nb == 0 and ms_jac > 0
+    assert all(c == 1 and ms > 0 for c, ms in eig.values())
+    assert "eig_jacobi_round" not in rep
     assert fkf.trace_report() == {}
 
 
