@@ -366,6 +366,15 @@ struct DcNode {
   int32_t off, s, m, pad;
 };
 
+// Device arrays of the merges (indexed by the node's range [off, off + s)):
+// qsrc[off + u] = child column of Qp column u; rot_x/rot_y/rot_c/rot_s[off +
+// q] the deflation rotations (Qp columns, cosine, sine) in order and
+// nrot[off] their number.
+struct DcArrays {
+  double *lam, *Qc, *Qp, *U, *dels, *dd, *zz, *dv, *zh, *rho, *rot_c, *rot_s;
+  int *kk, *csrc, *qsrc, *rot_x, *rot_y, *nrot;
+};
+
 constexpr int kPrepThreads = 256;
 
 __device__ double block_max256(double v, double *red) {
@@ -424,11 +433,11 @@ __device__ int block_scan256(const int *f, int s, int *pos, int *cnt) {
 // dd, zz, dv, kk, rho.  The neighbour test is evaluated for all pairs at
 // once on the unrotated values; only when some pair deflates does one
 // thread rescan in order (each rotation changes the next comparison).
-__global__ void __launch_bounds__(kPrepThreads) k_dc_prep(
-    const DcNode *__restrict__ nodes, int n, const double *__restrict__ eg,
-    const double *__restrict__ lam, const double *__restrict__ Qc, double *__restrict__ Qp,
-    double *__restrict__ dd, double *__restrict__ zz, double *__restrict__ dv,
-    int *__restrict__ kk, double *__restrict__ rho_out) {
+__global__ void __launch_bounds__(kPrepThreads) k_dc_prep(const DcNode *__restrict__ nodes, int n,
+                                                         const double *__restrict__ eg,
+                                                         DcArrays ar) {
+  const double *__restrict__ lam = ar.lam;
+  const double *__restrict__ Qc = ar.Qc;
   __shared__ double L0[kDcMaxN], Z0[kDcMaxN], Ds[kDcMaxN], Zs[kDcMaxN];
   __shared__ int perm[kDcMaxN], keep[kDcMaxN], pos[kDcMaxN], col[kDcMaxN];
   __shared__ int rp[kDcMaxN], rj[kDcMaxN], trig[kDcMaxN];
@@ -548,36 +557,25 @@ __global__ void __launch_bounds__(kPrepThreads) k_dc_prep(
   __syncthreads();
   for (int r = tid; r < s; r += kPrepThreads) {
     const int u = col[r];
+    ar.qsrc[off + u] = perm[r];
     if (u < k) {
-      dd[off + u] = Ds[r];
-      zz[off + u] = Zs[r];
+      ar.dd[off + u] = Ds[r];
+      ar.zz[off + u] = Zs[r];
     } else {
-      dv[off + u] = Ds[r];
+      ar.dv[off + u] = Ds[r];
     }
+  }
+  const int nr = any_close ? nrot : 0;
+  for (int q = tid; q < nr; q += kPrepThreads) {
+    ar.rot_x[off + q] = col[rp[q]];
+    ar.rot_y[off + q] = col[rj[q]];
+    ar.rot_c[off + q] = rc[q];
+    ar.rot_s[off + q] = rs[q];
   }
   if (tid == 0) {
-    kk[off] = k;
-    rho_out[off] = rho;
-  }
-  // copy the children's eigenvectors into Qp (block diagonal, permuted)
-  for (int r = tid >> 6; r < s; r += kPrepThreads / 64) {
-    const int t = perm[r], u = col[r];
-    for (int i = tid & 63; i < s; i += 64)
-      Qp[(off + i) + (int64_t)n * (off + u)] =
-          ((t < m) == (i < m)) ? Qc[(off + i) + (int64_t)n * (off + t)] : 0.0;
-  }
-  // deflation rotations, in the order they were found
-  const int nr = any_close ? nrot : 0;
-  for (int q = 0; q < nr; ++q) {
-    __syncthreads();
-    double *x = Qp + (off + (int64_t)n * (off + col[rp[q]]));
-    double *y = Qp + (off + (int64_t)n * (off + col[rj[q]]));
-    const double c = rc[q], sn = rs[q];
-    for (int i = tid; i < s; i += kPrepThreads) {
-      const double a = x[i], b = y[i];
-      x[i] = c * a + sn * b;
-      y[i] = c * b - sn * a;
-    }
+    ar.kk[off] = k;
+    ar.rho[off] = rho;
+    ar.nrot[off] = nr;
   }
 }
 
@@ -602,18 +600,27 @@ __device__ __forceinline__ double lattice_mid(double lo, double hi) {
 
 __global__ void __launch_bounds__(256) k_dc_secular(const DcNode *__restrict__ nodes,
                                                     const int2 *__restrict__ wmap, int nw, int n,
-                                                    const double *__restrict__ dd,
-                                                    const double *__restrict__ zz,
-                                                    const int *__restrict__ kk,
-                                                    const double *__restrict__ rho_in,
-                                                    double *__restrict__ dels,
-                                                    double *__restrict__ dv) {
+                                                    DcArrays ar) {
   const int q = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (q >= nw) return;
   const int2 wm = wmap[q];
-  const int off = nodes[wm.x].off, i = wm.y;
-  const int k = kk[off];
+  const DcNode nd = nodes[wm.x];
+  const int off = nd.off, i = wm.y;
+  {
+    // Qp column i: the children's eigenvector it comes from, zero outside
+    // that child's rows (block diagonal)
+    const int t = ar.qsrc[off + i];
+    const double *src = ar.Qc + off + (int64_t)n * (off + t);
+    double *dst = ar.Qp + off + (int64_t)n * (off + i);
+    for (int r = lane; r < nd.s; r += 64) dst[r] = ((t < nd.m) == (r < nd.m)) ? src[r] : 0.0;
+  }
+  const double *__restrict__ dd = ar.dd;
+  const double *__restrict__ zz = ar.zz;
+  double *__restrict__ dels = ar.dels;
+  double *__restrict__ dv = ar.dv;
+  const int k = ar.kk[off];
   if (i >= k) return;
+  const double *rho_in = ar.rho;
   const double rho = rho_in[off];
   double z2[kKR], bs[kKR];
   double zsum = 0.0;
@@ -735,17 +742,33 @@ __global__ void __launch_bounds__(256) k_dc_secular(const DcNode *__restrict__ n
 // is O(1) by interlacing).
 __global__ void __launch_bounds__(256) k_dc_zhat(const DcNode *__restrict__ nodes,
                                                  const int2 *__restrict__ wmap, int nw, int n,
-                                                 const double *__restrict__ dd,
-                                                 const double *__restrict__ zz,
-                                                 const int *__restrict__ kk,
-                                                 const double *__restrict__ rho_in,
-                                                 const double *__restrict__ dels,
-                                                 double *__restrict__ zh) {
+                                                 DcArrays ar) {
   const int q = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (q >= nw) return;
   const int2 wm = wmap[q];
-  const int off = nodes[wm.x].off, i = wm.y;
-  const int k = kk[off];
+  const DcNode nd = nodes[wm.x];
+  const int off = nd.off, i = wm.y;
+  if (i == nd.s - 1) {
+    // the node's deflation rotations, in order, on its Qp columns (each lane
+    // keeps its rows, so the wavefront's program order orders them)
+    const int nr = ar.nrot[off];
+    for (int e = 0; e < nr; ++e) {
+      double *x = ar.Qp + off + (int64_t)n * (off + ar.rot_x[off + e]);
+      double *y = ar.Qp + off + (int64_t)n * (off + ar.rot_y[off + e]);
+      const double c = ar.rot_c[off + e], sn = ar.rot_s[off + e];
+      for (int r = lane; r < nd.s; r += 64) {
+        const double a = x[r], b = y[r];
+        x[r] = c * a + sn * b;
+        y[r] = c * b - sn * a;
+      }
+    }
+  }
+  const double *__restrict__ dd = ar.dd;
+  const double *__restrict__ zz = ar.zz;
+  const double *__restrict__ dels = ar.dels;
+  const double *rho_in = ar.rho;
+  double *__restrict__ zh = ar.zh;
+  const int k = ar.kk[off];
   if (i >= k) return;
   const double di = dd[off + i];
   double p = 1.0;
@@ -758,20 +781,34 @@ __global__ void __launch_bounds__(256) k_dc_zhat(const DcNode *__restrict__ node
   if (lane == 0) zh[off + i] = copysign(sqrt(fabs(p)), zz[off + i]);
 }
 
-// One wavefront per (node, root j): column j of U, u_i = zh_i / (d_i -
-// lambda_j), normalised.
+// One wavefront per (node, Qp column j): the rank of its eigenvalue among
+// the node's s (the k roots dv[0..k), the deflated values dv[k..s); ties by
+// column) gives lam[off + rank] and csrc[off + rank] = j; for a root, column
+// j of U, u_i = zh_i / (d_i - lambda_j), normalised.
 __global__ void __launch_bounds__(256) k_dc_ucol(const DcNode *__restrict__ nodes,
                                                  const int2 *__restrict__ wmap, int nw, int n,
-                                                 const int *__restrict__ kk,
-                                                 const double *__restrict__ dels,
-                                                 const double *__restrict__ zh,
-                                                 double *__restrict__ U) {
+                                                 DcArrays ar) {
   const int q = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (q >= nw) return;
   const int2 wm = wmap[q];
-  const int off = nodes[wm.x].off, j = wm.y;
-  const int k = kk[off];
+  const DcNode nd = nodes[wm.x];
+  const int off = nd.off, j = wm.y;
+  const double x = ar.dv[off + j];
+  double below = 0.0;
+  for (int t = lane; t < nd.s; t += 64) {
+    const double y = ar.dv[off + t];
+    below += ((y < x) || (y == x && t < j)) ? 1.0 : 0.0;
+  }
+  const int rank = (int)wsum(below);
+  if (lane == 0) {
+    ar.lam[off + rank] = x;
+    ar.csrc[off + rank] = j;
+  }
+  const int k = ar.kk[off];
   if (j >= k) return;
+  const double *__restrict__ zh = ar.zh;
+  const double *__restrict__ dels = ar.dels;
+  double *__restrict__ U = ar.U;
   double u[kKR];
   double um = 0.0;
 #pragma unroll
@@ -791,27 +828,6 @@ __global__ void __launch_bounds__(256) k_dc_ucol(const DcNode *__restrict__ node
   for (int r = 0; r < kKR; ++r) {
     const int i = lane + 64 * r;
     if (i < k) U[(off + i) + (int64_t)n * (off + j)] = u[r] * inv;
-  }
-}
-
-// One workgroup per node: ascending order of the node's s eigenvalues (the
-// k roots dv[0..k) and the deflated values dv[k..s)), ties by Qp column:
-// lam[off + rank] and csrc[off + rank] = Qp column.
-__global__ void __launch_bounds__(512) k_dc_rank(const DcNode *__restrict__ nodes,
-                                                 const double *__restrict__ dv,
-                                                 double *__restrict__ lam,
-                                                 int *__restrict__ csrc) {
-  __shared__ double v[kDcMaxN];
-  const DcNode nd = nodes[blockIdx.x];
-  const int off = nd.off, s = nd.s;
-  for (int t = threadIdx.x; t < s; t += 512) v[t] = dv[off + t];
-  __syncthreads();
-  for (int t = threadIdx.x; t < s; t += 512) {
-    const double x = v[t];
-    int r = 0;
-    for (int u = 0; u < s; ++u) r += (v[u] < x) || (v[u] == x && u < t);
-    lam[off + r] = x;
-    csrc[off + r] = t;
   }
 }
 
@@ -1010,12 +1026,30 @@ void sym_eig_dc(const double *A, int64_t lda, int n, double *w, double *W, int64
   ws.Qp.reserve(nn);
   ws.U.reserve(nn);
   ws.dels.reserve(nn);
-  ws.vec.reserve((size_t)17 * n);
-  ws.ivec.reserve((size_t)2 * n + 2);
+  ws.vec.reserve((size_t)19 * n);
+  ws.ivec.reserve((size_t)6 * n + 2);
   double *htau = ws.vec.p, *dg = htau + n, *eg = dg + n, *xb = eg + n;   // xb: 8n words
-  double *lam = xb + 8 * n, *dd = lam + n, *zz = dd + n, *dv = zz + n, *zh = dv + n,
-         *rho = zh + n;
-  int *kk = ws.ivec.p, *csrc = kk + n, *sync = csrc + n;
+  DcArrays ar;
+  ar.lam = xb + 8 * n;
+  ar.dd = ar.lam + n;
+  ar.zz = ar.dd + n;
+  ar.dv = ar.zz + n;
+  ar.zh = ar.dv + n;
+  ar.rho = ar.zh + n;
+  ar.rot_c = ar.rho + n;
+  ar.rot_s = ar.rot_c + n;
+  ar.Qc = ws.Qc.p;
+  ar.Qp = ws.Qp.p;
+  ar.U = ws.U.p;
+  ar.dels = ws.dels.p;
+  ar.kk = ws.ivec.p;
+  ar.csrc = ar.kk + n;
+  ar.qsrc = ar.csrc + n;
+  ar.rot_x = ar.qsrc + n;
+  ar.rot_y = ar.rot_x + n;
+  ar.nrot = ar.rot_y + n;
+  int *sync = ar.nrot + n;
+  double *lam = ar.lam;
   {
     FKF_TRACE("eig_tridiag", st);
     // columns in registers: RM rows per lane (n <= 64 RM), at most 8 CW
@@ -1048,18 +1082,16 @@ void sym_eig_dc(const double *A, int64_t lda, int n, double *w, double *W, int64
     for (const auto &L : ws.dc_levels) {
       const DcNode *nl = nodes + L.node0;
       // wave and tile tables index nodes globally
-      hipLaunchKernelGGL(k_dc_prep, dim3(L.nodes), dim3(kPrepThreads), 0, st, nl, n, eg, lam,
-                         ws.Qc.p, ws.Qp.p, dd, zz, dv, kk, rho);
+      hipLaunchKernelGGL(k_dc_prep, dim3(L.nodes), dim3(kPrepThreads), 0, st, nl, n, eg, ar);
       const unsigned gw = (unsigned)((L.waves + 3) / 4);
       hipLaunchKernelGGL(k_dc_secular, dim3(gw), dim3(256), 0, st, nodes, wmap + L.wave0, L.waves,
-                         n, dd, zz, kk, rho, ws.dels.p, dv);
+                         n, ar);
       hipLaunchKernelGGL(k_dc_zhat, dim3(gw), dim3(256), 0, st, nodes, wmap + L.wave0, L.waves, n,
-                         dd, zz, kk, rho, ws.dels.p, zh);
+                         ar);
       hipLaunchKernelGGL(k_dc_ucol, dim3(gw), dim3(256), 0, st, nodes, wmap + L.wave0, L.waves, n,
-                         kk, ws.dels.p, zh, ws.U.p);
-      hipLaunchKernelGGL(k_dc_rank, dim3(L.nodes), dim3(512), 0, st, nl, dv, lam, csrc);
+                         ar);
       hipLaunchKernelGGL(k_dc_gemm, dim3((unsigned)((L.tiles + 3) / 4)), dim3(256), 0, st, nodes,
-                         tiles + L.tile0, L.tiles, n, kk, csrc, ws.Qp.p, ws.U.p, ws.Qc.p);
+                         tiles + L.tile0, L.tiles, n, ar.kk, ar.csrc, ws.Qp.p, ws.U.p, ws.Qc.p);
     }
   }
   {

@@ -1558,7 +1558,8 @@ __global__ void __launch_bounds__(512) k_couple_mfma2(
       if (j < ncb && f[j]) m |= 1 << j;
     return __builtin_amdgcn_readfirstlane(m);
   };
-  auto load_b = [&](int e, int k0, double *b) {
+  // B operands of a chunk; blocks that the mask marks zero are not loaded
+  auto load_b = [&](int e, int k0, int msk, double *b) {
     const FarCluster ct = fc[far_col[e]];
     const double *x = xhat + ct.coef_off * nrhs;
 #pragma unroll
@@ -1568,7 +1569,7 @@ __global__ void __launch_bounds__(512) k_couple_mfma2(
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int c = c0 + 16 * j + lr;
-        b[4 * kk + j] = x[kc + (int64_t)ct.pd * (c < nrhs ? c : 0)];
+        b[4 * kk + j] = (msk >> j & 1) ? x[kc + (int64_t)ct.pd * (c < nrhs ? c : 0)] : 0.0;
       }
     }
   };
@@ -1580,7 +1581,7 @@ __global__ void __launch_bounds__(512) k_couple_mfma2(
   double bcur[16], bnext[16];
   int e = e0, k0 = 0, buf = 0;
   int mcur = e < e1 ? nz_mask(e) : 0, mnext = mcur;
-  if (e < e1) load_b(e, k0, bcur);
+  if (e < e1) load_b(e, k0, mcur, bcur);
   while (e < e1) {
     eval_chunk(e, k0, buf);
     // next chunk
@@ -1590,7 +1591,7 @@ __global__ void __launch_bounds__(512) k_couple_mfma2(
       kn = 0;
       if (en < e1) mnext = nz_mask(en);
     }
-    if (en < e1) load_b(en, kn, bnext);
+    if (en < e1) load_b(en, kn, mnext, bnext);
     __syncthreads();
     const double *K = Ks[buf];
 #pragma unroll
@@ -2035,7 +2036,8 @@ extern "C" fkf_status fkf_cov_build(const double *pts_host, int64_t n, int32_t d
       // several-column coupling blocks: (cluster, 64-row block), ordered by
       // decreasing work (rows x sum of the partners' coefficients).  (Dealing
       // them to the eight XCDs level by level in spatial runs, so that an
-      // XCD's items share partners, measured 10 % slower than this order.)
+      // XCD's items share partners, measured 10 % slower than this order;
+      // keeping a cluster's row blocks on one XCD, no faster.)
       std::vector<std::pair<int64_t, CoupleMItem>> cm;
       for (int s = 0; s < cov->n_fc; ++s) {
         int64_t kext = 0;
