@@ -43,6 +43,12 @@ struct fkf_obs {
   std::vector<int64_t> rowptr_h;
   std::vector<int32_t> col_h;
   std::vector<double> val_h, noise_h;
+  // rows of ray operators in Morton order of their endpoints (rays that cross
+  // the same region close together; empty for a CSR operator): the order in
+  // which the cross covariance takes them as columns, so that a cluster's
+  // moments are nonzero in few 16-column blocks
+  std::vector<int32_t> order_h;
+  fkf::DevBuf<int32_t> order;
   fkf::DevBuf<int64_t> rowptr;
   fkf::DevBuf<int32_t> col;
   fkf::DevBuf<double> val, noise, inv_sqrt_noise;
@@ -117,10 +123,12 @@ bool cov_mixed(const fkf_cov *cov);
 int cov_kind(const fkf_cov *cov);
 double cov_length(const fkf_cov *cov);
 // Gamma H^T from the rows of the sparse H (CSR, device): false, with nothing
-// queued, where that form does not apply
+// queued, where that form does not apply.  order (device, n_m, or null): the
+// rows in the order in which they are taken as columns of the product (the
+// result is in row order either way).
 bool cov_apply_sparse_rows(fkf_cov *cov, int n_m, const int64_t *rowptr, const int32_t *col,
-                           const double *val, int64_t nnz, int64_t max_row, double *Y,
-                           int64_t ldy, hipStream_t st);
+                           const double *val, int64_t nnz, int64_t max_row, const int32_t *order,
+                           double *Y, int64_t ldy, hipStream_t st);
 
 static std::atomic<uint64_t> g_obs_gen{1};
 
@@ -552,8 +560,8 @@ static double gep_tol(const fkf_filter *f) { return f->mixed ? 1e-10 : 1e-12; }
 static void cross_cov(fkf_cov *cov, const fkf_obs *o, DevBuf<double> &Ht, double *P,
                       int64_t ldp, hipStream_t st, bool ht_ready = false) {
   const int64_t n = o->n;
-  if (cov_apply_sparse_rows(cov, o->n_m, o->rowptr.p, o->col.p, o->val.p, o->nnz, o->max_row, P,
-                            ldp, st))
+  if (cov_apply_sparse_rows(cov, o->n_m, o->rowptr.p, o->col.p, o->val.p, o->nnz, o->max_row,
+                            o->order.p, P, ldp, st))
     return;
   if (!ht_ready) {
     Ht.reserve((size_t)n * o->n_m);
@@ -1170,6 +1178,7 @@ static void obs_finish(fkf_obs *o, hipStream_t st) {
   o->col.upload(o->col_h, st);
   o->val.upload(o->val_h, st);
   o->noise.upload(o->noise_h, st);
+  if (!o->order_h.empty()) o->order.upload(o->order_h, st);
   std::vector<double> isr(o->noise_h.size());
   for (size_t i = 0; i < isr.size(); ++i) isr[i] = 1.0 / std::sqrt(o->noise_h[i]);
   o->inv_sqrt_noise.upload(isr, st);
@@ -1230,6 +1239,26 @@ extern "C" fkf_status fkf_obs_create_rays(int32_t d, const int32_t *grid, int32_
                   "fkf_obs_create_rays: ray endpoints must lie in the unit box");
     auto o = std::make_unique<fkf_obs>();
     trace_rays(d, grid, n_m, src, rcv, o->rowptr_h, o->col_h, o->val_h);
+    {
+      // Morton key of (source, receiver): 10 bits per coordinate, bits
+      // interleaved from the most significant down
+      std::vector<std::pair<uint64_t, int32_t>> key(n_m);
+      for (int32_t m = 0; m < n_m; ++m) {
+        uint32_t q[6];
+        for (int k = 0; k < d; ++k) {
+          q[k] = (uint32_t)std::min(1023.0, std::floor(src[(int64_t)m * d + k] * 1024.0));
+          q[d + k] = (uint32_t)std::min(1023.0, std::floor(rcv[(int64_t)m * d + k] * 1024.0));
+        }
+        uint64_t kv = 0;
+        for (int b = 9; b >= 0; --b)
+          for (int k = 0; k < 2 * d; ++k) kv = (kv << 1) | ((q[k] >> b) & 1u);
+        key[m] = {kv, m};
+      }
+      std::stable_sort(key.begin(), key.end(),
+                       [](const auto &a, const auto &b) { return a.first < b.first; });
+      o->order_h.resize(n_m);
+      for (int32_t m = 0; m < n_m; ++m) o->order_h[m] = key[m].second;
+    }
     o->n_m = n_m;
     o->n = n;
     o->nnz = (int64_t)o->col_h.size();

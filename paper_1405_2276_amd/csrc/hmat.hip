@@ -1349,7 +1349,7 @@ __global__ void __launch_bounds__(512) k_down_mfma2(
     const double *__restrict__ cheb, const FarCluster *__restrict__ fc,
     const int32_t *__restrict__ anc_ptr, const int32_t *__restrict__ anc_idx,
     const double *__restrict__ yhat, const int64_t *__restrict__ perm, int nrhs,
-    double *__restrict__ Y, int64_t ldy) {
+    const int32_t *__restrict__ ocol, int ocol0, double *__restrict__ Y, int64_t ldy) {
   constexpr int PM = PMax<D>::v, LDK = 18;
   __shared__ double Ls[D][64][PM + 1];
   __shared__ double As[2][64 * LDK];
@@ -1472,7 +1472,8 @@ __global__ void __launch_bounds__(512) k_down_mfma2(
         const int i = 16 * q + lk + 4 * r;
         const int cc = c0 + 16 * j + lr;
         if (i < ms && cc < nrhs) {
-          double *y = Y + perm[s0 + i] + ldy * cc;
+          const int oc = ocol ? ocol[ocol0 + cc] : ocol0 + cc;
+          double *y = Y + perm[s0 + i] + ldy * oc;
           *y += acc[q][j][r];
         }
       }
@@ -2446,10 +2447,10 @@ constexpr int kSpRowMax = 2048;
 __global__ void __launch_bounds__(256) k_sparse_rows(
     const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
     const double *__restrict__ val, const int32_t *__restrict__ iperm,
-    const int64_t *__restrict__ leaf_off, int n_leaves, int j0, int32_t *__restrict__ tix,
-    double *__restrict__ tval, int32_t *__restrict__ cnt) {
+    const int64_t *__restrict__ leaf_off, int n_leaves, int j0, const int32_t *__restrict__ order,
+    int32_t *__restrict__ tix, double *__restrict__ tval, int32_t *__restrict__ cnt) {
   __shared__ int64_t key[kSpRowMax];
-  const int j = j0 + blockIdx.x, tid = threadIdx.x;
+  const int j = order ? order[j0 + blockIdx.x] : j0 + blockIdx.x, tid = threadIdx.x;
   const int64_t e0 = rowptr[j];
   const int len = (int)(rowptr[j + 1] - e0);
   int m = 1;
@@ -2522,14 +2523,15 @@ __global__ void __launch_bounds__(256) k_sparse_nzb(const int32_t *__restrict__ 
 template <int D>
 __global__ void __launch_bounds__(256) k_up_sparse(
     const FarCluster *__restrict__ fc, const int32_t *__restrict__ fc_leaf,
-    const double *__restrict__ lag, const int64_t *__restrict__ rowptr, int j0, int nrhs,
-    const int32_t *__restrict__ tix, const double *__restrict__ tval,
-    const int32_t *__restrict__ cnt, int n_leaves, double *__restrict__ xhat) {
+    const double *__restrict__ lag, const int64_t *__restrict__ rowptr, int j0,
+    const int32_t *__restrict__ order, int nrhs, const int32_t *__restrict__ tix,
+    const double *__restrict__ tval, const int32_t *__restrict__ cnt, int n_leaves,
+    double *__restrict__ xhat) {
   constexpr int PM = PMax<D>::v;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int jj = blockIdx.y * 4 + w;
   if (jj >= nrhs) return;
-  const int j = j0 + jj;
+  const int j = order ? order[j0 + jj] : j0 + jj;
   const FarCluster c = fc[blockIdx.x];
   const int32_t *cj = cnt + (int64_t)jj * (n_leaves + 1);
   const int64_t base = rowptr[j] - rowptr[0];
@@ -2586,13 +2588,14 @@ template <typename TT>
 __global__ void __launch_bounds__(256) k_near_sparse(
     const TT *__restrict__ frag, const int32_t *__restrict__ near_ptr,
     const int32_t *__restrict__ near_src, const int64_t *__restrict__ leaf_off,
-    const int64_t *__restrict__ rowptr, int j0, int nrhs, const int32_t *__restrict__ tix,
-    const double *__restrict__ tval, const int32_t *__restrict__ cnt, int n_leaves,
-    const int64_t *__restrict__ perm, double *__restrict__ Y, int64_t ldy) {
+    const int64_t *__restrict__ rowptr, int j0, const int32_t *__restrict__ order, int nrhs,
+    const int32_t *__restrict__ tix, const double *__restrict__ tval,
+    const int32_t *__restrict__ cnt, int n_leaves, const int64_t *__restrict__ perm,
+    double *__restrict__ Y, int64_t ldy) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int jj = blockIdx.y * 4 + w;
   if (jj >= nrhs) return;
-  const int s = blockIdx.x, j = j0 + jj;
+  const int s = blockIdx.x, j = order ? order[j0 + jj] : j0 + jj;
   const int e0 = near_ptr[s], e1 = near_ptr[s + 1];
   const int64_t s0 = leaf_off[s], ms = leaf_off[s + 1] - s0;
   const int32_t *cj = cnt + (int64_t)jj * (n_leaves + 1);
@@ -2611,7 +2614,7 @@ __global__ void __launch_bounds__(256) k_near_sparse(
       acc = fma((double)A[(k >> 2) * 64 + (k & 3) * 16], tval[h], acc);
     }
   }
-  if (l < ms) Y[perm[s0 + l] + ldy * (int64_t)jj] = acc;
+  if (l < ms) Y[perm[s0 + l] + ldy * (int64_t)j] = acc;   // column of row j of H
 }
 
 // Columns of a several-column product given as sparse rows: row pointers
@@ -2619,11 +2622,14 @@ __global__ void __launch_bounds__(256) k_near_sparse(
 struct SparseRhs {
   const int64_t *rowptr;
   int j0;
+  const int32_t *order;   // column c of the product is row order[c] of H (null: row c)
 };
 
 // Several columns on the FP64 matrix cores: the near field on a forked
 // stream, concurrently with the far-field chain (upward chunks + reduction,
-// couplings per cluster row block); the downward pass then adds to Y.
+// couplings per cluster row block); the downward pass then adds to Y.  With
+// sparse rows (sp), column c of the block is row r = sp->order[sp->j0 + c]
+// (or sp->j0 + c) of H and lands in column r of Y (Y not offset by the block).
 template <int D, bool F32>
 void apply_multi_t(fkf_cov *cov, const ApplyWs &ws, int nrhs, double *Y, int64_t ldy,
                    hipStream_t st, const SparseRhs *sp) {
@@ -2640,7 +2646,7 @@ void apply_multi_t(fkf_cov *cov, const ApplyWs &ws, int nrhs, double *Y, int64_t
       const TT *frag = F32 ? (const TT *)cov->frag32.p : (const TT *)cov->frag.p;
       hipLaunchKernelGGL(k_near_sparse<TT>, dim3(cov->n_leaves, (unsigned)((nrhs + 3) / 4)),
                          dim3(256), 0, cov->side, frag, cov->near_ptr.p, cov->near_src.p,
-                         cov->leaf_off.p, sp->rowptr, sp->j0, nrhs, cov->sp_tix.p,
+                         cov->leaf_off.p, sp->rowptr, sp->j0, sp->order, nrhs, cov->sp_tix.p,
                          cov->sp_val.p, cov->sp_cnt.p, cov->n_leaves, cov->perm.p, Y, ldy);
     } else {
       FKF_TRACE("hmat_near_multi", cov->side);
@@ -2651,7 +2657,7 @@ void apply_multi_t(fkf_cov *cov, const ApplyWs &ws, int nrhs, double *Y, int64_t
       FKF_TRACE("hmat_far_up_sparse", st);
       hipLaunchKernelGGL((k_up_sparse<D>), dim3((unsigned)cov->n_fc, (unsigned)((nrhs + 3) / 4)),
                          dim3(256), 0, st, cov->fc.p, cov->fc_leaf.p, cov->lag.p, sp->rowptr,
-                         sp->j0, nrhs, cov->sp_tix.p, cov->sp_val.p, cov->sp_cnt.p,
+                         sp->j0, sp->order, nrhs, cov->sp_tix.p, cov->sp_val.p, cov->sp_cnt.p,
                          cov->n_leaves, ws.xhat);
     } else {
       FKF_TRACE("hmat_far_up_multi", st);
@@ -2696,7 +2702,8 @@ void apply_multi_t(fkf_cov *cov, const ApplyWs &ws, int nrhs, double *Y, int64_t
   FKF_CHECK_HIP(hipStreamWaitEvent(st, cov->ev_join, 0));
   hipLaunchKernelGGL(k_down_mfma2<D>, dim3(cov->n_leaves, (unsigned)((nrhs + 511) / 512)),
                      dim3(512), 0, st, cov->leaf_off.p, cov->pts.p, n, cov->cheb.p, cov->fc.p,
-                     cov->anc_ptr.p, cov->anc_idx.p, ws.yhat, cov->perm.p, nrhs, Y, ldy);
+                     cov->anc_ptr.p, cov->anc_idx.p, ws.yhat, cov->perm.p, nrhs,
+                     sp ? sp->order : nullptr, sp ? sp->j0 : 0, Y, ldy);
 }
 
 void apply_multi(fkf_cov *cov, const ApplyWs &ws, int nrhs, double *Y, int64_t ldy,
@@ -2866,8 +2873,8 @@ extern "C" fkf_status fkf_cov_apply_noalloc(fkf_cov *cov, const double *X, int64
 namespace fkf {
 
 bool cov_apply_sparse_rows(fkf_cov *cov, int n_m, const int64_t *rowptr, const int32_t *col,
-                           const double *val, int64_t nnz, int64_t max_row, double *Y,
-                           int64_t ldy, hipStream_t st) {
+                           const double *val, int64_t nnz, int64_t max_row, const int32_t *order,
+                           double *Y, int64_t ldy, hipStream_t st) {
   if (!cov->sp_ok || cov->n_fc == 0 || n_m < 2 || max_row > kSpRowMax) return false;
   cov->sp_tix.reserve((size_t)std::max<int64_t>(nnz, 1));
   cov->sp_val.reserve((size_t)std::max<int64_t>(nnz, 1));
@@ -2890,10 +2897,10 @@ bool cov_apply_sparse_rows(fkf_cov *cov, int n_m, const int64_t *rowptr, const i
   for (int32_t c0 = 0; c0 < n_m; c0 += chunk) {
     const int32_t nc = std::min(chunk, n_m - c0);
     hipLaunchKernelGGL(k_sparse_rows, dim3((unsigned)nc), dim3(256), 0, st, rowptr, col, val,
-                       cov->iperm.p, cov->leaf_off.p, cov->n_leaves, c0, cov->sp_tix.p,
+                       cov->iperm.p, cov->leaf_off.p, cov->n_leaves, c0, order, cov->sp_tix.p,
                        cov->sp_val.p, cov->sp_cnt.p);
-    const SparseRhs sp{rowptr, c0};
-    apply_multi(cov, ws, nc, Y + ldy * (int64_t)c0, ldy, st, &sp);
+    const SparseRhs sp{rowptr, c0, order};
+    apply_multi(cov, ws, nc, Y, ldy, st, &sp);
     FKF_CHECK_HIP(hipGetLastError());
   }
   return true;
