@@ -1344,7 +1344,7 @@ __device__ __forceinline__ int xcd_contiguous(int b, int n) {
 // [32 w, 32 w + 32) of Yhat_c read straight from global memory one chunk
 // ahead.  (A 64 x 32 tile per wavefront keeps it within 128 registers, so
 // two workgroups share a CU and one's matrix-core work covers the other's
-// barriers: 23 % faster than 64 x 64 tiles with one workgroup per CU.)
+// barriers: 13 % faster than 64 x 64 tiles with one workgroup per CU.)
 template <int D>
 __global__ void __launch_bounds__(512, 2) k_down_mfma2(
     const int64_t *__restrict__ leaf_off, const double *__restrict__ pts, int64_t n,
@@ -1454,8 +1454,8 @@ __global__ void __launch_bounds__(512, 2) k_down_mfma2(
         if (q < nrb) {
           const double av = A[(16 * q + lr) * LDK + 4 * kk + lk];
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
-            if (j < ncb) acc[q][j] = mfma4(av, bcur[4 * kk + j], acc[q][j]);
+          for (int j = 0; j < 2; ++j)
+            if (j < ncb) acc[q][j] = mfma4(av, bcur[2 * kk + j], acc[q][j]);
         }
       }
     }
@@ -1487,20 +1487,27 @@ __global__ void k_zero(double *__restrict__ p, int64_t len) {
 }
 
 // Couplings of the several-column product, Yhat_s = sum over admissible t of
-// K(xi_s, xi_t) Xhat_t, for one 64-row block of cluster s and 512 columns per
-// workgroup.  The workgroup evaluates each 64 x 16 chunk of K once into LDS
-// (double-buffered, one barrier per chunk); wavefront w multiplies it with
-// columns [64 w, 64 w + 64) of Xhat_t, whose B operands it reads straight from
-// global memory one chunk ahead (every 32-byte sector fully used).  Rows past
-// the cluster and coefficients past the partner are zero in K; only the
-// 16-row blocks inside the cluster are multiplied.
-template <int D, bool F32>
-__global__ void __launch_bounds__(512) k_couple_mfma2(
+// K(xi_s, xi_t) Xhat_t, for one 64-row block of cluster s and 256 columns per
+// workgroup.  Each 64 x 16 chunk of K goes to LDS once per workgroup
+// (double-buffered, one barrier per chunk): read from the pair's stored
+// matrix one chunk ahead where the couplings are stored (ST), else evaluated;
+// wavefront w multiplies it with columns [32 w, 32 w + 32) of Xhat_t, whose B
+// operands it reads straight from global memory one chunk ahead (every
+// 32-byte sector fully used).  Rows past the cluster and coefficients past
+// the partner are zero in K; only the 16-row blocks inside the cluster are
+// multiplied.  (Reading the stored matrices instead of evaluating K: 2.20 ->
+// 1.49 ms on the 480-ray crosswell; 64 x 32 tiles instead of 64 x 64, with two
+// workgroups per CU: 1.49 -> 1.34 ms.)
+template <int D, bool F32, bool ST>
+__global__ void __launch_bounds__(512, 2) k_couple_mfma2(
     const CoupleMItem *__restrict__ items, const FarCluster *__restrict__ fc,
     const int32_t *__restrict__ far_ptr, const int32_t *__restrict__ far_col,
     const double *__restrict__ cheb, int kind, double inv_ell, double amp,
+    const int64_t *__restrict__ far_koff, const void *__restrict__ kst_v,
     const double *__restrict__ xhat, int nrhs, double *__restrict__ yhat,
     const int32_t *__restrict__ nzb) {
+  typedef typename std::conditional<F32, float, double>::type KT;
+  const KT *__restrict__ kst = reinterpret_cast<const KT *>(kst_v);
   constexpr int KC = 16, LDK = 18;
   __shared__ double Ks[2][64 * LDK];
   const CoupleMItem it = items[blockIdx.x];
@@ -1511,14 +1518,14 @@ __global__ void __launch_bounds__(512) k_couple_mfma2(
   const int r0 = 64 * it.rb;
   const int rows = min(64, cs.pd - r0);
   const int nrb = (rows + 15) >> 4;
-  const int c0 = blockIdx.y * 512 + 64 * w;
+  const int c0 = blockIdx.y * 256 + 32 * w;
   // 16-column blocks of this wavefront inside nrhs (wave-uniform)
-  const int ncb = min(4, max(0, (nrhs - c0 + 15) >> 4));
+  const int ncb = min(2, max(0, (nrhs - c0 + 15) >> 4));
   const double scale = kernel_c(kind) * inv_ell;
   // K evaluation role of this thread: row er, chunk columns ek, ek + 1
   const int er = tid >> 3, ek = 2 * (tid & 7);
   double xs[D];
-  {
+  if (!ST) {
     int r = er < rows ? r0 + er : 0;
     const double *us = cheb + cs.p * 2 * kMaxCheb;
 #pragma unroll
@@ -1547,17 +1554,29 @@ __global__ void __launch_bounds__(512) k_couple_mfma2(
       Ks[buf][er * LDK + ek + h] = (er < rows && kb < ct.pd) ? kv : 0.0;
     }
   };
+  // stored couplings (ST): this thread's two entries of a chunk, read from
+  // the pair's matrix (column-major, leading dimension pd of the target)
+  // one chunk ahead and put in LDS at the top of the chunk
+  auto load_k = [&](int e, int k0, double *kv) {
+    const KT *K = kst + far_koff[e];
+    const int pdt = fc[far_col[e]].pd;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int kb = k0 + ek + h;
+      kv[h] = (er < rows && kb < pdt) ? (double)K[(r0 + er) + (int64_t)kb * cs.pd] : 0.0;
+    }
+  };
   // with nzb (moments of sparse columns: nzb[t ncb16 + b] = 0 when the
   // 16-column block b of partner t's coefficients is exactly zero): bit j of
   // the wave-uniform mask is set when block j of this wavefront is nonzero;
   // zero blocks are not multiplied (their products would add zeros)
   const int ncb16 = (nrhs + 15) >> 4;
   auto nz_mask = [&](int e) -> int {
-    if (!nzb) return 0xf;
+    if (!nzb) return 3;
     const int32_t *f = nzb + (int64_t)far_col[e] * ncb16 + (c0 >> 4);
     int m = 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 2; ++j)
       if (j < ncb && f[j]) m |= 1 << j;
     return __builtin_amdgcn_readfirstlane(m);
   };
@@ -1570,23 +1589,31 @@ __global__ void __launch_bounds__(512) k_couple_mfma2(
       const int kb = k0 + 4 * kk + lk;
       const int kc = kb < ct.pd ? kb : 0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < 2; ++j) {
         const int c = c0 + 16 * j + lr;
-        b[4 * kk + j] = (msk >> j & 1) ? x[kc + (int64_t)ct.pd * (c < nrhs ? c : 0)] : 0.0;
+        b[2 * kk + j] = (msk >> j & 1) ? x[kc + (int64_t)ct.pd * (c < nrhs ? c : 0)] : 0.0;
       }
     }
   };
-  v4d acc[4][4];
+  v4d acc[4][2];
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[q][j] = v4d{0, 0, 0, 0};
-  double bcur[16], bnext[16];
+    for (int j = 0; j < 2; ++j) acc[q][j] = v4d{0, 0, 0, 0};
+  double bcur[8], bnext[8], kcur[2] = {0.0, 0.0}, knext[2] = {0.0, 0.0};
   int e = e0, k0 = 0, buf = 0;
   int mcur = e < e1 ? nz_mask(e) : 0, mnext = mcur;
-  if (e < e1) load_b(e, k0, mcur, bcur);
+  if (e < e1) {
+    load_b(e, k0, mcur, bcur);
+    if (ST) load_k(e, k0, kcur);
+  }
   while (e < e1) {
-    eval_chunk(e, k0, buf);
+    if (ST) {
+      Ks[buf][er * LDK + ek] = kcur[0];
+      Ks[buf][er * LDK + ek + 1] = kcur[1];
+    } else {
+      eval_chunk(e, k0, buf);
+    }
     // next chunk
     int en = e, kn = k0 + KC;
     if (kn >= fc[far_col[e]].pd) {
@@ -1594,7 +1621,10 @@ __global__ void __launch_bounds__(512) k_couple_mfma2(
       kn = 0;
       if (en < e1) mnext = nz_mask(en);
     }
-    if (en < e1) load_b(en, kn, mnext, bnext);
+    if (en < e1) {
+      load_b(en, kn, mnext, bnext);
+      if (ST) load_k(en, kn, knext);
+    }
     __syncthreads();
     const double *K = Ks[buf];
 #pragma unroll
@@ -1604,13 +1634,15 @@ __global__ void __launch_bounds__(512) k_couple_mfma2(
         if (q < nrb) {
           const double a = K[(16 * q + lr) * LDK + 4 * kk + lk];
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
-            if (j < ncb && (mcur >> j & 1)) acc[q][j] = mfma4(a, bcur[4 * kk + j], acc[q][j]);
+          for (int j = 0; j < 2; ++j)
+            if (j < ncb && (mcur >> j & 1)) acc[q][j] = mfma4(a, bcur[2 * kk + j], acc[q][j]);
         }
       }
     }
 #pragma unroll
-    for (int i = 0; i < 16; ++i) bcur[i] = bnext[i];
+    for (int i = 0; i < 8; ++i) bcur[i] = bnext[i];
+    kcur[0] = knext[0];
+    kcur[1] = knext[1];
     e = en;
     k0 = kn;
     mcur = mnext;
@@ -1620,7 +1652,7 @@ __global__ void __launch_bounds__(512) k_couple_mfma2(
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int a = 16 * q + lk + 4 * r;
@@ -2687,12 +2719,22 @@ void apply_multi_t(fkf_cov *cov, const ApplyWs &ws, int nrhs, double *Y, int64_t
                            cov->sp_nzb.p);
         nzb = cov->sp_nzb.p;
       }
-      if (cov->n_cm_items > 0)
-        hipLaunchKernelGGL((k_couple_mfma2<D, F32>),
-                           dim3((unsigned)cov->n_cm_items, (unsigned)((nrhs + 511) / 512)),
-                           dim3(512), 0, st, cov->cm_items.p, cov->fc.p, cov->far_ptr.p,
-                           cov->far_col.p, cov->cheb.p, cov->kind, 1.0 / cov->ell, cov->amp,
-                           ws.xhat, nrhs, ws.yhat, nzb);
+      if (cov->n_cm_items > 0) {
+        // couplings read from the stored matrices where they are kept, else
+        // evaluated into LDS chunk by chunk
+        const dim3 grid((unsigned)cov->n_cm_items, (unsigned)((nrhs + 255) / 256));
+        const void *kst = F32 ? (const void *)cov->kst32.p : (const void *)cov->kst.p;
+        if (cov->stored)
+          hipLaunchKernelGGL((k_couple_mfma2<D, F32, true>), grid, dim3(512), 0, st,
+                             cov->cm_items.p, cov->fc.p, cov->far_ptr.p, cov->far_col.p,
+                             cov->cheb.p, cov->kind, 1.0 / cov->ell, cov->amp, cov->far_koff.p,
+                             kst, ws.xhat, nrhs, ws.yhat, nzb);
+        else
+          hipLaunchKernelGGL((k_couple_mfma2<D, F32, false>), grid, dim3(512), 0, st,
+                             cov->cm_items.p, cov->fc.p, cov->far_ptr.p, cov->far_col.p,
+                             cov->cheb.p, cov->kind, 1.0 / cov->ell, cov->amp, nullptr,
+                             nullptr, ws.xhat, nrhs, ws.yhat, nzb);
+      }
     }
   }
   if (cov->n_fc == 0) {
