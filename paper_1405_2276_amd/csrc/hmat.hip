@@ -182,6 +182,7 @@ struct fkf_cov {
   fkf::DevBuf<double> ws;                // product workspace (grown on demand)
   fkf::DevBuf<int32_t> sp_tix, sp_cnt;   // sparse rows in tree order, per-leaf counts
   fkf::DevBuf<int32_t> sp_nzb;           // nonzero 16-column blocks of the moments
+  fkf::DevBuf<int32_t> sp_ynz;           // nonzero 16-column blocks of Yhat
   fkf::DevBuf<double> sp_val;
   // fork/join of the near field onto a second stream
   hipStream_t side = nullptr;
@@ -1350,8 +1351,9 @@ __global__ void __launch_bounds__(512, 2) k_down_mfma2(
     const int64_t *__restrict__ leaf_off, const double *__restrict__ pts, int64_t n,
     const double *__restrict__ cheb, const FarCluster *__restrict__ fc,
     const int32_t *__restrict__ anc_ptr, const int32_t *__restrict__ anc_idx,
-    const double *__restrict__ yhat, const int64_t *__restrict__ perm, int nrhs,
-    const int32_t *__restrict__ ocol, int ocol0, double *__restrict__ Y, int64_t ldy) {
+    const double *__restrict__ yhat, const int32_t *__restrict__ ynz,
+    const int64_t *__restrict__ perm, int nrhs, const int32_t *__restrict__ ocol, int ocol0,
+    double *__restrict__ Y, int64_t ldy) {
   constexpr int PM = PMax<D>::v, LDK = 18;
   __shared__ double Ls[D][64][PM + 1];
   __shared__ double As[2][64 * LDK];
@@ -1366,7 +1368,20 @@ __global__ void __launch_bounds__(512, 2) k_down_mfma2(
   const int ncb = min(2, max(0, (nrhs - c0 + 15) >> 4));
   const int er = tid >> 3, ek = 2 * (tid & 7);   // basis role: point er, coefficients ek, ek+1
   const int ea = anc_ptr[s], eb = anc_ptr[s + 1];
-  auto load_b = [&](int e, int a0, double *b) {
+  // with ynz (nonzero 16-column blocks of each cluster's Yhat): bit j of the
+  // wave-uniform mask is set when block j of this wavefront is nonzero for
+  // ancestor e; zero blocks are neither loaded nor multiplied
+  const int ncb16 = (nrhs + 15) >> 4;
+  auto nz_mask = [&](int e) -> int {
+    if (!ynz) return 3;
+    const int32_t *f = ynz + (int64_t)anc_idx[e] * ncb16 + (c0 >> 4);
+    int m = 0;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      if (j < ncb && f[j]) m |= 1 << j;
+    return __builtin_amdgcn_readfirstlane(m);
+  };
+  auto load_b = [&](int e, int a0, int msk, double *b) {
     const FarCluster c = fc[anc_idx[e]];
     const double *y = yhat + c.coef_off * nrhs;
 #pragma unroll
@@ -1376,7 +1391,7 @@ __global__ void __launch_bounds__(512, 2) k_down_mfma2(
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int cc = c0 + 16 * j + lr;
-        b[2 * kk + j] = y[ac + (int64_t)c.pd * (cc < nrhs ? cc : 0)];
+        b[2 * kk + j] = (msk >> j & 1) ? y[ac + (int64_t)c.pd * (cc < nrhs ? cc : 0)] : 0.0;
       }
     }
   };
@@ -1388,7 +1403,8 @@ __global__ void __launch_bounds__(512, 2) k_down_mfma2(
   double bcur[8], bnext[8];
   int buf = 0;
   int e = ea, a0 = 0;
-  if (e < eb) load_b(e, 0, bcur);
+  int mcur = e < eb ? nz_mask(e) : 0, mnext = mcur;
+  if (e < eb) load_b(e, 0, mcur, bcur);
   while (e < eb) {
     const int ci = anc_idx[e];
     const int p = fc[ci].p, pd = fc[ci].pd;
@@ -1427,8 +1443,9 @@ __global__ void __launch_bounds__(512, 2) k_down_mfma2(
     if (an >= pd) {
       ++en;
       an = 0;
+      if (en < eb) mnext = nz_mask(en);
     }
-    if (en < eb) load_b(en, an, bnext);
+    if (en < eb) load_b(en, an, mnext, bnext);
     __syncthreads();
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -1455,12 +1472,13 @@ __global__ void __launch_bounds__(512, 2) k_down_mfma2(
           const double av = A[(16 * q + lr) * LDK + 4 * kk + lk];
 #pragma unroll
           for (int j = 0; j < 2; ++j)
-            if (j < ncb) acc[q][j] = mfma4(av, bcur[2 * kk + j], acc[q][j]);
+            if (j < ncb && (mcur >> j & 1)) acc[q][j] = mfma4(av, bcur[2 * kk + j], acc[q][j]);
         }
       }
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) bcur[i] = bnext[i];
+    mcur = mnext;
     buf ^= 1;
     e = en;
     a0 = an;
@@ -1603,6 +1621,7 @@ __global__ void __launch_bounds__(512, 2) k_couple_mfma2(
   double bcur[8], bnext[8], kcur[2] = {0.0, 0.0}, knext[2] = {0.0, 0.0};
   int e = e0, k0 = 0, buf = 0;
   int mcur = e < e1 ? nz_mask(e) : 0, mnext = mcur;
+  int mor = 0;   // blocks nonzero for some partner (the others of Yhat stay zero)
   if (e < e1) {
     load_b(e, k0, mcur, bcur);
     if (ST) load_k(e, k0, kcur);
@@ -1643,11 +1662,15 @@ __global__ void __launch_bounds__(512, 2) k_couple_mfma2(
     for (int i = 0; i < 8; ++i) bcur[i] = bnext[i];
     kcur[0] = knext[0];
     kcur[1] = knext[1];
+    mor |= mcur;
     e = en;
     k0 = kn;
     mcur = mnext;
     buf ^= 1;
   }
+  // with sparse moments a zero block of Yhat is not written (the downward
+  // pass skips it by the same mask)
+  if (!nzb) mor = 3;
   double *o = yhat + cs.coef_off * nrhs;
 #pragma unroll
   for (int q = 0; q < 4; ++q)
@@ -1657,7 +1680,7 @@ __global__ void __launch_bounds__(512, 2) k_couple_mfma2(
       for (int r = 0; r < 4; ++r) {
         const int a = 16 * q + lk + 4 * r;
         const int cc = c0 + 16 * j + lr;
-        if (a < rows && cc < nrhs) o[r0 + a + (int64_t)cs.pd * cc] = acc[q][j][r];
+        if (a < rows && cc < nrhs && (mor >> j & 1)) o[r0 + a + (int64_t)cs.pd * cc] = acc[q][j][r];
       }
 }
 
@@ -2548,6 +2571,22 @@ __global__ void __launch_bounds__(256) k_sparse_nzb(const int32_t *__restrict__ 
   nzb[g] = any;
 }
 
+// Nonzero 16-column blocks of each far cluster's Yhat: block b of cluster s
+// is nonzero when block b of some partner's moments is (nzb of the partners).
+__global__ void __launch_bounds__(256) k_sparse_ynz(const int32_t *__restrict__ far_ptr,
+                                                    const int32_t *__restrict__ far_col,
+                                                    int n_fc, int ncb16,
+                                                    const int32_t *__restrict__ nzb,
+                                                    int32_t *__restrict__ ynz) {
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= (int64_t)n_fc * ncb16) return;
+  const int c = (int)(g / ncb16), b = (int)(g % ncb16);
+  int any = 0;
+  for (int e = far_ptr[c]; e < far_ptr[c + 1] && !any; ++e)
+    any = nzb[(int64_t)far_col[e] * ncb16 + b];
+  ynz[g] = any;
+}
+
 // Moments of far cluster c = blockIdx.x for four sparse rows per workgroup
 // (rows j0 + 4 blockIdx.y + w, one wavefront each, lanes over the
 // coefficients a): xhat[c.coef_off nrhs + a + pd (j - j0)] = sum over the
@@ -2560,11 +2599,14 @@ __global__ void __launch_bounds__(256) k_up_sparse(
     const double *__restrict__ lag, const int64_t *__restrict__ rowptr, int j0,
     const int32_t *__restrict__ order, int nrhs, const int32_t *__restrict__ tix,
     const double *__restrict__ tval, const int32_t *__restrict__ cnt, int n_leaves,
-    double *__restrict__ xhat) {
+    const int32_t *__restrict__ nzb, double *__restrict__ xhat) {
   constexpr int PM = PMax<D>::v;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int jj = blockIdx.y * 4 + w;
   if (jj >= nrhs) return;
+  // a column whose 16-column block of this cluster is zero is never read
+  // (the couplings skip such blocks): nothing to write
+  if (!nzb[(int64_t)blockIdx.x * ((nrhs + 15) >> 4) + (jj >> 4)]) return;
   const int j = order ? order[j0 + jj] : j0 + jj;
   const FarCluster c = fc[blockIdx.x];
   const int32_t *cj = cnt + (int64_t)jj * (n_leaves + 1);
@@ -2689,10 +2731,21 @@ void apply_multi_t(fkf_cov *cov, const ApplyWs &ws, int nrhs, double *Y, int64_t
     FKF_CHECK_HIP(hipEventRecord(cov->ev_join, cov->side));
     if (sp) {
       FKF_TRACE("hmat_far_up_sparse", st);
+      // zero 16-column blocks of every far cluster's moments (from the
+      // per-leaf counts of the rows), then the moments of the others
+      const int64_t nf = (int64_t)cov->n_fc * ((nrhs + 15) / 16);
+      cov->sp_nzb.reserve((size_t)nf);
+      hipLaunchKernelGGL(k_sparse_nzb, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, st,
+                         cov->fc_leaf.p, cov->n_fc, cov->sp_cnt.p, cov->n_leaves, nrhs,
+                         cov->sp_nzb.p);
       hipLaunchKernelGGL((k_up_sparse<D>), dim3((unsigned)cov->n_fc, (unsigned)((nrhs + 3) / 4)),
                          dim3(256), 0, st, cov->fc.p, cov->fc_leaf.p, cov->lag.p, sp->rowptr,
                          sp->j0, sp->order, nrhs, cov->sp_tix.p, cov->sp_val.p, cov->sp_cnt.p,
-                         cov->n_leaves, ws.xhat);
+                         cov->n_leaves, cov->sp_nzb.p, ws.xhat);
+      cov->sp_ynz.reserve((size_t)nf);
+      hipLaunchKernelGGL(k_sparse_ynz, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, st,
+                         cov->far_ptr.p, cov->far_col.p, cov->n_fc, (nrhs + 15) / 16,
+                         cov->sp_nzb.p, cov->sp_ynz.p);
     } else {
       FKF_TRACE("hmat_far_up_multi", st);
       hipLaunchKernelGGL((k_up_mfma2<D>),
@@ -2710,15 +2763,7 @@ void apply_multi_t(fkf_cov *cov, const ApplyWs &ws, int nrhs, double *Y, int64_t
         hipLaunchKernelGGL(k_zero, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st,
                            ws.yhat, len);
       }
-      const int32_t *nzb = nullptr;
-      if (sp && cov->n_cm_items > 0) {
-        const int64_t nf = (int64_t)cov->n_fc * ((nrhs + 15) / 16);
-        cov->sp_nzb.reserve((size_t)nf);
-        hipLaunchKernelGGL(k_sparse_nzb, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, st,
-                           cov->fc_leaf.p, cov->n_fc, cov->sp_cnt.p, cov->n_leaves, nrhs,
-                           cov->sp_nzb.p);
-        nzb = cov->sp_nzb.p;
-      }
+      const int32_t *nzb = sp ? cov->sp_nzb.p : nullptr;   // formed before the upward pass
       if (cov->n_cm_items > 0) {
         // couplings read from the stored matrices where they are kept, else
         // evaluated into LDS chunk by chunk
@@ -2746,8 +2791,8 @@ void apply_multi_t(fkf_cov *cov, const ApplyWs &ws, int nrhs, double *Y, int64_t
   FKF_CHECK_HIP(hipStreamWaitEvent(st, cov->ev_join, 0));
   hipLaunchKernelGGL(k_down_mfma2<D>, dim3(cov->n_leaves, (unsigned)((nrhs + 255) / 256)),
                      dim3(512), 0, st, cov->leaf_off.p, cov->pts.p, n, cov->cheb.p, cov->fc.p,
-                     cov->anc_ptr.p, cov->anc_idx.p, ws.yhat, cov->perm.p, nrhs,
-                     sp ? sp->order : nullptr, sp ? sp->j0 : 0, Y, ldy);
+                     cov->anc_ptr.p, cov->anc_idx.p, ws.yhat, sp ? cov->sp_ynz.p : nullptr,
+                     cov->perm.p, nrhs, sp ? sp->order : nullptr, sp ? sp->j0 : 0, Y, ldy);
 }
 
 void apply_multi(fkf_cov *cov, const ApplyWs &ws, int nrhs, double *Y, int64_t ldy,
