@@ -44,50 +44,10 @@ constexpr int kKR = kDcMaxN / 64;    // secular terms per lane
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// Lane-to-lane move of a double by a DPP pattern; lanes of rows outside
-// ROWS receive 0.
-template <int CTRL, int ROWS = 0xf>
-__device__ __forceinline__ double dpp_d(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Largest of v over the 64 lanes (same DPP pattern as wsum; v >= 0).
-__device__ __forceinline__ double wmax(double v) {
-  v = fmax(v, dpp_d<0xb1>(v));
-  v = fmax(v, dpp_d<0x4e>(v));
-  v = fmax(v, dpp_d<0x141>(v));
-  v = fmax(v, dpp_d<0x140>(v));
-  v = fmax(v, dpp_d<0x142, 0xa>(v));
-  v = fmax(v, dpp_d<0x143, 0xc>(v));
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)b, 63);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Sum over the 64 lanes of a wavefront with DPP moves (pairs, quads, rows of
-// 16 by mirrors, then row broadcasts; fixed order), returned to every lane
-// from lane 63.  All 64 lanes must be active.
-__device__ __forceinline__ double wsum(double v) {
-  v += dpp_d<0xb1>(v);         // quad_perm [1,0,3,2]
-  v += dpp_d<0x4e>(v);         // quad_perm [2,3,0,1]
-  v += dpp_d<0x141>(v);        // row_half_mirror
-  v += dpp_d<0x140>(v);        // row_mirror
-  v += dpp_d<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
-  v += dpp_d<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)b, 63);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
 // Sum over the 512 threads of a workgroup in a fixed order; every thread
 // gets the result.  red: 8 doubles of LDS.
 __device__ double block_sum512(double v, double *red) {
-  v = wsum(v);
+  v = wave_sum_all(v);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
@@ -227,7 +187,7 @@ __global__ void __launch_bounds__(kTrThreads) k_tridiag(const double *__restrict
         acc = fma(y, nr[m], acc);
       }
       if (vnext) {
-        acc = wsum(acc);
+        acc = wave_sum_all(acc);
         if (lane == 0) put_tagged(x + 2 * j, acc, tag);
         if (j == jmin) {
 #pragma unroll
@@ -387,7 +347,7 @@ __device__ double block_max256(double v, double *red) {
 }
 
 __device__ double block_sum256(double v, double *red) {
-  v = wsum(v);
+  v = wave_sum_all(v);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
@@ -633,7 +593,7 @@ __global__ void __launch_bounds__(256) k_dc_secular(const DcNode *__restrict__ n
     bs[r] = in ? dd[off + j] : 0.0;
     zsum += z2[r];
   }
-  zsum = wsum(zsum);
+  zsum = wave_sum_all(zsum);
   const double di = dd[off + i];
   const bool last = i == k - 1;
   int o = i;
@@ -645,7 +605,7 @@ __global__ void __launch_bounds__(256) k_dc_secular(const DcNode *__restrict__ n
 #pragma unroll
     for (int r = 0; r < kKR; ++r)
       if (lane + 64 * r < k) f += z2[r] / ((bs[r] - di) - mid);
-    if (1.0 + wsum(f) >= 0.0) {
+    if (1.0 + wave_sum_all(f) >= 0.0) {
       hi = mid;
     } else {
       o = i + 1;
@@ -679,8 +639,8 @@ __global__ void __launch_bounds__(256) k_dc_secular(const DcNode *__restrict__ n
         }
       }
     }
-    const double psi = wsum(a0), dpsi = wsum(a1);
-    const double phi = wsum(b0), dphi = wsum(b1);
+    const double psi = wave_sum_all(a0), dpsi = wave_sum_all(a1);
+    const double phi = wave_sum_all(b0), dphi = wave_sum_all(b1);
     const double f = 1.0 + psi + phi;
     // f is zero to within its rounding error (terms of psi are negative,
     // those of phi positive)
@@ -799,7 +759,7 @@ __global__ void __launch_bounds__(256) k_dc_ucol(const DcNode *__restrict__ node
     const double y = ar.dv[off + t];
     below += ((y < x) || (y == x && t < j)) ? 1.0 : 0.0;
   }
-  const int rank = (int)wsum(below);
+  const int rank = (int)wave_sum_all(below);
   if (lane == 0) {
     ar.lam[off + rank] = x;
     ar.csrc[off + rank] = j;
@@ -819,11 +779,11 @@ __global__ void __launch_bounds__(256) k_dc_ucol(const DcNode *__restrict__ node
   }
   // normalised with the entries scaled by the largest one (no underflow of
   // the squares when the entries are tiny, no overflow when they are huge)
-  const double sc = 1.0 / wmax(um);
+  const double sc = 1.0 / wave_max_all(um);
   double ss = 0.0;
 #pragma unroll
   for (int r = 0; r < kKR; ++r) ss = fma(u[r] * sc, u[r] * sc, ss);
-  const double inv = sc / sqrt(wsum(ss));
+  const double inv = sc / sqrt(wave_sum_all(ss));
 #pragma unroll
   for (int r = 0; r < kKR; ++r) {
     const int i = lane + 64 * r;
@@ -944,7 +904,7 @@ __global__ void __launch_bounds__(512) k_dc_back(int n, const double *__restrict
       double sm = 0.0;
 #pragma unroll
       for (int m = 0; m < RM; ++m) sm = fma(v[lane + 64 * m], z[m], sm);
-      sm = ts[r] * wsum(sm);
+      sm = ts[r] * wave_sum_all(sm);
 #pragma unroll
       for (int m = 0; m < RM; ++m) z[m] = fma(-sm, v[lane + 64 * m], z[m]);
     }

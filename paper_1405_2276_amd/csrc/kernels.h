@@ -14,6 +14,46 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Lane-to-lane move of a double by a DPP pattern; lanes of rows outside
+// ROWS receive 0.
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Largest of v over the 64 lanes (same DPP pattern as wave_sum_all).
+__device__ __forceinline__ double wave_max_all(double v) {
+  v = fmax(v, dpp_d<0xb1>(v));
+  v = fmax(v, dpp_d<0x4e>(v));
+  v = fmax(v, dpp_d<0x141>(v));
+  v = fmax(v, dpp_d<0x140>(v));
+  v = fmax(v, dpp_d<0x142, 0xa>(v));
+  v = fmax(v, dpp_d<0x143, 0xc>(v));
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes of a wavefront with DPP moves (pairs, quads, rows of
+// 16 by mirrors, then row broadcasts; fixed order), returned to every lane
+// from lane 63.  All 64 lanes must be active.
+__device__ __forceinline__ double wave_sum_all(double v) {
+  v += dpp_d<0xb1>(v);         // quad_perm [1,0,3,2]
+  v += dpp_d<0x4e>(v);         // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);        // row_half_mirror
+  v += dpp_d<0x140>(v);        // row_mirror
+  v += dpp_d<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_d<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // exp(x) for x <= 0 (finite), used for Matern kernel entries.  Method: Cody &
 // Waite argument reduction x = k ln2 + r with |r| <= ln2/2 (ln2 split into a
 // 32-bit-exact high part and a low correction), a degree-12 Taylor polynomial

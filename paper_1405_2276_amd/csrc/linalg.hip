@@ -676,22 +676,37 @@ void dense_ht(const int64_t *rowptr, const int32_t *col, const double *val, int 
 }
 
 // G[m, j] = H_m . P[:, j]: one wavefront per entry, lanes split the row's nnz.
+// G = H P (n_m x n_m) for CSR H and P (n x n_m, ld n): one wavefront per
+// (row m of H, 8 columns of P); lanes run over the row's entries (cells in
+// index order, so neighbouring lanes mostly read neighbouring rows of P) and
+// each entry is read once for the eight columns.
+constexpr int kGramCols = 8;
 __global__ void __launch_bounds__(256) k_gram_hp(const int64_t *__restrict__ rowptr,
                                                  const int32_t *__restrict__ col,
                                                  const double *__restrict__ val, int n_m, int64_t n,
                                                  const double *__restrict__ P,
                                                  double *__restrict__ G) {
-  int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (e >= (int64_t)n_m * n_m) return;
-  int m = (int)(e % n_m), j = (int)(e / n_m);
-  int l = threadIdx.x & 63;
-  const double *Pj = P + n * j;
-  double s = 0;
-  for (int64_t q = rowptr[m] + l; q < rowptr[m + 1]; q += 64) s = fma(val[q], Pj[col[q]], s);
-  s = wave_sum(s);
-  if (l == 0) G[m + (int64_t)n_m * j] = s;
+  const int64_t wv = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int ngrp = (n_m + kGramCols - 1) / kGramCols;
+  if (wv >= (int64_t)n_m * ngrp) return;
+  const int m = (int)(wv % n_m), j0 = (int)(wv / n_m) * kGramCols;
+  const int l = threadIdx.x & 63;
+  double s[kGramCols];
+#pragma unroll
+  for (int u = 0; u < kGramCols; ++u) s[u] = 0.0;
+  for (int64_t q = rowptr[m] + l; q < rowptr[m + 1]; q += 64) {
+    const double v = val[q];
+    const double *Pc = P + col[q];
+#pragma unroll
+    for (int u = 0; u < kGramCols; ++u)
+      if (j0 + u < n_m) s[u] = fma(v, Pc[n * (j0 + u)], s[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < kGramCols; ++u) {
+    const double t = wave_sum_all(s[u]);
+    if (l == 0 && j0 + u < n_m) G[m + (int64_t)n_m * (j0 + u)] = t;
+  }
 }
-
 __global__ void k_gram_sym(const double *__restrict__ G, int n_m, const double *__restrict__ r,
                            double *__restrict__ A) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -705,8 +720,9 @@ void innovation_gram(const int64_t *rowptr, const int32_t *col, const double *va
                      hipStream_t st) {
   int64_t e = (int64_t)n_m * n_m;
   if (e == 0) return;
-  hipLaunchKernelGGL(k_gram_hp, dim3((unsigned)((e + 3) / 4)), dim3(256), 0, st, rowptr, col, val,
-                     n_m, n, P, G);
+  const int64_t waves = (int64_t)n_m * ((n_m + kGramCols - 1) / kGramCols);
+  hipLaunchKernelGGL(k_gram_hp, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, rowptr, col,
+                     val, n_m, n, P, G);
   hipLaunchKernelGGL(k_gram_sym, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, st, G, n_m,
                      noise_var, A);
 }
