@@ -2660,6 +2660,10 @@ __global__ void __launch_bounds__(256) k_up_sparse(
 // tile e at e 4096 + (i / 16) 1024 + (k / 4) 64 + (k % 4) 16 + i % 16).  One
 // workgroup per (target leaf s = blockIdx.x, 4 rows), one wavefront per row
 // j, lanes over the leaf's points.  Rows without entries near s give zeros.
+// The counts of up to 64 near pairs are read at once (one pair per lane) and
+// only the pairs that hold entries of the row are visited; a pair's entries
+// are read 64 at a time and taken in turn across lanes, four tile entries in
+// flight.
 template <typename TT>
 __global__ void __launch_bounds__(256) k_near_sparse(
     const TT *__restrict__ frag, const int32_t *__restrict__ near_ptr,
@@ -2679,15 +2683,53 @@ __global__ void __launch_bounds__(256) k_near_sparse(
   const int ir = l < ms ? l : 0;
   const int64_t rowoff = (ir >> 4) * 1024 + (ir & 15);
   double acc = 0.0;
-  for (int e = e0; e < e1; ++e) {
-    const int t = near_src[e];
-    const int64_t lo = base + cj[t], hi = base + cj[t + 1];
-    if (lo == hi) continue;
-    const int64_t t0 = leaf_off[t];
-    const TT *A = frag + (int64_t)e * 4096 + rowoff;
-    for (int64_t h = lo; h < hi; ++h) {
-      const int k = (int)(tix[h] - t0);
-      acc = fma((double)A[(k >> 2) * 64 + (k & 3) * 16], tval[h], acc);
+  for (int eb = e0; eb < e1; eb += 64) {
+    int t = 0, clo = 0, chi = 0;
+    if (eb + l < e1) {
+      t = near_src[eb + l];
+      clo = cj[t];
+      chi = cj[t + 1];
+    }
+    uint64_t m = __ballot(chi > clo);
+    while (m) {
+      const int q = __builtin_ctzll(m);
+      m &= m - 1;
+      const int64_t lo = base + __builtin_amdgcn_readlane(clo, q);
+      const int64_t hi = base + __builtin_amdgcn_readlane(chi, q);
+      const int64_t t0 = leaf_off[__builtin_amdgcn_readlane(t, q)];
+      const TT *A = frag + (int64_t)(eb + q) * 4096 + rowoff;
+      for (int64_t h0 = lo; h0 < hi; h0 += 64) {
+        const int n = (int)min((int64_t)64, hi - h0);
+        int k = 0;
+        double v = 0.0;
+        if (l < n) {
+          k = (int)(tix[h0 + l] - t0);
+          v = tval[h0 + l];
+        }
+        const int64_t vb = __double_as_longlong(v);
+        const int vlo = (int)vb, vhi = (int)(vb >> 32);
+        int u = 0;
+        for (; u + 4 <= n; u += 4) {
+          double a[4], vv[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int kr = __builtin_amdgcn_readlane(k, u + r);
+            a[r] = (double)A[(kr >> 2) * 64 + (kr & 3) * 16];
+            vv[r] = __longlong_as_double(
+                ((int64_t)__builtin_amdgcn_readlane(vhi, u + r) << 32) |
+                (uint32_t)__builtin_amdgcn_readlane(vlo, u + r));
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc = fma(a[r], vv[r], acc);
+        }
+        for (; u < n; ++u) {
+          const int kr = __builtin_amdgcn_readlane(k, u);
+          const double vu = __longlong_as_double(
+              ((int64_t)__builtin_amdgcn_readlane(vhi, u) << 32) |
+              (uint32_t)__builtin_amdgcn_readlane(vlo, u));
+          acc = fma((double)A[(kr >> 2) * 64 + (kr & 3) * 16], vu, acc);
+        }
+      }
     }
   }
   if (l < ms) Y[perm[s0 + l] + ldy * (int64_t)j] = acc;   // column of row j of H
@@ -2712,23 +2754,29 @@ void apply_multi_t(fkf_cov *cov, const ApplyWs &ws, int nrhs, double *Y, int64_t
   const int64_t n = cov->n;
   if (cov->n_fc > 0) {
     // near field on the side stream, concurrent with the far-field chain;
-    // the downward pass then adds to its result
+    // the downward pass then adds to its result.  The sparse near field is
+    // forked after the sparse upward pass: both are latency-bound and gain
+    // nothing side by side, while the couplings leave it room
     ensure_side_stream(cov);
-    FKF_CHECK_HIP(hipEventRecord(cov->ev_fork, st));
-    FKF_CHECK_HIP(hipStreamWaitEvent(cov->side, cov->ev_fork, 0));
-    if (sp) {
-      FKF_TRACE("hmat_near_sparse", cov->side);
-      typedef typename std::conditional<F32, float, double>::type TT;
-      const TT *frag = F32 ? (const TT *)cov->frag32.p : (const TT *)cov->frag.p;
-      hipLaunchKernelGGL(k_near_sparse<TT>, dim3(cov->n_leaves, (unsigned)((nrhs + 3) / 4)),
-                         dim3(256), 0, cov->side, frag, cov->near_ptr.p, cov->near_src.p,
-                         cov->leaf_off.p, sp->rowptr, sp->j0, sp->order, nrhs, cov->sp_tix.p,
-                         cov->sp_val.p, cov->sp_cnt.p, cov->n_leaves, cov->perm.p, Y, ldy);
-    } else {
-      FKF_TRACE("hmat_near_multi", cov->side);
-      near_multi<F32>(cov, ws, nrhs, Y, ldy, cov->side);
-    }
-    FKF_CHECK_HIP(hipEventRecord(cov->ev_join, cov->side));
+    auto fork_near = [&] {
+      FKF_CHECK_HIP(hipEventRecord(cov->ev_fork, st));
+      FKF_CHECK_HIP(hipStreamWaitEvent(cov->side, cov->ev_fork, 0));
+      if (sp) {
+        FKF_TRACE("hmat_near_sparse", cov->side);
+        typedef typename std::conditional<F32, float, double>::type TT;
+        const TT *frag = F32 ? (const TT *)cov->frag32.p : (const TT *)cov->frag.p;
+        hipLaunchKernelGGL(k_near_sparse<TT>, dim3(cov->n_leaves, (unsigned)((nrhs + 3) / 4)),
+                           dim3(256), 0, cov->side, frag, cov->near_ptr.p, cov->near_src.p,
+                           cov->leaf_off.p, sp->rowptr, sp->j0, sp->order, nrhs,
+                           cov->sp_tix.p, cov->sp_val.p, cov->sp_cnt.p, cov->n_leaves,
+                           cov->perm.p, Y, ldy);
+      } else {
+        FKF_TRACE("hmat_near_multi", cov->side);
+        near_multi<F32>(cov, ws, nrhs, Y, ldy, cov->side);
+      }
+      FKF_CHECK_HIP(hipEventRecord(cov->ev_join, cov->side));
+    };
+    if (!sp) fork_near();
     if (sp) {
       FKF_TRACE("hmat_far_up_sparse", st);
       // zero 16-column blocks of every far cluster's moments (from the
@@ -2746,6 +2794,7 @@ void apply_multi_t(fkf_cov *cov, const ApplyWs &ws, int nrhs, double *Y, int64_t
       hipLaunchKernelGGL(k_sparse_ynz, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, st,
                          cov->far_ptr.p, cov->far_col.p, cov->n_fc, (nrhs + 15) / 16,
                          cov->sp_nzb.p, cov->sp_ynz.p);
+      fork_near();
     } else {
       FKF_TRACE("hmat_far_up_multi", st);
       hipLaunchKernelGGL((k_up_mfma2<D>),
