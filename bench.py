@@ -627,8 +627,10 @@ def main():
     k_entries = 2.0 * info["far_pair_entries"]
     models = {
         # site: (bound, algorithmic units per launch, unit)
-        "filter_gemv": ("hbm", 8.0 * n * n_m + 16.0 * n_m, "GB/s"),
-        "filter_gemv_sq": ("hbm", 8.0 * n * n_m + 16.0 * n_m, "GB/s"),
+        # basis U0 (N x n_m) read once; the state read and written (or the
+        # variance written) and the n_m coefficients read
+        "filter_gemv": ("hbm", 8.0 * n * n_m + 16.0 * n + 8.0 * n_m, "GB/s"),
+        "filter_gemv_sq": ("hbm", 8.0 * n * n_m + 8.0 * n + 8.0 * n_m, "GB/s"),
         # n_m-column H-matrix product on the FP64 matrix cores, one FMA per
         # entry and column: couplings of the ordered admissible pairs; the
         # near-field tiles plus the downward interpolation; the upward one

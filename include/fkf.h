@@ -408,6 +408,23 @@ fkf_status fkf_filter_realize(const fkf_filter *f, const double *g_dev, int32_t 
  * gives numbers e (cosine, e even) and e + 1 (sine). */
 fkf_status fkf_gaussian_sketch(uint64_t seed, int64_t count, double *out_dev, void *stream);
 
+/* Eigen-decomposition of a symmetric n x n FP64 matrix on the device: the
+ * solver of the projected eigenproblem of the generalized eigenvalue
+ * problem (Section 2.2.2, eq. geneigendecomposition) and of the small
+ * symmetric problems of the low-rank updates (Section 2.4, Algorithm 5).
+ * A (device, column-major, lda >= n; read only, both triangles are read and
+ * must agree) -> w (device, n eigenvalues in descending order) and W
+ * (device, n x n column-major, ldw >= n; column i the unit eigenvector of
+ * w[i]; W must not overlap A).  Orders 3..1024 take Householder
+ * tridiagonalization, divide and conquer and back-transformation; other
+ * orders take two-sided block Jacobi (off-diagonal norm below
+ * 1e-12 ||A||_F).  The workspace is allocated and freed inside the call,
+ * which synchronises the stream before it returns.  FKF_E_ARG for n < 1,
+ * lda < n, ldw < n or a null pointer; FKF_E_HIP when the workgroups of the
+ * reduction could not all run at once (the outputs are then undefined). */
+fkf_status fkf_sym_eig(const double *A, int64_t lda, int32_t n, double *w, double *W,
+                       int64_t ldw, void *stream);
+
 /* Step count k, alpha_k and the rank of the low-rank term (any may be NULL). */
 fkf_status fkf_filter_info(const fkf_filter *f, int64_t *k, double *alpha,
                            int32_t *rank);

@@ -125,6 +125,7 @@ _sig("fkf_filter_modes", _i, [_vp, _c_dbl_p, _c_dbl_p])
 _sig("fkf_filter_lowrank", _i, [_vp, _vp, ctypes.c_int64, _vp, ctypes.c_int64, _vp,
                                 ctypes.c_int32, _c_i32_p, _vp])
 _sig("fkf_filter_destroy", None, [_vp])
+_sig("fkf_sym_eig", _i, [_vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, ctypes.c_int64, _vp])
 _sig("fkf_trace_enable", _i, [ctypes.c_int32])
 _sig("fkf_trace_query", _i, [ctypes.c_char_p, _c_i64_p, _c_dbl_p])
 _sig("fkf_trace_names", _i, [ctypes.c_char_p, ctypes.c_int64])
@@ -231,6 +232,21 @@ def gaussian_sketch(seed: int, count: int, stream=None):
     out = torch.empty(max(int(count), 1), dtype=torch.float64, device="cuda")
     _check(_lib.fkf_gaussian_sketch(int(seed), int(count), out.data_ptr(), _stream(stream)))
     return out[:count]
+
+
+def sym_eig(A, stream=None):
+    """Eigen-decomposition of a symmetric CUDA float64 matrix (n, n)
+    (fkf_sym_eig): (w, W), eigenvalues descending and the unit eigenvectors
+    as the columns of a column-major (n, n) tensor."""
+    torch = _torch()
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("expected a square matrix")
+    a, lda, _ = _colmajor(A)
+    n = A.shape[0]
+    w = torch.empty(max(n, 1), dtype=torch.float64, device="cuda")
+    W = fortran_empty(max(n, 1), max(n, 1))
+    _check(_lib.fkf_sym_eig(a, lda, n, w.data_ptr(), W.data_ptr(), max(n, 1), _stream(stream)))
+    return w[:n], W[:n, :n]
 
 
 def version() -> str:

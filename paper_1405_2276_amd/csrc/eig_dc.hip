@@ -3,27 +3,28 @@
 // 2.2.2) and the small symmetric problems of the low-rank updates (Section
 // 2.4, Algorithm 5).  Three stages:
 //
-//  1. Householder reduction to tridiagonal form T = Q^T A Q.  The columns of
-//     A are dealt cyclically to G workgroups and stay in their LDS for the
-//     whole reduction; each reflector step is one exchange between the
-//     workgroups (agent-scope counter), in which every workgroup publishes
+//  1. Householder reduction to tridiagonal form T = Q^T A Q in one launch.
+//     The columns of A are dealt cyclically to G workgroups and stay in
+//     their registers for the whole reduction; each reflector step is one
+//     exchange between the workgroups, in which every workgroup publishes
 //     p = S v for its own columns and the owner of the next pivot column
-//     publishes that column.  Every workgroup then forms w, the updated
-//     pivot column and the next reflector itself (identical arithmetic in
-//     every workgroup), and applies the rank-2 update to its columns fused
-//     with the next step's p.
+//     publishes that column (each double as two tagged 64-bit words, read
+//     by polling until the tags match).  Every workgroup then forms w, the
+//     updated pivot column and the next reflector itself (identical
+//     arithmetic in every workgroup), and applies the rank-2 update to its
+//     columns fused with the next step's p.
 //  2. Divide and conquer on T (Cuppen's splitting into halves coupled by a
 //     rank-one term, down to 1 x 1 leaves).  A merge sorts the children's
 //     eigenvalues, deflates tiny components of the coupling vector and
 //     nearly equal eigenvalues (plane rotations), finds each remaining root
-//     of the secular equation 1 + rho sum z_j^2 / (d_j - lambda) = 0 by
-//     bisection on the lattice of doubles (at most 64 halvings, origin at the
-//     nearer pole so that every d_j - lambda is formed without
-//     cancellation), recomputes z from the roots by the Gu-Eisenstat product
-//     formula so that the eigenvectors z_i / (d_i - lambda_j) are numerically
-//     orthogonal, and multiplies them into the children's eigenvectors on the
-//     FP64 matrix cores.  All merges of one tree height form one launch per
-//     phase.
+//     of the secular equation 1 + rho sum z_j^2 / (d_j - lambda) = 0 by a
+//     two-pole rational model safeguarded by bisection on the lattice of
+//     doubles (origin at the nearer pole so that every d_j - lambda is
+//     formed without cancellation), recomputes z from the roots by the
+//     Gu-Eisenstat product formula so that the eigenvectors
+//     z_i / (d_i - lambda_j) are numerically orthogonal, and multiplies them
+//     into the children's eigenvectors on the FP64 matrix cores.  All merges
+//     of one tree height form one launch per phase.
 //  3. Back-transformation of T's eigenvectors by the reflectors, written in
 //     descending eigenvalue order.
 #include <algorithm>

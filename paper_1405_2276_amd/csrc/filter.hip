@@ -252,22 +252,31 @@ __global__ void __launch_bounds__(256) k_modes_step_eta(const double *__restrict
   int j = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= nmode) return;
   int l = threadIdx.x & 63;
+  // the mode's scalars are loaded before the dot product, so that their
+  // latency overlaps it
+  double *qj = llq + (int64_t)kLLStride * j;
+  const double ej = eta[j], lj = lam[j], dj = delta[j];
+  double q[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) q[c] = qj[c];
   const double *v = Ve + (int64_t)n_m * j;
   double z = 0;
   for (int m = l; m < n_m; m += 64) z = fma(v[m], y[m], z);
   z = wave_sum(z);
   if (l == 0) {
-    z -= eta[j];
-    double lj = lam[j], dj = delta[j];
+    z -= ej;
     double a = alpha - dj * lj;          // alpha_{k+1} - D_k
     double den = 1.0 + a * lj;           // (alpha - D) lambda + 1: S_k in the eigenbasis
     double g = a / den;
     double zpj = g * z;
+    const double dn = dj + a * g;        // D_{k+1} / lambda
     zp[j] = zpj;
-    delta[j] = dj + a * g;               // D_{k+1} / lambda
-    eta[j] += lj * zpj;
-    loglik_mode_step(llq + (int64_t)kLLStride * j, a * lj, lj, z);
-    if (!isfinite(zpj) || !isfinite(delta[j])) atomicExch(err, (int)FKF_E_NONFINITE);
+    delta[j] = dn;
+    eta[j] = ej + lj * zpj;
+    loglik_mode_step(q, a * lj, lj, z);
+#pragma unroll
+    for (int c = 0; c < 9; ++c) qj[c] = q[c];
+    if (!isfinite(zpj) || !isfinite(dn)) atomicExch(err, (int)FKF_E_NONFINITE);
   }
 }
 
