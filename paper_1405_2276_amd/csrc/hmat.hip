@@ -1464,8 +1464,11 @@ __global__ void __launch_bounds__(512, 2) k_down_mfma2(
     }
     __syncthreads();
     const double *A = As[buf];
+    // k-steps past the ancestor's pd multiply zeros: skipped
+    const int nkk = min(4, (pd - a0 + 3) >> 2);
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
+      if (kk >= nkk) break;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         if (q < nrb) {
@@ -1621,6 +1624,7 @@ __global__ void __launch_bounds__(512, 2) k_couple_mfma2(
   double bcur[8], bnext[8], kcur[2] = {0.0, 0.0}, knext[2] = {0.0, 0.0};
   int e = e0, k0 = 0, buf = 0;
   int mcur = e < e1 ? nz_mask(e) : 0, mnext = mcur;
+  int pdc = e < e1 ? fc[far_col[e]].pd : 0, pdn = pdc;   // partner pd of the chunk
   int mor = 0;   // blocks nonzero for some partner (the others of Yhat stay zero)
   if (e < e1) {
     load_b(e, k0, mcur, bcur);
@@ -1635,10 +1639,13 @@ __global__ void __launch_bounds__(512, 2) k_couple_mfma2(
     }
     // next chunk
     int en = e, kn = k0 + KC;
-    if (kn >= fc[far_col[e]].pd) {
+    if (kn >= pdc) {
       ++en;
       kn = 0;
-      if (en < e1) mnext = nz_mask(en);
+      if (en < e1) {
+        mnext = nz_mask(en);
+        pdn = fc[far_col[en]].pd;
+      }
     }
     if (en < e1) {
       load_b(en, kn, mnext, bnext);
@@ -1646,8 +1653,11 @@ __global__ void __launch_bounds__(512, 2) k_couple_mfma2(
     }
     __syncthreads();
     const double *K = Ks[buf];
+    // k-steps past the partner's pd multiply zeros: skipped
+    const int nkk = min(4, (pdc - k0 + 3) >> 2);
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
+      if (kk >= nkk) break;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         if (q < nrb) {
@@ -1666,6 +1676,7 @@ __global__ void __launch_bounds__(512, 2) k_couple_mfma2(
     e = en;
     k0 = kn;
     mcur = mnext;
+    pdc = pdn;
     buf ^= 1;
   }
   // with sparse moments a zero block of Yhat is not written (the downward
