@@ -46,10 +46,10 @@ constexpr int kKR = kDcMaxN / 64;    // secular terms per lane
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // Sum over the 512 threads of a workgroup in a fixed order; every thread
-// gets the result.  red: 8 doubles of LDS.
+// gets the result.  red: 8 doubles of LDS, whose previous readers must have
+// passed a barrier since (the callers alternate two such buffers).
 __device__ double block_sum512(double v, double *red) {
   v = wave_sum_all(v);
-  __syncthreads();
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
   double s = 0.0;
@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(kTrThreads) k_tridiag(const double *__restrict
   constexpr int NP = 64 * RM, NR = (NP + kTrThreads - 1) / kTrThreads;
   __shared__ double vecs[4 * NP];
   double *vv = vecs, *vn = vv + NP, *ww = vn + NP, *cc = ww + NP;
-  __shared__ double red[8];
+  __shared__ double red[16];   // two reduction buffers, used in turn
   __shared__ double pk1s;
   __shared__ int bad;
   const int g = blockIdx.x, tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
@@ -259,7 +259,7 @@ __global__ void __launch_bounds__(kTrThreads) k_tridiag(const double *__restrict
         if (i > k + 2) npart = fma(cr[r], cr[r], npart);
       }
     }
-    const double xn2 = block_sum512(npart, red);   // also orders the LDS writes
+    const double xn2 = block_sum512(npart, red + 8);   // also orders the LDS writes
     double tau_n = 0.0, beta_n = 0.0;
     if (more) {
       // reflector k + 1 from the pivot column below its diagonal
