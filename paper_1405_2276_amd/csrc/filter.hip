@@ -744,6 +744,8 @@ static void build_bases(fkf_filter *const *fs, const fkf_obs *const *os, int cou
                         hipStream_t st) {
   FKF_TRACE("gep_total", st);
   std::vector<EigProblem> probs(count);
+  int nbatch = 0;
+  double tol = 1.0;
   const bool multi = count > 1;
   LanePool *lp = multi ? &lane_pool() : nullptr;
   const std::vector<int> lane = lanes_of(fs, count);
@@ -766,14 +768,23 @@ static void build_bases(fkf_filter *const *fs, const fkf_obs *const *os, int cou
     }
     innovation_gram(o->rowptr.p, o->col.p, o->val.p, nm, n, fs[i]->bw.P.p, o->noise.p, fs[i]->bw.G.p,
                     fs[i]->bw.A.p, si);
-    probs[i] = EigProblem{fs[i]->bw.A.p, nm, nm, 0, f->lam.p, f->Ve.p, nm};
+    if (multi && sym_eig_dc_supported(nm)) {
+      // the divide-and-conquer solver per filter, on the filter's lane (up
+      // to one reduction per lane at a time: their workgroups fit the chip
+      // together, so the reductions' waits always end)
+      FKF_TRACE("gep_eig", si);
+      sym_eig(fs[i]->bw.A.p, nm, nm, f->lam.p, f->Ve.p, nm, si, f->eig, gep_tol(f), f->err.p);
+    } else {
+      probs[nbatch] = EigProblem{fs[i]->bw.A.p, nm, nm, 0, f->lam.p, f->Ve.p, nm};
+      tol = std::min(tol, gep_tol(f));
+      ++nbatch;
+    }
   }
   if (multi) lanes_join(*lp, st);
-  {
+  if (nbatch > 0) {
+    // other orders (and a single filter) as one batch
     FKF_TRACE("gep_eig", st);
-    double tol = 1.0;
-    for (int i = 0; i < count; ++i) tol = std::min(tol, gep_tol(fs[i]));
-    sym_eig_batched(probs.data(), count, st, fs[0]->eig, tol, fs[0]->err.p);
+    sym_eig_batched(probs.data(), nbatch, st, fs[0]->eig, tol, fs[0]->err.p);
   }
   if (multi) lanes_fork(*lp, st);
   for (int i = 0; i < count; ++i) {
