@@ -71,7 +71,8 @@ void spmv(const int64_t *rowptr, const int32_t *col, const double *val, int n_m,
 void dense_ht(const int64_t *rowptr, const int32_t *col, const double *val, int n_m, int64_t n,
               double *D, hipStream_t st);
 
-// A (n_m x n_m) = R^-1/2 sym(H P) R^-1/2 where P is n x n_m (ld n), R diagonal.
+// G (n_m x n_m) = H P from its upper triangle (H Gamma H^T is symmetric) and
+// A = R^-1/2 G R^-1/2, where P is n x n_m (ld n) and R diagonal.
 void innovation_gram(const int64_t *rowptr, const int32_t *col, const double *val, int n_m,
                      int64_t n, const double *P, const double *noise_var, double *G,
                      double *A, hipStream_t st);

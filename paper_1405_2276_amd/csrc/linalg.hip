@@ -694,11 +694,12 @@ void dense_ht(const int64_t *rowptr, const int32_t *col, const double *val, int 
     hipLaunchKernelGGL(k_scatter_ht, dim3(n_m), dim3(64), 0, st, rowptr, col, val, n, D);
 }
 
-// G[m, j] = H_m . P[:, j]: one wavefront per entry, lanes split the row's nnz.
-// G = H P (n_m x n_m) for CSR H and P (n x n_m, ld n): one wavefront per
-// (row m of H, 8 columns of P); lanes run over the row's entries (cells in
-// index order, so neighbouring lanes mostly read neighbouring rows of P) and
-// each entry is read once for the eight columns.
+// G = H P (n_m x n_m) for CSR H and P (n x n_m, ld n), upper triangle: one
+// wavefront per (row m of H, 8 columns of P that reach the diagonal or beyond,
+// j0 + 7 >= m); lanes run over the row's entries (cells in index order, so
+// neighbouring lanes mostly read neighbouring rows of P) and each entry is
+// read once for the eight columns.  Entries left of the diagonal in a group
+// that straddles it are formed too but not read.
 constexpr int kGramCols = 8;
 __global__ void __launch_bounds__(256) k_gram_hp(const int64_t *__restrict__ rowptr,
                                                  const int32_t *__restrict__ col,
@@ -709,6 +710,7 @@ __global__ void __launch_bounds__(256) k_gram_hp(const int64_t *__restrict__ row
   const int ngrp = (n_m + kGramCols - 1) / kGramCols;
   if (wv >= (int64_t)n_m * ngrp) return;
   const int m = (int)(wv % n_m), j0 = (int)(wv / n_m) * kGramCols;
+  if (j0 + kGramCols - 1 < m) return;   // group left of the diagonal
   const int l = threadIdx.x & 63;
   double s[kGramCols];
 #pragma unroll
@@ -726,12 +728,23 @@ __global__ void __launch_bounds__(256) k_gram_hp(const int64_t *__restrict__ row
     if (l == 0 && j0 + u < n_m) G[m + (int64_t)n_m * (j0 + u)] = t;
   }
 }
-__global__ void k_gram_sym(const double *__restrict__ G, int n_m, const double *__restrict__ r,
+// H Gamma H^T is symmetric: the upper triangle of G as formed defines it.
+// The lower triangle of G is filled from the upper one (threads below the
+// diagonal read only entries above it, which no thread writes), and
+// A = R^-1/2 G R^-1/2.
+__global__ void k_gram_sym(double *__restrict__ G, int n_m, const double *__restrict__ r,
                            double *__restrict__ A) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)n_m * n_m) return;
   int m = (int)(e % n_m), j = (int)(e / n_m);
-  A[e] = 0.5 * (G[e] + G[j + (int64_t)n_m * m]) / sqrt(r[m] * r[j]);
+  double g;
+  if (j >= m) {
+    g = G[e];
+  } else {
+    g = G[j + (int64_t)n_m * m];
+    G[e] = g;
+  }
+  A[e] = g / sqrt(r[m] * r[j]);
 }
 
 void innovation_gram(const int64_t *rowptr, const int32_t *col, const double *val, int n_m,
