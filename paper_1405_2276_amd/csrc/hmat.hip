@@ -183,6 +183,7 @@ struct fkf_cov {
   fkf::DevBuf<int32_t> sp_tix, sp_cnt;   // sparse rows in tree order, per-leaf counts
   fkf::DevBuf<int32_t> sp_nzb;           // nonzero 16-column blocks of the moments
   fkf::DevBuf<int32_t> sp_ynz;           // nonzero 16-column blocks of Yhat
+  fkf::DevBuf<int32_t> sp_plist, sp_pcnt; // partners with nonzero moments per 256 columns
   fkf::DevBuf<double> sp_val;
   // fork/join of the near field onto a second stream
   hipStream_t side = nullptr;
@@ -1526,7 +1527,8 @@ __global__ void __launch_bounds__(512, 2) k_couple_mfma2(
     const double *__restrict__ cheb, int kind, double inv_ell, double amp,
     const int64_t *__restrict__ far_koff, const void *__restrict__ kst_v,
     const double *__restrict__ xhat, int nrhs, double *__restrict__ yhat,
-    const int32_t *__restrict__ nzb) {
+    const int32_t *__restrict__ nzb, const int32_t *__restrict__ plist,
+    const int32_t *__restrict__ pcnt) {
   typedef typename std::conditional<F32, float, double>::type KT;
   const KT *__restrict__ kst = reinterpret_cast<const KT *>(kst_v);
   constexpr int KC = 16, LDK = 18;
@@ -1555,10 +1557,19 @@ __global__ void __launch_bounds__(512, 2) k_couple_mfma2(
       r /= cs.p;
     }
   }
-  const int e0 = far_ptr[it.s], e1 = far_ptr[it.s + 1];
-  // chunk sequence: (partner e, first coefficient k0)
+  // partners: the far list of it.s, or (plist) those of its partners whose
+  // moments are nonzero somewhere in this workgroup's 256 columns; chunk
+  // sequence: (partner index e, first coefficient k0), far-list entry E(e)
+  int e0 = far_ptr[it.s], e1 = far_ptr[it.s + 1];
+  const int32_t *pl = nullptr;
+  if (plist) {
+    pl = plist + (int64_t)e0 * gridDim.y + (int64_t)blockIdx.y * (e1 - e0);
+    e1 = pcnt[(int64_t)it.s * gridDim.y + blockIdx.y];
+    e0 = 0;
+  }
+  auto E = [&](int e) { return pl ? pl[e] : e; };
   auto eval_chunk = [&](int e, int k0, int buf) {
-    const FarCluster ct = fc[far_col[e]];
+    const FarCluster ct = fc[far_col[E(e)]];
     const double *ut = cheb + ct.p * 2 * kMaxCheb;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -1579,8 +1590,8 @@ __global__ void __launch_bounds__(512, 2) k_couple_mfma2(
   // the pair's matrix (column-major, leading dimension pd of the target)
   // one chunk ahead and put in LDS at the top of the chunk
   auto load_k = [&](int e, int k0, double *kv) {
-    const KT *K = kst + far_koff[e];
-    const int pdt = fc[far_col[e]].pd;
+    const KT *K = kst + far_koff[E(e)];
+    const int pdt = fc[far_col[E(e)]].pd;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int kb = k0 + ek + h;
@@ -1594,7 +1605,7 @@ __global__ void __launch_bounds__(512, 2) k_couple_mfma2(
   const int ncb16 = (nrhs + 15) >> 4;
   auto nz_mask = [&](int e) -> int {
     if (!nzb) return 3;
-    const int32_t *f = nzb + (int64_t)far_col[e] * ncb16 + (c0 >> 4);
+    const int32_t *f = nzb + (int64_t)far_col[E(e)] * ncb16 + (c0 >> 4);
     int m = 0;
 #pragma unroll
     for (int j = 0; j < 2; ++j)
@@ -1603,7 +1614,7 @@ __global__ void __launch_bounds__(512, 2) k_couple_mfma2(
   };
   // B operands of a chunk; blocks that the mask marks zero are not loaded
   auto load_b = [&](int e, int k0, int msk, double *b) {
-    const FarCluster ct = fc[far_col[e]];
+    const FarCluster ct = fc[far_col[E(e)]];
     const double *x = xhat + ct.coef_off * nrhs;
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
@@ -1624,7 +1635,7 @@ __global__ void __launch_bounds__(512, 2) k_couple_mfma2(
   double bcur[8], bnext[8], kcur[2] = {0.0, 0.0}, knext[2] = {0.0, 0.0};
   int e = e0, k0 = 0, buf = 0;
   int mcur = e < e1 ? nz_mask(e) : 0, mnext = mcur;
-  int pdc = e < e1 ? fc[far_col[e]].pd : 0, pdn = pdc;   // partner pd of the chunk
+  int pdc = e < e1 ? fc[far_col[E(e)]].pd : 0, pdn = pdc;   // partner pd of the chunk
   int mor = 0;   // blocks nonzero for some partner (the others of Yhat stay zero)
   if (e < e1) {
     load_b(e, k0, mcur, bcur);
@@ -1644,7 +1655,7 @@ __global__ void __launch_bounds__(512, 2) k_couple_mfma2(
       kn = 0;
       if (en < e1) {
         mnext = nz_mask(en);
-        pdn = fc[far_col[en]].pd;
+        pdn = fc[far_col[E(en)]].pd;
       }
     }
     if (en < e1) {
@@ -2598,6 +2609,39 @@ __global__ void __launch_bounds__(256) k_sparse_ynz(const int32_t *__restrict__ 
   ynz[g] = any;
 }
 
+// Partners of far cluster s whose moments are not all zero in the 256-column
+// block cb (some of its 16-column blocks 16 cb .. 16 cb + 15 marked in nzb),
+// in far-list order: plist[far_ptr[s] ncbw + cb deg(s) + i], i < pcnt[s ncbw
+// + cb] (deg(s) = far_ptr[s + 1] - far_ptr[s]).  One wavefront per (s, cb),
+// lanes over up to 64 partners at a time.
+__global__ void __launch_bounds__(256) k_sparse_plist(const int32_t *__restrict__ far_ptr,
+                                                      const int32_t *__restrict__ far_col,
+                                                      int n_fc, int ncb16, int ncbw,
+                                                      const int32_t *__restrict__ nzb,
+                                                      int32_t *__restrict__ plist,
+                                                      int32_t *__restrict__ pcnt) {
+  const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (g >= (int64_t)n_fc * ncbw) return;
+  const int l = threadIdx.x & 63;
+  const int s = (int)(g / ncbw), cb = (int)(g % ncbw);
+  const int e0 = far_ptr[s], e1 = far_ptr[s + 1];
+  const int b0 = 16 * cb, b1 = min(ncb16, b0 + 16);
+  int32_t *out = plist + (int64_t)e0 * ncbw + (int64_t)cb * (e1 - e0);
+  int n = 0;
+  for (int eb = e0; eb < e1; eb += 64) {
+    const int e = eb + l;
+    int any = 0;
+    if (e < e1) {
+      const int32_t *f = nzb + (int64_t)far_col[e] * ncb16;
+      for (int b = b0; b < b1; ++b) any |= f[b];
+    }
+    const uint64_t m = __ballot(any != 0);
+    if (any) out[n + __popcll(m & ((1ull << l) - 1))] = e;
+    n += __popcll(m);
+  }
+  if (l == 0) pcnt[g] = n;
+}
+
 // Moments of far cluster c = blockIdx.x for four sparse rows per workgroup
 // (rows j0 + 4 blockIdx.y + w, one wavefront each, lanes over the
 // coefficients a): xhat[c.coef_off nrhs + a + pd (j - j0)] = sum over the
@@ -2805,6 +2849,13 @@ void apply_multi_t(fkf_cov *cov, const ApplyWs &ws, int nrhs, double *Y, int64_t
       hipLaunchKernelGGL(k_sparse_ynz, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, st,
                          cov->far_ptr.p, cov->far_col.p, cov->n_fc, (nrhs + 15) / 16,
                          cov->sp_nzb.p, cov->sp_ynz.p);
+      const int ncbw = (nrhs + 255) / 256;   // column blocks of the couplings' workgroups
+      const int64_t nl = (int64_t)cov->n_fc * ncbw;
+      cov->sp_plist.reserve(std::max<size_t>(cov->far_col.n * (size_t)ncbw, 1));
+      cov->sp_pcnt.reserve((size_t)std::max<int64_t>(nl, 1));
+      hipLaunchKernelGGL(k_sparse_plist, dim3((unsigned)((nl + 3) / 4)), dim3(256), 0, st,
+                         cov->far_ptr.p, cov->far_col.p, cov->n_fc, (nrhs + 15) / 16, ncbw,
+                         cov->sp_nzb.p, cov->sp_plist.p, cov->sp_pcnt.p);
       fork_near();
     } else {
       FKF_TRACE("hmat_far_up_multi", st);
@@ -2824,6 +2875,7 @@ void apply_multi_t(fkf_cov *cov, const ApplyWs &ws, int nrhs, double *Y, int64_t
                            ws.yhat, len);
       }
       const int32_t *nzb = sp ? cov->sp_nzb.p : nullptr;   // formed before the upward pass
+      const int32_t *plist = sp ? cov->sp_plist.p : nullptr, *pcnt = sp ? cov->sp_pcnt.p : nullptr;
       if (cov->n_cm_items > 0) {
         // couplings read from the stored matrices where they are kept, else
         // evaluated into LDS chunk by chunk
@@ -2833,12 +2885,12 @@ void apply_multi_t(fkf_cov *cov, const ApplyWs &ws, int nrhs, double *Y, int64_t
           hipLaunchKernelGGL((k_couple_mfma2<D, F32, true>), grid, dim3(512), 0, st,
                              cov->cm_items.p, cov->fc.p, cov->far_ptr.p, cov->far_col.p,
                              cov->cheb.p, cov->kind, 1.0 / cov->ell, cov->amp, cov->far_koff.p,
-                             kst, ws.xhat, nrhs, ws.yhat, nzb);
+                             kst, ws.xhat, nrhs, ws.yhat, nzb, plist, pcnt);
         else
           hipLaunchKernelGGL((k_couple_mfma2<D, F32, false>), grid, dim3(512), 0, st,
                              cov->cm_items.p, cov->fc.p, cov->far_ptr.p, cov->far_col.p,
                              cov->cheb.p, cov->kind, 1.0 / cov->ell, cov->amp, nullptr,
-                             nullptr, ws.xhat, nrhs, ws.yhat, nzb);
+                             nullptr, ws.xhat, nrhs, ws.yhat, nzb, plist, pcnt);
       }
     }
   }
