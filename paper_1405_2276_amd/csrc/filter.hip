@@ -803,17 +803,19 @@ static void build_bases(fkf_filter *const *fs, const fkf_obs *const *os, int cou
       gemm_nn(n, nm, nm, fs[i]->bw.P.p, n, f->Ve.p, nm, f->U0.p, f->ldu, si);
     }
     if (f->dcov) {
-      // Ad = X^T (dGamma/d ell) X with X = H^T Ve; Cd starts at alpha Ad
+      // Ad = Ve^T H (dGamma/d ell) H^T Ve: the derivative operator applied to
+      // the sparse rows of H as for the cross covariance (P, free once the
+      // basis GEMM above has read it), G' = H (dGamma/d ell) H^T from its
+      // upper triangle, then Ad = Ve^T G' Ve; Cd starts at alpha Ad
       FKF_TRACE("loglik_length_setup", si);
-      fs[i]->bw.X.reserve((size_t)n * nm);
-      fs[i]->bw.Ht.reserve((size_t)n * nm);
-      dense_ht(o->rowptr.p, o->col.p, o->val.p, nm, n, fs[i]->bw.Ht.p, si);
-      gemm_nn(n, nm, nm, fs[i]->bw.Ht.p, n, f->Ve.p, nm, fs[i]->bw.X.p, n, si);
-      fkf_status rc = fkf_cov_apply(f->dcov, fs[i]->bw.X.p, n, nm, fs[i]->bw.P.p, n, (void *)si);
-      if (rc != FKF_OK) throw Error{rc, std::string("derivative product failed: ") + fkf_last_error()};
+      cross_cov(f->dcov, o, fs[i]->bw.Ht, fs[i]->bw.P.p, n, si);
+      innovation_gram(o->rowptr.p, o->col.p, o->val.p, nm, n, fs[i]->bw.P.p, o->noise.p,
+                      fs[i]->bw.G.p, fs[i]->bw.A.p, si);
+      gemm(false, false, nm, nm, nm, 1.0, fs[i]->bw.G.p, nm, f->Ve.p, nm, 0.0, fs[i]->bw.A.p, nm,
+           si, &f->gwork);
       f->ll_Ad.reserve((size_t)nm * nm);
       f->ll_Cd.reserve((size_t)nm * nm);
-      gemm(true, false, nm, nm, n, 1.0, fs[i]->bw.X.p, n, fs[i]->bw.P.p, n, 0.0, f->ll_Ad.p, nm, si,
+      gemm(true, false, nm, nm, nm, 1.0, f->Ve.p, nm, fs[i]->bw.A.p, nm, 0.0, f->ll_Ad.p, nm, si,
            &f->gwork);
       symmetrize(f->ll_Ad.p, nm, si);
       copy2d(nm, nm, f->ll_Ad.p, nm, f->ll_Cd.p, nm, si);
