@@ -1016,7 +1016,10 @@ void sym_eig_dc(const double *A, int64_t lda, int n, double *w, double *W, int64
   {
     FKF_TRACE("eig_tridiag", st);
     // columns in registers: RM rows per lane (n <= 64 RM), at most 8 CW
-    // columns per workgroup
+    // columns per workgroup; for 256 < n <= 512 one column per wavefront (60
+    // workgroups at n = 480: 6 % faster than two columns per wavefront on
+    // 30); at most 64 workgroups for every order, so that four reductions on
+    // separate streams always fit the chip together
     // exchange words (tags 0) and the failure flag cleared by kernels
     hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, sync, 1);
     hipLaunchKernelGGL(k_zero_d, dim3((unsigned)((8 * n + 255) / 256)), dim3(256), 0, st, xb,
@@ -1031,7 +1034,7 @@ void sym_eig_dc(const double *A, int64_t lda, int n, double *w, double *W, int64
     else if (n <= 256)
       launch(k_tridiag<4, 8>, 64);
     else if (n <= 512)
-      launch(k_tridiag<8, 2>, 16);
+      launch(k_tridiag<8, 1>, 8);
     else
       launch(k_tridiag<16, 2>, 16);
   }
