@@ -358,7 +358,7 @@ def loglik_gradient(fkf, torch, cov, wl, ys, reps=3):
 
 # kernel (name prefix in the counter output) -> launch site of the trace
 TRAFFIC_KERNELS = {
-    "void fkf::(anonymous namespace)::k_tridiag<8, 2>": "eig_tridiag",
+    "void fkf::(anonymous namespace)::k_tridiag<8, 1>": "eig_tridiag",
     "void fkf::k_couple_mfma2<2, false, true>": "hmat_far_couple_multi",
     "void (anonymous namespace)::k_near_sparse<double>": "hmat_near_sparse",
     "void fkf::k_down_mfma2<2>": "hmat_down_multi",
