@@ -18,7 +18,7 @@ import bench
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY = ("void at::native::vectorized_elementwise_kernel<4, at::native::AUnaryFunctor<double, "
         "double, double, at::native::MulFunctor<double> > >(int, ...)")
-TRIDIAG = ("void fkf::(anonymous namespace)::k_tridiag<8, 2>(double const*, long, int, int, "
+TRIDIAG = ("void fkf::(anonymous namespace)::k_tridiag<8, 1>(double const*, long, int, int, "
            "double*, double*, double*, double*, unsigned long long*, int*)")
 
 
