@@ -2642,33 +2642,25 @@ __global__ void __launch_bounds__(256) k_sparse_plist(const int32_t *__restrict_
   if (l == 0) pcnt[g] = n;
 }
 
-// Moments of far cluster c = blockIdx.x for four sparse rows per workgroup
-// (rows j0 + 4 blockIdx.y + w, one wavefront each, lanes over the
-// coefficients a): xhat[c.coef_off nrhs + a + pd (j - j0)] = sum over the
-// row's entries (i, v) inside c of v * prod_k l_{a_k}(z_k(x_i)), in the
-// sorted order; the entries inside c are those between the counts at the
-// cluster's first and end leaf.  Rows without entries in c give zeros.
+// Moments of far cluster c = blockIdx.x: xhat[c.coef_off nrhs + a + pd (j -
+// j0)] = sum over row j's entries (i, v) inside c of v * prod_k
+// l_{a_k}(z_k(x_i)), in the sorted order; the entries inside c are those
+// between the counts at the cluster's first and end leaf.  Rows without
+// entries in c give zeros; 16-column blocks marked zero in nzb are not
+// written (the couplings never read them).  Lanes run over the
+// coefficients a, four entries' loads in flight.  Clusters of more than
+// kUpBlockPts points: one wavefront per row (rows j0 + 4 blockIdx.y + w);
+// smaller ones, whose rows hold few entries: one wavefront per 16-row block
+// (block 4 blockIdx.y + w), the rows' counts read at once (one row per lane)
+// and the rows taken in turn, zero rows written without further loads.
+constexpr int64_t kUpBlockPts = 512;
+
 template <int D>
-__global__ void __launch_bounds__(256) k_up_sparse(
-    const FarCluster *__restrict__ fc, const int32_t *__restrict__ fc_leaf,
-    const double *__restrict__ lag, const int64_t *__restrict__ rowptr, int j0,
-    const int32_t *__restrict__ order, int nrhs, const int32_t *__restrict__ tix,
-    const double *__restrict__ tval, const int32_t *__restrict__ cnt, int n_leaves,
-    const int32_t *__restrict__ nzb, double *__restrict__ xhat) {
+__device__ __forceinline__ void up_sparse_row(const FarCluster &c, const double *__restrict__ lag,
+                                              const int32_t *__restrict__ tix,
+                                              const double *__restrict__ tval, int64_t lo,
+                                              int64_t hi, double *__restrict__ o, int l) {
   constexpr int PM = PMax<D>::v;
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int jj = blockIdx.y * 4 + w;
-  if (jj >= nrhs) return;
-  // a column whose 16-column block of this cluster is zero is never read
-  // (the couplings skip such blocks): nothing to write
-  if (!nzb[(int64_t)blockIdx.x * ((nrhs + 15) >> 4) + (jj >> 4)]) return;
-  const int j = order ? order[j0 + jj] : j0 + jj;
-  const FarCluster c = fc[blockIdx.x];
-  const int32_t *cj = cnt + (int64_t)jj * (n_leaves + 1);
-  const int64_t base = rowptr[j] - rowptr[0];
-  const int64_t lo = base + cj[fc_leaf[2 * blockIdx.x]];
-  const int64_t hi = base + cj[fc_leaf[2 * blockIdx.x + 1]];
-  double *o = xhat + c.coef_off * nrhs + (int64_t)c.pd * jj;
   for (int a0 = 0; a0 < c.pd; a0 += 64) {
     const int a = a0 + l;
     int dig[D];
@@ -2704,6 +2696,59 @@ __global__ void __launch_bounds__(256) k_up_sparse(
       acc = fma(tval[e], b, acc);
     }
     if (a < c.pd) o[a] = acc;
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) k_up_sparse(
+    const FarCluster *__restrict__ fc, const int32_t *__restrict__ fc_leaf,
+    const double *__restrict__ lag, const int64_t *__restrict__ rowptr, int j0,
+    const int32_t *__restrict__ order, int nrhs, const int32_t *__restrict__ tix,
+    const double *__restrict__ tval, const int32_t *__restrict__ cnt, int n_leaves,
+    const int32_t *__restrict__ nzb, double *__restrict__ xhat) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int ncb16 = (nrhs + 15) >> 4;
+  const FarCluster c = fc[blockIdx.x];
+  const int L0 = fc_leaf[2 * blockIdx.x], L1 = fc_leaf[2 * blockIdx.x + 1];
+  double *oc = xhat + c.coef_off * nrhs;
+  if (c.end - c.begin > kUpBlockPts) {
+    const int jj = blockIdx.y * 4 + w;
+    if (jj >= nrhs) return;
+    // a column whose 16-column block of this cluster is zero is never read
+    // (the couplings skip such blocks): nothing to write
+    if (!nzb[(int64_t)blockIdx.x * ncb16 + (jj >> 4)]) return;
+    const int j = order ? order[j0 + jj] : j0 + jj;
+    const int32_t *cj = cnt + (int64_t)jj * (n_leaves + 1);
+    const int64_t base = rowptr[j] - rowptr[0];
+    up_sparse_row<D>(c, lag, tix, tval, base + cj[L0], base + cj[L1], oc + (int64_t)c.pd * jj,
+                     l);
+    return;
+  }
+  const int b = blockIdx.y * 4 + w;   // 16-row block
+  if (b >= ncb16) return;
+  if (!nzb[(int64_t)blockIdx.x * ncb16 + b]) return;
+  const int jb = 16 * b, nq = min(16, nrhs - jb);
+  // lane q < nq: the entries of row jb + q inside c
+  int64_t lo_l = 0, hi_l = 0;
+  if (l < nq) {
+    const int jj = jb + l;
+    const int j = order ? order[j0 + jj] : j0 + jj;
+    const int32_t *cj = cnt + (int64_t)jj * (n_leaves + 1);
+    const int64_t base = rowptr[j] - rowptr[0];
+    lo_l = base + cj[L0];
+    hi_l = base + cj[L1];
+  }
+  for (int q = 0; q < nq; ++q) {
+    const int64_t lo = ((int64_t)__builtin_amdgcn_readlane((int)(lo_l >> 32), q) << 32) |
+                       (uint32_t)__builtin_amdgcn_readlane((int)lo_l, q);
+    const int64_t hi = ((int64_t)__builtin_amdgcn_readlane((int)(hi_l >> 32), q) << 32) |
+                       (uint32_t)__builtin_amdgcn_readlane((int)hi_l, q);
+    double *o = oc + (int64_t)c.pd * (jb + q);
+    if (lo == hi) {
+      for (int a = l; a < c.pd; a += 64) o[a] = 0.0;
+    } else {
+      up_sparse_row<D>(c, lag, tix, tval, lo, hi, o, l);
+    }
   }
 }
 
